@@ -1,0 +1,277 @@
+"""Pins of the FP64 oracle against facts fixed by the paper and by mathematics.
+
+Each test pins the oracle to something other than itself: a closed form, an
+invariant, a library routine or brute force.  A plausible slip (a dropped term,
+a wrong sign or index, a transposed operand) in the oracle fails at least one.
+"""
+import numpy as np
+import pytest
+
+import oracle as O
+
+P_CFG1 = dict(D=20e-9, Ms=474e3, K=2e3, alpha=0.1, T=295.0)
+
+
+def rng(seed):
+    return np.random.default_rng(seed)
+
+
+def random_unit(r):
+    v = r.normal(size=3)
+    return v / np.linalg.norm(v)
+
+
+def random_rotation(r):
+    q, _ = np.linalg.qr(r.normal(size=(3, 3)))
+    if np.linalg.det(q) < 0:
+        q[:, 0] *= -1
+    return q
+
+
+# ---------------------------------------------------------------- basis ---
+
+@pytest.mark.parametrize("L", [4, 10, 16])
+def test_basis_orthonormal_and_convention(L):
+    th, ph, W = O.quadrature(L + 6, 2 * L + 12)
+    Y, G = O.real_sh(L, th, ph)
+    N = (L + 1) ** 2
+    assert np.abs((Y * W) @ Y.T - np.eye(N)).max() < 1e-12
+    m, _, _ = O.unit_vectors(th, ph)
+    c = np.sqrt(3 / (4 * np.pi))
+    # no Condon-Shortley phase: Y_{1,1} ~ x, Y_{1,-1} ~ y, Y_{1,0} ~ z
+    assert np.abs(Y[O.sh_index(1, 1)] - c * m[:, 0]).max() < 1e-14
+    assert np.abs(Y[O.sh_index(1, -1)] - c * m[:, 1]).max() < 1e-14
+    assert np.abs(Y[O.sh_index(1, 0)] - c * m[:, 2]).max() < 1e-14
+
+
+@pytest.mark.parametrize("L", [6, 16])
+def test_surface_gradient_stiffness_is_laplace_spectrum(L):
+    """int grad Y_i . grad Y_j = l(l+1) delta_ij pins every gradient (theta and phi parts)."""
+    th, ph, W = O.quadrature(L + 6, 2 * L + 12)
+    Y, G = O.real_sh(L, th, ph)
+    K = np.einsum("iqa,jqa,q->ij", G, G, W)
+    ls = O.sh_degrees(L)
+    assert np.abs(K - np.diag(ls * (ls + 1.0))).max() < 1e-9
+    # gradients are tangent
+    m, _, _ = O.unit_vectors(th, ph)
+    assert np.abs(np.einsum("iqa,qa->iq", G, m)).max() < 1e-12
+
+
+def test_quadrature_exactness_brute_force():
+    """Product rule vs. brute-force closed-form moments of monomials on the sphere."""
+    from math import gamma
+    th, ph, W = O.quadrature(8, 16)
+    m, _, _ = O.unit_vectors(th, ph)
+    for (a, b, c) in [(0, 0, 0), (2, 0, 0), (2, 2, 0), (4, 2, 2), (6, 0, 4), (2, 2, 2)]:
+        num = np.sum(W * m[:, 0] ** a * m[:, 1] ** b * m[:, 2] ** c)
+        be = [(k + 1) / 2 for k in (a, b, c)]
+        exact = 2 * gamma(be[0]) * gamma(be[1]) * gamma(be[2]) / gamma(sum(be))
+        assert abs(num - exact) < 1e-13
+
+
+# ------------------------------------------------------------ operator ---
+
+def test_reduced_drift_equals_paper_drift():
+    """2 tau b(m,H,n) with the paper's p1..p4 equals grad Phi - m x grad Phi / alpha (tangent form)."""
+    r = rng(1)
+    for _ in range(5):
+        p = dict(D=r.uniform(12e-9, 30e-9), Ms=r.uniform(3e5, 5e5), K=r.uniform(100, 2e4),
+                 alpha=r.uniform(0.05, 0.5), T=r.uniform(250, 320))
+        sc = O.particle_scalars(**p)
+        n = random_unit(r)
+        B = r.normal(size=3) * 0.01            # mu0 H in tesla
+        H = B / O.MU0
+        m = random_unit(r)
+        b = (sc["p1"] * np.cross(H, m) + sc["p2"] * np.cross(np.cross(m, H), m)
+             + sc["p3"] * (n @ m) * np.cross(n, m) + sc["p4"] * (n @ m) * np.cross(np.cross(m, n), m))
+        gradPhi = sc["beta_T"] * (B - (B @ m) * m) + 2 * sc["sigma"] * (n @ m) * (n - (n @ m) * m)
+        v = gradPhi - np.cross(m, gradPhi) / p["alpha"]
+        assert np.allclose(2 * sc["tau"] * b, v, rtol=1e-12, atol=1e-12 * np.abs(v).max())
+
+
+def test_conservation_row_zero():
+    """Total probability is conserved: row 0 of every piece vanishes."""
+    r = rng(2)
+    A0, Aa, _ = O.operator_parts(P_CFG1, random_unit(r), 10)
+    scale = np.abs(A0).max()
+    assert np.abs(A0[0]).max() < 1e-13 * scale
+    for A in Aa:
+        assert np.abs(A[0]).max() < 1e-13 * np.abs(A).max()
+
+
+@pytest.mark.parametrize("seed", [3, 4, 5])
+def test_boltzmann_stationary(seed):
+    """Static field: the stationary Galerkin state reproduces the Boltzmann mean of exp(beta H.m + sigma (n.m)^2).
+
+    This pins the precession terms too (they must cancel for the Boltzmann density)."""
+    r = rng(seed)
+    n = random_unit(r)
+    B = random_unit(r) * r.uniform(2e-3, 6e-3)
+    p = dict(P_CFG1)
+    p["alpha"] = r.uniform(0.05, 0.3)
+    A0, Aa, sc = O.operator_parts(p, n, 16)
+    A = A0 + sum(B[a] * Aa[a] for a in range(3))
+    m = O.moment(O.stationary(A))
+    mb = O.boltzmann_mean(sc["beta_T"] * B, sc["sigma"], n)
+    assert np.abs(m - mb).max() < 1e-9
+
+
+def test_langevin_limit_isotropic():
+    """K = 0: <m> . H_hat = coth(beta|H|) - 1/(beta|H|) (paper Eq. Langevin)."""
+    r = rng(6)
+    p = dict(P_CFG1, K=0.0)
+    n = random_unit(r)
+    for mag in [0.5e-3, 3e-3, 8e-3]:
+        hhat = random_unit(r)
+        B = mag * hhat
+        A0, Aa, sc = O.operator_parts(p, n, 24)
+        A = A0 + sum(B[a] * Aa[a] for a in range(3))
+        m = O.moment(O.stationary(A))
+        x = sc["beta_T"] * mag
+        assert abs(m @ hhat - O.langevin(x)) < 1e-10
+        assert np.linalg.norm(m - (m @ hhat) * hhat) < 1e-10
+
+
+def test_stationary_matches_svd_null_vector():
+    r = rng(7)
+    A0, Aa, _ = O.operator_parts(P_CFG1, random_unit(r), 8)
+    A = A0 + 3e-3 * Aa[0] - 1e-3 * Aa[2]
+    c = O.stationary(A)
+    _, s, vh = np.linalg.svd(A)
+    v = vh[-1] / vh[-1][0] * c[0]
+    assert s[-1] < 1e-8 * s[0]
+    assert np.abs(v - c).max() < 1e-11
+
+
+# ---------------------------------------------------------- dynamics ---
+
+def test_isotropic_diffusion_decay():
+    """H = 0, K = 0: each coefficient decays as exp(-l(l+1) t / (2 tau))."""
+    L = 6
+    p = dict(P_CFG1, K=0.0)
+    A0, Aa, sc = O.operator_parts(p, [0, 0, 1], L)
+    r = rng(8)
+    c0 = r.normal(size=(L + 1) ** 2)
+    tau = sc["tau"]
+    period = 2 * tau
+    ns = 8
+    cs = O.integrate_samples(lambda t: A0, c0, period, ns, 0, 32)
+    ls = O.sh_degrees(L)
+    ts = np.arange(ns) * period / ns
+    exact = c0[None, :] * np.exp(-ls[None, :] * (ls[None, :] + 1) * ts[:, None] / (2 * tau))
+    assert np.abs(cs - exact).max() < 1e-7 * np.abs(c0).max()
+
+
+def test_radau_order_five():
+    """y' = cos(t) y, y(0) = 1 has y = exp(sin t); global error falls as h^5."""
+    errs = []
+    for r in [2, 4, 8]:
+        cs = O.integrate_samples(lambda t: np.array([[np.cos(t)]]), [1.0], 2.0, 2, 0, r)
+        errs.append(abs(cs[1, 0] - np.exp(np.sin(1.0))))
+    orders = np.log2(np.array(errs[:-1]) / np.array(errs[1:]))
+    assert np.all(orders > 4.6), orders
+
+
+def test_probability_conserved_in_time():
+    r = rng(9)
+    drive = dict(amp=(12e-3, 0, 0), freq=(25e3, 0, 0), phase=(0, 0, 0), period=40e-6)
+    res = O.solve_instance(P_CFG1, random_unit(r), 8, drive, 40, 0, 5, r=1)
+    assert abs(res["c_last"][0] - 1 / np.sqrt(4 * np.pi)) < 1e-15
+
+
+def test_debye_linear_response():
+    """K = 0, weak drive beta*H0 = 1e-3: bin 1 of m_x equals (beta H0 / 6) / (1 + i omega tau)."""
+    p = dict(P_CFG1, K=0.0)
+    sc = O.particle_scalars(**p)
+    H0 = 1e-3 / sc["beta_T"]
+    f = 5e6
+    drive = dict(amp=(H0, 0, 0), freq=(f, 0, 0), phase=(0, 0, 0), period=1 / f)
+    ns = 32
+    res = O.solve_instance(p, [0, 0, 1], 4, drive, ns, 6, 2, r=4)
+    M1 = np.sum(res["m"][:, 0] * np.exp(-2j * np.pi * np.arange(ns) / ns)) / ns
+    omega_tau = 2 * np.pi * f * sc["tau"]
+    pred = (1e-3 / 6) / (1 + 1j * omega_tau)
+    assert abs(M1 - pred) < 2e-5 * abs(pred)
+    assert abs(res["Phi"][1, 0] - (2j * np.pi * f) * pred) < 2e-5 * abs(2j * np.pi * f * pred)
+
+
+def test_rotating_field_matches_rotating_frame_null_vector():
+    """n = z, H = H0 (cos wt, sin wt, 0): settled m(t) = R_z(wt) m_rot, with m_rot from the
+    null vector of the static rotating-frame operator A(H0 x) + w d/dphi."""
+    L = 10
+    f = 25e3
+    H0 = 8e-3
+    drive = dict(amp=(H0, H0, 0), freq=(f, f, 0), phase=(0, -np.pi / 2, 0), period=1 / f)
+    ns = 100
+    res = O.solve_instance(P_CFG1, [0, 0, 1], L, drive, ns, 2, 3, r=2)
+    A0, Aa, _ = O.operator_parts(P_CFG1, [0, 0, 1], L)
+    g = O.stationary(A0 + H0 * Aa[0] + 2 * np.pi * f * O.azimuth_generator(L))
+    mg = O.moment(g)
+    w = 2 * np.pi * f
+    ts = 2 / f + np.arange(ns) / (ns * f)
+    pred = np.stack([np.cos(w * ts) * mg[0] - np.sin(w * ts) * mg[1],
+                     np.sin(w * ts) * mg[0] + np.cos(w * ts) * mg[1],
+                     np.full(ns, mg[2])], 1)
+    assert np.abs(pred - res["m"]).max() < 1e-9
+
+
+def test_rotation_invariance():
+    """m(Qn, QH(t)) = Q m(n, H(t)) for a proper rotation Q (static and driven)."""
+    r = rng(10)
+    Q = random_rotation(r)
+    n = random_unit(r)
+    B = random_unit(r) * 5e-3
+    L = 10
+    A0, Aa, _ = O.operator_parts(P_CFG1, n, L)
+    m1 = O.moment(O.stationary(A0 + sum(B[a] * Aa[a] for a in range(3))))
+    A0q, Aaq, _ = O.operator_parts(P_CFG1, Q @ n, L)
+    QB = Q @ B
+    m2 = O.moment(O.stationary(A0q + sum(QB[a] * Aaq[a] for a in range(3))))
+    assert np.abs(Q @ m1 - m2).max() < 1e-12
+    # driven along a rotated 1D axis
+    e = np.array([1.0, 0.0, 0.0])
+    amp = 10e-3
+    d1 = dict(amp=tuple(amp * e), freq=(25e3,) * 3, phase=(0, 0, 0), period=40e-6)
+    d2 = dict(amp=tuple(amp * (Q @ e)), freq=(25e3,) * 3, phase=(0, 0, 0), period=40e-6)
+    off = np.array([1e-3, -2e-3, 0.5e-3])
+    ra = O.solve_instance(P_CFG1, n, 8, d1, 40, 1, 4, r=1, offset=off)
+    rb = O.solve_instance(P_CFG1, Q @ n, 8, d2, 40, 1, 4, r=1, offset=Q @ off)
+    assert np.abs(ra["m"] @ Q.T - rb["m"]).max() < 1e-11
+
+
+def test_axisymmetric_drive_half_wave_symmetry():
+    """K = 0, 1D drive along x, zero offset: m stays on x and even harmonics vanish."""
+    p = dict(P_CFG1, K=0.0)
+    drive = dict(amp=(12e-3, 0, 0), freq=(25e3, 0, 0), phase=(0, 0, 0), period=40e-6)
+    res = O.solve_instance(p, [0.3, 0.4, np.sqrt(0.75)], 10, drive, 64, 2, 8, r=1)
+    assert np.abs(res["m"][:, 1:]).max() < 1e-12
+    ph = np.abs(res["Phi"][:, 0])
+    assert ph[[0, 2, 4, 6, 8]].max() < 1e-9 * ph[1]
+
+
+# ------------------------------------------------------------ signal ---
+
+def test_harmonics_match_library_fft_and_band_limited_derivative():
+    r = rng(11)
+    T = 1e-3
+    ns = 64
+    m = r.normal(size=(ns, 3))
+    Phi = O.harmonics_from_samples(m, T, 20)
+    F = np.fft.fft(m, axis=0) / ns
+    k = np.arange(21)
+    assert np.abs(Phi - (2j * np.pi * k / T)[:, None] * F[:21]).max() < 1e-12 * np.abs(Phi).max()
+    # band-limited: m = cos(2 pi 3 t / T) => Phi_3 = (2 pi i 3 / T) / 2, others 0
+    t = np.arange(ns) * T / ns
+    Phi = O.harmonics_from_samples(np.cos(2 * np.pi * 3 * t / T)[:, None], T, 10)
+    assert abs(Phi[3, 0] - 1j * np.pi * 3 / T) < 1e-10 * (3 / T)
+    assert np.abs(np.delete(Phi[:, 0], 3)).max() < 1e-10 * (3 / T)
+
+
+def test_exact_by_parts_route_agrees_with_rhs_route_when_resolved():
+    """When the trajectory is band-limited well below Nyquist (slow drive, weak field),
+    the by-parts harmonics equal the rectangle rule on RHS-evaluated dm/dt."""
+    p = dict(P_CFG1)
+    drive = dict(amp=(2e-3, 1e-3, 0), freq=(25e3, 50e3, 0), phase=(0, 0, 0), period=40e-6)
+    res = O.solve_instance(p, [np.cos(0.5), np.sin(0.5), 0], 8, drive, 400, 1, 10, r=2)
+    a, b = res["Phi"][1:, :2], res["Phi_rect"][1:, :2]
+    assert np.linalg.norm(a - b) < 1e-6 * np.linalg.norm(b)
