@@ -1,0 +1,192 @@
+#!/usr/bin/env python3
+"""Throughput of the Fokker-Planck system-matrix solver on one MI355X.
+
+Workload: the 2D Lissajous system matrix (17 x 17 offsets on +-12 mT x 8 easy-axis
+angles = 2312 instances, L = 16, 1632 samples, 1 settle + 1 recorded period,
+harmonics 0..200).  One step = one fpn_solve over the whole batch: instance
+preparation, FP64 stationary start, FP32 time stepping, moment sampling and the
+harmonic reduction.  Inputs are resident in device memory before timing starts.
+
+Prints one JSON line with the contract fields plus "roofline" (time stepper,
+algorithmic FP32 flops per launch over its HIP-event-measured launch duration)
+and "cpu_baseline" (the FP64 oracle timed on a bounded sample on the host).
+"""
+import argparse
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+FP32_VECTOR_PEAK_TFLOPS = 157.3   # MI355X: 256 CU x 2.4 GHz x 256 FP32 flop/clk/CU
+
+
+def block_structure(L):
+    """|m|-block sizes of the block order used by the solver (block 0 padded to even size)."""
+    n0 = (L + 1) + ((L + 1) % 2)
+    return [n0] + [2 * (L + 1 - k) for k in range(1, L + 1)]
+
+
+def coupling_counts(fpn, L):
+    """Nonzeros of the operator per |m| block: diagonal (D), lower (B) and upper (C) couplings."""
+    A = fpn.fpn_host_operator(L, 20e-9, 474e3, 2e3, 0.1, 295.0, [3e-3, -2e-3, 1e-3])
+    ms = np.array([m for l in range(L + 1) for m in range(-l, l + 1)])
+    blk = np.abs(ms)
+    nz = A != 0
+    nD = np.zeros(L + 1, int)
+    nB = np.zeros(L + 1, int)
+    nC = np.zeros(L + 1, int)
+    for k in range(L + 1):
+        rows = blk == k
+        nD[k] = nz[np.ix_(rows, blk == k)].sum()
+        if k > 0:
+            nB[k] = nz[np.ix_(rows, blk == k - 1)].sum()
+        if k < L:
+            nC[k] = nz[np.ix_(rows, blk == k + 1)].sum()
+    return nD, nB, nC, int(nz.sum())
+
+
+def flops_per_step(fpn, L):
+    """Algorithmic FP32 flops of one RODAS4 step of one instance (6 stages, one factorisation):
+      factorisation: sum_k 2 n_k^3 (block inverse) + 2 nnz(B_k) n_{k-1} + 2 nnz(C_{k-1}) n_k (Schur)
+                     + 2 nnz(D) (assembly)
+      per stage:     2 nnz (matvec) + sum_k [4 n_k^2 + 2 nnz(B_k) + 2 nnz(C_k)] (block solve)
+                     + 13 N (stage combinations, on average)
+      plus one matvec for the time derivative of the field term."""
+    n = block_structure(L)
+    N = (L + 1) ** 2
+    nD, nB, nC, nnz = coupling_counts(fpn, L)
+    fac = sum(2 * nk ** 3 for nk in n) + 2 * int(nD.sum())
+    fac += sum(2 * nB[k] * n[k - 1] + 2 * nC[k - 1] * n[k] for k in range(1, L + 1))
+    solve = sum(4 * nk ** 2 for nk in n) + 2 * int(nB.sum()) + 2 * int(nC.sum())
+    stage = 2 * nnz + solve + 13 * N
+    return fac + 6 * stage + 2 * nnz
+
+
+def cpu_baseline(ws, budget_s=15.0):
+    """The FP64 oracle (as it stands) on a bounded sample: one instance of the workload,
+    operator build + stationary start + as many Radau IIA steps (2 per sample) as fit in
+    the budget; the per-solve time is extrapolated to the full (settle+1)*N_s*2 steps."""
+    import oracle as O
+    try:
+        from threadpoolctl import threadpool_info
+        threads = max([i.get("num_threads", 1) for i in threadpool_info()] or [1])
+    except Exception:
+        threads = os.cpu_count()
+    inst = {k: v[0] for k, v in ws["inst"].items()}
+    p = dict(D=inst["D"], Ms=inst["Ms"], K=inst["K"], alpha=inst["alpha"], T=inst["T"])
+    t0 = time.perf_counter()
+    A0, Aa, _ = O.operator_parts(p, inst["easy_axis"], int(inst["L"]))
+    off = inst["offset"]
+
+    def Afun(t):
+        B = O.drive_field(ws["drive"], off, t)
+        return A0 + B[0] * Aa[0] + B[1] * Aa[1] + B[2] * Aa[2]
+
+    c = O.stationary(Afun(0.0))
+    t_setup = time.perf_counter() - t0
+    r = 2
+    h = ws["drive"]["period"] / (ws["samples"] * r)
+    steps = 0
+    t1 = time.perf_counter()
+    while time.perf_counter() - t1 < budget_s:
+        c = O.radau_step(Afun, steps * h, c, h)
+        steps += 1
+    t_step = (time.perf_counter() - t1) / steps
+    total_steps = (ws["settle"] + 1) * ws["samples"] * r
+    per_solve = t_setup + total_steps * t_step
+    return {"value": 1.0 / per_solve, "unit": "solves/s", "cores": int(threads), "kind": "oracle",
+            "sample": f"1 instance (L={int(inst['L'])}): operator build + stationary start + {steps} of "
+                      f"{total_steps} Radau IIA steps (r={r}); per-solve time extrapolated"}
+
+
+def main():
+    ap = argparse.ArgumentParser(description=__doc__.split("\n")[0])
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=3)
+    ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--substeps", type=int, default=3)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--cpu-budget", type=float, default=15.0)
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print("bench.py measures one GPU only: this build has no multi-GPU path "
+              "(instances are independent; see DESIGN.md for how the batch would shard).", file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+    import paper_2106_08040_amd as fpn
+    import workloads as W
+
+    ws = W.lissajous_grid()
+    n = ws["inst"]["D"].size
+    dev = "cuda:0"
+    torch.cuda.set_device(0)
+    ctx = fpn.Context(0)
+    inst = {k: torch.as_tensor(v, dtype=torch.float64, device=dev) for k, v in ws["inst"].items() if k != "L"}
+    L = ws["inst"]["L"]
+    d = ws["drive"]
+    drive = fpn.make_drive(d["amp"], d["freq"], d["period"], d["phase"])
+    out = {"m": torch.empty((n, 3, ws["samples"]), dtype=torch.float32, device=dev),
+           "harm": torch.empty((n, 2, ws["n_harm"] + 1, 2), dtype=torch.float32, device=dev),
+           "status": torch.empty((n,), dtype=torch.int32, device=dev)}
+
+    def step():
+        ctx.solve(inst, L, drive, ws["samples"], ws["settle"], ws["n_harm"], substeps=args.substeps, out=out)
+
+    for _ in range(args.warmup):
+        step()
+    torch.cuda.synchronize()
+    bad = int((out["status"] != 0).sum().item())
+    ctx.timing_enable(True)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        step()
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    timing = ctx.timing_read()
+    ctx.timing_enable(False)
+    wall = t1 - t0
+    ms_per_step = wall / args.steps * 1e3
+    value = n * args.steps / wall
+
+    Lv = int(L[0])
+    spp = (ws["settle"] + 1) * ws["samples"] * args.substeps
+    step_ms, launches = timing["stepper"]
+    flops_launch = float(flops_per_step(fpn, Lv)) * spp * n
+    avg_ms = step_ms / max(launches, 1)
+    achieved = flops_launch / (avg_ms * 1e-3) / 1e12
+    res = {
+        "metric": "FP solves/sec & surrogate evals/sec at ≤1e-3 rel-L2 vs FP64 oracle",
+        "value": value,
+        "unit": "solves/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": ms_per_step,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32",
+        "data": "synthetic",
+        "config": {"workload": ws["name"], "instances": n, "L": Lv, "samples": ws["samples"],
+                   "settle_periods": ws["settle"], "n_harm": ws["n_harm"], "substeps": args.substeps,
+                   "integrator": "RODAS4", "failed_instances": bad},
+        "roofline": {"bound": "alu", "kernel": "stepper", "achieved": achieved, "peak": FP32_VECTOR_PEAK_TFLOPS,
+                     "unit": "TFLOP/s", "frac": achieved / FP32_VECTOR_PEAK_TFLOPS, "traffic": None,
+                     "avg_launch_ms": avg_ms, "flops_per_launch": flops_launch,
+                     "kernel_ms": {k: v[0] / max(v[1], 1) for k, v in timing.items()}},
+    }
+    if not args.no_cpu_baseline:
+        res["cpu_baseline"] = cpu_baseline(ws, args.cpu_budget)
+    print(json.dumps(res), flush=True)
+    ctx.close()
+
+
+if __name__ == "__main__":
+    main()

@@ -1,0 +1,163 @@
+/*
+ * fpn.h -- C ABI of the MI355X Neel-rotation Fokker-Planck solver (libfpn.so).
+ *
+ * Physics (arXiv 2106.08040, Methods, "Particle magnetization model"):
+ *   mean moment  m(t) = int_{S^2} m f(m,t) dm          (Eq. mean_magmom_FP, reported / m0)
+ *   df/dt = div(grad f)/(2 tau) - div(b f)             (Eq. FP-general)
+ *   b = p1 H x m + p2 (m x H) x m + p3 (n.m) n x m + p4 (n.m)(m x n) x m   (Eq. convection)
+ *   with p1..p4, tau, gamma~ as defined right after Eq. convection, beta and V_C as in model M0.
+ * Signal (Eq. MPI_model_fourier and the phi-hat definition of model M1):
+ *   Phi_k = (1/T) int_0^T dm/dt e^{-2 pi i t k / T} dt, evaluated as
+ *   (2 pi i k / T) (1/N_s) sum_j m(t_j) e^{-2 pi i j k / N_s}  (exact integration by parts
+ *   of the periodic moment, rectangle rule on m).
+ *
+ * Discretisation: real spherical-harmonic Galerkin expansion of degree <= L,
+ * solved in the easy-axis frame; L-stable linearly implicit stepping (RODAS4)
+ * in FP32 with the stationary initial state computed in FP64.
+ *
+ * Conventions shared by every call:
+ *   - Fields are mu0*H in tesla, lab frame.  Outputs are lab frame.
+ *   - Every instance array is DEVICE memory unless stated otherwise; the caller
+ *     owns all buffers and keeps them alive until the stream has completed.
+ *   - Calls are asynchronous on `stream` (a hipStream_t passed as void*, NULL = default
+ *     stream).  Argument errors are detected on the host before any launch and
+ *     returned synchronously; numerical failures are per instance in `status`
+ *     (outputs of a failed instance are NaN) and the call still returns FPN_OK.
+ *   - All calls are thread-safe for distinct contexts; one context per host thread.
+ */
+#ifndef FPN_H
+#define FPN_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef int32_t fpn_status;
+enum {
+  FPN_OK = 0,
+  FPN_E_ARG = -1,          /* invalid argument (NULL pointer, bad size, bad option) */
+  FPN_E_RANGE = -2,        /* value out of the supported range (e.g. L) */
+  FPN_E_DEVICE = -3,       /* HIP runtime error */
+  FPN_E_NOMEM = -4,        /* device allocation failed */
+  FPN_E_UNSUPPORTED = -7   /* valid request this build does not implement */
+};
+
+/* per-instance status codes written to `status[i]` */
+enum {
+  FPN_INST_OK = 0,
+  FPN_INST_BAD_PARAM = 1,  /* non-finite or non-positive parameter, |n| != 1 */
+  FPN_INST_NONFINITE = 2,  /* non-finite state during stepping */
+  FPN_INST_SINGULAR = 3    /* zero pivot in a block inversion */
+};
+
+/* Static description of a status code (never NULL). */
+const char* fpn_status_string(fpn_status s);
+/* Detail text of the last error on the calling host thread ("" if none). */
+const char* fpn_last_error(void);
+
+typedef struct fpn_ctx_s* fpn_ctx;
+
+/* Create a context bound to HIP device `device`.  The context owns the per-L
+ * operator tables, drive tables and workspace; the caller owns *out and frees it
+ * with fpn_destroy.  Errors: FPN_E_ARG (out == NULL), FPN_E_DEVICE. */
+fpn_status fpn_create(fpn_ctx* out, int device);
+fpn_status fpn_destroy(fpn_ctx ctx);
+
+/* Drive field (Eq. complete-problem's H_DF):
+ *   mu0 H_a(t) = amp[a] * cos(2 pi freq[a] t + phase[a])   [T],  a = x, y, z.
+ * `period` is the repetition time T [s]; every freq[a]*period must be an
+ * integer (checked to 1e-9), so the field is T-periodic.  Host memory. */
+typedef struct {
+  double amp[3];
+  double freq[3];
+  double phase[3];
+  double period;
+} fpn_drive;
+
+/* Flags for fpn_solve_opts.flags */
+enum {
+  FPN_OUT_M = 1u,          /* write m_out */
+  FPN_OUT_HARM = 2u,       /* write harm_out */
+  FPN_HARM_Z = 4u          /* harm_out has 3 channels (x, y, z) instead of 2 (x, y) */
+};
+
+/* Host memory. */
+typedef struct {
+  int32_t samples_per_period;  /* N_s >= 2 */
+  int32_t settle_periods;      /* >= 0; the period with index settle_periods is recorded */
+  int32_t n_harm;              /* K_h: harmonic bins 0..K_h, 0 <= K_h < N_s/2 */
+  int32_t substeps;            /* time steps per sample interval, 1..64 */
+  uint32_t flags;              /* FPN_OUT_* */
+} fpn_solve_opts;
+
+/* One batch of instances in structure-of-arrays form.  Instance parameters
+ * (paper: D, M_S, K^anis, alpha, T_B, easy axis n, selection-field offset) are
+ * DEVICE arrays of length n in SI units; `L` (Galerkin degree per instance) is a
+ * HOST array because the launch plan depends on it. */
+typedef struct {
+  const double* D;         /* core diameter [m] */
+  const double* Ms;        /* saturation magnetisation [A/m] */
+  const double* K;         /* uniaxial anisotropy constant [J/m^3], >= 0 */
+  const double* alpha;     /* damping, > 0 */
+  const double* temp;      /* temperature T_B [K] */
+  const double* easy_axis; /* [n][3], unit vectors (|n| = 1 within 1e-6) */
+  const double* offset;    /* [n][3], static offset mu0*H_SF [T] */
+  const int32_t* L;        /* HOST [n], 1 <= L <= FPN_MAX_L */
+} fpn_batch;
+
+#define FPN_MAX_L 16
+
+/* Periodic response of every instance to drive + offset (the system-matrix columns).
+ * Procedure: stationary density of the field at t = 0 (FP64), then
+ * (settle_periods + 1) periods of FP32 time stepping; the last period is sampled
+ * at t_j = settle_periods*T + j T / N_s.
+ * Outputs (DEVICE, may be NULL when the matching flag is off):
+ *   m_out    [n][3][N_s]          float, dimensionless <m> (lab frame)
+ *   harm_out [n][ch][K_h+1][2]    float, (re, im) of Phi_k [1/s], ch = 2 or 3
+ *   status   [n]                  int32, FPN_INST_* (required)
+ * Errors: FPN_E_ARG, FPN_E_RANGE (L), FPN_E_DEVICE, FPN_E_NOMEM. */
+fpn_status fpn_solve(fpn_ctx ctx, const fpn_drive* drive, const fpn_solve_opts* opts,
+                     const fpn_batch* batch, int64_t n,
+                     float* m_out, float* harm_out, int32_t* status, void* stream);
+
+/* Stationary mean moment under a static field (FP64 on the device):
+ * the null vector of the Galerkin operator with total probability 1.
+ *   field  [n][3] DEVICE, mu0*H [T] lab frame
+ *   m_out  [n][3] DEVICE, dimensionless <m> (lab frame)
+ *   status [n]    DEVICE int32 */
+fpn_status fpn_stationary(fpn_ctx ctx, const fpn_batch* batch, int64_t n, const double* field,
+                          double* m_out, int32_t* status, void* stream);
+
+/* Kernel timing (diagnostic).  When enabled, every kernel launch of fpn_solve and
+ * fpn_stationary is bracketed by HIP events recorded on the launch stream; reading
+ * synchronises those events and returns the accumulated device time.
+ *   fpn_timing_enable: enable != 0 starts (and clears) the counters, 0 stops them.
+ *   fpn_timing_read:   ms_out[4] and launches_out[4] (HOST) receive, in this order,
+ *                      instance preparation, stationary solve, time stepper, harmonics.
+ * Errors: FPN_E_ARG, FPN_E_DEVICE. */
+fpn_status fpn_timing_enable(fpn_ctx ctx, int enable);
+fpn_status fpn_timing_read(fpn_ctx ctx, double* ms_out, int64_t* launches_out);
+
+/* ---- host-only helpers (no device needed; used to check the operator build) ---- */
+
+/* Dense Galerkin operator A (1/s) of one particle in its easy-axis frame, built
+ * from the library's own operator tables: dc/dt = A c with c in flat SH order
+ * i = l*l + l + m.  field_easy is mu0*H [T] in the easy-axis frame (n = z).
+ * A_out: HOST, (L+1)^2 x (L+1)^2 row-major doubles.  Errors: FPN_E_ARG, FPN_E_RANGE. */
+fpn_status fpn_host_operator(int32_t L, double D, double Ms, double K, double alpha, double temp,
+                             const double field_easy[3], double* A_out);
+
+/* The rotation R (row-major 3x3, HOST) with R * (0,0,1) = n used to map lab vectors
+ * into the easy-axis frame (v_easy = R^T v_lab).  Errors: FPN_E_ARG (|n| not 1). */
+fpn_status fpn_host_frame(const double n[3], double R_out[9]);
+
+/* Number of nonzeros of the operator tables for degree L (diagnostic). */
+int64_t fpn_host_table_nnz(int32_t L);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* FPN_H */

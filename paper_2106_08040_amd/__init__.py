@@ -1,0 +1,240 @@
+"""Python binding of libfpn (include/fpn.h): argument marshalling only.
+
+Every step of the solver runs in the library's HIP kernels; PyTorch is used here
+for device memory and streams.  Importing this package fails loudly when the
+compiled library is missing (build it with ``python paper_2106_08040_amd/build.py``).
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libfpn.so")
+
+if not os.path.exists(LIB_PATH):
+    raise ImportError(f"libfpn.so not built at {LIB_PATH}; run `python paper_2106_08040_amd/build.py`")
+
+# PyTorch's HIP runtime must be the one in the process before libfpn is loaded, so that the
+# library binds to it (same SONAME) instead of loading a second HIP/HSA runtime.
+try:
+    import torch as _torch_mod  # noqa: F401
+except ImportError:  # host-only helpers still work without torch
+    _torch_mod = None
+
+_lib = ctypes.CDLL(LIB_PATH)
+
+FPN_OK, FPN_E_ARG, FPN_E_RANGE, FPN_E_DEVICE, FPN_E_NOMEM, FPN_E_UNSUPPORTED = 0, -1, -2, -3, -4, -7
+FPN_INST_OK, FPN_INST_BAD_PARAM, FPN_INST_NONFINITE, FPN_INST_SINGULAR = 0, 1, 2, 3
+FPN_OUT_M, FPN_OUT_HARM, FPN_HARM_Z = 1, 2, 4
+FPN_MAX_L = 16
+
+EXPORTED = ["fpn_status_string", "fpn_last_error", "fpn_create", "fpn_destroy", "fpn_solve",
+            "fpn_stationary", "fpn_timing_enable", "fpn_timing_read", "fpn_host_operator", "fpn_host_frame",
+            "fpn_host_table_nnz"]
+
+
+class fpn_drive(ctypes.Structure):
+    _fields_ = [("amp", ctypes.c_double * 3), ("freq", ctypes.c_double * 3),
+                ("phase", ctypes.c_double * 3), ("period", ctypes.c_double)]
+
+
+class fpn_solve_opts(ctypes.Structure):
+    _fields_ = [("samples_per_period", ctypes.c_int32), ("settle_periods", ctypes.c_int32),
+                ("n_harm", ctypes.c_int32), ("substeps", ctypes.c_int32), ("flags", ctypes.c_uint32)]
+
+
+class fpn_batch(ctypes.Structure):
+    _fields_ = [("D", ctypes.c_void_p), ("Ms", ctypes.c_void_p), ("K", ctypes.c_void_p),
+                ("alpha", ctypes.c_void_p), ("temp", ctypes.c_void_p), ("easy_axis", ctypes.c_void_p),
+                ("offset", ctypes.c_void_p), ("L", ctypes.POINTER(ctypes.c_int32))]
+
+
+_vp = ctypes.c_void_p
+_lib.fpn_status_string.restype = ctypes.c_char_p
+_lib.fpn_status_string.argtypes = [ctypes.c_int32]
+_lib.fpn_last_error.restype = ctypes.c_char_p
+_lib.fpn_last_error.argtypes = []
+_lib.fpn_create.restype = ctypes.c_int32
+_lib.fpn_create.argtypes = [ctypes.POINTER(_vp), ctypes.c_int]
+_lib.fpn_destroy.restype = ctypes.c_int32
+_lib.fpn_destroy.argtypes = [_vp]
+_lib.fpn_solve.restype = ctypes.c_int32
+_lib.fpn_solve.argtypes = [_vp, ctypes.POINTER(fpn_drive), ctypes.POINTER(fpn_solve_opts),
+                           ctypes.POINTER(fpn_batch), ctypes.c_int64, _vp, _vp, _vp, _vp]
+_lib.fpn_stationary.restype = ctypes.c_int32
+_lib.fpn_stationary.argtypes = [_vp, ctypes.POINTER(fpn_batch), ctypes.c_int64, _vp, _vp, _vp, _vp]
+_lib.fpn_timing_enable.restype = ctypes.c_int32
+_lib.fpn_timing_enable.argtypes = [_vp, ctypes.c_int]
+_lib.fpn_timing_read.restype = ctypes.c_int32
+_lib.fpn_timing_read.argtypes = [_vp, ctypes.POINTER(ctypes.c_double), ctypes.POINTER(ctypes.c_int64)]
+_lib.fpn_host_operator.restype = ctypes.c_int32
+_lib.fpn_host_operator.argtypes = [ctypes.c_int32, ctypes.c_double, ctypes.c_double, ctypes.c_double,
+                                   ctypes.c_double, ctypes.c_double, ctypes.POINTER(ctypes.c_double),
+                                   ctypes.POINTER(ctypes.c_double)]
+_lib.fpn_host_frame.restype = ctypes.c_int32
+_lib.fpn_host_frame.argtypes = [ctypes.POINTER(ctypes.c_double), ctypes.POINTER(ctypes.c_double)]
+_lib.fpn_host_table_nnz.restype = ctypes.c_int64
+_lib.fpn_host_table_nnz.argtypes = [ctypes.c_int32]
+
+
+class FpnError(RuntimeError):
+    def __init__(self, code, where):
+        msg = _lib.fpn_status_string(code).decode()
+        detail = _lib.fpn_last_error().decode()
+        super().__init__(f"{where}: {msg} ({code}): {detail}")
+        self.code = code
+
+
+def _check(code, where):
+    if code != FPN_OK:
+        raise FpnError(code, where)
+
+
+def fpn_status_string(code):
+    return _lib.fpn_status_string(code).decode()
+
+
+def fpn_last_error():
+    return _lib.fpn_last_error().decode()
+
+
+# ------------------------------------------------------------------ host helpers ---
+
+def fpn_host_operator(L, D, Ms, K, alpha, T, field_easy):
+    """Dense Galerkin operator (1/s, SH order) built from the library's tables."""
+    N = (L + 1) ** 2
+    A = np.zeros((N, N), dtype=np.float64)
+    f = (ctypes.c_double * 3)(*[float(x) for x in field_easy])
+    _check(_lib.fpn_host_operator(int(L), D, Ms, K, alpha, T, f,
+                                  A.ctypes.data_as(ctypes.POINTER(ctypes.c_double))), "fpn_host_operator")
+    return A
+
+
+def fpn_host_frame(n):
+    R = np.zeros(9, dtype=np.float64)
+    nn = (ctypes.c_double * 3)(*[float(x) for x in n])
+    _check(_lib.fpn_host_frame(nn, R.ctypes.data_as(ctypes.POINTER(ctypes.c_double))), "fpn_host_frame")
+    return R.reshape(3, 3)
+
+
+def fpn_host_table_nnz(L):
+    return int(_lib.fpn_host_table_nnz(int(L)))
+
+
+# ------------------------------------------------------------------ device calls ---
+
+def _torch():
+    import torch
+    return torch
+
+
+def _dev_f64(x, device):
+    torch = _torch()
+    t = torch.as_tensor(x, dtype=torch.float64, device=device)
+    return t.contiguous()
+
+
+def make_drive(amp, freq, period, phase=(0.0, 0.0, 0.0)):
+    d = fpn_drive()
+    d.amp[:] = [float(a) for a in amp]
+    d.freq[:] = [float(f) for f in freq]
+    d.phase[:] = [float(p) for p in phase]
+    d.period = float(period)
+    return d
+
+
+class Context:
+    """Owns an fpn context on one HIP device (tables, drive tables, workspace)."""
+
+    def __init__(self, device=0):
+        torch = _torch()
+        if not torch.cuda.is_available():
+            raise RuntimeError("no HIP device visible: the fpn library needs an MI355X (gfx950)")
+        self.device = device
+        self._h = _vp()
+        torch.cuda.set_device(device)
+        _check(_lib.fpn_create(ctypes.byref(self._h), int(device)), "fpn_create")
+
+    def close(self):
+        if self._h:
+            _lib.fpn_destroy(self._h)
+            self._h = _vp()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def _batch(self, inst, L):
+        """inst: dict of D, Ms, K, alpha, T, easy_axis [n,3], offset [n,3]; kept alive by the caller."""
+        dev = f"cuda:{self.device}"
+        t = {k: _dev_f64(inst[k], dev) for k in ("D", "Ms", "K", "alpha", "T", "easy_axis")}
+        t["offset"] = _dev_f64(inst["offset"], dev) if inst.get("offset") is not None else None
+        Lh = np.ascontiguousarray(np.broadcast_to(np.asarray(L, dtype=np.int32), (t["D"].numel(),)))
+        b = fpn_batch(t["D"].data_ptr(), t["Ms"].data_ptr(), t["K"].data_ptr(), t["alpha"].data_ptr(),
+                      t["T"].data_ptr(), t["easy_axis"].data_ptr(),
+                      t["offset"].data_ptr() if t["offset"] is not None else None,
+                      Lh.ctypes.data_as(ctypes.POINTER(ctypes.c_int32)))
+        return b, t, Lh
+
+    def solve(self, inst, L, drive, samples, settle, n_harm, substeps=3, want_m=True, want_harm=True,
+              harm_z=False, stream=None, out=None):
+        """Run fpn_solve.  Returns (m [n,3,Ns] float32, harm [n,ch,Kh+1] complex64, status [n] int32)
+        as torch tensors on the device (None for outputs not requested)."""
+        torch = _torch()
+        dev = f"cuda:{self.device}"
+        b, keep, Lh = self._batch(inst, L)
+        n = keep["D"].numel()
+        ch = 3 if harm_z else 2
+        if out is None:
+            out = {}
+        m = out.get("m") if want_m else None
+        if want_m and m is None:
+            m = torch.empty((n, 3, samples), dtype=torch.float32, device=dev)
+        hm = out.get("harm") if want_harm else None
+        if want_harm and hm is None:
+            hm = torch.empty((n, ch, n_harm + 1, 2), dtype=torch.float32, device=dev)
+        st = out.get("status")
+        if st is None:
+            st = torch.empty((n,), dtype=torch.int32, device=dev)
+        opts = fpn_solve_opts(samples, settle, n_harm, substeps,
+                              (FPN_OUT_M if want_m else 0) | (FPN_OUT_HARM if want_harm else 0) |
+                              (FPN_HARM_Z if harm_z else 0))
+        s = stream if stream is not None else torch.cuda.current_stream(self.device)
+        code = _lib.fpn_solve(self._h, ctypes.byref(drive), ctypes.byref(opts), ctypes.byref(b), n,
+                              m.data_ptr() if m is not None else None,
+                              hm.data_ptr() if hm is not None else None, st.data_ptr(), s.cuda_stream)
+        _check(code, "fpn_solve")
+        self._keep = (keep, Lh)  # inputs alive until the next call on this context
+        harm = torch.view_as_complex(hm) if hm is not None else None
+        return m, harm, st
+
+    TIMING_KERNELS = ("instance_prep", "stationary", "stepper", "harmonics")
+
+    def timing_enable(self, on=True):
+        _check(_lib.fpn_timing_enable(self._h, 1 if on else 0), "fpn_timing_enable")
+
+    def timing_read(self):
+        """{kernel: (total_ms, launches)} accumulated since timing_enable(True)."""
+        ms = (ctypes.c_double * 4)()
+        cnt = (ctypes.c_int64 * 4)()
+        _check(_lib.fpn_timing_read(self._h, ms, cnt), "fpn_timing_read")
+        return {k: (ms[i], cnt[i]) for i, k in enumerate(self.TIMING_KERNELS)}
+
+    def stationary(self, inst, L, field):
+        torch = _torch()
+        dev = f"cuda:{self.device}"
+        b, keep, Lh = self._batch(inst, L)
+        n = keep["D"].numel()
+        f = _dev_f64(field, dev)
+        m = torch.empty((n, 3), dtype=torch.float64, device=dev)
+        st = torch.empty((n,), dtype=torch.int32, device=dev)
+        s = torch.cuda.current_stream(self.device)
+        _check(_lib.fpn_stationary(self._h, ctypes.byref(b), n, f.data_ptr(), m.data_ptr(), st.data_ptr(),
+                                   s.cuda_stream), "fpn_stationary")
+        torch.cuda.synchronize(self.device)
+        return m, st

@@ -1,0 +1,68 @@
+"""Build libfpn.so (HIP kernels for gfx950 + C ABI) in-tree.
+
+Usage: python paper_2106_08040_amd/build.py [-v]
+"""
+import os
+import subprocess
+import sys
+from concurrent.futures import ThreadPoolExecutor
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+CSRC = os.path.join(HERE, "csrc")
+BUILD = os.path.join(HERE, "_build")
+LIB = os.path.join(HERE, "libfpn.so")
+ARCH = "gfx950"
+HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
+CLANG = "/opt/rocm/llvm/bin/clang++"
+
+
+def _runtime_dir():
+    """Directory of the libamdhip64.so the Python process uses (PyTorch's), else /opt/rocm/lib."""
+    try:
+        import importlib.util
+        spec = importlib.util.find_spec("torch")
+        if spec and spec.origin:
+            d = os.path.join(os.path.dirname(spec.origin), "lib")
+            if os.path.exists(os.path.join(d, "libamdhip64.so")):
+                return d
+    except Exception:
+        pass
+    return "/opt/rocm/lib"
+# packed FP32 VALU instructions are disabled for all device code
+HIP_FLAGS = ["-O3", "-std=c++17", f"--offload-arch={ARCH}", "-fPIC",
+             "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops", "-Wno-unused-result"]
+
+
+def _run(cmd):
+    r = subprocess.run(cmd, stdout=subprocess.PIPE, stderr=subprocess.STDOUT, text=True)
+    if r.returncode != 0:
+        raise RuntimeError("build step failed:\n" + " ".join(cmd) + "\n" + r.stdout)
+    return r.stdout
+
+
+def build(jobs=4, verbose=False):
+    os.makedirs(BUILD, exist_ok=True)
+    steps = [
+        [HIPCC, *HIP_FLAGS, "-c", os.path.join(CSRC, "kernels.hip"), "-o", os.path.join(BUILD, "kernels.o")],
+        [HIPCC, *HIP_FLAGS, "-c", os.path.join(CSRC, "capi.hip"), "-o", os.path.join(BUILD, "capi.o")],
+        ["g++", "-O2", "-std=c++17", "-fPIC", "-c", os.path.join(CSRC, "structure.cpp"),
+         "-o", os.path.join(BUILD, "structure.o")],
+    ]
+    with ThreadPoolExecutor(max_workers=jobs) as ex:
+        outs = list(ex.map(_run, steps))
+    if verbose:
+        for o in outs:
+            print(o, end="")
+    tmp = LIB + ".tmp"
+    # Link against the HIP runtime that PyTorch loads (NEEDED libamdhip64.so, torch's copy first on
+    # the runpath) so one process never holds two HIP/HSA runtimes; /opt/rocm/lib is the fallback.
+    hiplib = _runtime_dir()
+    _run([CLANG, "-shared", "-fPIC", "-o", tmp,
+          os.path.join(BUILD, "kernels.o"), os.path.join(BUILD, "capi.o"), os.path.join(BUILD, "structure.o"),
+          f"-L{hiplib}", "-l:libamdhip64.so", f"-Wl,-rpath,{hiplib}:/opt/rocm/lib", "-lstdc++"])
+    os.replace(tmp, LIB)
+    return LIB
+
+
+if __name__ == "__main__":
+    print(build(verbose="-v" in sys.argv))

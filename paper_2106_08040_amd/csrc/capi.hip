@@ -1,0 +1,530 @@
+// C ABI of libfpn (include/fpn.h): argument validation, launch planning, context state.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <map>
+#include <memory>
+#include <mutex>
+#include <string>
+#include <vector>
+
+#include "../../include/fpn.h"
+#include "device_common.hpp"
+#include "kernels.hpp"
+#include "physics.hpp"
+#include "structure.hpp"
+
+namespace {
+
+thread_local std::string g_last_error;
+
+fpn_status fail(fpn_status s, const std::string& msg) {
+  g_last_error = msg;
+  return s;
+}
+
+#define FPN_HIP(call)                                                                      \
+  do {                                                                                     \
+    hipError_t e_ = (call);                                                                \
+    if (e_ != hipSuccess)                                                                  \
+      return fail(e_ == hipErrorOutOfMemory ? FPN_E_NOMEM : FPN_E_DEVICE,                  \
+                  std::string(#call) + ": " + hipGetErrorString(e_));                      \
+  } while (0)
+
+template <typename T>
+struct DevBuf {
+  T* p = nullptr;
+  size_t cap = 0;
+  hipError_t ensure(size_t n) {
+    if (n <= cap) return hipSuccess;
+    if (p) (void)hipFree(p);
+    p = nullptr;
+    cap = 0;
+    hipError_t e = hipMalloc(&p, std::max<size_t>(n, 1) * sizeof(T));
+    if (e == hipSuccess) cap = n;
+    return e;
+  }
+  void release() {
+    if (p) (void)hipFree(p);
+    p = nullptr;
+    cap = 0;
+  }
+};
+
+struct TableSet {
+  fpn::DevTables t{};
+  std::vector<void*> allocs;
+};
+
+struct DriveCache {
+  fpn_drive d{};
+  int Ns = 0, r = 0;
+  bool valid = false;
+  DevBuf<float4> table;
+};
+
+}  // namespace
+
+struct fpn_ctx_s {
+  int device = 0;
+  std::mutex mu;
+  std::map<int, TableSet> tables;
+  DriveCache drive;
+  DevBuf<double2> twiddle;
+  int tw_N = 0;
+  DevBuf<fpn::InstParams> ip;
+  DevBuf<double> c0;
+  DevBuf<double> wsinv;
+  DevBuf<float> msamp;
+  DevBuf<int32_t> idx;
+  // kernel timing
+  bool timing = false;
+  std::vector<std::pair<int, std::pair<hipEvent_t, hipEvent_t>>> events;
+  double ms[4] = {0, 0, 0, 0};
+  int64_t launches[4] = {0, 0, 0, 0};
+};
+
+namespace {
+
+fpn_status get_tables(fpn_ctx ctx, int L, const fpn::DevTables** out) {
+  auto it = ctx->tables.find(L);
+  if (it != ctx->tables.end()) {
+    *out = &it->second.t;
+    return FPN_OK;
+  }
+  const fpn::OperatorTables* h = nullptr;
+  try {
+    h = &fpn::operator_tables(L);
+  } catch (const std::exception& e) {
+    return fail(FPN_E_RANGE, e.what());
+  }
+  TableSet ts;
+  fpn::DevTables& t = ts.t;
+  t.L = L;
+  t.N = h->N;
+  t.Np = h->Np;
+  t.n0 = h->n0;
+  t.nnz = int(h->colkind.size());
+  t.nnzc = int(h->crowkind.size());
+  t.inv_doubles = 0;
+  for (int b : h->bn) t.inv_doubles += int64_t(b) * b;
+  auto up = [&](auto** dst, const auto& src) -> hipError_t {
+    using E = typename std::remove_reference<decltype(src)>::type::value_type;
+    void* p = nullptr;
+    hipError_t e = hipMalloc(&p, std::max<size_t>(src.size(), 1) * sizeof(E));
+    if (e != hipSuccess) return e;
+    ts.allocs.push_back(p);
+    e = hipMemcpy(p, src.data(), src.size() * sizeof(E), hipMemcpyHostToDevice);
+    *dst = reinterpret_cast<typename std::remove_pointer<typename std::remove_reference<decltype(dst)>::type>::type>(p);
+    return e;
+  };
+  std::vector<int32_t> boff(h->boff.begin(), h->boff.end()), bn(h->bn.begin(), h->bn.end());
+  hipError_t e = hipSuccess;
+  if (e == hipSuccess) e = up(&t.seg, h->seg);
+  if (e == hipSuccess) e = up(&t.colkind, h->colkind);
+  if (e == hipSuccess) e = up(&t.val, h->val);
+  if (e == hipSuccess) e = up(&t.val64, h->val64);
+  if (e == hipSuccess) e = up(&t.cptr, h->cptr);
+  if (e == hipSuccess) e = up(&t.crowkind, h->crowkind);
+  if (e == hipSuccess) e = up(&t.cval, h->cval);
+  if (e == hipSuccess) e = up(&t.cval64, h->cval64);
+  if (e == hipSuccess) e = up(&t.boff, boff);
+  if (e == hipSuccess) e = up(&t.bn, bn);
+  if (e != hipSuccess) {
+    for (void* p : ts.allocs) (void)hipFree(p);
+    return fail(e == hipErrorOutOfMemory ? FPN_E_NOMEM : FPN_E_DEVICE, hipGetErrorString(e));
+  }
+  auto res = ctx->tables.emplace(L, std::move(ts));
+  *out = &res.first->second.t;
+  return FPN_OK;
+}
+
+// Records a pair of events around `launch` on `stream` when timing is on.
+template <typename F>
+fpn_status timed(fpn_ctx ctx, int which, hipStream_t stream, F&& launch) {
+  hipEvent_t a = nullptr, b = nullptr;
+  if (ctx->timing) {
+    FPN_HIP(hipEventCreate(&a));
+    FPN_HIP(hipEventCreate(&b));
+    FPN_HIP(hipEventRecord(a, stream));
+  }
+  fpn_status st = launch();
+  if (ctx->timing) {
+    FPN_HIP(hipEventRecord(b, stream));
+    ctx->events.push_back({which, {a, b}});
+  }
+  return st;
+}
+
+bool same_drive(const fpn_drive& a, const fpn_drive& b) { return std::memcmp(&a, &b, sizeof(fpn_drive)) == 0; }
+
+fpn_status validate_drive(const fpn_drive* d) {
+  if (!d) return fail(FPN_E_ARG, "drive is NULL");
+  if (!(d->period > 0.0) || !std::isfinite(d->period)) return fail(FPN_E_ARG, "drive.period must be > 0");
+  for (int a = 0; a < 3; ++a) {
+    if (!std::isfinite(d->amp[a]) || !std::isfinite(d->freq[a]) || !std::isfinite(d->phase[a]))
+      return fail(FPN_E_ARG, "drive has a non-finite entry");
+    if (d->freq[a] < 0.0) return fail(FPN_E_ARG, "drive.freq must be >= 0");
+    const double cyc = d->freq[a] * d->period;
+    if (d->amp[a] != 0.0 && std::fabs(cyc - std::round(cyc)) > 1e-9 * std::max(1.0, cyc))
+      return fail(FPN_E_ARG, "drive.freq * period must be an integer (T-periodic drive)");
+  }
+  return FPN_OK;
+}
+
+// Drive table for one period: for step n, t_n = n h:
+//   [0..3] mu0 H(t_n + al h), al = 0, 0.386, 0.21, 0.63;  [4] d(mu0 H)/dt (t_n).
+fpn_status ensure_drive(fpn_ctx ctx, const fpn_drive& d, int Ns, int r, hipStream_t stream) {
+  DriveCache& c = ctx->drive;
+  if (c.valid && same_drive(c.d, d) && c.Ns == Ns && c.r == r) return FPN_OK;
+  const int spp = Ns * r;
+  const double h = d.period / spp;
+  const double al[4] = {0.0, 0.386, 0.21, 0.63};
+  std::vector<float4> tab(size_t(spp) * 5);
+  for (int n = 0; n < spp; ++n) {
+    for (int e = 0; e < 5; ++e) {
+      const double t = (n + (e < 4 ? al[e] : 0.0)) * h;
+      double v[3];
+      for (int a = 0; a < 3; ++a) {
+        const double w = 2.0 * fpn::kPi * d.freq[a];
+        v[a] = (e < 4) ? d.amp[a] * std::cos(w * t + d.phase[a]) : -d.amp[a] * w * std::sin(w * t + d.phase[a]);
+      }
+      tab[size_t(n) * 5 + e] = make_float4(float(v[0]), float(v[1]), float(v[2]), 0.0f);
+    }
+  }
+  FPN_HIP(c.table.ensure(tab.size()));
+  FPN_HIP(hipMemcpyAsync(c.table.p, tab.data(), tab.size() * sizeof(float4), hipMemcpyHostToDevice, stream));
+  FPN_HIP(hipStreamSynchronize(stream));
+  c.d = d;
+  c.Ns = Ns;
+  c.r = r;
+  c.valid = true;
+  return FPN_OK;
+}
+
+fpn_status ensure_twiddle(fpn_ctx ctx, int Ns, hipStream_t stream) {
+  if (ctx->tw_N == Ns) return FPN_OK;
+  std::vector<double2> tw(Ns);
+  for (int j = 0; j < Ns; ++j) {
+    const double a = 2.0 * fpn::kPi * double(j) / double(Ns);
+    tw[j] = make_double2(std::cos(a), std::sin(a));
+  }
+  FPN_HIP(ctx->twiddle.ensure(Ns));
+  FPN_HIP(hipMemcpyAsync(ctx->twiddle.p, tw.data(), Ns * sizeof(double2), hipMemcpyHostToDevice, stream));
+  FPN_HIP(hipStreamSynchronize(stream));
+  ctx->tw_N = Ns;
+  return FPN_OK;
+}
+
+fpn_status validate_batch(const fpn_batch* b, int64_t n) {
+  if (!b) return fail(FPN_E_ARG, "batch is NULL");
+  if (!b->D || !b->Ms || !b->K || !b->alpha || !b->temp || !b->easy_axis || !b->L)
+    return fail(FPN_E_ARG, "batch has a NULL array");
+  for (int64_t i = 0; i < n; ++i)
+    if (b->L[i] < 1 || b->L[i] > FPN_MAX_L)
+      return fail(FPN_E_RANGE, "batch.L[" + std::to_string(i) + "] = " + std::to_string(b->L[i]) +
+                                   " outside [1, " + std::to_string(FPN_MAX_L) + "]");
+  return FPN_OK;
+}
+
+// Instances grouped by L (ascending), each group in batch order.
+std::vector<std::pair<int, std::vector<int32_t>>> group_by_L(const int32_t* L, int64_t n) {
+  std::map<int, std::vector<int32_t>> g;
+  for (int64_t i = 0; i < n; ++i) g[L[i]].push_back(int32_t(i));
+  return {g.begin(), g.end()};
+}
+
+}  // namespace
+
+extern "C" {
+
+const char* fpn_status_string(fpn_status s) {
+  switch (s) {
+    case FPN_OK: return "ok";
+    case FPN_E_ARG: return "invalid argument";
+    case FPN_E_RANGE: return "value out of supported range";
+    case FPN_E_DEVICE: return "HIP device error";
+    case FPN_E_NOMEM: return "device out of memory";
+    case FPN_E_UNSUPPORTED: return "unsupported";
+    default: return "unknown status";
+  }
+}
+
+const char* fpn_last_error(void) { return g_last_error.c_str(); }
+
+fpn_status fpn_create(fpn_ctx* out, int device) {
+  if (!out) return fail(FPN_E_ARG, "out is NULL");
+  *out = nullptr;
+  int count = 0;
+  FPN_HIP(hipGetDeviceCount(&count));
+  if (device < 0 || device >= count) return fail(FPN_E_ARG, "device index out of range");
+  auto* c = new fpn_ctx_s();
+  c->device = device;
+  *out = c;
+  return FPN_OK;
+}
+
+fpn_status fpn_destroy(fpn_ctx ctx) {
+  if (!ctx) return fail(FPN_E_ARG, "ctx is NULL");
+  (void)hipSetDevice(ctx->device);
+  (void)hipDeviceSynchronize();
+  for (auto& kv : ctx->tables)
+    for (void* p : kv.second.allocs) (void)hipFree(p);
+  ctx->drive.table.release();
+  ctx->twiddle.release();
+  ctx->ip.release();
+  ctx->c0.release();
+  ctx->wsinv.release();
+  ctx->msamp.release();
+  ctx->idx.release();
+  delete ctx;
+  return FPN_OK;
+}
+
+fpn_status fpn_solve(fpn_ctx ctx, const fpn_drive* drive, const fpn_solve_opts* opts, const fpn_batch* batch,
+                     int64_t n, float* m_out, float* harm_out, int32_t* status, void* stream_) {
+  if (!ctx) return fail(FPN_E_ARG, "ctx is NULL");
+  if (!opts) return fail(FPN_E_ARG, "opts is NULL");
+  if (n < 0) return fail(FPN_E_ARG, "n < 0");
+  if (fpn_status s = validate_drive(drive)) return s;
+  const int Ns = opts->samples_per_period, r = opts->substeps, Kh = opts->n_harm;
+  if (Ns < 2) return fail(FPN_E_ARG, "samples_per_period must be >= 2");
+  if (opts->settle_periods < 0) return fail(FPN_E_ARG, "settle_periods must be >= 0");
+  if (r < 1 || r > 64) return fail(FPN_E_ARG, "substeps must be in [1, 64]");
+  if (Kh < 0 || 2 * Kh >= Ns) return fail(FPN_E_ARG, "n_harm must satisfy 0 <= n_harm < samples_per_period/2");
+  if (int64_t(Ns) * r * (opts->settle_periods + 1) > (int64_t(1) << 30))
+    return fail(FPN_E_ARG, "too many time steps");
+  if (opts->flags & ~uint32_t(FPN_OUT_M | FPN_OUT_HARM | FPN_HARM_Z)) return fail(FPN_E_ARG, "unknown flag");
+  const bool want_m = opts->flags & FPN_OUT_M, want_h = opts->flags & FPN_OUT_HARM;
+  if (want_m && !m_out) return fail(FPN_E_ARG, "FPN_OUT_M set but m_out is NULL");
+  if (want_h && !harm_out) return fail(FPN_E_ARG, "FPN_OUT_HARM set but harm_out is NULL");
+  if (!status && n > 0) return fail(FPN_E_ARG, "status is NULL");
+  if (n == 0) return FPN_OK;
+  if (n > (int64_t(1) << 31) - 1) return fail(FPN_E_ARG, "n too large");
+  if (fpn_status s = validate_batch(batch, n)) return s;
+  std::lock_guard<std::mutex> lk(ctx->mu);
+  hipStream_t stream = reinterpret_cast<hipStream_t>(stream_);
+  FPN_HIP(hipSetDevice(ctx->device));
+
+  auto groups = group_by_L(batch->L, n);
+  int Lmax = 0;
+  for (auto& g : groups) Lmax = std::max(Lmax, g.first);
+  std::map<int, const fpn::DevTables*> tabs;
+  int64_t inv_max = 0, np_max = 0;
+  for (auto& g : groups) {
+    const fpn::DevTables* t = nullptr;
+    if (fpn_status s = get_tables(ctx, g.first, &t)) return s;
+    tabs[g.first] = t;
+    inv_max = std::max<int64_t>(inv_max, t->inv_doubles);
+    np_max = std::max<int64_t>(np_max, t->Np);
+  }
+  if (fpn_status s = ensure_drive(ctx, *drive, Ns, r, stream)) return s;
+  if (want_h)
+    if (fpn_status s = ensure_twiddle(ctx, Ns, stream)) return s;
+  FPN_HIP(ctx->ip.ensure(n));
+  FPN_HIP(ctx->c0.ensure(size_t(n) * np_max));
+  FPN_HIP(ctx->idx.ensure(n));
+  float* msamp = m_out;
+  if (!want_m) {
+    FPN_HIP(ctx->msamp.ensure(size_t(n) * 3 * Ns));
+    msamp = ctx->msamp.p;
+  }
+  // largest group bounds the stationary workspace
+  size_t maxg = 0;
+  for (auto& g : groups) maxg = std::max(maxg, g.second.size());
+  FPN_HIP(ctx->wsinv.ensure(maxg * size_t(inv_max)));
+  std::vector<int32_t> order;
+  order.reserve(n);
+  for (auto& g : groups) order.insert(order.end(), g.second.begin(), g.second.end());
+  FPN_HIP(hipMemcpyAsync(ctx->idx.p, order.data(), n * sizeof(int32_t), hipMemcpyHostToDevice, stream));
+
+  if (fpn_status s = timed(ctx, 0, stream, [&]() -> fpn_status {
+        fpn::launch_instance_prep(n, batch->D, batch->Ms, batch->K, batch->alpha, batch->temp, batch->easy_axis,
+                                  batch->offset, ctx->ip.p, status, stream);
+        FPN_HIP(hipGetLastError());
+        return FPN_OK;
+      }))
+    return s;
+  double3 d0;
+  d0.x = drive->amp[0] * std::cos(drive->phase[0]);
+  d0.y = drive->amp[1] * std::cos(drive->phase[1]);
+  d0.z = drive->amp[2] * std::cos(drive->phase[2]);
+  int64_t start = 0;
+  for (auto& g : groups) {
+    const fpn::DevTables& t = *tabs[g.first];
+    const int cnt = int(g.second.size());
+    const int32_t* idx = ctx->idx.p + start;
+    if (fpn_status s = timed(ctx, 1, stream, [&]() -> fpn_status {
+          fpn::launch_stationary(t, idx, cnt, ctx->ip.p, nullptr, d0, ctx->c0.p, np_max, ctx->wsinv.p, status,
+                                 stream);
+          FPN_HIP(hipGetLastError());
+          return FPN_OK;
+        }))
+      return s;
+    fpn::StepLaunch sl;
+    sl.ip = ctx->ip.p;
+    sl.inst_idx = idx;
+    sl.n_inst = cnt;
+    sl.c0 = ctx->c0.p;
+    sl.c_stride = np_max;
+    sl.drive = ctx->drive.table.p;
+    sl.spp = Ns * r;
+    sl.substeps = r;
+    sl.settle = opts->settle_periods;
+    sl.Ns = Ns;
+    sl.h = float(drive->period / (double(Ns) * r));
+    sl.msamp = msamp;
+    sl.status = status;
+    if (fpn_status s = timed(ctx, 2, stream, [&]() -> fpn_status {
+          FPN_HIP(fpn::launch_stepper(g.first, sl, t, stream));
+          return FPN_OK;
+        }))
+      return s;
+    start += cnt;
+  }
+  if (want_h) {
+    const int nch = (opts->flags & FPN_HARM_Z) ? 3 : 2;
+    if (fpn_status s = timed(ctx, 3, stream, [&]() -> fpn_status {
+          fpn::launch_harmonics(msamp, Ns, Kh, nch, drive->period, ctx->twiddle.p, harm_out, status, n, stream);
+          FPN_HIP(hipGetLastError());
+          return FPN_OK;
+        }))
+      return s;
+  }
+  return FPN_OK;
+}
+
+fpn_status fpn_timing_enable(fpn_ctx ctx, int enable) {
+  if (!ctx) return fail(FPN_E_ARG, "ctx is NULL");
+  std::lock_guard<std::mutex> lk(ctx->mu);
+  for (auto& e : ctx->events) {
+    (void)hipEventSynchronize(e.second.second);
+    (void)hipEventDestroy(e.second.first);
+    (void)hipEventDestroy(e.second.second);
+  }
+  ctx->events.clear();
+  for (int k = 0; k < 4; ++k) { ctx->ms[k] = 0.0; ctx->launches[k] = 0; }
+  ctx->timing = enable != 0;
+  return FPN_OK;
+}
+
+fpn_status fpn_timing_read(fpn_ctx ctx, double* ms_out, int64_t* launches_out) {
+  if (!ctx || !ms_out || !launches_out) return fail(FPN_E_ARG, "NULL argument");
+  std::lock_guard<std::mutex> lk(ctx->mu);
+  FPN_HIP(hipSetDevice(ctx->device));
+  for (auto& e : ctx->events) {
+    FPN_HIP(hipEventSynchronize(e.second.second));
+    float ms = 0.0f;
+    FPN_HIP(hipEventElapsedTime(&ms, e.second.first, e.second.second));
+    ctx->ms[e.first] += ms;
+    ctx->launches[e.first] += 1;
+    (void)hipEventDestroy(e.second.first);
+    (void)hipEventDestroy(e.second.second);
+  }
+  ctx->events.clear();
+  for (int k = 0; k < 4; ++k) {
+    ms_out[k] = ctx->ms[k];
+    launches_out[k] = ctx->launches[k];
+  }
+  return FPN_OK;
+}
+
+fpn_status fpn_stationary(fpn_ctx ctx, const fpn_batch* batch, int64_t n, const double* field, double* m_out,
+                          int32_t* status, void* stream_) {
+  if (!ctx) return fail(FPN_E_ARG, "ctx is NULL");
+  if (n < 0) return fail(FPN_E_ARG, "n < 0");
+  if (n == 0) return FPN_OK;
+  if (!field || !m_out || !status) return fail(FPN_E_ARG, "field, m_out and status are required");
+  if (fpn_status s = validate_batch(batch, n)) return s;
+  std::lock_guard<std::mutex> lk(ctx->mu);
+  hipStream_t stream = reinterpret_cast<hipStream_t>(stream_);
+  FPN_HIP(hipSetDevice(ctx->device));
+  auto groups = group_by_L(batch->L, n);
+  std::map<int, const fpn::DevTables*> tabs;
+  int64_t inv_max = 0, np_max = 0;
+  size_t maxg = 0;
+  for (auto& g : groups) {
+    const fpn::DevTables* t = nullptr;
+    if (fpn_status s = get_tables(ctx, g.first, &t)) return s;
+    tabs[g.first] = t;
+    inv_max = std::max<int64_t>(inv_max, t->inv_doubles);
+    np_max = std::max<int64_t>(np_max, t->Np);
+    maxg = std::max(maxg, g.second.size());
+  }
+  FPN_HIP(ctx->ip.ensure(n));
+  FPN_HIP(ctx->c0.ensure(size_t(n) * np_max));
+  FPN_HIP(ctx->idx.ensure(n));
+  FPN_HIP(ctx->wsinv.ensure(maxg * size_t(inv_max)));
+  std::vector<int32_t> order;
+  for (auto& g : groups) order.insert(order.end(), g.second.begin(), g.second.end());
+  FPN_HIP(hipMemcpyAsync(ctx->idx.p, order.data(), n * sizeof(int32_t), hipMemcpyHostToDevice, stream));
+  fpn::launch_instance_prep(n, batch->D, batch->Ms, batch->K, batch->alpha, batch->temp, batch->easy_axis,
+                            nullptr, ctx->ip.p, status, stream);
+  FPN_HIP(hipGetLastError());
+  int64_t start = 0;
+  double3 zero;
+  zero.x = zero.y = zero.z = 0.0;
+  for (auto& g : groups) {
+    const fpn::DevTables& t = *tabs[g.first];
+    const int cnt = int(g.second.size());
+    fpn::launch_stationary(t, ctx->idx.p + start, cnt, ctx->ip.p, field, zero, ctx->c0.p, np_max, ctx->wsinv.p,
+                           status, stream);
+    FPN_HIP(hipGetLastError());
+    start += cnt;
+  }
+  // moments from the block-order states: (1,+1) at n0, (1,-1) at n0+1, (1,0) at 1
+  std::vector<fpn::InstParams> hip_ip(n);
+  std::vector<double> c(size_t(n) * np_max);
+  FPN_HIP(hipMemcpyAsync(hip_ip.data(), ctx->ip.p, n * sizeof(fpn::InstParams), hipMemcpyDeviceToHost, stream));
+  FPN_HIP(hipMemcpyAsync(c.data(), ctx->c0.p, c.size() * sizeof(double), hipMemcpyDeviceToHost, stream));
+  FPN_HIP(hipStreamSynchronize(stream));
+  std::vector<double> m(size_t(n) * 3);
+  const double rc = std::sqrt(4.0 * fpn::kPi / 3.0);
+  for (int64_t i = 0; i < n; ++i) {
+    const int n0 = tabs[batch->L[i]]->n0;
+    const double* ci = c.data() + i * np_max;
+    const double mp[3] = {rc * ci[n0], rc * ci[n0 + 1], rc * ci[1]};
+    for (int a = 0; a < 3; ++a)
+      m[3 * i + a] = hip_ip[i].R[3 * a] * mp[0] + hip_ip[i].R[3 * a + 1] * mp[1] + hip_ip[i].R[3 * a + 2] * mp[2];
+  }
+  FPN_HIP(hipMemcpyAsync(m_out, m.data(), m.size() * sizeof(double), hipMemcpyHostToDevice, stream));
+  FPN_HIP(hipStreamSynchronize(stream));
+  return FPN_OK;
+}
+
+fpn_status fpn_host_operator(int32_t L, double D, double Ms, double K, double alpha, double temp,
+                             const double field_easy[3], double* A_out) {
+  if (!field_easy || !A_out) return fail(FPN_E_ARG, "NULL argument");
+  if (L < 1 || L > 32) return fail(FPN_E_RANGE, "L outside [1, 32]");
+  if (!(D > 0) || !(Ms > 0) || !(K >= 0) || !(alpha > 0) || !(temp > 0))
+    return fail(FPN_E_ARG, "non-physical particle parameter");
+  const fpn::ParticleScalars s = fpn::particle_scalars(D, Ms, K, alpha, temp);
+  double mult[fpn::K_COUNT];
+  fpn::kind_multipliers(s.inv2tau, s.sigma, s.beta_T, s.alpha, field_easy, mult);
+  try {
+    fpn::dense_operator(fpn::operator_tables(L), mult, A_out);
+  } catch (const std::exception& e) {
+    return fail(FPN_E_RANGE, e.what());
+  }
+  return FPN_OK;
+}
+
+fpn_status fpn_host_frame(const double n[3], double R_out[9]) {
+  if (!n || !R_out) return fail(FPN_E_ARG, "NULL argument");
+  if (!fpn::easy_axis_frame(n, R_out)) return fail(FPN_E_ARG, "|n| differs from 1");
+  return FPN_OK;
+}
+
+int64_t fpn_host_table_nnz(int32_t L) {
+  if (L < 1 || L > 32) return -1;
+  try {
+    return int64_t(fpn::operator_tables(L).colkind.size());
+  } catch (...) {
+    return -1;
+  }
+}
+
+}  // extern "C"

@@ -1,0 +1,38 @@
+// Launch entry points of the fpn kernels (host side).
+#pragma once
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+
+#include "device_common.hpp"
+
+namespace fpn {
+
+struct StepLaunch {
+  const InstParams* ip;
+  const int32_t* inst_idx;   // instances of this launch (indices into the batch)
+  int n_inst;
+  const double* c0;          // stationary states, block order, stride c_stride
+  int64_t c_stride;
+  const float4* drive;       // [spp][5]
+  int spp;
+  int substeps;
+  int settle;
+  int Ns;
+  float h;
+  float* msamp;              // [n][3][Ns]
+  int32_t* status;
+};
+
+void launch_instance_prep(int64_t n, const double* D, const double* Ms, const double* K, const double* alpha,
+                          const double* temp, const double* easy, const double* offset, InstParams* ip,
+                          int32_t* status, hipStream_t stream);
+void launch_stationary(const DevTables& t, const int32_t* idx, int n_inst, const InstParams* ip,
+                       const double* field_lab, double3 drive0, double* c_out, int64_t c_stride, double* wsinv,
+                       int32_t* status, hipStream_t stream);
+hipError_t launch_stepper(int L, const StepLaunch& s, const DevTables& t, hipStream_t stream);
+size_t stepper_lds_bytes(const DevTables& t);
+void launch_harmonics(const float* msamp, int Ns, int n_harm, int nch, double period, const double2* tw,
+                      float* harm, const int32_t* status, int64_t n, hipStream_t stream);
+
+}  // namespace fpn

@@ -1,0 +1,86 @@
+"""CPU-only checks of the C-ABI library: it loads, exports every declared symbol, and
+its host-built operator tables agree with the oracle's independent assembly."""
+import ctypes
+import os
+import re
+
+import numpy as np
+import pytest
+
+import oracle as O
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "fpn.h")
+
+fpn = pytest.importorskip("paper_2106_08040_amd")
+
+
+def declared_functions():
+    src = open(HEADER).read()
+    src = re.sub(r"/\*.*?\*/", "", src, flags=re.S)
+    return sorted(set(re.findall(r"\b(fpn_[a-z_]+)\s*\(", src)))
+
+
+def test_library_exports_every_declared_symbol():
+    lib = ctypes.CDLL(fpn.LIB_PATH)
+    names = declared_functions()
+    assert "fpn_solve" in names and "fpn_stationary" in names
+    for name in names:
+        assert hasattr(lib, name), name
+    assert sorted(fpn.EXPORTED) == names
+
+
+@pytest.mark.parametrize("L,seed", [(2, 0), (6, 1), (10, 2), (16, 3)])
+def test_host_operator_matches_oracle_assembly(L, seed):
+    """Library tables (algebraic construction in the easy-axis frame) vs the oracle's direct
+    quadrature of the weak form with n = z: entry-wise to 1e-11 of the largest entry."""
+    r = np.random.default_rng(seed)
+    p = dict(D=r.uniform(14e-9, 28e-9), Ms=r.uniform(3e5, 5e5), K=r.uniform(0, 1e4), alpha=r.uniform(0.05, 0.4),
+             T=r.uniform(250, 320))
+    h = r.normal(size=3) * 6e-3
+    A = fpn.fpn_host_operator(L, p["D"], p["Ms"], p["K"], p["alpha"], p["T"], h)
+    A0, Aa, _ = O.operator_parts(p, [0.0, 0.0, 1.0], L)
+    Ao = A0 + h[0] * Aa[0] + h[1] * Aa[1] + h[2] * Aa[2]
+    scale = np.abs(Ao).max()
+    assert np.abs(A - Ao).max() < 1e-11 * scale
+
+
+def test_frame_is_a_rotation_onto_the_easy_axis():
+    r = np.random.default_rng(5)
+    for _ in range(20):
+        n = r.normal(size=3)
+        n /= np.linalg.norm(n)
+        R = fpn.fpn_host_frame(n)
+        assert np.allclose(R @ np.array([0, 0, 1.0]), n, atol=1e-14)
+        assert np.allclose(R.T @ R, np.eye(3), atol=1e-14)
+        assert abs(np.linalg.det(R) - 1) < 1e-14
+    for n in ([1, 0, 0], [0, 1, 0], [0, 0, -1]):
+        R = fpn.fpn_host_frame(n)
+        assert np.allclose(R[:, 2], n)
+
+
+def test_host_argument_errors():
+    with pytest.raises(fpn.FpnError) as e:
+        fpn.fpn_host_operator(0, 20e-9, 474e3, 2e3, 0.1, 295.0, [0, 0, 0])
+    assert e.value.code == fpn.FPN_E_RANGE
+    with pytest.raises(fpn.FpnError) as e:
+        fpn.fpn_host_operator(4, -1.0, 474e3, 2e3, 0.1, 295.0, [0, 0, 0])
+    assert e.value.code == fpn.FPN_E_ARG
+    with pytest.raises(fpn.FpnError) as e:
+        fpn.fpn_host_frame([1.0, 1.0, 0.0])
+    assert e.value.code == fpn.FPN_E_ARG
+    assert fpn.fpn_host_table_nnz(0) == -1
+    assert fpn.fpn_status_string(fpn.FPN_E_DEVICE) == "HIP device error"
+
+
+def test_table_sizes_and_selection_rules():
+    for L in (4, 10, 16):
+        nnz = fpn.fpn_host_table_nnz(L)
+        N = (L + 1) ** 2
+        assert 10 * N < nnz < 30 * N
+        # row 0 of the operator vanishes (probability conservation) and couplings stay within |dl| <= 2
+        A = fpn.fpn_host_operator(L, 20e-9, 474e3, 2e3, 0.1, 295.0, [3e-3, -2e-3, 1e-3])
+        assert np.abs(A[0]).max() == 0.0
+        ls = O.sh_degrees(L)
+        far = np.abs(ls[:, None] - ls[None, :]) > 2
+        assert np.abs(A[far]).max() == 0.0

@@ -1,0 +1,108 @@
+"""Seeded synthetic workloads (instance sets) shared by the tests, the bench and the oracle checks.
+
+This module only draws and lays out inputs; it contains none of the solver's
+arithmetic.  Shapes follow the paper's experiment (Experimental Setup and
+Simulation Setting): a 2D Lissajous drive with f_x = 2.5 MHz / 102 and
+f_y = 2.5 MHz / 96 (repetition time 652.8 us, 1632 samples at 2.5 MHz), easy axes
+in the xy-plane at angles measured from x, offset (selection) fields on a regular
+grid, particle diameters and anisotropies in the ranges of the simulation sets.
+They stand in for the measured calibration data, which is not available.
+
+Every instance set is a dict with SoA arrays (SI units, fields as mu0*H in tesla):
+  D, Ms, K, alpha, T  [n]      easy_axis [n,3]   offset [n,3]   L [n] (int32)
+plus the drive (amp, freq, phase, period) and the sampling options.
+"""
+import numpy as np
+
+MAGNETITE_MS = 474e3      # A/m
+ROOM_T = 295.0            # K
+LISSAJOUS_T = 652.8e-6    # s
+LISSAJOUS_F = (2.5e6 / 102, 2.5e6 / 96, 0.0)
+
+
+def _instances(D, Ms, K, alpha, T, easy, offset, L):
+    n = len(D)
+    return dict(D=np.asarray(D, float), Ms=np.asarray(Ms, float), K=np.asarray(K, float),
+                alpha=np.asarray(alpha, float), T=np.asarray(T, float),
+                easy_axis=np.asarray(easy, float).reshape(n, 3), offset=np.asarray(offset, float).reshape(n, 3),
+                L=np.asarray(L, np.int32).reshape(n))
+
+
+def lissajous_drive(amp=(12e-3, 12e-3, 0.0)):
+    return dict(amp=tuple(amp), freq=LISSAJOUS_F, phase=(0.0, 0.0, 0.0), period=LISSAJOUS_T)
+
+
+def single_1d():
+    """One instance: 1D drive along x, 12 mT at 25 kHz, zero offset, easy axis at 30 deg to x in the
+    xy-plane, magnetite D = 20 nm, K = 2 kJ/m^3, alpha = 0.1, T = 295 K, L = 10, 3 periods with the
+    last recorded at 1000 samples, harmonics 0..20 of x, y, z."""
+    th = np.deg2rad(30.0)
+    inst = _instances([20e-9], [MAGNETITE_MS], [2e3], [0.1], [ROOM_T], [[np.cos(th), np.sin(th), 0.0]],
+                      [[0.0, 0.0, 0.0]], [10])
+    drive = dict(amp=(12e-3, 0.0, 0.0), freq=(25e3, 0.0, 0.0), phase=(0.0, 0.0, 0.0), period=40e-6)
+    return dict(name="single_1d_L10", inst=inst, drive=drive, samples=1000, settle=2, n_harm=20, harm_z=True)
+
+
+def lissajous_grid(n_off=17, n_ang=8, L=16, span=12e-3):
+    """2D Lissajous system matrix: 17 x 17 offsets on +-12 mT x 8 easy-axis angles j*pi/8 in the
+    xy-plane; D = 20 nm, K = 2 kJ/m^3, alpha = 0.1, L = 16.  Instance id = (j*17 + iy)*17 + ix."""
+    offs = -span + (2 * span / (n_off - 1)) * np.arange(n_off)
+    j, iy, ix = np.meshgrid(np.arange(n_ang), np.arange(n_off), np.arange(n_off), indexing="ij")
+    j, iy, ix = j.ravel(), iy.ravel(), ix.ravel()
+    th = j * np.pi / n_ang
+    n = th.size
+    easy = np.stack([np.cos(th), np.sin(th), np.zeros(n)], 1)
+    off = np.stack([offs[ix], offs[iy], np.zeros(n)], 1)
+    inst = _instances(np.full(n, 20e-9), np.full(n, MAGNETITE_MS), np.full(n, 2e3), np.full(n, 0.1),
+                      np.full(n, ROOM_T), easy, off, np.full(n, L))
+    return dict(name=f"lissajous_{n_off}x{n_off}x{n_ang}_L{L}", inst=inst, drive=lissajous_drive(),
+                samples=1632, settle=1, n_harm=200, harm_z=False)
+
+
+def truncation_degree(D, K, T=ROOM_T, lo=8, hi=24):
+    """Galerkin degree rule of the uneven sweep: L = clamp(ceil(8 + 2 sqrt(sigma)), lo, hi),
+    sigma = K (pi D^3 / 6) / (k_B T); evaluated once here so every consumer reads the same integer."""
+    sigma = np.asarray(K) * (np.pi * np.asarray(D) ** 3 / 6) / (1.380649e-23 * T)
+    return np.clip(np.ceil(8 + 2 * np.sqrt(sigma)), lo, hi).astype(np.int32)
+
+
+def uneven_sweep(n=4096, seed=3, L_max=24):
+    """Batched uneven sweep: D ~ U[15, 30] nm, K log-uniform in [0.5, 20] kJ/m^3, alpha ~ U[0.05, 0.3],
+    easy axes uniform on the sphere, offsets U[-12, 12] mT in x and y, L by truncation_degree."""
+    r = np.random.default_rng(seed)
+    D = r.uniform(15e-9, 30e-9, n)
+    K = np.exp(r.uniform(np.log(500.0), np.log(2e4), n))
+    alpha = r.uniform(0.05, 0.3, n)
+    z = r.uniform(-1, 1, n)
+    ph = r.uniform(0, 2 * np.pi, n)
+    s = np.sqrt(1 - z * z)
+    easy = np.stack([s * np.cos(ph), s * np.sin(ph), z], 1)
+    off = np.stack([r.uniform(-12e-3, 12e-3, n), r.uniform(-12e-3, 12e-3, n), np.zeros(n)], 1)
+    L = truncation_degree(D, K, hi=L_max)
+    inst = _instances(D, np.full(n, MAGNETITE_MS), K, alpha, np.full(n, ROOM_T), easy, off, L)
+    return dict(name=f"uneven_{n}_seed{seed}", inst=inst, drive=lissajous_drive(), samples=1632, settle=1,
+                n_harm=200, harm_z=False)
+
+
+def small_random(n, L, seed, samples=64, settle=1, n_harm=10, freq_scale=1.0):
+    """Small random instances for parity tests (short synthetic drive with 3 and 4 cycles per period)."""
+    r = np.random.default_rng(seed)
+    D = r.uniform(14e-9, 24e-9, n)
+    K = np.exp(r.uniform(np.log(300.0), np.log(8e3), n))
+    alpha = r.uniform(0.05, 0.3, n)
+    v = r.normal(size=(n, 3))
+    easy = v / np.linalg.norm(v, axis=1, keepdims=True)
+    off = r.uniform(-6e-3, 6e-3, (n, 3))
+    inst = _instances(D, np.full(n, MAGNETITE_MS), K, alpha, np.full(n, ROOM_T), easy, off, np.full(n, L))
+    T = 40e-6 / freq_scale
+    drive = dict(amp=(10e-3, 8e-3, 3e-3), freq=(3 / T, 4 / T, 1 / T), phase=(0.0, 0.3, -0.7), period=T)
+    return dict(name=f"small_L{L}_seed{seed}", inst=inst, drive=drive, samples=samples, settle=settle,
+                n_harm=n_harm, harm_z=True)
+
+
+def take(ws, idx):
+    """Sub-workload with the instances at `idx`."""
+    idx = np.asarray(idx, dtype=np.int64)
+    out = dict(ws)
+    out["inst"] = {k: v[idx] for k, v in ws["inst"].items()}
+    return out
