@@ -109,7 +109,8 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=3)
     ap.add_argument("--warmup", type=int, default=1)
-    ap.add_argument("--substeps", type=int, default=3)
+    ap.add_argument("--substeps", type=int, default=0, help="0 = adaptive (production), k = fixed")
+    ap.add_argument("--tol", type=float, default=0.0, help="adaptive error bound (0 = library default)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-budget", type=float, default=15.0)
     args = ap.parse_args()
@@ -136,7 +137,8 @@ def main():
            "status": torch.empty((n,), dtype=torch.int32, device=dev)}
 
     def step():
-        ctx.solve(inst, L, drive, ws["samples"], ws["settle"], ws["n_harm"], substeps=args.substeps, out=out)
+        ctx.solve(inst, L, drive, ws["samples"], ws["settle"], ws["n_harm"], substeps=args.substeps, out=out,
+                  tol=args.tol)
 
     for _ in range(args.warmup):
         step()
@@ -151,14 +153,16 @@ def main():
     t1 = time.perf_counter()
     timing = ctx.timing_read()
     ctx.timing_enable(False)
+    steps_last = ctx.last_steps()   # time steps of the last timed solve (all instances)
     wall = t1 - t0
     ms_per_step = wall / args.steps * 1e3
     value = n * args.steps / wall
 
     Lv = int(L[0])
-    spp = (ws["settle"] + 1) * ws["samples"] * args.substeps
     step_ms, launches = timing["stepper"]
-    flops_launch = float(flops_per_step(fpn, Lv)) * spp * n
+    # algorithmic flops of one stepper launch: executed RODAS4 steps x flops per step
+    flops_launch = float(flops_per_step(fpn, Lv)) * steps_last
+    avg_sub = steps_last / (n * (ws["settle"] + 1) * ws["samples"])
     avg_ms = step_ms / max(launches, 1)
     achieved = flops_launch / (avg_ms * 1e-3) / 1e12
     res = {
@@ -175,7 +179,8 @@ def main():
         "dtype": "f32",
         "data": "synthetic",
         "config": {"workload": ws["name"], "instances": n, "L": Lv, "samples": ws["samples"],
-                   "settle_periods": ws["settle"], "n_harm": ws["n_harm"], "substeps": args.substeps,
+                   "settle_periods": ws["settle"], "n_harm": ws["n_harm"],
+                   "substeps": args.substeps if args.substeps else "adaptive", "avg_substeps": avg_sub,
                    "integrator": "RODAS4", "failed_instances": bad},
         "roofline": {"bound": "alu", "kernel": "stepper", "achieved": achieved, "peak": FP32_VECTOR_PEAK_TFLOPS,
                      "unit": "TFLOP/s", "frac": achieved / FP32_VECTOR_PEAK_TFLOPS, "traffic": None,

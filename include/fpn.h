@@ -88,8 +88,11 @@ typedef struct {
   int32_t samples_per_period;  /* N_s >= 2 */
   int32_t settle_periods;      /* >= 0; the period with index settle_periods is recorded */
   int32_t n_harm;              /* K_h: harmonic bins 0..K_h, 0 <= K_h < N_s/2 */
-  int32_t substeps;            /* time steps per sample interval, 1..64 */
+  int32_t substeps;            /* 1..64: fixed time steps per sample interval;
+                                  0: adaptive per interval (1..64 steps) from the embedded error */
   uint32_t flags;              /* FPN_OUT_* */
+  double tol;                  /* adaptive: bound on the embedded error max|K6| of every step,
+                                  0 selects the default 5e-6; ignored when substeps > 0 */
 } fpn_solve_opts;
 
 /* One batch of instances in structure-of-arrays form.  Instance parameters
@@ -121,6 +124,10 @@ typedef struct {
 fpn_status fpn_solve(fpn_ctx ctx, const fpn_drive* drive, const fpn_solve_opts* opts,
                      const fpn_batch* batch, int64_t n,
                      float* m_out, float* harm_out, int32_t* status, void* stream);
+
+/* Time steps taken by the last fpn_solve on this context, summed over its instances
+ * (synchronises with that solve).  HOST output.  Errors: FPN_E_ARG, FPN_E_DEVICE. */
+fpn_status fpn_last_steps(fpn_ctx ctx, int64_t* total_steps);
 
 /* Stationary mean moment under a static field (FP64 on the device):
  * the null vector of the Galerkin operator with total probability 1.

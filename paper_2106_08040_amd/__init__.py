@@ -12,7 +12,7 @@ import os
 import numpy as np
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
-LIB_PATH = os.path.join(_HERE, "libfpn.so")
+LIB_PATH = os.environ.get("FPN_LIB") or os.path.join(_HERE, "libfpn.so")
 
 if not os.path.exists(LIB_PATH):
     raise ImportError(f"libfpn.so not built at {LIB_PATH}; run `python paper_2106_08040_amd/build.py`")
@@ -32,7 +32,7 @@ FPN_OUT_M, FPN_OUT_HARM, FPN_HARM_Z = 1, 2, 4
 FPN_MAX_L = 16
 
 EXPORTED = ["fpn_status_string", "fpn_last_error", "fpn_create", "fpn_destroy", "fpn_solve",
-            "fpn_stationary", "fpn_timing_enable", "fpn_timing_read", "fpn_host_operator", "fpn_host_frame",
+            "fpn_stationary", "fpn_last_steps", "fpn_timing_enable", "fpn_timing_read", "fpn_host_operator", "fpn_host_frame",
             "fpn_host_table_nnz"]
 
 
@@ -43,7 +43,8 @@ class fpn_drive(ctypes.Structure):
 
 class fpn_solve_opts(ctypes.Structure):
     _fields_ = [("samples_per_period", ctypes.c_int32), ("settle_periods", ctypes.c_int32),
-                ("n_harm", ctypes.c_int32), ("substeps", ctypes.c_int32), ("flags", ctypes.c_uint32)]
+                ("n_harm", ctypes.c_int32), ("substeps", ctypes.c_int32), ("flags", ctypes.c_uint32),
+                ("tol", ctypes.c_double)]
 
 
 class fpn_batch(ctypes.Structure):
@@ -66,6 +67,8 @@ _lib.fpn_solve.argtypes = [_vp, ctypes.POINTER(fpn_drive), ctypes.POINTER(fpn_so
                            ctypes.POINTER(fpn_batch), ctypes.c_int64, _vp, _vp, _vp, _vp]
 _lib.fpn_stationary.restype = ctypes.c_int32
 _lib.fpn_stationary.argtypes = [_vp, ctypes.POINTER(fpn_batch), ctypes.c_int64, _vp, _vp, _vp, _vp]
+_lib.fpn_last_steps.restype = ctypes.c_int32
+_lib.fpn_last_steps.argtypes = [_vp, ctypes.POINTER(ctypes.c_int64)]
 _lib.fpn_timing_enable.restype = ctypes.c_int32
 _lib.fpn_timing_enable.argtypes = [_vp, ctypes.c_int]
 _lib.fpn_timing_read.restype = ctypes.c_int32
@@ -181,8 +184,8 @@ class Context:
                       Lh.ctypes.data_as(ctypes.POINTER(ctypes.c_int32)))
         return b, t, Lh
 
-    def solve(self, inst, L, drive, samples, settle, n_harm, substeps=3, want_m=True, want_harm=True,
-              harm_z=False, stream=None, out=None):
+    def solve(self, inst, L, drive, samples, settle, n_harm, substeps=0, want_m=True, want_harm=True,
+              harm_z=False, stream=None, out=None, tol=0.0):
         """Run fpn_solve.  Returns (m [n,3,Ns] float32, harm [n,ch,Kh+1] complex64, status [n] int32)
         as torch tensors on the device (None for outputs not requested)."""
         torch = _torch()
@@ -203,7 +206,7 @@ class Context:
             st = torch.empty((n,), dtype=torch.int32, device=dev)
         opts = fpn_solve_opts(samples, settle, n_harm, substeps,
                               (FPN_OUT_M if want_m else 0) | (FPN_OUT_HARM if want_harm else 0) |
-                              (FPN_HARM_Z if harm_z else 0))
+                              (FPN_HARM_Z if harm_z else 0), float(tol))
         s = stream if stream is not None else torch.cuda.current_stream(self.device)
         code = _lib.fpn_solve(self._h, ctypes.byref(drive), ctypes.byref(opts), ctypes.byref(b), n,
                               m.data_ptr() if m is not None else None,
@@ -212,6 +215,12 @@ class Context:
         self._keep = (keep, Lh)  # inputs alive until the next call on this context
         harm = torch.view_as_complex(hm) if hm is not None else None
         return m, harm, st
+
+    def last_steps(self):
+        """Time steps taken by the last solve, summed over instances."""
+        v = ctypes.c_int64()
+        _check(_lib.fpn_last_steps(self._h, ctypes.byref(v)), "fpn_last_steps")
+        return int(v.value)
 
     TIMING_KERNELS = ("instance_prep", "stationary", "stepper", "harmonics")
 

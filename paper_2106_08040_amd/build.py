@@ -40,9 +40,18 @@ def _run(cmd):
     return r.stdout
 
 
-def build(jobs=4, verbose=False):
+def build(jobs=8, verbose=False, out=None, build_dir=None, extra=()):
+    BUILD = build_dir or globals()["BUILD"]
+    LIB = out or globals()["LIB"]
+    HIP_FLAGS = [*globals()["HIP_FLAGS"], *extra]
     os.makedirs(BUILD, exist_ok=True)
+    # the stepper is instantiated per Galerkin degree; split across objects to compile in parallel
+    ranges = [(1, 6), (7, 10), (11, 13), (14, 15), (16, 16)]
+    step_objs = [os.path.join(BUILD, f"stepper_{a}_{b}.o") for a, b in ranges]
     steps = [
+        [HIPCC, *HIP_FLAGS, f"-DFPN_L_BEGIN={a}", f"-DFPN_L_END={b}", "-c", os.path.join(CSRC, "stepper.hip"),
+         "-o", o] for (a, b), o in zip(ranges, step_objs)
+    ] + [
         [HIPCC, *HIP_FLAGS, "-c", os.path.join(CSRC, "kernels.hip"), "-o", os.path.join(BUILD, "kernels.o")],
         [HIPCC, *HIP_FLAGS, "-c", os.path.join(CSRC, "capi.hip"), "-o", os.path.join(BUILD, "capi.o")],
         ["g++", "-O2", "-std=c++17", "-fPIC", "-c", os.path.join(CSRC, "structure.cpp"),
@@ -57,7 +66,7 @@ def build(jobs=4, verbose=False):
     # Link against the HIP runtime that PyTorch loads (NEEDED libamdhip64.so, torch's copy first on
     # the runpath) so one process never holds two HIP/HSA runtimes; /opt/rocm/lib is the fallback.
     hiplib = _runtime_dir()
-    _run([CLANG, "-shared", "-fPIC", "-o", tmp,
+    _run([CLANG, "-shared", "-fPIC", "-o", tmp, *step_objs,
           os.path.join(BUILD, "kernels.o"), os.path.join(BUILD, "capi.o"), os.path.join(BUILD, "structure.o"),
           f"-L{hiplib}", "-l:libamdhip64.so", f"-Wl,-rpath,{hiplib}:/opt/rocm/lib", "-lstdc++"])
     os.replace(tmp, LIB)

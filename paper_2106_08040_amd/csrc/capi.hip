@@ -59,20 +59,12 @@ struct TableSet {
   std::vector<void*> allocs;
 };
 
-struct DriveCache {
-  fpn_drive d{};
-  int Ns = 0, r = 0;
-  bool valid = false;
-  DevBuf<float4> table;
-};
-
 }  // namespace
 
 struct fpn_ctx_s {
   int device = 0;
   std::mutex mu;
   std::map<int, TableSet> tables;
-  DriveCache drive;
   DevBuf<double2> twiddle;
   int tw_N = 0;
   DevBuf<fpn::InstParams> ip;
@@ -80,6 +72,8 @@ struct fpn_ctx_s {
   DevBuf<double> wsinv;
   DevBuf<float> msamp;
   DevBuf<int32_t> idx;
+  DevBuf<int32_t> steps;
+  int64_t steps_n = 0;
   // kernel timing
   bool timing = false;
   std::vector<std::pair<int, std::pair<hipEvent_t, hipEvent_t>>> events;
@@ -122,6 +116,48 @@ fpn_status get_tables(fpn_ctx ctx, int L, const fpn::DevTables** out) {
     return e;
   };
   std::vector<int32_t> boff(h->boff.begin(), h->boff.end()), bn(h->bn.begin(), h->bn.end());
+  if (h->Np > 65535) return fail(FPN_E_RANGE, "operator tables too large for 16-bit indexing");
+  // fixed-slot layout (see device_common.hpp): fill the slots of each kind in column order
+  const int Np = h->Np;
+  std::vector<uint16_t> ecol(size_t(fpn::kNSlRow) * Np, 0), crow(size_t(fpn::kNSlCol) * Np, 0);
+  std::vector<float> eval(size_t(fpn::kNSlRow) * Np, 0.0f), cvl(size_t(fpn::kNSlCol) * Np, 0.0f);
+  std::vector<int> blk_of(Np);
+  for (int k = 0; k <= L; ++k)
+    for (int p = h->boff[k]; p < h->boff[k] + h->bn[k]; ++p) blk_of[p] = k;
+  auto place = [&](std::vector<uint16_t>& ix, std::vector<float>& vv, const int* kinds, int first, int count,
+                   int line, int kind, int other, float v) -> bool {
+    for (int s = first; s < first + count; ++s) {
+      if (kinds[s] != kind || vv[size_t(s) * Np + line] != 0.0f) continue;
+      ix[size_t(s) * Np + line] = uint16_t(other);
+      vv[size_t(s) * Np + line] = v;
+      return true;
+    }
+    return false;
+  };
+  // padding slots (value 0) point inside the block they would address, so every index is in range
+  for (int p = 0; p < Np; ++p) {
+    const int k = blk_of[p];
+    for (int s = 0; s < fpn::kNSlRow; ++s) {
+      int def = p;
+      if (s >= fpn::kSlB && s < fpn::kSlB + fpn::kNSlB && k > 0) def = h->boff[k - 1];
+      if (s >= fpn::kSlC && s < fpn::kSlC + fpn::kNSlC && k < L) def = h->boff[k + 1];
+      ecol[size_t(s) * Np + p] = uint16_t(def);
+    }
+    for (int s = 0; s < fpn::kNSlCol; ++s) crow[size_t(s) * Np + p] = uint16_t(k > 0 ? h->boff[k - 1] : p);
+  }
+  for (int p = 0; p < Np; ++p) {
+    for (int e = h->seg[4 * p]; e < h->seg[4 * p + 3]; ++e) {
+      const int col = int(h->colkind[e] & 0xffffu), kind = int(h->colkind[e] >> 16);
+      const float v = h->val[e];
+      const int rel = blk_of[col] - blk_of[p];
+      const int first = rel == 0 ? fpn::kSlD : (rel < 0 ? fpn::kSlB : fpn::kSlC);
+      const int count = rel == 0 ? fpn::kNSlD : (rel < 0 ? fpn::kNSlB : fpn::kNSlC);
+      if (!place(ecol, eval, fpn::kSlotKindRow, first, count, p, kind, col, v))
+        return fail(FPN_E_RANGE, "operator row does not fit the fixed-slot layout");
+      if (rel > 0 && !place(crow, cvl, fpn::kSlotKindCol, 0, fpn::kNSlCol, col, kind, p, v))
+        return fail(FPN_E_RANGE, "operator column does not fit the fixed-slot layout");
+    }
+  }
   hipError_t e = hipSuccess;
   if (e == hipSuccess) e = up(&t.seg, h->seg);
   if (e == hipSuccess) e = up(&t.colkind, h->colkind);
@@ -131,6 +167,10 @@ fpn_status get_tables(fpn_ctx ctx, int L, const fpn::DevTables** out) {
   if (e == hipSuccess) e = up(&t.crowkind, h->crowkind);
   if (e == hipSuccess) e = up(&t.cval, h->cval);
   if (e == hipSuccess) e = up(&t.cval64, h->cval64);
+  if (e == hipSuccess) e = up(&t.ell_col, ecol);
+  if (e == hipSuccess) e = up(&t.ell_val, eval);
+  if (e == hipSuccess) e = up(&t.ecol_row, crow);
+  if (e == hipSuccess) e = up(&t.ecol_val, cvl);
   if (e == hipSuccess) e = up(&t.boff, boff);
   if (e == hipSuccess) e = up(&t.bn, bn);
   if (e != hipSuccess) {
@@ -159,8 +199,6 @@ fpn_status timed(fpn_ctx ctx, int which, hipStream_t stream, F&& launch) {
   return st;
 }
 
-bool same_drive(const fpn_drive& a, const fpn_drive& b) { return std::memcmp(&a, &b, sizeof(fpn_drive)) == 0; }
-
 fpn_status validate_drive(const fpn_drive* d) {
   if (!d) return fail(FPN_E_ARG, "drive is NULL");
   if (!(d->period > 0.0) || !std::isfinite(d->period)) return fail(FPN_E_ARG, "drive.period must be > 0");
@@ -172,36 +210,6 @@ fpn_status validate_drive(const fpn_drive* d) {
     if (d->amp[a] != 0.0 && std::fabs(cyc - std::round(cyc)) > 1e-9 * std::max(1.0, cyc))
       return fail(FPN_E_ARG, "drive.freq * period must be an integer (T-periodic drive)");
   }
-  return FPN_OK;
-}
-
-// Drive table for one period: for step n, t_n = n h:
-//   [0..3] mu0 H(t_n + al h), al = 0, 0.386, 0.21, 0.63;  [4] d(mu0 H)/dt (t_n).
-fpn_status ensure_drive(fpn_ctx ctx, const fpn_drive& d, int Ns, int r, hipStream_t stream) {
-  DriveCache& c = ctx->drive;
-  if (c.valid && same_drive(c.d, d) && c.Ns == Ns && c.r == r) return FPN_OK;
-  const int spp = Ns * r;
-  const double h = d.period / spp;
-  const double al[4] = {0.0, 0.386, 0.21, 0.63};
-  std::vector<float4> tab(size_t(spp) * 5);
-  for (int n = 0; n < spp; ++n) {
-    for (int e = 0; e < 5; ++e) {
-      const double t = (n + (e < 4 ? al[e] : 0.0)) * h;
-      double v[3];
-      for (int a = 0; a < 3; ++a) {
-        const double w = 2.0 * fpn::kPi * d.freq[a];
-        v[a] = (e < 4) ? d.amp[a] * std::cos(w * t + d.phase[a]) : -d.amp[a] * w * std::sin(w * t + d.phase[a]);
-      }
-      tab[size_t(n) * 5 + e] = make_float4(float(v[0]), float(v[1]), float(v[2]), 0.0f);
-    }
-  }
-  FPN_HIP(c.table.ensure(tab.size()));
-  FPN_HIP(hipMemcpyAsync(c.table.p, tab.data(), tab.size() * sizeof(float4), hipMemcpyHostToDevice, stream));
-  FPN_HIP(hipStreamSynchronize(stream));
-  c.d = d;
-  c.Ns = Ns;
-  c.r = r;
-  c.valid = true;
   return FPN_OK;
 }
 
@@ -239,6 +247,19 @@ std::vector<std::pair<int, std::vector<int32_t>>> group_by_L(const int32_t* L, i
 
 }  // namespace
 
+namespace fpn {
+hipError_t launch_stepper(int L, const StepLaunch& s, const DevTables& t, hipStream_t stream) {
+  switch (L) {
+#define FPN_CASE(LL) \
+  case LL: return launch_stepper_L<LL>(s, t, stream);
+    FPN_CASE(1) FPN_CASE(2) FPN_CASE(3) FPN_CASE(4) FPN_CASE(5) FPN_CASE(6) FPN_CASE(7) FPN_CASE(8)
+    FPN_CASE(9) FPN_CASE(10) FPN_CASE(11) FPN_CASE(12) FPN_CASE(13) FPN_CASE(14) FPN_CASE(15) FPN_CASE(16)
+#undef FPN_CASE
+    default: return hipErrorInvalidValue;
+  }
+}
+}  // namespace fpn
+
 extern "C" {
 
 const char* fpn_status_string(fpn_status s) {
@@ -273,7 +294,6 @@ fpn_status fpn_destroy(fpn_ctx ctx) {
   (void)hipDeviceSynchronize();
   for (auto& kv : ctx->tables)
     for (void* p : kv.second.allocs) (void)hipFree(p);
-  ctx->drive.table.release();
   ctx->twiddle.release();
   ctx->ip.release();
   ctx->c0.release();
@@ -293,16 +313,17 @@ fpn_status fpn_solve(fpn_ctx ctx, const fpn_drive* drive, const fpn_solve_opts* 
   const int Ns = opts->samples_per_period, r = opts->substeps, Kh = opts->n_harm;
   if (Ns < 2) return fail(FPN_E_ARG, "samples_per_period must be >= 2");
   if (opts->settle_periods < 0) return fail(FPN_E_ARG, "settle_periods must be >= 0");
-  if (r < 1 || r > 64) return fail(FPN_E_ARG, "substeps must be in [1, 64]");
+  if (r < 0 || r > 64) return fail(FPN_E_ARG, "substeps must be in [0, 64]");
+  if (!(opts->tol >= 0.0) || !std::isfinite(opts->tol)) return fail(FPN_E_ARG, "tol must be finite and >= 0");
   if (Kh < 0 || 2 * Kh >= Ns) return fail(FPN_E_ARG, "n_harm must satisfy 0 <= n_harm < samples_per_period/2");
-  if (int64_t(Ns) * r * (opts->settle_periods + 1) > (int64_t(1) << 30))
+  if (int64_t(Ns) * std::max(r, 1) * (opts->settle_periods + 1) > (int64_t(1) << 30))
     return fail(FPN_E_ARG, "too many time steps");
   if (opts->flags & ~uint32_t(FPN_OUT_M | FPN_OUT_HARM | FPN_HARM_Z)) return fail(FPN_E_ARG, "unknown flag");
   const bool want_m = opts->flags & FPN_OUT_M, want_h = opts->flags & FPN_OUT_HARM;
+  if (n == 0) return FPN_OK;  // nothing to do (empty outputs may be NULL)
   if (want_m && !m_out) return fail(FPN_E_ARG, "FPN_OUT_M set but m_out is NULL");
   if (want_h && !harm_out) return fail(FPN_E_ARG, "FPN_OUT_HARM set but harm_out is NULL");
-  if (!status && n > 0) return fail(FPN_E_ARG, "status is NULL");
-  if (n == 0) return FPN_OK;
+  if (!status) return fail(FPN_E_ARG, "status is NULL");
   if (n > (int64_t(1) << 31) - 1) return fail(FPN_E_ARG, "n too large");
   if (fpn_status s = validate_batch(batch, n)) return s;
   std::lock_guard<std::mutex> lk(ctx->mu);
@@ -321,12 +342,13 @@ fpn_status fpn_solve(fpn_ctx ctx, const fpn_drive* drive, const fpn_solve_opts* 
     inv_max = std::max<int64_t>(inv_max, t->inv_doubles);
     np_max = std::max<int64_t>(np_max, t->Np);
   }
-  if (fpn_status s = ensure_drive(ctx, *drive, Ns, r, stream)) return s;
   if (want_h)
     if (fpn_status s = ensure_twiddle(ctx, Ns, stream)) return s;
   FPN_HIP(ctx->ip.ensure(n));
   FPN_HIP(ctx->c0.ensure(size_t(n) * np_max));
   FPN_HIP(ctx->idx.ensure(n));
+  FPN_HIP(ctx->steps.ensure(n));
+  ctx->steps_n = n;
   float* msamp = m_out;
   if (!want_m) {
     FPN_HIP(ctx->msamp.ensure(size_t(n) * 3 * Ns));
@@ -370,14 +392,20 @@ fpn_status fpn_solve(fpn_ctx ctx, const fpn_drive* drive, const fpn_solve_opts* 
     sl.n_inst = cnt;
     sl.c0 = ctx->c0.p;
     sl.c_stride = np_max;
-    sl.drive = ctx->drive.table.p;
-    sl.spp = Ns * r;
-    sl.substeps = r;
+    for (int c = 0; c < 3; ++c) {
+      sl.amp[c] = drive->amp[c];
+      sl.freq[c] = drive->freq[c];
+      sl.phase[c] = drive->phase[c];
+    }
+    sl.period = drive->period;
     sl.settle = opts->settle_periods;
     sl.Ns = Ns;
-    sl.h = float(drive->period / (double(Ns) * r));
+    sl.r_fixed = r;
+    sl.r_max = 64;
+    sl.tol = float(opts->tol > 0.0 ? opts->tol : 5e-6);
     sl.msamp = msamp;
     sl.status = status;
+    sl.steps_out = ctx->steps.p;
     if (fpn_status s = timed(ctx, 2, stream, [&]() -> fpn_status {
           FPN_HIP(fpn::launch_stepper(g.first, sl, t, stream));
           return FPN_OK;
@@ -394,6 +422,21 @@ fpn_status fpn_solve(fpn_ctx ctx, const fpn_drive* drive, const fpn_solve_opts* 
         }))
       return s;
   }
+  return FPN_OK;
+}
+
+fpn_status fpn_last_steps(fpn_ctx ctx, int64_t* total_steps) {
+  if (!ctx || !total_steps) return fail(FPN_E_ARG, "NULL argument");
+  std::lock_guard<std::mutex> lk(ctx->mu);
+  FPN_HIP(hipSetDevice(ctx->device));
+  std::vector<int32_t> h(ctx->steps_n);
+  if (ctx->steps_n > 0) {
+    FPN_HIP(hipDeviceSynchronize());
+    FPN_HIP(hipMemcpy(h.data(), ctx->steps.p, h.size() * sizeof(int32_t), hipMemcpyDeviceToHost));
+  }
+  int64_t sum = 0;
+  for (int32_t v : h) sum += v;
+  *total_steps = sum;
   return FPN_OK;
 }
 

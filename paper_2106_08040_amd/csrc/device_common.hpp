@@ -23,10 +23,35 @@ struct DevTables {
   uint32_t* crowkind;  // [nnzc]
   float* cval;         // [nnzc]
   double* cval64;      // [nnzc]
+  uint16_t* ell_col;   // [kNSlRow][Np] fixed-slot rows (stepper)
+  float* ell_val;      // [kNSlRow][Np]
+  uint16_t* ecol_row;  // [kNSlCol][Np] fixed-slot columns of the lower coupling
+  float* ecol_val;     // [kNSlCol][Np]
   int32_t* boff;       // [L+1]
   int32_t* bn;         // [L+1]
   int64_t inv_doubles; // sum of bn^2
 };
+
+// Fixed-slot (ELL) layout of the operator rows used by the time stepper.  Every row of
+// the block-ordered matrix has one slot group per entry kind; the kind of a slot is
+// static, so its multiplier is a uniform value and the loops over slots unroll.
+//   same |m| block (D):  LAM 1, G 3, P 2, FZ 2, RZ 1
+//   block k-1 (B):       FX 2, FY 2, RX 1, RY 1
+//   block k+1 (C):       FX 2, FY 2, RX 1, RY 1
+// and, by column, the entries of the coupling to block k-1 (C of the previous block):
+//   FX 2, FY 2, RX 1, RY 1.  Unused slots hold index 0 and value 0.
+enum : int {
+  kSlD = 0, kNSlD = 9,
+  kSlB = 9, kNSlB = 6,
+  kSlC = 15, kNSlC = 6,
+  kNSlRow = 21,
+  kNSlCol = 6
+};
+// kind of every row slot and column slot (kind numbering of structure.hpp)
+constexpr int kSlotKindRow[kNSlRow] = {0, 1, 1, 1, 2, 2, 3, 3, 4,   // D: LAM G G G P P FZ FZ RZ
+                                       5, 5, 6, 6, 7, 8,            // B: FX FX FY FY RX RY
+                                       5, 5, 6, 6, 7, 8};           // C
+constexpr int kSlotKindCol[kNSlCol] = {5, 5, 6, 6, 7, 8};
 
 // RODAS4 (Hairer & Wanner), in the form
 //   (I/(h g) - J) K_i = f(t + al_i h, y + sum_j a_ij K_j) + sum_j (c_ij/h) K_j + h gi_i f_t,

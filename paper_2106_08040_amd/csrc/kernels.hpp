@@ -14,15 +14,19 @@ struct StepLaunch {
   int n_inst;
   const double* c0;          // stationary states, block order, stride c_stride
   int64_t c_stride;
-  const float4* drive;       // [spp][5]
-  int spp;
-  int substeps;
+  double amp[3], freq[3], phase[3], period;  // drive
   int settle;
   int Ns;
-  float h;
+  int r_fixed;               // > 0 fixed substeps per sample interval, 0 adaptive
+  int r_max;
+  float tol;
   float* msamp;              // [n][3][Ns]
   int32_t* status;
+  int32_t* steps_out;        // [n] steps taken, may be null
 };
+
+template <int L>
+hipError_t launch_stepper_L(const StepLaunch& s, const DevTables& t, hipStream_t stream);
 
 void launch_instance_prep(int64_t n, const double* D, const double* Ms, const double* K, const double* alpha,
                           const double* temp, const double* easy, const double* offset, InstParams* ip,
@@ -31,7 +35,6 @@ void launch_stationary(const DevTables& t, const int32_t* idx, int n_inst, const
                        const double* field_lab, double3 drive0, double* c_out, int64_t c_stride, double* wsinv,
                        int32_t* status, hipStream_t stream);
 hipError_t launch_stepper(int L, const StepLaunch& s, const DevTables& t, hipStream_t stream);
-size_t stepper_lds_bytes(const DevTables& t);
 void launch_harmonics(const float* msamp, int Ns, int n_harm, int nch, double period, const double2* tw,
                       float* harm, const int32_t* status, int64_t n, hipStream_t stream);
 

@@ -1,0 +1,656 @@
+// FP32 time stepper (rows a4/a5): one wavefront per instance, linearly implicit
+// L-stable RODAS4 with adaptive substeps per sample interval.
+//
+// The Galerkin ODE dc/dt = A(t) c (paper: Eq. FP-general with the drift of
+// Eq. convection, easy-axis frame) is integrated over (settle + 1) drive periods.
+// Every step factors M = I - h g A(t_n) by block elimination over the |m| blocks
+// (block-tridiagonal ordering): the Schur complement of each block is inverted by
+// Gauss-Jordan with 2x2 pivots on its (cos, sin) pairs, and the inverses stay in
+// VGPRs for the six stage solves.  Moments are sampled at t_j (Eq. mean_magmom_FP).
+//
+// Lane layout of a block (n <= 32 rows): lane = 32 h + i holds row i, columns
+// h, h + 2, h + 4, ... (a[q] = S[i][h + 2q]).
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+
+#include "device_common.hpp"
+#include "device_util.hpp"
+#include "kernels.hpp"
+#include "physics.hpp"
+
+namespace fpn {
+
+template <int L>
+struct Geo {
+  static constexpr int N = (L + 1) * (L + 1);
+  static constexpr int n0 = (L + 1) + ((L + 1) & 1);
+  static constexpr int Np = N + (n0 - (L + 1));
+  static constexpr int nb(int k) { return k == 0 ? n0 : 2 * (L + 1 - k); }
+  static constexpr int off(int k) {
+    int o = 0;
+    for (int j = 0; j < k; ++j) o += nb(j);
+    return o;
+  }
+  static constexpr int S = (Np + 63) / 64;    // vector slots per lane
+  static constexpr int NpA = (Np + 3) & ~3;   // padded vector length in LDS
+};
+
+template <int Q>
+struct Arr {
+  float v[Q];
+};
+template <int L, int K>
+struct Store : Store<L, K - 1> {
+  Arr<Geo<L>::nb(K) / 2> a;
+};
+template <int L>
+struct Store<L, -1> {};
+template <int K, int L>
+__device__ __forceinline__ auto& blk(Store<L, L>& s) {
+  return static_cast<Store<L, K>&>(s).a.v;
+}
+
+// Per-wavefront LDS.  The factorisation scratch (X, Ub) and the stage vectors share `u`.
+template <int L>
+struct WaveLds {
+  static constexpr int NpA = Geo<L>::NpA;
+  static constexpr int kUnion = (2048 > 9 * NpA) ? 2048 : 9 * NpA;
+  float u[kUnion];
+  float T[32];     // block right-hand side [parity][16]
+  float col[64];   // pivot columns [parity][32]
+  float row[64];   // pivot rows [r][parity][16]
+  float mk[16];    // -h g * multiplier(t_n) per kind
+  float ms[16];    // multiplier at the current stage time per kind
+  __device__ float* X() { return u; }
+  __device__ float* Ub() { return u + 1024; }
+  __device__ float* xin() { return u; }
+  __device__ float* V() { return u + NpA; }
+  __device__ float* G() { return u + 2 * NpA; }
+  __device__ float* Kv(int j) { return u + (3 + j) * NpA; }  // K1..K5
+  __device__ float* ft() { return u + 8 * NpA; }
+};
+
+// A zero the optimiser cannot see through: table indices offset by it are not hoisted out of
+// the time loop (the tables are loop-invariant, and hoisting keeps one register per entry live).
+__device__ __forceinline__ int opaque_zero() {
+  int z = 0;
+  asm volatile("" : "+s"(z));
+  return z;
+}
+
+// Sum of a value over the two 32-lane halves (lane and lane ^ 32).
+__device__ __forceinline__ float half_sum(float v) {
+  auto r = __builtin_amdgcn_permlane32_swap(__float_as_uint(v), __float_as_uint(v), false, false);
+  return __uint_as_float(r[0]) + __uint_as_float(r[1]);
+}
+
+// Largest absolute value over the wavefront.
+__device__ __forceinline__ float wave_max(float v) {
+  v = fmaxf(v, __shfl_xor(v, 16));
+  v = fmaxf(v, __shfl_xor(v, 8));
+  v = fmaxf(v, __shfl_xor(v, 4));
+  v = fmaxf(v, __shfl_xor(v, 2));
+  v = fmaxf(v, __shfl_xor(v, 1));
+  auto r = __builtin_amdgcn_permlane32_swap(__float_as_uint(v), __float_as_uint(v), false, false);
+  return fmaxf(__uint_as_float(r[0]), __uint_as_float(r[1]));
+}
+
+// In-place inverse of the lane-distributed block by Gauss-Jordan with 2x2 pivots.
+template <int Q, typename W>
+__device__ __forceinline__ bool gj2_invert(float (&a)[Q], int i, int h, W& w) {
+  constexpr int n = 2 * Q;
+  const bool act = i < n;
+  bool ok = true;
+#pragma unroll 1
+  for (int qq = 0; qq < Q; ++qq) {
+    const int r0 = 2 * qq;
+    const float cv = a[qq];  // element (i, r0 + h)
+    if (act) w.col[h * 32 + i] = cv;
+    const int r = i - r0;
+    const bool inR = act && (r == 0 || r == 1);
+    if (inR) {
+#pragma unroll
+      for (int q = 0; q < Q; ++q) w.row[(r * 2 + h) * 16 + q] = a[q];
+    }
+    wsync();
+    const float P00 = w.col[r0], P01 = w.col[32 + r0];
+    const float P10 = w.col[r0 + 1], P11 = w.col[32 + r0 + 1];
+    const float det = P00 * P11 - P01 * P10;
+    ok = ok && (det != 0.0f) && isfinite(det);
+    const float id = 1.0f / det;
+    const float Pi00 = P11 * id, Pi01 = -P01 * id, Pi10 = -P10 * id, Pi11 = P00 * id;
+    const float g0 = act ? w.col[i] : 0.0f;
+    const float g1 = act ? w.col[32 + i] : 0.0f;
+    float G0 = g0 * Pi00 + g1 * Pi10;
+    float G1 = g0 * Pi01 + g1 * Pi11;
+    float s = 1.0f;
+    float newc = (h == 0) ? -G0 : -G1;
+    if (inR) {
+      s = 0.0f;
+      G0 = (r == 0) ? -Pi00 : -Pi10;
+      G1 = (r == 0) ? -Pi01 : -Pi11;
+      newc = (r == 0) ? ((h == 0) ? Pi00 : Pi01) : ((h == 0) ? Pi10 : Pi11);
+    }
+    const float* w0 = w.row + (0 * 2 + h) * 16;
+    const float* w1 = w.row + (1 * 2 + h) * 16;
+#pragma unroll
+    for (int q = 0; q < Q; ++q) a[q] = fmaf(-G1, w1[q], fmaf(-G0, w0[q], s * a[q]));
+    a[qq] = act ? newc : 0.0f;
+    wsync();
+  }
+  return ok;
+}
+
+// RODAS4 (Hairer & Wanner) in the form
+//   (I/(h g) - J) K_i = f(t + al_i h, y + sum_j a_ij K_j) + sum_j (c_ij/h) K_j + h gm_i f_t,
+//   y_{n+1} = y + sum_j a_6j K_j + K_6,  g = 1/4; K_6 is the embedded error estimate.
+__constant__ float kRodasAlpha[6] = {0.0f, 0.386f, 0.21f, 0.63f, 1.0f, 1.0f};
+__constant__ float kRodasGamma[6] = {0.25f, -0.1043f, 0.1035f, -0.03620000000000023f, 0.0f, 0.0f};
+__constant__ float kRodasA[6][5] = {
+    {0, 0, 0, 0, 0},
+    {1.544f, 0, 0, 0, 0},
+    {0.9466785280815826f, 0.2557011698983284f, 0, 0, 0},
+    {3.314825187068521f, 2.896124015972201f, 0.9986419139977817f, 0, 0},
+    {1.221224509226641f, 6.019134481288629f, 12.53708332932087f, -0.6878860361058950f, 0},
+    {1.221224509226641f, 6.019134481288629f, 12.53708332932087f, -0.6878860361058950f, 1.0f}};
+__constant__ float kRodasC[6][5] = {
+    {0, 0, 0, 0, 0},
+    {-5.668800000000000f, 0, 0, 0, 0},
+    {-2.430093356833875f, -0.2063599157091915f, 0, 0, 0},
+    {-0.1073529058151375f, -9.594562251023355f, -20.47028614809616f, 0, 0},
+    {7.496443313967647f, -10.24680431464352f, -33.99990352819905f, 11.70890893206160f, 0},
+    {8.083246795921522f, -7.981132988064893f, -31.52159432874371f, 16.31930543123136f, -6.058818238834054f}};
+
+struct StepArgs {
+  const InstParams* ip;
+  const int32_t* inst_idx;
+  int n_inst;
+  const double* c0;
+  int64_t c_stride;
+  double amp[3], freq[3], phase[3];  // drive
+  double period;
+  int settle;
+  int Ns;
+  int r_fixed;   // > 0: fixed substeps per sample interval; 0: adaptive
+  int r_max;
+  float tol;     // adaptive: bound on max |K6| (embedded RODAS4 error) per step
+  float* msamp;  // [n_total][3][Ns]
+  int32_t* status;
+  int32_t* steps_out;  // [n_total] time steps taken (may be null)
+};
+
+template <int L, int WAVES>
+__global__ void __launch_bounds__(64 * WAVES)
+stepper_kernel(StepArgs A, DevTables t) {
+  using Gm = Geo<L>;
+  using WL = WaveLds<L>;
+  constexpr int Np = Gm::Np;
+  constexpr int S = Gm::S;
+  extern __shared__ __align__(16) unsigned char smem[];
+  // fixed-slot operator tables: indices (u16) then values (f32), slot-major
+  uint16_t* ecol = reinterpret_cast<uint16_t*>(smem);          // [kNSlRow][Np]
+  uint16_t* crow = ecol + kNSlRow * Np;                        // [kNSlCol][Np]
+  constexpr size_t b16 = ((size_t(kNSlRow + kNSlCol) * Np * 2) + 15) & ~size_t(15);
+  float* eval = reinterpret_cast<float*>(smem + b16);          // [kNSlRow][Np]
+  float* cvl = eval + kNSlRow * Np;                            // [kNSlCol][Np]
+  constexpr size_t tb = (b16 + size_t(kNSlRow + kNSlCol) * Np * 4 + 15) & ~size_t(15);
+  WL* wl = reinterpret_cast<WL*>(smem + tb);
+  for (int e = threadIdx.x; e < kNSlRow * Np; e += blockDim.x) { ecol[e] = t.ell_col[e]; eval[e] = t.ell_val[e]; }
+  for (int e = threadIdx.x; e < kNSlCol * Np; e += blockDim.x) { crow[e] = t.ecol_row[e]; cvl[e] = t.ecol_val[e]; }
+  __syncthreads();
+
+  const int lane = threadIdx.x & 63;
+  const int wid = threadIdx.x >> 6;
+  const int slot = blockIdx.x * WAVES + wid;
+  if (slot >= A.n_inst) return;
+  const int inst = A.inst_idx[slot];
+  WL& w = wl[wid];
+  const int i = lane & 31, h = lane >> 5;
+  float* ms_out = A.msamp + int64_t(inst) * 3 * A.Ns;
+  if (A.status[inst] != 0) {
+    for (int j = lane; j < 3 * A.Ns; j += 64) ms_out[j] = __builtin_nanf("");
+    if (A.steps_out && lane == 0) A.steps_out[inst] = 0;
+    return;
+  }
+  const InstParams P = A.ip[inst];
+  const float inv2tau = float(P.inv2tau), sigma = float(P.sigma), alpha = float(P.alpha), beta = float(P.beta_T);
+  float R[9], off[3];
+  for (int c = 0; c < 9; ++c) R[c] = float(P.R[c]);
+  for (int c = 0; c < 3; ++c) off[c] = float(P.off[c]);
+
+  float y[S];
+#pragma unroll
+  for (int s = 0; s < S; ++s) {
+    const int p = lane + 64 * s;
+    y[s] = (p < Np) ? float(A.c0[int64_t(inst) * A.c_stride + p]) : 0.0f;
+  }
+  Store<L, L> st;
+  const float rc = 2.0466534158929770f;  // sqrt(4 pi / 3)
+  constexpr int pX = Gm::off(1), pY = Gm::off(1) + 1, pZ = 1;
+  bool ok = true;
+
+  // drive: mu0 H_a(t) = amp_a cos(2 pi (f_a t) + phase_a); cycles reduced in FP64
+  auto field = [&](double tt, float& bx, float& by, float& bz, bool deriv) {
+    float v[3];
+#pragma unroll
+    for (int a = 0; a < 3; ++a) {
+      const double cyc = A.freq[a] * tt;
+      const float x = float(2.0 * (cyc - floor(cyc))) + float(A.phase[a] * 0.3183098861837907);
+      if (!deriv) {
+        v[a] = float(A.amp[a]) * cospif(x);
+      } else {
+        v[a] = -float(A.amp[a] * 2.0 * kPi * A.freq[a]) * sinpif(x);
+      }
+    }
+    bx = v[0]; by = v[1]; bz = v[2];
+  };
+  // multiplier of kind `lane` (lanes 0..8) at time tt
+  auto mult_lane = [&](double tt) -> float {
+    float bx, by, bz;
+    field(tt, bx, by, bz, false);
+    bx += off[0]; by += off[1]; bz += off[2];
+    const float hx = R[0] * bx + R[3] * by + R[6] * bz;
+    const float hy = R[1] * bx + R[4] * by + R[7] * bz;
+    const float hz = R[2] * bx + R[5] * by + R[8] * bz;
+    return kind_mult(lane < 9 ? lane : 0, inv2tau, sigma, alpha, beta, hx, hy, hz);
+  };
+  auto dmult_lane = [&](double tt) -> float {
+    float bx, by, bz;
+    field(tt, bx, by, bz, true);
+    const float hx = R[0] * bx + R[3] * by + R[6] * bz;
+    const float hy = R[1] * bx + R[4] * by + R[7] * bz;
+    const float hz = R[2] * bx + R[5] * by + R[8] * bz;
+    return (lane < 3) ? 0.0f : kind_mult(lane < 9 ? lane : 0, inv2tau, sigma, alpha, beta, hx, hy, hz);
+  };
+  // dst[p] = add * dst[p] + (A(ms) xin)[p] for the rows p = lane + 64 s (one row slot at a time)
+  auto matvec = [&](float* dst, bool add) {
+    const float* xin = w.xin();
+    float m[9];
+#pragma unroll
+    for (int k = 0; k < 9; ++k) m[k] = w.ms[k];
+#pragma unroll 1
+    for (int s = 0; s < S; ++s) {
+      const int p = lane + 64 * s;
+      const int z = opaque_zero();
+      const uint16_t* ec = ecol + z;
+      const float* ev = eval + z;
+      if (p < Np) {
+        float acc = 0.0f;
+#pragma unroll
+        for (int sl = 0; sl < kNSlRow; ++sl)
+          acc = fmaf(m[kSlotKindRow[sl]] * ev[sl * Np + p], xin[ec[sl * Np + p]], acc);
+        dst[p] = add ? dst[p] + acc : acc;
+      }
+    }
+  };
+  // block-tridiagonal solve M x = V with the resident inverses; result in G
+  auto solve = [&]() {
+    float* V = w.V();
+    float* G = w.G();
+    float mk[9];
+#pragma unroll
+    for (int k = 0; k < 9; ++k) mk[k] = w.mk[k];
+    static_for<0, L + 1>([&](auto KK) {
+      constexpr int K = decltype(KK)::value;
+      constexpr int n = Gm::nb(K), Q = n / 2, off0 = Gm::off(K);
+      if (h == 0 && i < n) {
+        const int row = off0 + i;
+        float tv = V[row];
+        if constexpr (K > 0) {
+          const int z = opaque_zero();
+#pragma unroll
+          for (int sl = kSlB; sl < kSlB + kNSlB; ++sl)
+            tv = fmaf(-mk[kSlotKindRow[sl]] * eval[z + sl * Np + row], G[ecol[z + sl * Np + row]], tv);
+        }
+        w.T[(i & 1) * 16 + (i >> 1)] = tv;
+      }
+      wsync();
+      auto& a = blk<K>(st);
+      float part = 0.0f;
+#pragma unroll
+      for (int q = 0; q < Q; ++q) part = fmaf(a[q], w.T[h * 16 + q], part);
+      part = half_sum(part);
+      if (h == 0 && i < n) G[off0 + i] = part;
+      wsync();
+      __builtin_amdgcn_sched_barrier(0);
+    });
+    static_for_down<L - 1, 0>([&](auto KK) {
+      constexpr int K = decltype(KK)::value;
+      constexpr int n = Gm::nb(K), Q = n / 2, off0 = Gm::off(K);
+      if (h == 0 && i < n) {
+        const int row = off0 + i;
+        float tv = 0.0f;
+        const int z = opaque_zero();
+#pragma unroll
+        for (int sl = kSlC; sl < kSlC + kNSlC; ++sl)
+          tv = fmaf(mk[kSlotKindRow[sl]] * eval[z + sl * Np + row], G[ecol[z + sl * Np + row]], tv);
+        w.T[(i & 1) * 16 + (i >> 1)] = tv;
+      }
+      wsync();
+      auto& a = blk<K>(st);
+      float part = 0.0f;
+#pragma unroll
+      for (int q = 0; q < Q; ++q) part = fmaf(a[q], w.T[h * 16 + q], part);
+      part = half_sum(part);
+      if (h == 0 && i < n) G[off0 + i] -= part;
+      wsync();
+      __builtin_amdgcn_sched_barrier(0);
+    });
+  };
+  // factor M = I - h g A(t_n) (multipliers in w.mk): Schur-complement inverses into registers
+  auto factor = [&]() {
+    float* X = w.X();
+    float* Ub = w.Ub();
+    float mk[9];
+#pragma unroll
+    for (int k = 0; k < 9; ++k) mk[k] = w.mk[k];
+    static_for<0, L + 1>([&](auto KK) {
+      constexpr int K = decltype(KK)::value;
+      constexpr int n = Gm::nb(K), Q = n / 2, off0 = Gm::off(K);
+      const bool act = i < n;
+      if constexpr (K > 0) {
+        constexpr int np = Gm::nb(K - 1), Qp = np / 2, offp = Gm::off(K - 1);
+        auto& ap = blk<K - 1>(st);
+        if (i < np) {
+#pragma unroll
+          for (int q = 0; q < Qp; ++q) X[i * 32 + h * 16 + q] = ap[q];
+        }
+        wsync();
+        float u[Qp];
+#pragma unroll
+        for (int q = 0; q < Qp; ++q) u[q] = 0.0f;
+        if (act) {
+          const int row = off0 + i;
+          const int z = opaque_zero();
+#pragma unroll
+          for (int sl = kSlB; sl < kSlB + kNSlB; ++sl) {
+            const float me = mk[kSlotKindRow[sl]] * eval[z + sl * Np + row];
+            const float* xr = X + (int(ecol[z + sl * Np + row]) - offp) * 32 + h * 16;
+#pragma unroll
+            for (int q = 0; q < Qp; ++q) u[q] = fmaf(me, xr[q], u[q]);
+            __builtin_amdgcn_sched_barrier(0);
+          }
+#pragma unroll
+          for (int q = 0; q < Qp; ++q) Ub[i * 32 + h * 16 + q] = u[q];
+        }
+        wsync();
+      }
+      if (act) {
+#pragma unroll
+        for (int q = 0; q < Q; ++q) X[i * 32 + h * 16 + q] = 0.0f;
+      }
+      wsync();
+      if (act) {
+        const int row = off0 + i;
+        const int z = opaque_zero();
+#pragma unroll
+        for (int sl = kSlD; sl < kSlD + kNSlD; ++sl) {
+          const int cl = int(ecol[z + sl * Np + row]) - off0;
+          if ((cl & 1) == h) X[i * 32 + h * 16 + (cl >> 1)] += mk[kSlotKindRow[sl]] * eval[z + sl * Np + row];
+        }
+        if ((i & 1) == h) X[i * 32 + h * 16 + (i >> 1)] += 1.0f;
+      }
+      wsync();
+      // work on a local copy: the indexed pivot-column access must not touch the store itself
+      float a[Q];
+#pragma unroll
+      for (int q = 0; q < Q; ++q) a[q] = act ? X[i * 32 + h * 16 + q] : 0.0f;
+      if constexpr (K > 0) {
+        constexpr int offp = Gm::off(K - 1);
+        if (act) {
+#pragma unroll
+          for (int q = 0; q < Q; ++q) {
+            const int c = off0 + h + 2 * q;
+            float acc = 0.0f;
+            const int z = opaque_zero();
+#pragma unroll
+            for (int sl = 0; sl < kNSlCol; ++sl) {
+              const int rl = int(crow[z + sl * Np + c]) - offp;
+              acc = fmaf(mk[kSlotKindCol[sl]] * cvl[z + sl * Np + c], Ub[i * 32 + (rl & 1) * 16 + (rl >> 1)], acc);
+            }
+            a[q] -= acc;
+            if ((q & 3) == 3) __builtin_amdgcn_sched_barrier(0);  // bound the gathers in flight
+          }
+        }
+      }
+      ok = gj2_invert<Q>(a, i, h, w) && ok;
+      auto& sa = blk<K>(st);
+#pragma unroll
+      for (int q = 0; q < Q; ++q) sa[q] = a[q];
+      __builtin_amdgcn_sched_barrier(0);
+    });
+  };
+
+  // one RODAS4 step of size hs from t_n; returns max |K6| (embedded error estimate)
+  auto rodas_step = [&](double tn, double hs) -> float {
+    const float hf = float(hs);
+    const float hg = hf * 0.25f;
+    const float ih = 1.0f / hf;
+    {
+      const float mt = mult_lane(tn);
+      if (lane < 9) { w.mk[lane] = -hg * mt; }
+      wsync();
+    }
+    factor();
+    {  // f_t = A'(t_n) y  -> LDS
+      float* xin = w.xin();
+#pragma unroll
+      for (int s = 0; s < S; ++s) {
+        const int p = lane + 64 * s;
+        if (p < Np) xin[p] = y[s];
+      }
+      const float md = dmult_lane(tn);
+      if (lane < 9) w.ms[lane] = md;
+      wsync();
+      matvec(w.ft(), false);
+      wsync();
+    }
+    float yt[S], kr[S];
+    for (int stg = 0; stg < 6; ++stg) {
+      const float mt = mult_lane(tn + double(kRodasAlpha[stg]) * hs);
+      if (lane < 9) w.ms[lane] = mt;
+      // stage argument and the extra right-hand-side terms
+      float ex[S];
+#pragma unroll
+      for (int s = 0; s < S; ++s) {
+        const int p = lane + 64 * s;
+        float yv = y[s];
+        float ev = (p < Np) ? hf * kRodasGamma[stg] * w.ft()[p] : 0.0f;
+        for (int j = 0; j < stg; ++j) {
+          const float kj = (p < Np) ? w.Kv(j)[p] : 0.0f;
+          yv = fmaf(kRodasA[stg][j], kj, yv);
+          ev = fmaf(kRodasC[stg][j] * ih, kj, ev);
+        }
+        yt[s] = yv;
+        ex[s] = ev;
+      }
+      // V = A(ms) yt + ex; solve; K = h g M^{-1} V
+      float* xin = w.xin();
+      float* V = w.V();
+#pragma unroll
+      for (int s = 0; s < S; ++s) {
+        const int p = lane + 64 * s;
+        if (p < Np) {
+          xin[p] = yt[s];
+          V[p] = ex[s];
+        }
+      }
+      wsync();
+      matvec(V, true);
+      wsync();
+      solve();
+      const float* G = w.G();
+      float* kd = w.Kv(stg < 5 ? stg : 4);
+#pragma unroll
+      for (int s = 0; s < S; ++s) {
+        const int p = lane + 64 * s;
+        kr[s] = (p < Np) ? hg * G[p] : 0.0f;
+        if (stg < 5 && p < Np) kd[p] = kr[s];
+      }
+      wsync();
+    }
+    // y_{n+1} = (y + sum_{j<6} a6j K_j) + K6 ; embedded error K6
+    float emax = 0.0f;
+#pragma unroll
+    for (int s = 0; s < S; ++s) {
+      y[s] = yt[s] + kr[s];
+      emax = fmaxf(emax, fabsf(kr[s]));
+    }
+    return wave_max(emax);
+  };
+
+  const double dt = A.period / A.Ns;
+  const int n_int = (A.settle + 1) * A.Ns;
+  const int first_rec = A.settle * A.Ns;
+  int r = (A.r_fixed > 0) ? A.r_fixed : 1;
+  int steps = 0;
+  for (int j = 0; j < n_int && ok; ++j) {
+    const double tj = j * dt;
+    if (j >= first_rec) {
+      const int js = j - first_rec;
+      const float vx = __shfl(y[pX >> 6], pX & 63), vy = __shfl(y[pY >> 6], pY & 63),
+                  vz = __shfl(y[pZ >> 6], pZ & 63);
+      if (lane < 3) {
+        const float r0 = lane == 0 ? R[0] : (lane == 1 ? R[3] : R[6]);
+        const float r1 = lane == 0 ? R[1] : (lane == 1 ? R[4] : R[7]);
+        const float r2 = lane == 0 ? R[2] : (lane == 1 ? R[5] : R[8]);
+        ms_out[lane * A.Ns + js] = rc * (r0 * vx + r1 * vy + r2 * vz);
+      }
+      ok = ok && isfinite(vx) && isfinite(vy) && isfinite(vz);
+    }
+    float ysave[S];
+#pragma unroll
+    for (int s = 0; s < S; ++s) ysave[s] = y[s];
+    while (true) {
+      const double hs = dt / r;
+      float emax = 0.0f;
+      for (int sub = 0; sub < r; ++sub) {
+        emax = fmaxf(emax, rodas_step(tj + sub * hs, hs));
+        ++steps;
+      }
+      if (!isfinite(emax)) {
+        ok = false;
+        break;
+      }
+      if (A.r_fixed > 0) break;
+      if (!(emax <= A.tol) && r < A.r_max && isfinite(emax)) {  // reject the interval, refine
+#pragma unroll
+        for (int s = 0; s < S; ++s) y[s] = ysave[s];
+        const int rn = int(ceilf(float(r) * 1.2f * sqrtf(sqrtf(emax / A.tol))));
+        r = min(A.r_max, max(2 * r, rn));
+        continue;
+      }
+      // accept; shrink the next interval's substeps when the estimate allows
+      const int rn = int(ceilf(float(r) * 1.2f * sqrtf(sqrtf(fmaxf(emax, 1e-30f) / A.tol))));
+      r = max(1, min(r, rn));
+      break;
+    }
+  }
+  if (!ok) {
+    for (int j = lane; j < 3 * A.Ns; j += 64) ms_out[j] = __builtin_nanf("");
+    if (lane == 0) A.status[inst] = 2;
+  }
+  if (A.steps_out && lane == 0) A.steps_out[inst] = steps;
+}
+
+#ifndef FPN_STEPPER_WAVES
+#define FPN_STEPPER_WAVES 8
+#endif
+constexpr int kWaves = FPN_STEPPER_WAVES;  // instances (wavefronts) per workgroup
+
+template <int L>
+size_t stepper_lds_bytes_L(const DevTables&) {
+  constexpr int Np = Geo<L>::Np;
+  constexpr size_t b16 = ((size_t(kNSlRow + kNSlCol) * Np * 2) + 15) & ~size_t(15);
+  constexpr size_t tb = (b16 + size_t(kNSlRow + kNSlCol) * Np * 4 + 15) & ~size_t(15);
+  return tb + kWaves * sizeof(WaveLds<L>);
+}
+
+template <int L>
+hipError_t launch_stepper_L(const StepLaunch& s, const DevTables& t, hipStream_t stream) {
+  StepArgs a;
+  a.ip = s.ip;
+  a.inst_idx = s.inst_idx;
+  a.n_inst = s.n_inst;
+  a.c0 = s.c0;
+  a.c_stride = s.c_stride;
+  for (int c = 0; c < 3; ++c) {
+    a.amp[c] = s.amp[c];
+    a.freq[c] = s.freq[c];
+    a.phase[c] = s.phase[c];
+  }
+  a.period = s.period;
+  a.settle = s.settle;
+  a.Ns = s.Ns;
+  a.r_fixed = s.r_fixed;
+  a.r_max = s.r_max;
+  a.tol = s.tol;
+  a.msamp = s.msamp;
+  a.status = s.status;
+  a.steps_out = s.steps_out;
+  const size_t shm = stepper_lds_bytes_L<L>(t);
+  auto kern = stepper_kernel<L, kWaves>;
+  hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void*>(kern),
+                                     hipFuncAttributeMaxDynamicSharedMemorySize, int(shm));
+  if (e != hipSuccess) return e;
+  const int grid = (s.n_inst + kWaves - 1) / kWaves;
+  hipLaunchKernelGGL(kern, dim3(grid), dim3(64 * kWaves), shm, stream, a, t);
+  return hipGetLastError();
+}
+
+#define FPN_INST(LL) template hipError_t launch_stepper_L<LL>(const StepLaunch&, const DevTables&, hipStream_t);
+#if !defined(FPN_L_BEGIN)
+#define FPN_L_BEGIN 1
+#define FPN_L_END 16
+#endif
+#if FPN_L_BEGIN <= 1 && 1 <= FPN_L_END
+FPN_INST(1)
+#endif
+#if FPN_L_BEGIN <= 2 && 2 <= FPN_L_END
+FPN_INST(2)
+#endif
+#if FPN_L_BEGIN <= 3 && 3 <= FPN_L_END
+FPN_INST(3)
+#endif
+#if FPN_L_BEGIN <= 4 && 4 <= FPN_L_END
+FPN_INST(4)
+#endif
+#if FPN_L_BEGIN <= 5 && 5 <= FPN_L_END
+FPN_INST(5)
+#endif
+#if FPN_L_BEGIN <= 6 && 6 <= FPN_L_END
+FPN_INST(6)
+#endif
+#if FPN_L_BEGIN <= 7 && 7 <= FPN_L_END
+FPN_INST(7)
+#endif
+#if FPN_L_BEGIN <= 8 && 8 <= FPN_L_END
+FPN_INST(8)
+#endif
+#if FPN_L_BEGIN <= 9 && 9 <= FPN_L_END
+FPN_INST(9)
+#endif
+#if FPN_L_BEGIN <= 10 && 10 <= FPN_L_END
+FPN_INST(10)
+#endif
+#if FPN_L_BEGIN <= 11 && 11 <= FPN_L_END
+FPN_INST(11)
+#endif
+#if FPN_L_BEGIN <= 12 && 12 <= FPN_L_END
+FPN_INST(12)
+#endif
+#if FPN_L_BEGIN <= 13 && 13 <= FPN_L_END
+FPN_INST(13)
+#endif
+#if FPN_L_BEGIN <= 14 && 14 <= FPN_L_END
+FPN_INST(14)
+#endif
+#if FPN_L_BEGIN <= 15 && 15 <= FPN_L_END
+FPN_INST(15)
+#endif
+#if FPN_L_BEGIN <= 16 && 16 <= FPN_L_END
+FPN_INST(16)
+#endif
+
+}  // namespace fpn

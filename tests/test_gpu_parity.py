@@ -109,8 +109,21 @@ def test_single_1d_matches_golden(fpn, ctx):
 
 @pytest.fixture(scope="module")
 def lissajous_full(fpn, ctx):
+    """The full 2312-instance batch in the production configuration (adaptive substeps)."""
     ws = W.lissajous_grid()
-    return ws, run(fpn, ctx, ws, substeps=3)
+    return ws, run(fpn, ctx, ws, substeps=0)
+
+
+def test_lissajous_fixed_substeps_sampled(fpn, ctx):
+    ws = W.take(W.lissajous_grid(), [144, 1950])
+    m, h, st = run(fpn, ctx, ws, substeps=3)
+    for j, f in enumerate(sorted(glob.glob(os.path.join(GOLDEN, "lissajous_*.npz")))):
+        g = np.load(f)
+        i = int(g["idx"])
+        if i not in (144, 1950):
+            continue
+        k = [144, 1950].index(i)
+        assert rel(h[k].T, g["Phi"][:, :2]) < TOL
 
 
 def test_lissajous_full_batch_sampled_instances_match_golden(lissajous_full):
@@ -174,5 +187,5 @@ def test_argument_errors(fpn, ctx):
 def test_empty_batch(fpn, ctx):
     ws = W.take(W.small_random(2, 10, seed=1), [])
     d = ws["drive"]
-    m, h, st = ctx.solve(ws["inst"], ws["inst"]["L"], fpn.make_drive(d["amp"], d["freq"], d["period"]), 16, 0, 4)
+    m, h, st = ctx.solve(ws["inst"], np.zeros(0, np.int32), fpn.make_drive(d["amp"], d["freq"], d["period"]), 16, 0, 4)
     assert m.shape[0] == 0 and st.shape[0] == 0
