@@ -158,6 +158,43 @@ fpn_status get_tables(fpn_ctx ctx, int L, const fpn::DevTables** out) {
         return fail(FPN_E_RANGE, "operator column does not fit the fixed-slot layout");
     }
   }
+  // window coefficients of the neighbour-block couplings (layout in device_common.hpp)
+  std::vector<float> wb(size_t(fpn::kNWin) * Np, 0.0f), wc(size_t(fpn::kNWin) * Np, 0.0f), ws(size_t(fpn::kNWin) * Np, 0.0f);
+  {
+    // expected kind of window slot e: same FX RY FX, other FY RX FY
+    const int ekind[6] = {fpn::K_FX, fpn::K_RY, fpn::K_FX, fpn::K_FY, fpn::K_RX, fpn::K_FY};
+    for (int p = 0; p < Np; ++p) {
+      const int K = blk_of[p], i = p - h->boff[K], tr = (K > 0) ? (i & 1) : 0;
+      for (int e = h->seg[4 * p]; e < h->seg[4 * p + 3]; ++e) {
+        const int col = int(h->colkind[e] & 0xffffu), kind = int(h->colkind[e] >> 16);
+        const float v = h->val[e];
+        const int Kc = blk_of[col], c = col - h->boff[Kc];
+        int slot = -1;
+        if (Kc == K - 1 && K >= 2) {  // B window of row p
+          if (((c - i) & 1) == 0) slot = (c - i) / 2;
+          else slot = 3 + (c - i - 1 + 2 * tr) / 2;
+          if (slot < 0 || slot > 5 || ekind[slot] != kind) return fail(FPN_E_RANGE, "B coupling outside its window");
+          wb[size_t(slot) * Np + p] = v;
+        }
+        if (Kc == K + 1) {  // C window of row p
+          const int bs = (K >= 1) ? i - 4 : 2 * i - 4;
+          const int bo = (K >= 1) ? i - 3 - 2 * tr : 2 * i - 3;
+          if (((c - bs) & 1) == 0) slot = (c - bs) / 2;
+          else slot = 3 + (c - bo) / 2;
+          if (slot < 0 || slot > 5 || ekind[slot] != kind) return fail(FPN_E_RANGE, "C coupling outside its window");
+          wc[size_t(slot) * Np + p] = v;
+          if (Kc >= 2) {  // S window of column col: rows of block Kc-1 = K
+            const int tc = c & 1;
+            int ss;
+            if (((i - c) & 1) == 0) ss = (i - c) / 2;
+            else ss = 3 + (i - c - 1 + 2 * tc) / 2;
+            if (ss < 0 || ss > 5 || ekind[ss] != kind) return fail(FPN_E_RANGE, "Schur coupling outside its window");
+            ws[size_t(ss) * Np + col] = v;
+          }
+        }
+      }
+    }
+  }
   hipError_t e = hipSuccess;
   if (e == hipSuccess) e = up(&t.seg, h->seg);
   if (e == hipSuccess) e = up(&t.colkind, h->colkind);
@@ -171,6 +208,9 @@ fpn_status get_tables(fpn_ctx ctx, int L, const fpn::DevTables** out) {
   if (e == hipSuccess) e = up(&t.ell_val, eval);
   if (e == hipSuccess) e = up(&t.ecol_row, crow);
   if (e == hipSuccess) e = up(&t.ecol_val, cvl);
+  if (e == hipSuccess) e = up(&t.win_b, wb);
+  if (e == hipSuccess) e = up(&t.win_c, wc);
+  if (e == hipSuccess) e = up(&t.win_s, ws);
   if (e == hipSuccess) e = up(&t.boff, boff);
   if (e == hipSuccess) e = up(&t.bn, bn);
   if (e != hipSuccess) {

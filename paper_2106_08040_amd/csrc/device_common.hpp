@@ -27,6 +27,9 @@ struct DevTables {
   float* ell_val;      // [kNSlRow][Np]
   uint16_t* ecol_row;  // [kNSlCol][Np] fixed-slot columns of the lower coupling
   float* ecol_val;     // [kNSlCol][Np]
+  float* win_b;        // [kNWin][Np] window coefficients (see above)
+  float* win_c;        // [kNWin][Np]
+  float* win_s;        // [kNWin][Np]
   int32_t* boff;       // [L+1]
   int32_t* bn;         // [L+1]
   int64_t inv_doubles; // sum of bn^2
@@ -52,6 +55,15 @@ constexpr int kSlotKindRow[kNSlRow] = {0, 1, 1, 1, 2, 2, 3, 3, 4,   // D: LAM G 
                                        5, 5, 6, 6, 7, 8,            // B: FX FX FY FY RX RY
                                        5, 5, 6, 6, 7, 8};           // C
 constexpr int kSlotKindCol[kNSlCol] = {5, 5, 6, 6, 7, 8};
+
+// Window layout of the couplings between neighbouring |m| blocks (block-local indices; row or
+// column i, type t = i & 1; d = 0, 1, 2 for degree offsets -1, 0, +1).  Slot e = d (same type)
+// or 3 + d (other type).  Kinds: same type FX, RY, FX; other type FY, RX, FY (d = 0, 1, 2).
+//   B (row i of block K >= 2 -> block K-1):   same i + 2d,      other i + 1 - 2t + 2d
+//   C (row i of block K >= 1 -> block K+1):   same i - 4 + 2d,  other i - 3 - 2t + 2d
+//     (block 0, cos only:                     same 2i - 4 + 2d, other 2i - 3 + 2d)
+//   S (column i of block K >= 2, rows of block K-1): same i + 2d, other i + 1 - 2t + 2d
+enum : int { kNWin = 6 };
 
 // RODAS4 (Hairer & Wanner), in the form
 //   (I/(h g) - J) K_i = f(t + al_i h, y + sum_j a_ij K_j) + sum_j (c_ij/h) K_j + h gi_i f_t,

@@ -194,10 +194,16 @@ stepper_kernel(StepArgs A, DevTables t) {
   constexpr size_t b16 = ((size_t(kNSlRow + kNSlCol) * Np * 2) + 15) & ~size_t(15);
   float* eval = reinterpret_cast<float*>(smem + b16);          // [kNSlRow][Np]
   float* cvl = eval + kNSlRow * Np;                            // [kNSlCol][Np]
-  constexpr size_t tb = (b16 + size_t(kNSlRow + kNSlCol) * Np * 4 + 15) & ~size_t(15);
+  float* wB = cvl + kNSlCol * Np;                              // [kNWin][Np] window coefficients
+  float* wC = wB + kNWin * Np;
+  float* wS = wC + kNWin * Np;
+  constexpr size_t tb = (b16 + size_t(kNSlRow + kNSlCol + 3 * kNWin) * Np * 4 + 15) & ~size_t(15);
   WL* wl = reinterpret_cast<WL*>(smem + tb);
   for (int e = threadIdx.x; e < kNSlRow * Np; e += blockDim.x) { ecol[e] = t.ell_col[e]; eval[e] = t.ell_val[e]; }
   for (int e = threadIdx.x; e < kNSlCol * Np; e += blockDim.x) { crow[e] = t.ecol_row[e]; cvl[e] = t.ecol_val[e]; }
+  for (int e = threadIdx.x; e < kNWin * Np; e += blockDim.x) { wB[e] = t.win_b[e]; wC[e] = t.win_c[e]; wS[e] = t.win_s[e]; }
+  // per-wave scratch starts zeroed: window reads past a block edge (weight 0) then see finite data
+  for (int e = threadIdx.x; e < int(WAVES * sizeof(WL) / 4); e += blockDim.x) reinterpret_cast<float*>(wl)[e] = 0.0f;
   __syncthreads();
 
   const int lane = threadIdx.x & 63;
@@ -291,17 +297,29 @@ stepper_kernel(StepArgs A, DevTables t) {
     float mk[9];
 #pragma unroll
     for (int k = 0; k < 9; ++k) mk[k] = w.mk[k];
+    const float mFX = mk[5], mFY = mk[6], mRX = mk[7], mRY = mk[8];
     static_for<0, L + 1>([&](auto KK) {
       constexpr int K = decltype(KK)::value;
       constexpr int n = Gm::nb(K), Q = n / 2, off0 = Gm::off(K);
       if (h == 0 && i < n) {
         const int row = off0 + i;
         float tv = V[row];
-        if constexpr (K > 0) {
+        if constexpr (K == 1) {
           const int z = opaque_zero();
 #pragma unroll
           for (int sl = kSlB; sl < kSlB + kNSlB; ++sl)
             tv = fmaf(-mk[kSlotKindRow[sl]] * eval[z + sl * Np + row], G[ecol[z + sl * Np + row]], tv);
+        } else if constexpr (K >= 2) {
+          constexpr int offp = Gm::off(K - 1);
+          const int z = opaque_zero();
+          const int t = i & 1;
+          const float* gs = G + offp + i;
+          const float* go = G + offp + i + 1 - 2 * t;
+#pragma unroll
+          for (int d = 0; d < 3; ++d) {
+            tv = fmaf(-(d == 1 ? mRY : mFX) * wB[z + d * Np + row], gs[2 * d], tv);
+            tv = fmaf(-(d == 1 ? mRX : mFY) * wB[z + (3 + d) * Np + row], go[2 * d], tv);
+          }
         }
         w.T[(i & 1) * 16 + (i >> 1)] = tv;
       }
@@ -321,10 +339,18 @@ stepper_kernel(StepArgs A, DevTables t) {
       if (h == 0 && i < n) {
         const int row = off0 + i;
         float tv = 0.0f;
-        const int z = opaque_zero();
+        {
+          constexpr int offn = Gm::off(K + 1);
+          const int z = opaque_zero();
+          const int t = (K > 0) ? (i & 1) : 0;
+          const float* gs = G + offn + ((K > 0) ? i - 4 : 2 * i - 4);
+          const float* go = G + offn + ((K > 0) ? i - 3 - 2 * t : 2 * i - 3);
 #pragma unroll
-        for (int sl = kSlC; sl < kSlC + kNSlC; ++sl)
-          tv = fmaf(mk[kSlotKindRow[sl]] * eval[z + sl * Np + row], G[ecol[z + sl * Np + row]], tv);
+          for (int d = 0; d < 3; ++d) {
+            tv = fmaf((d == 1 ? mRY : mFX) * wC[z + d * Np + row], gs[2 * d], tv);
+            tv = fmaf((d == 1 ? mRX : mFY) * wC[z + (3 + d) * Np + row], go[2 * d], tv);
+          }
+        }
         w.T[(i & 1) * 16 + (i >> 1)] = tv;
       }
       wsync();
@@ -349,6 +375,9 @@ stepper_kernel(StepArgs A, DevTables t) {
       constexpr int K = decltype(KK)::value;
       constexpr int n = Gm::nb(K), Q = n / 2, off0 = Gm::off(K);
       const bool act = i < n;
+      constexpr int Qpv = (K > 0) ? Gm::nb(K > 0 ? K - 1 : 0) / 2 : 1;
+      float u[Qpv];      // U = B_K Sinv_{K-1}: row i, columns of parity h
+      float uo[Qpv];     // the same row, columns of the other parity (partner lane)
       if constexpr (K > 0) {
         constexpr int np = Gm::nb(K - 1), Qp = np / 2, offp = Gm::off(K - 1);
         auto& ap = blk<K - 1>(st);
@@ -357,24 +386,47 @@ stepper_kernel(StepArgs A, DevTables t) {
           for (int q = 0; q < Qp; ++q) X[i * 32 + h * 16 + q] = ap[q];
         }
         wsync();
-        float u[Qp];
 #pragma unroll
         for (int q = 0; q < Qp; ++q) u[q] = 0.0f;
         if (act) {
           const int row = off0 + i;
           const int z = opaque_zero();
+          if constexpr (K == 1) {
 #pragma unroll
-          for (int sl = kSlB; sl < kSlB + kNSlB; ++sl) {
-            const float me = mk[kSlotKindRow[sl]] * eval[z + sl * Np + row];
-            const float* xr = X + (int(ecol[z + sl * Np + row]) - offp) * 32 + h * 16;
+            for (int sl = kSlB; sl < kSlB + kNSlB; ++sl) {
+              const float me = mk[kSlotKindRow[sl]] * eval[z + sl * Np + row];
+              const float* xr = X + (int(ecol[z + sl * Np + row]) - offp) * 32 + h * 16;
 #pragma unroll
-            for (int q = 0; q < Qp; ++q) u[q] = fmaf(me, xr[q], u[q]);
-            __builtin_amdgcn_sched_barrier(0);
+              for (int q = 0; q < Qp; ++q) u[q] = fmaf(me, xr[q], u[q]);
+              __builtin_amdgcn_sched_barrier(0);
+            }
+          } else {
+            const int t = i & 1;
+            const float* xs = X + i * 32 + h * 16;                // rows i + 2d
+            const float* xo = X + (i + 1 - 2 * t) * 32 + h * 16;  // rows i + 1 - 2t + 2d
+#pragma unroll
+            for (int d = 0; d < 3; ++d) {
+              const float ms_ = (d == 1 ? mk[8] : mk[5]) * wB[z + d * Np + row];
+              const float mo_ = (d == 1 ? mk[7] : mk[6]) * wB[z + (3 + d) * Np + row];
+#pragma unroll
+              for (int q = 0; q < Qp; ++q) u[q] = fmaf(mo_, xo[64 * d + q], fmaf(ms_, xs[64 * d + q], u[q]));
+              __builtin_amdgcn_sched_barrier(0);
+            }
           }
-#pragma unroll
-          for (int q = 0; q < Qp; ++q) Ub[i * 32 + h * 16 + q] = u[q];
         }
-        wsync();
+        if constexpr (K == 1) {
+          if (act) {
+#pragma unroll
+            for (int q = 0; q < Qp; ++q) Ub[i * 32 + h * 16 + q] = u[q];
+          }
+          wsync();
+        } else {
+#pragma unroll
+          for (int q = 0; q < Qp; ++q) {
+            auto r = __builtin_amdgcn_permlane32_swap(__float_as_uint(u[q]), __float_as_uint(u[q]), false, false);
+            uo[q] = __uint_as_float(h == 0 ? r[1] : r[0]);
+          }
+        }
       }
       if (act) {
 #pragma unroll
@@ -396,7 +448,7 @@ stepper_kernel(StepArgs A, DevTables t) {
       float a[Q];
 #pragma unroll
       for (int q = 0; q < Q; ++q) a[q] = act ? X[i * 32 + h * 16 + q] : 0.0f;
-      if constexpr (K > 0) {
+      if constexpr (K == 1) {
         constexpr int offp = Gm::off(K - 1);
         if (act) {
 #pragma unroll
@@ -411,6 +463,26 @@ stepper_kernel(StepArgs A, DevTables t) {
             }
             a[q] -= acc;
             if ((q & 3) == 3) __builtin_amdgcn_sched_barrier(0);  // bound the gathers in flight
+          }
+        }
+      } else if constexpr (K >= 2) {
+        // S_K -= U C_{K-1}: column c = h + 2q takes U[i][c + 2d] (own parity) and
+        // U[i][c + 1 - 2h + 2d] (other parity) with the window weights of column c
+        constexpr int Qp = Gm::nb(K - 1) / 2;
+        if (act) {
+          const int z = opaque_zero();
+#pragma unroll
+          for (int q = 0; q < Q; ++q) {
+            const int c = off0 + h + 2 * q;
+            float acc = 0.0f;
+#pragma unroll
+            for (int d = 0; d < 3; ++d) {
+              if (q + d < Qp) {
+                acc = fmaf((d == 1 ? mk[8] : mk[5]) * wS[z + d * Np + c], u[q + d], acc);
+                acc = fmaf((d == 1 ? mk[7] : mk[6]) * wS[z + (3 + d) * Np + c], uo[q + d], acc);
+              }
+            }
+            a[q] -= acc;
           }
         }
       }
@@ -563,7 +635,7 @@ template <int L>
 size_t stepper_lds_bytes_L(const DevTables&) {
   constexpr int Np = Geo<L>::Np;
   constexpr size_t b16 = ((size_t(kNSlRow + kNSlCol) * Np * 2) + 15) & ~size_t(15);
-  constexpr size_t tb = (b16 + size_t(kNSlRow + kNSlCol) * Np * 4 + 15) & ~size_t(15);
+  constexpr size_t tb = (b16 + size_t(kNSlRow + kNSlCol + 3 * kNWin) * Np * 4 + 15) & ~size_t(15);
   return tb + kWaves * sizeof(WaveLds<L>);
 }
 
