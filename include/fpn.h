@@ -147,6 +147,38 @@ fpn_status fpn_stationary(fpn_ctx ctx, const fpn_batch* batch, int64_t n, const 
 fpn_status fpn_timing_enable(fpn_ctx ctx, int enable);
 fpn_status fpn_timing_read(fpn_ctx ctx, double* ms_out, int64_t* launches_out);
 
+/* ---- surrogate network ----
+ * A multilayer perceptron (not part of the paper) that maps instance features to signal
+ * harmonics: affine layers z_l = W_l a_{l-1} + b_l with a_l = gelu(z_l) (exact erf form) on every
+ * layer but the last.  Products run on BF16 matrix cores with FP32 accumulation; the master
+ * parameters, gradients and Adam moments are FP32.  Inputs are standardised inside the network:
+ * x' = (x - mean) / std (fpn_mlp_set_input_norm; default mean 0, std 1).
+ * Parameter layout (flat FP32): for each layer l, W_l [out][in] row-major, then b_l [out].
+ * A model belongs to the device of the context it was created with; calls on one model must not
+ * overlap (they share its workspace). */
+typedef struct fpn_mlp_s* fpn_mlp;
+
+/* widths[0..n_layers]: input width, hidden widths (multiples of 32), output width (multiple of 32).
+ * Weights and biases start U(-1/sqrt(in), 1/sqrt(in)) from `seed`.  Errors: FPN_E_ARG, FPN_E_NOMEM. */
+fpn_status fpn_mlp_create(fpn_ctx ctx, int32_t n_layers, const int32_t* widths, uint64_t seed, fpn_mlp* out);
+fpn_status fpn_mlp_destroy(fpn_mlp m);
+/* number of FP32 parameters (-1 for NULL) */
+int64_t fpn_mlp_num_params(fpn_mlp m);
+/* Copy the parameters out to `dst` and/or in from `src` (DEVICE, flat layout above; either may
+ * be NULL).  Asynchronous on `stream`. */
+fpn_status fpn_mlp_params(fpn_mlp m, float* dst, const float* src, void* stream);
+/* Input standardisation, HOST arrays [input width]; std > 0.  Synchronous. */
+fpn_status fpn_mlp_set_input_norm(fpn_mlp m, const float* mean, const float* stdev);
+/* y [n][out] = network(x [n][in]) (DEVICE FP32).  n <= 2^30, processed in chunks of 2^17 rows. */
+fpn_status fpn_mlp_forward(fpn_mlp m, const float* x, int64_t n, float* y, void* stream);
+/* Gradient of loss = mean over n x out elements of (y - t)^2 (t DEVICE [n][out]).
+ * grad (DEVICE, flat layout, may be NULL) and loss (DEVICE, one double, may be NULL).  n <= 2^22. */
+fpn_status fpn_mlp_gradient(fpn_mlp m, const float* x, const float* t, int64_t n, float* grad, double* loss,
+                            void* stream);
+/* One Adam step (b1 = 0.9, b2 = 0.999, eps = 1e-8, learning rate lr) on that gradient. */
+fpn_status fpn_mlp_train_step(fpn_mlp m, const float* x, const float* t, int64_t n, float lr, double* loss,
+                              void* stream);
+
 /* ---- host-only helpers (no device needed; used to check the operator build) ---- */
 
 /* Dense Galerkin operator A (1/s) of one particle in its easy-axis frame, built

@@ -33,7 +33,8 @@ FPN_MAX_L = 16
 
 EXPORTED = ["fpn_status_string", "fpn_last_error", "fpn_create", "fpn_destroy", "fpn_solve",
             "fpn_stationary", "fpn_last_steps", "fpn_timing_enable", "fpn_timing_read", "fpn_host_operator", "fpn_host_frame",
-            "fpn_host_table_nnz"]
+            "fpn_host_table_nnz", "fpn_mlp_create", "fpn_mlp_destroy", "fpn_mlp_num_params", "fpn_mlp_params",
+            "fpn_mlp_set_input_norm", "fpn_mlp_forward", "fpn_mlp_gradient", "fpn_mlp_train_step"]
 
 
 class fpn_drive(ctypes.Structure):
@@ -81,6 +82,23 @@ _lib.fpn_host_frame.restype = ctypes.c_int32
 _lib.fpn_host_frame.argtypes = [ctypes.POINTER(ctypes.c_double), ctypes.POINTER(ctypes.c_double)]
 _lib.fpn_host_table_nnz.restype = ctypes.c_int64
 _lib.fpn_host_table_nnz.argtypes = [ctypes.c_int32]
+_lib.fpn_mlp_create.restype = ctypes.c_int32
+_lib.fpn_mlp_create.argtypes = [_vp, ctypes.c_int32, ctypes.POINTER(ctypes.c_int32), ctypes.c_uint64,
+                                ctypes.POINTER(_vp)]
+_lib.fpn_mlp_destroy.restype = ctypes.c_int32
+_lib.fpn_mlp_destroy.argtypes = [_vp]
+_lib.fpn_mlp_num_params.restype = ctypes.c_int64
+_lib.fpn_mlp_num_params.argtypes = [_vp]
+_lib.fpn_mlp_params.restype = ctypes.c_int32
+_lib.fpn_mlp_params.argtypes = [_vp, _vp, _vp, _vp]
+_lib.fpn_mlp_set_input_norm.restype = ctypes.c_int32
+_lib.fpn_mlp_set_input_norm.argtypes = [_vp, ctypes.POINTER(ctypes.c_float), ctypes.POINTER(ctypes.c_float)]
+_lib.fpn_mlp_forward.restype = ctypes.c_int32
+_lib.fpn_mlp_forward.argtypes = [_vp, _vp, ctypes.c_int64, _vp, _vp]
+_lib.fpn_mlp_gradient.restype = ctypes.c_int32
+_lib.fpn_mlp_gradient.argtypes = [_vp, _vp, _vp, ctypes.c_int64, _vp, _vp, _vp]
+_lib.fpn_mlp_train_step.restype = ctypes.c_int32
+_lib.fpn_mlp_train_step.argtypes = [_vp, _vp, _vp, ctypes.c_int64, ctypes.c_float, _vp, _vp]
 
 
 class FpnError(RuntimeError):
@@ -247,3 +265,93 @@ class Context:
                                    s.cuda_stream), "fpn_stationary")
         torch.cuda.synchronize(self.device)
         return m, st
+
+
+def _f32(x, device):
+    torch = _torch()
+    return torch.as_tensor(x, dtype=torch.float32, device=device).contiguous()
+
+
+class MLP:
+    """A surrogate network owned by the library (fpn_mlp_*): FP32 master parameters, BF16 matrix-core
+    products.  Parameters are exchanged as one flat FP32 tensor (per layer W [out, in], then b [out])."""
+
+    def __init__(self, ctx, widths, seed=0):
+        self.ctx = ctx
+        self.widths = [int(w) for w in widths]
+        self._h = _vp()
+        w = (ctypes.c_int32 * len(self.widths))(*self.widths)
+        _check(_lib.fpn_mlp_create(ctx._h, len(self.widths) - 1, w, int(seed), ctypes.byref(self._h)),
+               "fpn_mlp_create")
+        self.n_params = int(_lib.fpn_mlp_num_params(self._h))
+
+    def close(self):
+        if self._h:
+            _lib.fpn_mlp_destroy(self._h)
+            self._h = _vp()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    @property
+    def _dev(self):
+        return f"cuda:{self.ctx.device}"
+
+    def _stream(self):
+        return _torch().cuda.current_stream(self.ctx.device).cuda_stream
+
+    def get_params(self):
+        p = _torch().empty(self.n_params, dtype=_torch().float32, device=self._dev)
+        _check(_lib.fpn_mlp_params(self._h, p.data_ptr(), None, self._stream()), "fpn_mlp_params")
+        return p
+
+    def set_params(self, flat):
+        t = _f32(flat, self._dev)
+        assert t.numel() == self.n_params
+        _check(_lib.fpn_mlp_params(self._h, None, t.data_ptr(), self._stream()), "fpn_mlp_params")
+        _torch().cuda.synchronize(self.ctx.device)
+
+    def unflatten(self, flat):
+        """Split a flat parameter vector (numpy) into lists of W [out, in] and b [out]."""
+        flat = np.asarray(flat)
+        Ws, bs, o = [], [], 0
+        for i, j in zip(self.widths[:-1], self.widths[1:]):
+            Ws.append(flat[o:o + i * j].reshape(j, i))
+            o += i * j
+            bs.append(flat[o:o + j])
+            o += j
+        return Ws, bs
+
+    def set_input_norm(self, mean, std):
+        m = np.ascontiguousarray(mean, dtype=np.float32)
+        s = np.ascontiguousarray(std, dtype=np.float32)
+        _check(_lib.fpn_mlp_set_input_norm(self._h, m.ctypes.data_as(ctypes.POINTER(ctypes.c_float)),
+                                           s.ctypes.data_as(ctypes.POINTER(ctypes.c_float))), "fpn_mlp_set_input_norm")
+
+    def forward(self, x, out=None):
+        torch = _torch()
+        x = _f32(x, self._dev)
+        n = x.shape[0]
+        y = out if out is not None else torch.empty((n, self.widths[-1]), dtype=torch.float32, device=self._dev)
+        _check(_lib.fpn_mlp_forward(self._h, x.data_ptr(), n, y.data_ptr(), self._stream()), "fpn_mlp_forward")
+        return y
+
+    def gradient(self, x, t):
+        torch = _torch()
+        x, t = _f32(x, self._dev), _f32(t, self._dev)
+        g = torch.empty(self.n_params, dtype=torch.float32, device=self._dev)
+        loss = torch.empty(1, dtype=torch.float64, device=self._dev)
+        _check(_lib.fpn_mlp_gradient(self._h, x.data_ptr(), t.data_ptr(), x.shape[0], g.data_ptr(), loss.data_ptr(),
+                                     self._stream()), "fpn_mlp_gradient")
+        return g, loss / (x.shape[0] * self.widths[-1])
+
+    def train_step(self, x, t, lr, loss_out=None):
+        """One Adam step; returns the device tensor holding the loss sum (before the update)."""
+        torch = _torch()
+        loss = loss_out if loss_out is not None else torch.empty(1, dtype=torch.float64, device=self._dev)
+        _check(_lib.fpn_mlp_train_step(self._h, x.data_ptr(), t.data_ptr(), x.shape[0], float(lr), loss.data_ptr(),
+                                       self._stream()), "fpn_mlp_train_step")
+        return loss

@@ -12,74 +12,21 @@
 #include <vector>
 
 #include "../../include/fpn.h"
+#include "capi_internal.hpp"
 #include "device_common.hpp"
 #include "kernels.hpp"
 #include "physics.hpp"
 #include "structure.hpp"
 
-namespace {
+using namespace fpn_internal;
 
+namespace fpn_internal {
 thread_local std::string g_last_error;
-
 fpn_status fail(fpn_status s, const std::string& msg) {
   g_last_error = msg;
   return s;
 }
-
-#define FPN_HIP(call)                                                                      \
-  do {                                                                                     \
-    hipError_t e_ = (call);                                                                \
-    if (e_ != hipSuccess)                                                                  \
-      return fail(e_ == hipErrorOutOfMemory ? FPN_E_NOMEM : FPN_E_DEVICE,                  \
-                  std::string(#call) + ": " + hipGetErrorString(e_));                      \
-  } while (0)
-
-template <typename T>
-struct DevBuf {
-  T* p = nullptr;
-  size_t cap = 0;
-  hipError_t ensure(size_t n) {
-    if (n <= cap) return hipSuccess;
-    if (p) (void)hipFree(p);
-    p = nullptr;
-    cap = 0;
-    hipError_t e = hipMalloc(&p, std::max<size_t>(n, 1) * sizeof(T));
-    if (e == hipSuccess) cap = n;
-    return e;
-  }
-  void release() {
-    if (p) (void)hipFree(p);
-    p = nullptr;
-    cap = 0;
-  }
-};
-
-struct TableSet {
-  fpn::DevTables t{};
-  std::vector<void*> allocs;
-};
-
-}  // namespace
-
-struct fpn_ctx_s {
-  int device = 0;
-  std::mutex mu;
-  std::map<int, TableSet> tables;
-  DevBuf<double2> twiddle;
-  int tw_N = 0;
-  DevBuf<fpn::InstParams> ip;
-  DevBuf<double> c0;
-  DevBuf<double> wsinv;
-  DevBuf<float> msamp;
-  DevBuf<int32_t> idx;
-  DevBuf<int32_t> steps;
-  int64_t steps_n = 0;
-  // kernel timing
-  bool timing = false;
-  std::vector<std::pair<int, std::pair<hipEvent_t, hipEvent_t>>> events;
-  double ms[4] = {0, 0, 0, 0};
-  int64_t launches[4] = {0, 0, 0, 0};
-};
+}  // namespace fpn_internal
 
 namespace {
 
