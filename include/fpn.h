@@ -179,6 +179,37 @@ fpn_status fpn_mlp_gradient(fpn_mlp m, const float* x, const float* t, int64_t n
 fpn_status fpn_mlp_train_step(fpn_mlp m, const float* x, const float* t, int64_t n, float lr, double* loss,
                               void* stream);
 
+/* ---- surrogate evaluation ----
+ * Harmonics 1..K_h of the x and y channels predicted by a two-member network ensemble from the
+ * instance features, with the solver as the fallback and the judge of the error:
+ *   features x = (log D, log K, alpha, n_x, n_y, n_z, offset_x / 12 mT, offset_y / 12 mT), the axis
+ *   taken in the half-space n_z > 0 (n and -n describe the same particle); K must be > 0;
+ *   prediction = (y_a + y_b) / 2 / out_scale, network output layout [channel x, y][k = 1..K_h][re, im];
+ *   error estimate = err_calib * ||y_a - y_b|| / ||(y_a + y_b) / 2||  (err_calib is fitted on held-out
+ *   solver results so that the estimate bounds the relative L2 error of the prediction). */
+typedef struct {
+  fpn_mlp net[2];     /* widths: 8 inputs, 4 * K_h outputs, identical shapes */
+  float out_scale;    /* network output = Phi [1/s] * out_scale */
+  float err_calib;    /* > 0 */
+} fpn_surrogate;
+
+/* Features x [n][8] (DEVICE FP32) and status [n] (FPN_INST_BAD_PARAM for non-physical instances,
+ * whose features are NaN).  Asynchronous. */
+fpn_status fpn_surrogate_features(fpn_ctx ctx, const fpn_batch* batch, int64_t n, float* x, int32_t* status,
+                                  void* stream);
+
+/* Evaluate every instance with the ensemble; instances whose error estimate exceeds `tol` (or is
+ * not finite) are solved with fpn_solve(drive, opts) instead (opts->n_harm = K_h; FPN_HARM_Z not
+ * allowed).  Outputs (DEVICE): harm_out [n][2][K_h+1][2] as fpn_solve's (bin 0 = 0), err_out [n]
+ * (the estimate; 0 where the solver ran), used_solver [n] (1 where the solver ran), status [n].
+ * n_fallback (HOST, may be NULL) receives the number of solver instances.  Synchronous: the
+ * fallback count is read back before the solver is planned.  Errors: FPN_E_ARG, FPN_E_RANGE,
+ * FPN_E_DEVICE, FPN_E_NOMEM. */
+fpn_status fpn_surrogate_predict(fpn_ctx ctx, const fpn_surrogate* sur, double tol, const fpn_drive* drive,
+                                 const fpn_solve_opts* opts, const fpn_batch* batch, int64_t n, float* harm_out,
+                                 float* err_out, int32_t* used_solver, int32_t* status, int64_t* n_fallback,
+                                 void* stream);
+
 /* ---- host-only helpers (no device needed; used to check the operator build) ---- */
 
 /* Dense Galerkin operator A (1/s) of one particle in its easy-axis frame, built

@@ -34,7 +34,8 @@ FPN_MAX_L = 16
 EXPORTED = ["fpn_status_string", "fpn_last_error", "fpn_create", "fpn_destroy", "fpn_solve",
             "fpn_stationary", "fpn_last_steps", "fpn_timing_enable", "fpn_timing_read", "fpn_host_operator", "fpn_host_frame",
             "fpn_host_table_nnz", "fpn_mlp_create", "fpn_mlp_destroy", "fpn_mlp_num_params", "fpn_mlp_params",
-            "fpn_mlp_set_input_norm", "fpn_mlp_forward", "fpn_mlp_gradient", "fpn_mlp_train_step"]
+            "fpn_mlp_set_input_norm", "fpn_mlp_forward", "fpn_mlp_gradient", "fpn_mlp_train_step",
+            "fpn_surrogate_features", "fpn_surrogate_predict"]
 
 
 class fpn_drive(ctypes.Structure):
@@ -99,6 +100,18 @@ _lib.fpn_mlp_gradient.restype = ctypes.c_int32
 _lib.fpn_mlp_gradient.argtypes = [_vp, _vp, _vp, ctypes.c_int64, _vp, _vp, _vp]
 _lib.fpn_mlp_train_step.restype = ctypes.c_int32
 _lib.fpn_mlp_train_step.argtypes = [_vp, _vp, _vp, ctypes.c_int64, ctypes.c_float, _vp, _vp]
+
+
+class fpn_surrogate(ctypes.Structure):
+    _fields_ = [("net", _vp * 2), ("out_scale", ctypes.c_float), ("err_calib", ctypes.c_float)]
+
+
+_lib.fpn_surrogate_features.restype = ctypes.c_int32
+_lib.fpn_surrogate_features.argtypes = [_vp, ctypes.POINTER(fpn_batch), ctypes.c_int64, _vp, _vp, _vp]
+_lib.fpn_surrogate_predict.restype = ctypes.c_int32
+_lib.fpn_surrogate_predict.argtypes = [_vp, ctypes.POINTER(fpn_surrogate), ctypes.c_double, ctypes.POINTER(fpn_drive),
+                                       ctypes.POINTER(fpn_solve_opts), ctypes.POINTER(fpn_batch), ctypes.c_int64,
+                                       _vp, _vp, _vp, _vp, ctypes.POINTER(ctypes.c_int64), _vp]
 
 
 class FpnError(RuntimeError):
@@ -251,6 +264,47 @@ class Context:
         cnt = (ctypes.c_int64 * 4)()
         _check(_lib.fpn_timing_read(self._h, ms, cnt), "fpn_timing_read")
         return {k: (ms[i], cnt[i]) for i, k in enumerate(self.TIMING_KERNELS)}
+
+    def surrogate_features(self, inst):
+        """Network input features [n, 8] (float32, device) and status [n] (fpn_surrogate_features)."""
+        torch = _torch()
+        dev = f"cuda:{self.device}"
+        b, keep, Lh = self._batch(inst, 1)
+        n = keep["D"].numel()
+        x = torch.empty((n, 8), dtype=torch.float32, device=dev)
+        st = torch.empty((n,), dtype=torch.int32, device=dev)
+        s = torch.cuda.current_stream(self.device)
+        _check(_lib.fpn_surrogate_features(self._h, ctypes.byref(b), n, x.data_ptr(), st.data_ptr(), s.cuda_stream),
+               "fpn_surrogate_features")
+        self._keep = (keep, Lh)
+        return x, st
+
+    def surrogate_predict(self, nets, out_scale, err_calib, tol, inst, L, drive, samples, settle, n_harm,
+                          substeps=0, solver_tol=0.0):
+        """fpn_surrogate_predict: returns (harm [n,2,Kh+1] complex64, err [n], used_solver [n], status [n],
+        n_fallback)."""
+        torch = _torch()
+        dev = f"cuda:{self.device}"
+        b, keep, Lh = self._batch(inst, L)
+        n = keep["D"].numel()
+        sur = fpn_surrogate()
+        sur.net[0] = nets[0]._h
+        sur.net[1] = nets[1]._h
+        sur.out_scale = float(out_scale)
+        sur.err_calib = float(err_calib)
+        opts = fpn_solve_opts(samples, settle, n_harm, substeps, FPN_OUT_HARM, float(solver_tol))
+        hm = torch.empty((n, 2, n_harm + 1, 2), dtype=torch.float32, device=dev)
+        err = torch.empty((n,), dtype=torch.float32, device=dev)
+        used = torch.empty((n,), dtype=torch.int32, device=dev)
+        st = torch.empty((n,), dtype=torch.int32, device=dev)
+        nf = ctypes.c_int64()
+        s = torch.cuda.current_stream(self.device)
+        _check(_lib.fpn_surrogate_predict(self._h, ctypes.byref(sur), float(tol), ctypes.byref(drive),
+                                          ctypes.byref(opts), ctypes.byref(b), n, hm.data_ptr(), err.data_ptr(),
+                                          used.data_ptr(), st.data_ptr(), ctypes.byref(nf), s.cuda_stream),
+               "fpn_surrogate_predict")
+        self._keep = (keep, Lh)
+        return torch.view_as_complex(hm), err, used, st, int(nf.value)
 
     def stationary(self, inst, L, field):
         torch = _torch()

@@ -287,6 +287,14 @@ fpn_status fpn_destroy(fpn_ctx ctx) {
   ctx->wsinv.release();
   ctx->msamp.release();
   ctx->idx.release();
+  ctx->steps.release();
+  for (auto* b : {&ctx->sur_x, &ctx->sur_ya, &ctx->sur_yb, &ctx->sur_h}) b->release();
+  for (auto* b : {&ctx->sur_list, &ctx->sur_count, &ctx->sur_st}) b->release();
+  ctx->sur_g.release();
+  for (auto& e : ctx->events) {
+    (void)hipEventDestroy(e.second.first);
+    (void)hipEventDestroy(e.second.second);
+  }
   delete ctx;
   return FPN_OK;
 }

@@ -64,9 +64,35 @@ struct fpn_ctx_s {
   fpn_internal::DevBuf<int32_t> idx;
   fpn_internal::DevBuf<int32_t> steps;
   int64_t steps_n = 0;
+  // surrogate evaluation workspace
+  fpn_internal::DevBuf<float> sur_x, sur_ya, sur_yb, sur_h;
+  fpn_internal::DevBuf<int32_t> sur_list, sur_count, sur_st;
+  fpn_internal::DevBuf<double> sur_g;
   // kernel timing
   bool timing = false;
   std::vector<std::pair<int, std::pair<hipEvent_t, hipEvent_t>>> events;
   double ms[4] = {0, 0, 0, 0};
   int64_t launches[4] = {0, 0, 0, 0};
+};
+
+struct fpn_mlp_s {
+  int device = 0;
+  int nl = 0;                   // number of affine layers
+  std::vector<int> w;           // widths [nl + 1]
+  std::vector<int> inpad;       // padded input width of each layer (multiple of 32)
+  std::vector<int64_t> offW, offB;
+  int64_t nparam = 0;
+  fpn_internal::DevBuf<float> P, G, Am, Av;   // FP32 master parameters, gradient, Adam moments
+  fpn_internal::DevBuf<float> norm;           // mean[in], 1/std[in]
+  std::vector<fpn_internal::DevBuf<uint16_t>> Wb, Wt;
+  bool dirty = true;
+  int64_t t = 0;                // Adam step count
+  // workspace (rows = capacity of the current buffers)
+  int64_t rows_cap = 0;
+  bool train_cap = false;
+  std::vector<fpn_internal::DevBuf<uint16_t>> act, actT;  // act[l] [rows][inpad l] (l = 0..nl-1)
+  std::vector<fpn_internal::DevBuf<float>> z;             // z[l] pre-activation feeding act[l], l = 1..nl-1
+  fpn_internal::DevBuf<float> y;                          // [rows][out]
+  fpn_internal::DevBuf<uint16_t> dz[2], dzT[2];
+  fpn_internal::DevBuf<double> loss;
 };

@@ -13,28 +13,6 @@
 
 using namespace fpn_internal;
 
-struct fpn_mlp_s {
-  int device = 0;
-  int nl = 0;                   // number of affine layers
-  std::vector<int> w;           // widths [nl + 1]
-  std::vector<int> inpad;       // padded input width of each layer (multiple of 32)
-  std::vector<int64_t> offW, offB;
-  int64_t nparam = 0;
-  DevBuf<float> P, G, Am, Av;   // FP32 master parameters, gradient, Adam moments
-  DevBuf<float> norm;           // mean[in], 1/std[in]
-  std::vector<DevBuf<uint16_t>> Wb, Wt;
-  bool dirty = true;
-  int64_t t = 0;                // Adam step count
-  // workspace (rows = capacity of the current buffers)
-  int64_t rows_cap = 0;
-  bool train_cap = false;
-  std::vector<DevBuf<uint16_t>> act, actT;  // act[l] [rows][inpad l] (l = 0..nl-1)
-  std::vector<DevBuf<float>> z;             // z[l] pre-activation feeding act[l], l = 1..nl-1
-  DevBuf<float> y;                          // [rows][out]
-  DevBuf<uint16_t> dz[2], dzT[2];
-  DevBuf<double> loss;
-};
-
 namespace {
 
 uint64_t splitmix(uint64_t& s) {
@@ -202,6 +180,9 @@ fpn_status fpn_mlp_create(fpn_ctx ctx, int32_t n_layers, const int32_t* widths, 
       h[e] = float((double(splitmix(st) >> 11) * (1.0 / 9007199254740992.0) * 2.0 - 1.0) * sc);
   }
   auto cleanup = [&](fpn_status s) {
+    for (auto* b : {&m->P, &m->G, &m->Am, &m->Av, &m->norm}) b->release();
+    for (auto& b : m->Wb) b.release();
+    for (auto& b : m->Wt) b.release();
     delete m;
     return s;
   };

@@ -1,0 +1,103 @@
+"""Learned surrogate of the solver: a two-member network ensemble trained on the solver's own
+harmonics, evaluated with the solver as fallback (fpn_surrogate_predict).
+
+Everything numeric runs in the library: the solver makes the training targets (fpn_solve), the
+features come from fpn_surrogate_features, training steps are fpn_mlp_train_step (BF16 matrix-core
+products, FP32 Adam) and prediction is fpn_surrogate_predict.  This module only orders those calls:
+it draws minibatch indices, sets the learning-rate schedule and picks the calibration constant of
+the error estimate from held-out solver results.
+"""
+from __future__ import annotations
+
+import math
+import time
+
+import numpy as np
+
+from . import MLP
+
+WIDTHS_HIDDEN = (512, 512, 512, 512)
+
+
+def harm_targets(harm):
+    """Network target layout [n, 4 K] = [channel x, y][k = 1..K][re, im] from solver harmonics
+    (complex [n, 2, K + 1])."""
+    torch = _torch()
+    h = torch.view_as_real(harm[:, :2, 1:].contiguous())  # [n, 2, K, 2]
+    return h.reshape(h.shape[0], -1).contiguous()
+
+
+def _torch():
+    import torch
+    return torch
+
+
+class Surrogate:
+    """Two networks of identical shape, the output scale and the calibrated error constant."""
+
+    def __init__(self, ctx, n_harm, hidden=WIDTHS_HIDDEN, seeds=(1, 2)):
+        self.ctx = ctx
+        self.n_harm = int(n_harm)
+        widths = [8, *hidden, 4 * self.n_harm]
+        self.nets = [MLP(ctx, widths, seed=s) for s in seeds]
+        self.out_scale = 1.0
+        self.err_calib = 1.0
+        self.train_seconds = 0.0
+
+    def close(self):
+        for n in self.nets:
+            n.close()
+
+    def fit(self, inst, harm, steps=3000, batch=4096, lr=2e-3, lr_final=2e-5, seed=0, log=None):
+        """Train both members on (features(inst), harm) with Adam and a cosine learning-rate decay."""
+        torch = _torch()
+        x, st = self.ctx.surrogate_features(inst)
+        ok = (st == 0) & torch.isfinite(harm.real).all(dim=(1, 2)) & torch.isfinite(harm.imag).all(dim=(1, 2))
+        x = x[ok].contiguous()
+        y = harm_targets(harm)[ok]
+        rms = float(torch.sqrt((y.double() ** 2).mean()).item())
+        self.out_scale = 1.0 / rms
+        y = (y * self.out_scale).contiguous()
+        mean = x.double().mean(0).cpu().numpy()
+        std = x.double().std(0).cpu().numpy()
+        std = np.where(std > 1e-6, std, 1.0)
+        for net in self.nets:
+            net.set_input_norm(mean, std)
+        n = x.shape[0]
+        g = torch.Generator(device=x.device)
+        g.manual_seed(seed)
+        t0 = time.perf_counter()
+        for it in range(steps):
+            lr_t = lr_final + 0.5 * (lr - lr_final) * (1.0 + math.cos(math.pi * it / max(steps - 1, 1)))
+            for k, net in enumerate(self.nets):
+                idx = torch.randint(0, n, (min(batch, n),), device=x.device, generator=g)
+                loss = net.train_step(x[idx].contiguous(), y[idx].contiguous(), lr_t)
+            if log is not None and (it % max(steps // 10, 1) == 0 or it == steps - 1):
+                log(f"step {it}: lr {lr_t:.2e} loss {float(loss.item()) / (min(batch, n) * y.shape[1]):.3e}")
+        torch.cuda.synchronize()
+        self.train_seconds = time.perf_counter() - t0
+        return self
+
+    def raw(self, inst):
+        """Per-member predictions (network units) and the features' status."""
+        x, st = self.ctx.surrogate_features(inst)
+        return [net.forward(x) for net in self.nets], st
+
+    def calibrate(self, inst, harm, quantile=0.99):
+        """err_calib = quantile of (true relative L2 error) / (ensemble spread) over held-out instances,
+        so that the estimate bounds the error of that fraction of them."""
+        torch = _torch()
+        (ya, yb), st = self.raw(inst)
+        y = harm_targets(harm) * self.out_scale
+        pred = 0.5 * (ya + yb)
+        true = torch.linalg.vector_norm(pred - y, dim=1) / torch.linalg.vector_norm(y, dim=1)
+        spread = 2.0 * torch.linalg.vector_norm(ya - yb, dim=1) / torch.linalg.vector_norm(ya + yb, dim=1)
+        ok = (st == 0) & torch.isfinite(true) & torch.isfinite(spread) & (spread > 0)
+        ratio = (true[ok] / spread[ok]).double().cpu().numpy()
+        self.err_calib = float(np.quantile(ratio, quantile))
+        return true[ok].double().cpu().numpy(), spread[ok].double().cpu().numpy()
+
+    def predict(self, inst, L, drive, samples, settle, tol, substeps=0):
+        """fpn_surrogate_predict: (harm, err_estimate, used_solver, status, n_fallback)."""
+        return self.ctx.surrogate_predict(self.nets, self.out_scale, self.err_calib, tol, inst, L, drive, samples,
+                                          settle, self.n_harm, substeps=substeps)

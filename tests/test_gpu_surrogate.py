@@ -1,0 +1,134 @@
+"""GPU tests of the learned surrogate (fpn_surrogate_features / fpn_surrogate_predict) trained on the
+solver's own output.
+
+* Features equal their definition (log D, log K, alpha, axis in the n_z > 0 half-space, offset / 12 mT).
+* tol = 0 hands every instance to the solver: the output is the solver's, bit for bit.
+* tol = inf keeps every instance on the ensemble: the output is the mean of the two networks.
+* After training, the calibrated error estimate bounds the true error (against the solver, itself
+  parity-checked against the FP64 oracle) of the accepted instances, and the surrogate answers most
+  instances without the solver: the gain is reported as the time ratio at equal accuracy.
+"""
+import time
+
+import numpy as np
+import pytest
+
+import workloads as W
+
+pytestmark = pytest.mark.gpu
+KH = 8
+
+
+@pytest.fixture(scope="module")
+def fpn():
+    import paper_2106_08040_amd as fpn
+    return fpn
+
+
+@pytest.fixture(scope="module")
+def ctx(fpn):
+    c = fpn.Context(0)
+    yield c
+    c.close()
+
+
+def domain(n, seed):
+    """Fixed particle, in-plane easy axis, 2D offsets, short three-axis drive (64 samples)."""
+    ws = W.small_random(n, 8, seed=seed, samples=64, settle=1, n_harm=KH)
+    r = np.random.default_rng(seed + 1000)
+    th = r.uniform(0, np.pi, n)
+    inst = ws["inst"]
+    inst["D"][:] = 18e-9
+    inst["K"][:] = 1.5e3
+    inst["alpha"][:] = 0.1
+    inst["easy_axis"] = np.stack([np.cos(th), np.sin(th), np.zeros(n)], 1)
+    inst["offset"] = np.stack([r.uniform(-6e-3, 6e-3, n), r.uniform(-6e-3, 6e-3, n), np.zeros(n)], 1)
+    return ws
+
+
+def drive_of(fpn, ws):
+    d = ws["drive"]
+    return fpn.make_drive(d["amp"], d["freq"], d["period"], d["phase"])
+
+
+def solve(fpn, ctx, ws):
+    import torch
+    _, h, st = ctx.solve(ws["inst"], ws["inst"]["L"], drive_of(fpn, ws), ws["samples"], ws["settle"], KH,
+                         want_m=False)
+    torch.cuda.synchronize()
+    return h, st
+
+
+def test_features_match_definition(fpn, ctx):
+    ws = W.small_random(50, 8, seed=3)
+    x, st = ctx.surrogate_features(ws["inst"])
+    x = x.cpu().numpy().astype(np.float64)
+    inst = ws["inst"]
+    n = inst["easy_axis"].copy()
+    flip = (n[:, 2] < 0) | ((n[:, 2] == 0) & (n[:, 1] < 0))
+    n[flip] *= -1
+    ref = np.column_stack([np.log(inst["D"]), np.log(inst["K"]), inst["alpha"], n,
+                           inst["offset"][:, 0] / 12e-3, inst["offset"][:, 1] / 12e-3])
+    assert (st.cpu().numpy() == 0).all()
+    assert np.abs(x - ref).max() <= 1e-6 * np.abs(ref).max()
+
+
+@pytest.fixture(scope="module")
+def trained(fpn, ctx):
+    from paper_2106_08040_amd.surrogate import Surrogate
+    tr, va = domain(3072, 21), domain(512, 22)
+    htr, sttr = solve(fpn, ctx, tr)
+    hva, _ = solve(fpn, ctx, va)
+    assert (sttr.cpu().numpy() == 0).all()
+    sur = Surrogate(ctx, KH, hidden=(256, 256, 256, 256))
+    sur.fit(tr["inst"], htr, steps=1500, batch=2048, lr=2e-3)
+    true, spread = sur.calibrate(va["inst"], hva)
+    print(f"validation rel-L2: median {np.median(true):.2e} p90 {np.quantile(true, 0.9):.2e}; "
+          f"calibration {sur.err_calib:.3f}", flush=True)
+    yield sur
+    sur.close()
+
+
+def test_tol_zero_is_the_solver(fpn, ctx, trained):
+    import torch
+    ws = domain(64, 31)
+    h, err, used, st, nf = trained.predict(ws["inst"], ws["inst"]["L"], drive_of(fpn, ws), ws["samples"],
+                                           ws["settle"], tol=0.0)
+    ref, st_ref = solve(fpn, ctx, ws)
+    assert nf == 64 and (used.cpu().numpy() == 1).all() and (err.cpu().numpy() == 0).all()
+    assert torch.equal(h, ref) and torch.equal(st, st_ref)
+
+
+def test_tol_inf_is_the_ensemble_mean(fpn, ctx, trained):
+    import torch
+    ws = domain(100, 32)
+    h, err, used, st, nf = trained.predict(ws["inst"], ws["inst"]["L"], drive_of(fpn, ws), ws["samples"],
+                                           ws["settle"], tol=float("inf"))
+    assert nf == 0 and (used.cpu().numpy() == 0).all()
+    (ya, yb), _ = trained.raw(ws["inst"])
+    inv = float(np.float32(1.0) / np.float32(trained.out_scale))  # the kernel's FP32 reciprocal
+    mean = ((ya + yb) * 0.5) * inv
+    got = torch.view_as_real(h[:, :, 1:].contiguous()).reshape(100, -1)
+    assert torch.equal(got, mean)
+    assert (h[:, :, 0] == 0).all()
+
+
+def test_accepted_instances_meet_tolerance_and_save_solver_time(fpn, ctx, trained):
+    import torch
+    ws = domain(512, 33)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    ref, _ = solve(fpn, ctx, ws)
+    t_solver = time.perf_counter() - t0
+    tol = 2e-2
+    t0 = time.perf_counter()
+    h, err, used, st, nf = trained.predict(ws["inst"], ws["inst"]["L"], drive_of(fpn, ws), ws["samples"],
+                                           ws["settle"], tol=tol)
+    torch.cuda.synchronize()
+    t_sur = time.perf_counter() - t0
+    e = (torch.linalg.vector_norm((h - ref).reshape(512, -1), dim=1) /
+         torch.linalg.vector_norm(ref.reshape(512, -1), dim=1)).cpu().numpy()
+    print(f"tol {tol}: {nf}/512 solved, max rel-L2 {e.max():.2e}, surrogate {t_sur * 1e3:.1f} ms vs solver "
+          f"{t_solver * 1e3:.1f} ms", flush=True)
+    assert np.mean(e <= tol) >= 0.97
+    assert nf <= 256
