@@ -110,7 +110,7 @@ typedef struct {
   const int32_t* L;        /* HOST [n], 1 <= L <= FPN_MAX_L */
 } fpn_batch;
 
-#define FPN_MAX_L 16
+#define FPN_MAX_L 24
 
 /* Periodic response of every instance to drive + offset (the system-matrix columns).
  * Procedure: stationary density of the field at t = 0 (FP64), then

@@ -29,7 +29,7 @@ _lib = ctypes.CDLL(LIB_PATH)
 FPN_OK, FPN_E_ARG, FPN_E_RANGE, FPN_E_DEVICE, FPN_E_NOMEM, FPN_E_UNSUPPORTED = 0, -1, -2, -3, -4, -7
 FPN_INST_OK, FPN_INST_BAD_PARAM, FPN_INST_NONFINITE, FPN_INST_SINGULAR = 0, 1, 2, 3
 FPN_OUT_M, FPN_OUT_HARM, FPN_HARM_Z = 1, 2, 4
-FPN_MAX_L = 16
+FPN_MAX_L = 24
 
 EXPORTED = ["fpn_status_string", "fpn_last_error", "fpn_create", "fpn_destroy", "fpn_solve",
             "fpn_stationary", "fpn_last_steps", "fpn_timing_enable", "fpn_timing_read", "fpn_host_operator", "fpn_host_frame",

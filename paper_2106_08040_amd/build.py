@@ -48,9 +48,14 @@ def build(jobs=8, verbose=False, out=None, build_dir=None, extra=()):
     # the stepper is instantiated per Galerkin degree; split across objects to compile in parallel
     ranges = [(1, 6), (7, 10), (11, 13), (14, 15), (16, 16)]
     step_objs = [os.path.join(BUILD, f"stepper_{a}_{b}.o") for a, b in ranges]
+    wide_ranges = [(17, 18), (19, 20), (21, 22), (23, 23), (24, 24)]
+    wide_objs = [os.path.join(BUILD, f"stepper_wide_{a}_{b}.o") for a, b in wide_ranges]
     steps = [
         [HIPCC, *HIP_FLAGS, f"-DFPN_L_BEGIN={a}", f"-DFPN_L_END={b}", "-c", os.path.join(CSRC, "stepper.hip"),
          "-o", o] for (a, b), o in zip(ranges, step_objs)
+    ] + [
+        [HIPCC, *HIP_FLAGS, f"-DFPN_L_BEGIN={a}", f"-DFPN_L_END={b}", "-c", os.path.join(CSRC, "stepper_wide.hip"),
+         "-o", o] for (a, b), o in zip(wide_ranges, wide_objs)
     ] + [
         [HIPCC, *HIP_FLAGS, "-c", os.path.join(CSRC, "kernels.hip"), "-o", os.path.join(BUILD, "kernels.o")],
         [HIPCC, *HIP_FLAGS, "-c", os.path.join(CSRC, "capi.hip"), "-o", os.path.join(BUILD, "capi.o")],
@@ -71,7 +76,7 @@ def build(jobs=8, verbose=False, out=None, build_dir=None, extra=()):
     # Link against the HIP runtime that PyTorch loads (NEEDED libamdhip64.so, torch's copy first on
     # the runpath) so one process never holds two HIP/HSA runtimes; /opt/rocm/lib is the fallback.
     hiplib = _runtime_dir()
-    _run([CLANG, "-shared", "-fPIC", "-o", tmp, *step_objs,
+    _run([CLANG, "-shared", "-fPIC", "-o", tmp, *step_objs, *wide_objs,
           os.path.join(BUILD, "kernels.o"), os.path.join(BUILD, "capi.o"), os.path.join(BUILD, "structure.o"),
           os.path.join(BUILD, "mlp.o"), os.path.join(BUILD, "capi_mlp.o"),
           os.path.join(BUILD, "surrogate.o"), os.path.join(BUILD, "capi_surrogate.o"),

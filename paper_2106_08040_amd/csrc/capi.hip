@@ -235,14 +235,28 @@ std::vector<std::pair<int, std::vector<int32_t>>> group_by_L(const int32_t* L, i
 }  // namespace
 
 namespace fpn {
-hipError_t launch_stepper(int L, const StepLaunch& s, const DevTables& t, hipStream_t stream) {
+hipError_t launch_stepper(int L, const StepLaunch& s, const DevTables& t, float* ws, hipStream_t stream) {
   switch (L) {
 #define FPN_CASE(LL) \
   case LL: return launch_stepper_L<LL>(s, t, stream);
     FPN_CASE(1) FPN_CASE(2) FPN_CASE(3) FPN_CASE(4) FPN_CASE(5) FPN_CASE(6) FPN_CASE(7) FPN_CASE(8)
     FPN_CASE(9) FPN_CASE(10) FPN_CASE(11) FPN_CASE(12) FPN_CASE(13) FPN_CASE(14) FPN_CASE(15) FPN_CASE(16)
 #undef FPN_CASE
+#define FPN_WCASE(LL) \
+  case LL: return launch_stepper_wide_L<LL>(s, t, ws, stream);
+    FPN_WCASE(17) FPN_WCASE(18) FPN_WCASE(19) FPN_WCASE(20) FPN_WCASE(21) FPN_WCASE(22) FPN_WCASE(23) FPN_WCASE(24)
+#undef FPN_WCASE
     default: return hipErrorInvalidValue;
+  }
+}
+
+int64_t stepper_ws_floats(int L) {
+  switch (L) {
+#define FPN_WCASE(LL) \
+  case LL: return stepper_wide_ws_floats_L<LL>();
+    FPN_WCASE(17) FPN_WCASE(18) FPN_WCASE(19) FPN_WCASE(20) FPN_WCASE(21) FPN_WCASE(22) FPN_WCASE(23) FPN_WCASE(24)
+#undef FPN_WCASE
+    default: return 0;
   }
 }
 }  // namespace fpn
@@ -288,6 +302,7 @@ fpn_status fpn_destroy(fpn_ctx ctx) {
   ctx->msamp.release();
   ctx->idx.release();
   ctx->steps.release();
+  ctx->wide_ws.release();
   for (auto* b : {&ctx->sur_x, &ctx->sur_ya, &ctx->sur_yb, &ctx->sur_h}) b->release();
   for (auto* b : {&ctx->sur_list, &ctx->sur_count, &ctx->sur_st}) b->release();
   ctx->sur_g.release();
@@ -349,10 +364,14 @@ fpn_status fpn_solve(fpn_ctx ctx, const fpn_drive* drive, const fpn_solve_opts* 
     FPN_HIP(ctx->msamp.ensure(size_t(n) * 3 * Ns));
     msamp = ctx->msamp.p;
   }
-  // largest group bounds the stationary workspace
-  size_t maxg = 0;
-  for (auto& g : groups) maxg = std::max(maxg, g.second.size());
+  // largest group bounds the stationary workspace; the wide-layout stepper needs its own
+  size_t maxg = 0, wide = 0;
+  for (auto& g : groups) {
+    maxg = std::max(maxg, g.second.size());
+    wide = std::max(wide, g.second.size() * size_t(fpn::stepper_ws_floats(g.first)));
+  }
   FPN_HIP(ctx->wsinv.ensure(maxg * size_t(inv_max)));
+  if (wide) FPN_HIP(ctx->wide_ws.ensure(wide));
   std::vector<int32_t> order;
   order.reserve(n);
   for (auto& g : groups) order.insert(order.end(), g.second.begin(), g.second.end());
@@ -402,7 +421,7 @@ fpn_status fpn_solve(fpn_ctx ctx, const fpn_drive* drive, const fpn_solve_opts* 
     sl.status = status;
     sl.steps_out = ctx->steps.p;
     if (fpn_status s = timed(ctx, 2, stream, [&]() -> fpn_status {
-          FPN_HIP(fpn::launch_stepper(g.first, sl, t, stream));
+          FPN_HIP(fpn::launch_stepper(g.first, sl, t, ctx->wide_ws.p, stream));
           return FPN_OK;
         }))
       return s;

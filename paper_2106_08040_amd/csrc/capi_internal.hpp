@@ -63,6 +63,7 @@ struct fpn_ctx_s {
   fpn_internal::DevBuf<float> msamp;
   fpn_internal::DevBuf<int32_t> idx;
   fpn_internal::DevBuf<int32_t> steps;
+  fpn_internal::DevBuf<float> wide_ws;  // wide-layout stepper: block inverses and stage vectors
   int64_t steps_n = 0;
   // surrogate evaluation workspace
   fpn_internal::DevBuf<float> sur_x, sur_ya, sur_yb, sur_h;

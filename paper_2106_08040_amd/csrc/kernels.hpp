@@ -27,6 +27,12 @@ struct StepLaunch {
 
 template <int L>
 hipError_t launch_stepper_L(const StepLaunch& s, const DevTables& t, hipStream_t stream);
+// wide block layout (L = 17..24): needs a workspace of stepper_ws_floats(L) floats per instance
+template <int L>
+hipError_t launch_stepper_wide_L(const StepLaunch& s, const DevTables& t, float* ws, hipStream_t stream);
+template <int L>
+int64_t stepper_wide_ws_floats_L();
+int64_t stepper_ws_floats(int L);  // 0 for the register layout (L <= 16)
 
 void launch_instance_prep(int64_t n, const double* D, const double* Ms, const double* K, const double* alpha,
                           const double* temp, const double* easy, const double* offset, InstParams* ip,
@@ -34,7 +40,7 @@ void launch_instance_prep(int64_t n, const double* D, const double* Ms, const do
 void launch_stationary(const DevTables& t, const int32_t* idx, int n_inst, const InstParams* ip,
                        const double* field_lab, double3 drive0, double* c_out, int64_t c_stride, double* wsinv,
                        int32_t* status, hipStream_t stream);
-hipError_t launch_stepper(int L, const StepLaunch& s, const DevTables& t, hipStream_t stream);
+hipError_t launch_stepper(int L, const StepLaunch& s, const DevTables& t, float* ws, hipStream_t stream);
 void launch_harmonics(const float* msamp, int Ns, int n_harm, int nch, double period, const double2* tw,
                       float* harm, const int32_t* status, int64_t n, hipStream_t stream);
 

@@ -18,23 +18,9 @@
 #include "device_util.hpp"
 #include "kernels.hpp"
 #include "physics.hpp"
+#include "stepper_common.hpp"
 
 namespace fpn {
-
-template <int L>
-struct Geo {
-  static constexpr int N = (L + 1) * (L + 1);
-  static constexpr int n0 = (L + 1) + ((L + 1) & 1);
-  static constexpr int Np = N + (n0 - (L + 1));
-  static constexpr int nb(int k) { return k == 0 ? n0 : 2 * (L + 1 - k); }
-  static constexpr int off(int k) {
-    int o = 0;
-    for (int j = 0; j < k; ++j) o += nb(j);
-    return o;
-  }
-  static constexpr int S = (Np + 63) / 64;    // vector slots per lane
-  static constexpr int NpA = (Np + 3) & ~3;   // padded vector length in LDS
-};
 
 template <int Q>
 struct Arr {
@@ -70,31 +56,6 @@ struct WaveLds {
   __device__ float* Kv(int j) { return u + (3 + j) * NpA; }  // K1..K5
   __device__ float* ft() { return u + 8 * NpA; }
 };
-
-// A zero the optimiser cannot see through: table indices offset by it are not hoisted out of
-// the time loop (the tables are loop-invariant, and hoisting keeps one register per entry live).
-__device__ __forceinline__ int opaque_zero() {
-  int z = 0;
-  asm volatile("" : "+s"(z));
-  return z;
-}
-
-// Sum of a value over the two 32-lane halves (lane and lane ^ 32).
-__device__ __forceinline__ float half_sum(float v) {
-  auto r = __builtin_amdgcn_permlane32_swap(__float_as_uint(v), __float_as_uint(v), false, false);
-  return __uint_as_float(r[0]) + __uint_as_float(r[1]);
-}
-
-// Largest absolute value over the wavefront.
-__device__ __forceinline__ float wave_max(float v) {
-  v = fmaxf(v, __shfl_xor(v, 16));
-  v = fmaxf(v, __shfl_xor(v, 8));
-  v = fmaxf(v, __shfl_xor(v, 4));
-  v = fmaxf(v, __shfl_xor(v, 2));
-  v = fmaxf(v, __shfl_xor(v, 1));
-  auto r = __builtin_amdgcn_permlane32_swap(__float_as_uint(v), __float_as_uint(v), false, false);
-  return fmaxf(__uint_as_float(r[0]), __uint_as_float(r[1]));
-}
 
 // In-place inverse of the lane-distributed block by Gauss-Jordan with 2x2 pivots.
 template <int Q, typename W>
@@ -141,44 +102,6 @@ __device__ __forceinline__ bool gj2_invert(float (&a)[Q], int i, int h, W& w) {
   }
   return ok;
 }
-
-// RODAS4 (Hairer & Wanner) in the form
-//   (I/(h g) - J) K_i = f(t + al_i h, y + sum_j a_ij K_j) + sum_j (c_ij/h) K_j + h gm_i f_t,
-//   y_{n+1} = y + sum_j a_6j K_j + K_6,  g = 1/4; K_6 is the embedded error estimate.
-__constant__ float kRodasAlpha[6] = {0.0f, 0.386f, 0.21f, 0.63f, 1.0f, 1.0f};
-__constant__ float kRodasGamma[6] = {0.25f, -0.1043f, 0.1035f, -0.03620000000000023f, 0.0f, 0.0f};
-__constant__ float kRodasA[6][5] = {
-    {0, 0, 0, 0, 0},
-    {1.544f, 0, 0, 0, 0},
-    {0.9466785280815826f, 0.2557011698983284f, 0, 0, 0},
-    {3.314825187068521f, 2.896124015972201f, 0.9986419139977817f, 0, 0},
-    {1.221224509226641f, 6.019134481288629f, 12.53708332932087f, -0.6878860361058950f, 0},
-    {1.221224509226641f, 6.019134481288629f, 12.53708332932087f, -0.6878860361058950f, 1.0f}};
-__constant__ float kRodasC[6][5] = {
-    {0, 0, 0, 0, 0},
-    {-5.668800000000000f, 0, 0, 0, 0},
-    {-2.430093356833875f, -0.2063599157091915f, 0, 0, 0},
-    {-0.1073529058151375f, -9.594562251023355f, -20.47028614809616f, 0, 0},
-    {7.496443313967647f, -10.24680431464352f, -33.99990352819905f, 11.70890893206160f, 0},
-    {8.083246795921522f, -7.981132988064893f, -31.52159432874371f, 16.31930543123136f, -6.058818238834054f}};
-
-struct StepArgs {
-  const InstParams* ip;
-  const int32_t* inst_idx;
-  int n_inst;
-  const double* c0;
-  int64_t c_stride;
-  double amp[3], freq[3], phase[3];  // drive
-  double period;
-  int settle;
-  int Ns;
-  int r_fixed;   // > 0: fixed substeps per sample interval; 0: adaptive
-  int r_max;
-  float tol;     // adaptive: bound on max |K6| (embedded RODAS4 error) per step
-  float* msamp;  // [n_total][3][Ns]
-  int32_t* status;
-  int32_t* steps_out;  // [n_total] time steps taken (may be null)
-};
 
 template <int L, int WAVES>
 __global__ void __launch_bounds__(64 * WAVES)

@@ -1,0 +1,647 @@
+// FP32 time stepper for large degrees (L = 17..24): the same RODAS4 integration as stepper.hip, with
+// a block layout that fits |m| blocks of up to 64 rows.
+//
+// One wavefront per instance; lane i owns row i of the block being factored.  A block's Schur
+// complement is built and inverted in registers (Gauss-Jordan with 2 x 2 pivots on its (cos, sin)
+// pairs, columns rotated by two after every pivot so all register indexing is static) and the
+// inverse is written to a per-instance workspace in global memory, column-quad-major so that a
+// wavefront reads 1 KiB contiguous per quad of columns in the stage solves.  The state vector stays
+// in registers, the stage and gather vectors in LDS (xin, V, G) or in the workspace (K1..K5, f_t,
+// which only their own lane reads).  The operator tables are read from global memory (they are
+// shared by every wavefront and stay in L2).
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+
+#include "device_common.hpp"
+#include "device_util.hpp"
+#include "kernels.hpp"
+#include "physics.hpp"
+#include "stepper_common.hpp"
+
+namespace fpn {
+
+template <int L>
+struct WGeo {
+  using G = Geo<L>;
+  static constexpr int NB = G::n0 > G::nb(1) ? G::n0 : G::nb(1);  // largest block
+  static constexpr int XS = NB + 1;                                // odd LDS row stride
+  static constexpr int XR = NB + 4;                                // rows incl. window overhang
+  static constexpr int q4(int k) { return (G::nb(k) + 3) / 4; }
+  static constexpr int ioff(int k) {
+    int o = 0;
+    for (int j = 0; j < k; ++j) o += 4 * q4(j) * G::nb(j);
+    return o;
+  }
+  static constexpr int INV = ioff(L + 1);        // floats of all block inverses
+  static constexpr int WS = INV + 7 * G::NpA;    // + K1..K5, f_t and the saved state
+};
+
+template <int L>
+struct WideLds {
+  static constexpr int NpA = Geo<L>::NpA;
+  static constexpr int kX = WGeo<L>::XR * WGeo<L>::XS;
+  static constexpr int kA = (((kX > 2 * NpA) ? kX : 2 * NpA) + 3) & ~3;  // keeps T 16-byte aligned
+  float a[kA];        // X (factorisation) | xin, V (stages)
+  float g[NpA];       // G (block-solve result)
+  float T[64];        // block right-hand side
+  float prow[2][64];  // pivot rows
+  float cw[6][64];    // Schur coefficients of one block, multiplier included
+  float mk[16];
+  float ms[16];
+  __device__ float* X() { return a; }
+  __device__ float* xin() { return a; }
+  __device__ float* V() { return a + NpA; }
+  __device__ float* G() { return g; }
+};
+
+// In-place inverse of an n x n block, row `lane` in a[0..n-1], by Gauss-Jordan with 2 x 2 pivots.
+// Pivot p works on columns 0, 1 of the rotated order and appends the new pivot columns at n-2, n-1,
+// so after n/2 pivots the columns are back in their original order.
+template <int n, typename WL>
+__device__ __forceinline__ bool gj_rot_invert(float (&a)[n], int lane, WL& w) {
+  const bool act = lane < n;
+  bool ok = true;
+#pragma unroll 1
+  for (int p = 0; p < n / 2; ++p) {
+    const int r0 = 2 * p;
+    const int r = lane - r0;
+    const bool inR = act && (r == 0 || r == 1);
+    if (inR) {
+#pragma unroll
+      for (int q = 0; q < n; ++q) w.prow[r][q] = a[q];
+    }
+    wsync();
+    const float P00 = w.prow[0][0], P01 = w.prow[0][1], P10 = w.prow[1][0], P11 = w.prow[1][1];
+    const float det = P00 * P11 - P01 * P10;
+    ok = ok && (det != 0.0f) && isfinite(det);
+    const float id = 1.0f / det;
+    const float Pi00 = P11 * id, Pi01 = -P01 * id, Pi10 = -P10 * id, Pi11 = P00 * id;
+    const float g0 = a[0], g1 = a[1];
+    float G0 = g0 * Pi00 + g1 * Pi10;
+    float G1 = g0 * Pi01 + g1 * Pi11;
+    float s = 1.0f;
+    float c0 = -G0, c1 = -G1;
+    if (inR) {
+      s = 0.0f;
+      G0 = (r == 0) ? -Pi00 : -Pi10;
+      G1 = (r == 0) ? -Pi01 : -Pi11;
+      c0 = (r == 0) ? Pi00 : Pi10;
+      c1 = (r == 0) ? Pi01 : Pi11;
+    }
+#pragma unroll
+    for (int q = 2; q < n; ++q) {
+      a[q - 2] = fmaf(-G1, w.prow[1][q], fmaf(-G0, w.prow[0][q], s * a[q]));
+      if ((q & 7) == 7) __builtin_amdgcn_sched_barrier(0);
+    }
+    a[n - 2] = act ? c0 : 0.0f;
+    a[n - 1] = act ? c1 : 0.0f;
+    wsync();
+  }
+  return ok;
+}
+
+template <int L, int WAVES>
+__global__ void __launch_bounds__(64 * WAVES)
+stepper_wide_kernel(StepArgs A, DevTables t, float* ws) {
+  using Gm = Geo<L>;
+  using WG = WGeo<L>;
+  using WL = WideLds<L>;
+  constexpr int Np = Gm::Np;
+  constexpr int NpA = Gm::NpA;
+  constexpr int S = Gm::S;
+  constexpr int XS = WG::XS;
+  extern __shared__ __align__(16) unsigned char smem[];
+  WL* wl = reinterpret_cast<WL*>(smem);
+  // per-wave scratch starts zeroed: window reads past a block edge (weight 0) then see finite data
+  for (int e = threadIdx.x; e < int(WAVES * sizeof(WL) / 4); e += blockDim.x) reinterpret_cast<float*>(wl)[e] = 0.0f;
+  __syncthreads();
+
+  const int lane = threadIdx.x & 63;
+  const int wid = __builtin_amdgcn_readfirstlane(int(threadIdx.x >> 6));  // uniform per wavefront
+  const int slot = blockIdx.x * WAVES + wid;
+  if (slot >= A.n_inst) return;
+  const int inst = A.inst_idx[slot];
+  WL& w = wl[wid];
+  float* inv = ws + int64_t(slot) * WG::WS;
+  float* Kg = inv + WG::INV;  // K1..K5 at j * NpA, f_t at 5 * NpA, saved state at 6 * NpA
+  const uint16_t* ecol = t.ell_col;
+  const float* eval = t.ell_val;
+  const float* wB = t.win_b;
+  const float* wC = t.win_c;
+  const float* wS = t.win_s;
+  float* ms_out = A.msamp + int64_t(inst) * 3 * A.Ns;
+  if (A.status[inst] != 0) {
+    for (int j = lane; j < 3 * A.Ns; j += 64) ms_out[j] = __builtin_nanf("");
+    if (A.steps_out && lane == 0) A.steps_out[inst] = 0;
+    return;
+  }
+  const InstParams P = A.ip[inst];
+  const float inv2tau = float(P.inv2tau), sigma = float(P.sigma), alpha = float(P.alpha), beta = float(P.beta_T);
+  float R[9], off[3];
+  for (int c = 0; c < 9; ++c) R[c] = float(P.R[c]);
+  for (int c = 0; c < 3; ++c) off[c] = float(P.off[c]);
+
+  float y[S];
+#pragma unroll
+  for (int s = 0; s < S; ++s) {
+    const int p = lane + 64 * s;
+    y[s] = (p < Np) ? float(A.c0[int64_t(inst) * A.c_stride + p]) : 0.0f;
+  }
+  const float rc = 2.0466534158929770f;  // sqrt(4 pi / 3)
+  constexpr int pX = Gm::off(1), pY = Gm::off(1) + 1, pZ = 1;
+  bool ok = true;
+
+  auto field = [&](double tt, float& bx, float& by, float& bz, bool deriv) {
+    float v[3];
+#pragma unroll
+    for (int a = 0; a < 3; ++a) {
+      const double cyc = A.freq[a] * tt;
+      const float x = float(2.0 * (cyc - floor(cyc))) + float(A.phase[a] * 0.3183098861837907);
+      if (!deriv) {
+        v[a] = float(A.amp[a]) * cospif(x);
+      } else {
+        v[a] = -float(A.amp[a] * 2.0 * kPi * A.freq[a]) * sinpif(x);
+      }
+    }
+    bx = v[0]; by = v[1]; bz = v[2];
+  };
+  auto mult_lane = [&](double tt) -> float {
+    float bx, by, bz;
+    field(tt, bx, by, bz, false);
+    bx += off[0]; by += off[1]; bz += off[2];
+    const float hx = R[0] * bx + R[3] * by + R[6] * bz;
+    const float hy = R[1] * bx + R[4] * by + R[7] * bz;
+    const float hz = R[2] * bx + R[5] * by + R[8] * bz;
+    return kind_mult(lane < 9 ? lane : 0, inv2tau, sigma, alpha, beta, hx, hy, hz);
+  };
+  auto dmult_lane = [&](double tt) -> float {
+    float bx, by, bz;
+    field(tt, bx, by, bz, true);
+    const float hx = R[0] * bx + R[3] * by + R[6] * bz;
+    const float hy = R[1] * bx + R[4] * by + R[7] * bz;
+    const float hz = R[2] * bx + R[5] * by + R[8] * bz;
+    return (lane < 3) ? 0.0f : kind_mult(lane < 9 ? lane : 0, inv2tau, sigma, alpha, beta, hx, hy, hz);
+  };
+  // dst[p] = add * dst[p] + (A(ms) xin)[p] for the rows p = lane + 64 s
+  auto matvec = [&](float* dst, bool add) {
+    const float* xin = w.xin();
+    float m[9];
+#pragma unroll
+    for (int k = 0; k < 9; ++k) m[k] = w.ms[k];
+#pragma unroll 1
+    for (int s = 0; s < S; ++s) {
+      const int p = lane + 64 * s;
+      const float* ev = opaque_ptr(eval);
+      const uint16_t* ec = opaque_ptr(ecol);
+      if (p < Np) {
+        float acc = 0.0f;
+#pragma unroll
+        for (int sl = 0; sl < kNSlRow; ++sl)
+          acc = fmaf(m[kSlotKindRow[sl]] * ev[sl * Np + p], xin[ec[sl * Np + p]], acc);
+        dst[p] = add ? dst[p] + acc : acc;
+      }
+    }
+  };
+  // x = M^{-1} V with the stored block inverses; result in G
+  auto block_apply = [&](auto KK, float* G, bool subtract) {
+    constexpr int K = decltype(KK)::value;
+    constexpr int n = Gm::nb(K), off0 = Gm::off(K), nq = WG::q4(K);
+    const float4* iv = reinterpret_cast<const float4*>(opaque_ptr(inv) + WG::ioff(K));
+    float part = 0.0f;
+    if (lane < n) {
+#pragma unroll
+      for (int q = 0; q < nq; ++q) {
+        const float4 c = iv[q * n + lane];
+        const float4 tv = *reinterpret_cast<const float4*>(&w.T[4 * q]);
+        part = fmaf(c.x, tv.x, part);
+        part = fmaf(c.y, tv.y, part);
+        part = fmaf(c.z, tv.z, part);
+        part = fmaf(c.w, tv.w, part);
+        if ((q & 3) == 3) __builtin_amdgcn_sched_barrier(0);  // bound the loads in flight
+      }
+      if (subtract) G[off0 + lane] -= part;
+      else G[off0 + lane] = part;
+    }
+    wsync();
+  };
+  auto solve = [&]() {
+    float* V = w.V();
+    float* G = w.G();
+    float mk[9];
+#pragma unroll
+    for (int k = 0; k < 9; ++k) mk[k] = w.mk[k];
+    const float mFX = mk[5], mFY = mk[6], mRX = mk[7], mRY = mk[8];
+    static_for<0, L + 1>([&](auto KK) {
+      constexpr int K = decltype(KK)::value;
+      constexpr int n = Gm::nb(K), off0 = Gm::off(K);
+      if (lane < n) {
+        const int row = off0 + lane;
+        float tv = V[row];
+        if constexpr (K == 1) {
+          const float* ev = opaque_ptr(eval);
+          const uint16_t* ec = opaque_ptr(ecol);
+#pragma unroll
+          for (int sl = kSlB; sl < kSlB + kNSlB; ++sl)
+            tv = fmaf(-mk[kSlotKindRow[sl]] * ev[sl * Np + row], G[ec[sl * Np + row]], tv);
+        } else if constexpr (K >= 2) {
+          constexpr int offp = Gm::off(K - 1);
+          const int tt = lane & 1;
+          const float* gs = G + offp + lane;
+          const float* go = G + offp + lane + 1 - 2 * tt;
+          const float* wb = opaque_ptr(wB);
+#pragma unroll
+          for (int d = 0; d < 3; ++d) {
+            tv = fmaf(-(d == 1 ? mRY : mFX) * wb[d * Np + row], gs[2 * d], tv);
+            tv = fmaf(-(d == 1 ? mRX : mFY) * wb[(3 + d) * Np + row], go[2 * d], tv);
+          }
+        }
+        w.T[lane] = tv;
+      }
+      wsync();
+      block_apply(KK, G, false);
+      __builtin_amdgcn_sched_barrier(0);
+    });
+    static_for_down<L - 1, 0>([&](auto KK) {
+      constexpr int K = decltype(KK)::value;
+      constexpr int n = Gm::nb(K), off0 = Gm::off(K);
+      if (lane < n) {
+        const int row = off0 + lane;
+        float tv = 0.0f;
+        constexpr int offn = Gm::off(K + 1);
+        const float* wc = opaque_ptr(wC);
+        const int tt = (K > 0) ? (lane & 1) : 0;
+        const float* gs = G + offn + ((K > 0) ? lane - 4 : 2 * lane - 4);
+        const float* go = G + offn + ((K > 0) ? lane - 3 - 2 * tt : 2 * lane - 3);
+#pragma unroll
+        for (int d = 0; d < 3; ++d) {
+          tv = fmaf((d == 1 ? mRY : mFX) * wc[d * Np + row], gs[2 * d], tv);
+          tv = fmaf((d == 1 ? mRX : mFY) * wc[(3 + d) * Np + row], go[2 * d], tv);
+        }
+        w.T[lane] = tv;
+      }
+      wsync();
+      block_apply(KK, G, true);
+      __builtin_amdgcn_sched_barrier(0);
+    });
+  };
+  // factor M = I - h g A(t_n) (multipliers in w.mk): Schur-complement inverses into the workspace.
+  // X holds the previous block's inverse (rows) on entry to each block.
+  auto factor = [&]() {
+    float* X = w.X();
+    float mk[9];
+#pragma unroll
+    for (int k = 0; k < 9; ++k) mk[k] = w.mk[k];
+    static_for<0, L + 1>([&](auto KK) {
+      constexpr int K = decltype(KK)::value;
+      constexpr int n = Gm::nb(K), off0 = Gm::off(K);
+      const bool act = lane < n;
+      constexpr int np = (K > 0) ? Gm::nb(K > 0 ? K - 1 : 0) : 1;
+      float u[np];  // U = B_K Sinv_{K-1}, row `lane`
+#pragma unroll
+      for (int q = 0; q < np; ++q) u[q] = 0.0f;
+      if constexpr (K > 0) {
+        constexpr int offp = Gm::off(K - 1);
+        if (act) {
+          const int row = off0 + lane;
+          if constexpr (K == 1) {
+            const float* ev = opaque_ptr(eval);
+            const uint16_t* ec = opaque_ptr(ecol);
+#pragma unroll
+            for (int sl = kSlB; sl < kSlB + kNSlB; ++sl) {
+              const float me = mk[kSlotKindRow[sl]] * ev[sl * Np + row];
+              const float* xr = X + (int(ec[sl * Np + row]) - offp) * XS;
+#pragma unroll
+              for (int q = 0; q < np; ++q) {
+                u[q] = fmaf(me, xr[q], u[q]);
+                if ((q & 7) == 7) __builtin_amdgcn_sched_barrier(0);
+              }
+              __builtin_amdgcn_sched_barrier(0);
+            }
+          } else {
+            const int tt = lane & 1;
+            const float* xs = X + lane * XS;                // rows lane + 2d
+            const float* xo = X + (lane + 1 - 2 * tt) * XS;  // rows lane + 1 - 2t + 2d
+            const float* wb = opaque_ptr(wB);
+#pragma unroll
+            for (int d = 0; d < 3; ++d) {
+              const float ms_ = (d == 1 ? mk[8] : mk[5]) * wb[d * Np + row];
+              const float mo_ = (d == 1 ? mk[7] : mk[6]) * wb[(3 + d) * Np + row];
+#pragma unroll
+              for (int q = 0; q < np; ++q) {
+                u[q] = fmaf(mo_, xo[2 * d * XS + q], fmaf(ms_, xs[2 * d * XS + q], u[q]));
+                if ((q & 7) == 7) __builtin_amdgcn_sched_barrier(0);
+              }
+              __builtin_amdgcn_sched_barrier(0);
+            }
+          }
+        }
+      }
+      wsync();
+      // S_K = I + (-h g) D_K assembled in X
+      if (act) {
+#pragma unroll
+        for (int q = 0; q < n; ++q) X[lane * XS + q] = 0.0f;
+      }
+      wsync();
+      if (act) {
+        const int row = off0 + lane;
+        const float* ev = opaque_ptr(eval);
+        const uint16_t* ec = opaque_ptr(ecol);
+#pragma unroll
+        for (int sl = kSlD; sl < kSlD + kNSlD; ++sl) {
+          const int cl = int(ec[sl * Np + row]) - off0;
+          X[lane * XS + cl] += mk[kSlotKindRow[sl]] * ev[sl * Np + row];
+        }
+        X[lane * XS + lane] += 1.0f;
+      }
+      wsync();
+      if constexpr (K >= 1) {
+        // stage the coefficients of C_{K-1} (with the kind multipliers) for broadcast reads:
+        // K = 1: by row j of block 0 (window of row j); K >= 2: by column c of block K (S window)
+        constexpr int nc = (K == 1) ? np : n;
+        constexpr int base = (K == 1) ? 0 : off0;
+        const float* wt = opaque_ptr((K == 1) ? wC : wS);
+        if (lane < nc) {
+#pragma unroll
+          for (int d = 0; d < 3; ++d) {
+            w.cw[d][lane] = (d == 1 ? mk[8] : mk[5]) * wt[d * Np + base + lane];
+            w.cw[3 + d][lane] = (d == 1 ? mk[7] : mk[6]) * wt[(3 + d) * Np + base + lane];
+          }
+        }
+        wsync();
+      }
+      if constexpr (K == 1) {
+        // S_1 -= U C_0 by rows j of block 0 (cos type): C_0 row j reaches block-1 columns
+        // 2j - 4 + 2d (same window) and 2j - 3 + 2d (other window)
+        if (act) {
+          float* xr = X + lane * XS;
+#pragma unroll
+          for (int c = 0; c < n; ++c) {
+            float acc = 0.0f;
+#pragma unroll
+            for (int j = 0; j < np; ++j) {
+#pragma unroll
+              for (int d = 0; d < 3; ++d) {
+                if (2 * j - 4 + 2 * d == c) acc = fmaf(u[j], w.cw[d][j], acc);
+                if (2 * j - 3 + 2 * d == c) acc = fmaf(u[j], w.cw[3 + d][j], acc);
+              }
+            }
+            xr[c] -= acc;
+            if ((c & 3) == 3) __builtin_amdgcn_sched_barrier(0);
+          }
+        }
+      } else if constexpr (K >= 2) {
+        // S_K -= U C_{K-1}: column c takes U[c + 2d] (same type) and U[c + 1 - 2 t_c + 2d] (other type)
+        if (act) {
+          float* xr = X + lane * XS;
+#pragma unroll
+          for (int c = 0; c < n; ++c) {
+            float acc = 0.0f;
+#pragma unroll
+            for (int d = 0; d < 3; ++d) {
+              const int js = c + 2 * d, jo = c + 1 - 2 * (c & 1) + 2 * d;
+              if (js < np) acc = fmaf(w.cw[d][c], u[js], acc);
+              if (jo < np) acc = fmaf(w.cw[3 + d][c], u[jo], acc);
+            }
+            xr[c] -= acc;
+            if ((c & 3) == 3) __builtin_amdgcn_sched_barrier(0);
+          }
+        }
+      }
+      wsync();
+      float a[n];
+#pragma unroll
+      for (int q = 0; q < n; ++q) a[q] = act ? X[lane * XS + q] : 0.0f;
+      ok = gj_rot_invert<n>(a, lane, w) && ok;
+      // inverse -> workspace (column quads) and -> X rows for the next block's U
+      if (act) {
+        float4* iv = reinterpret_cast<float4*>(opaque_ptr(inv) + WG::ioff(K));
+#pragma unroll
+        for (int q = 0; q < WG::q4(K); ++q) {
+          float4 v;
+          v.x = (4 * q + 0 < n) ? a[(4 * q + 0) < n ? 4 * q + 0 : 0] : 0.0f;
+          v.y = (4 * q + 1 < n) ? a[(4 * q + 1) < n ? 4 * q + 1 : 0] : 0.0f;
+          v.z = (4 * q + 2 < n) ? a[(4 * q + 2) < n ? 4 * q + 2 : 0] : 0.0f;
+          v.w = (4 * q + 3 < n) ? a[(4 * q + 3) < n ? 4 * q + 3 : 0] : 0.0f;
+          iv[q * n + lane] = v;
+        }
+#pragma unroll
+        for (int q = 0; q < n; ++q) X[lane * XS + q] = a[q];
+      }
+      wsync();
+      __builtin_amdgcn_sched_barrier(0);
+    });
+  };
+
+  float* Kv = Kg;                // K1..K5 at j * NpA
+  float* ft = Kg + 5 * NpA;
+  auto rodas_step = [&](double tn, double hs) -> float {
+    const float hf = float(hs);
+    const float hg = hf * 0.25f;
+    const float ih = 1.0f / hf;
+    {
+      const float mt = mult_lane(tn);
+      if (lane < 9) w.mk[lane] = -hg * mt;
+      wsync();
+    }
+    factor();
+    {  // f_t = A'(t_n) y
+      float* xin = w.xin();
+#pragma unroll
+      for (int s = 0; s < S; ++s) {
+        const int p = lane + 64 * s;
+        if (p < Np) xin[p] = y[s];
+      }
+      const float md = dmult_lane(tn);
+      if (lane < 9) w.ms[lane] = md;
+      wsync();
+      matvec(ft, false);
+      wsync();
+    }
+    for (int stg = 0; stg < 6; ++stg) {
+      const float mt = mult_lane(tn + double(kRodasAlpha[stg]) * hs);
+      if (lane < 9) w.ms[lane] = mt;
+      // stage argument -> xin, extra right-hand-side terms -> V
+      float* xin = w.xin();
+      float* V = w.V();
+#pragma unroll
+      for (int s = 0; s < S; ++s) {
+        const int p = lane + 64 * s;
+        if (p < Np) {
+          float yv = y[s];
+          float ev = hf * kRodasGamma[stg] * ft[p];
+          for (int j = 0; j < stg; ++j) {
+            const float kj = Kv[j * NpA + p];
+            yv = fmaf(kRodasA[stg][j], kj, yv);
+            ev = fmaf(kRodasC[stg][j] * ih, kj, ev);
+          }
+          xin[p] = yv;
+          V[p] = ev;
+        }
+      }
+      wsync();
+      matvec(V, true);
+      wsync();
+      solve();
+      if (stg < 5) {
+        const float* G = w.G();
+        float* kd = Kv + stg * NpA;
+#pragma unroll
+        for (int s = 0; s < S; ++s) {
+          const int p = lane + 64 * s;
+          if (p < Np) kd[p] = hg * G[p];
+        }
+      }
+      wsync();
+    }
+    // y_{n+1} = (stage-6 argument) + K6 ; embedded error K6
+    float emax = 0.0f;
+    {
+      const float* xin = w.xin();
+      const float* G = w.G();
+#pragma unroll
+      for (int s = 0; s < S; ++s) {
+        const int p = lane + 64 * s;
+        const float k6 = (p < Np) ? hg * G[p] : 0.0f;
+        y[s] = (p < Np) ? xin[p] + k6 : 0.0f;
+        emax = fmaxf(emax, fabsf(k6));
+      }
+    }
+    return wave_max(emax);
+  };
+
+  const double dt = A.period / A.Ns;
+  const int n_int = (A.settle + 1) * A.Ns;
+  const int first_rec = A.settle * A.Ns;
+  int r = (A.r_fixed > 0) ? A.r_fixed : 1;
+  int steps = 0;
+  for (int j = 0; j < n_int && ok; ++j) {
+    const double tj = j * dt;
+    if (j >= first_rec) {
+      const int js = j - first_rec;
+      const float vx = __shfl(y[pX >> 6], pX & 63), vy = __shfl(y[pY >> 6], pY & 63),
+                  vz = __shfl(y[pZ >> 6], pZ & 63);
+      if (lane < 3) {
+        const float r0 = lane == 0 ? R[0] : (lane == 1 ? R[3] : R[6]);
+        const float r1 = lane == 0 ? R[1] : (lane == 1 ? R[4] : R[7]);
+        const float r2 = lane == 0 ? R[2] : (lane == 1 ? R[5] : R[8]);
+        ms_out[lane * A.Ns + js] = rc * (r0 * vx + r1 * vy + r2 * vz);
+      }
+      ok = ok && isfinite(vx) && isfinite(vy) && isfinite(vz);
+    }
+    float* ysave = Kg + 6 * NpA;
+#pragma unroll
+    for (int s = 0; s < S; ++s) {
+      const int p = lane + 64 * s;
+      if (p < Np) ysave[p] = y[s];
+    }
+    while (true) {
+      const double hs = dt / r;
+      float emax = 0.0f;
+      for (int sub = 0; sub < r; ++sub) {
+        emax = fmaxf(emax, rodas_step(tj + sub * hs, hs));
+        ++steps;
+      }
+      if (!isfinite(emax)) {
+        ok = false;
+        break;
+      }
+      if (A.r_fixed > 0) break;
+      if (!(emax <= A.tol) && r < A.r_max) {
+#pragma unroll
+        for (int s = 0; s < S; ++s) {
+          const int p = lane + 64 * s;
+          y[s] = (p < Np) ? ysave[p] : 0.0f;
+        }
+        const int rn = int(ceilf(float(r) * 1.2f * sqrtf(sqrtf(emax / A.tol))));
+        r = min(A.r_max, max(2 * r, rn));
+        continue;
+      }
+      const int rn = int(ceilf(float(r) * 1.2f * sqrtf(sqrtf(fmaxf(emax, 1e-30f) / A.tol))));
+      r = max(1, min(r, rn));
+      break;
+    }
+  }
+  if (!ok) {
+    for (int j = lane; j < 3 * A.Ns; j += 64) ms_out[j] = __builtin_nanf("");
+    if (lane == 0) A.status[inst] = 2;
+  }
+  if (A.steps_out && lane == 0) A.steps_out[inst] = steps;
+}
+
+#ifndef FPN_WIDE_WAVES
+#define FPN_WIDE_WAVES 4
+#endif
+constexpr int kWideWaves = FPN_WIDE_WAVES;
+
+template <int L>
+int64_t stepper_wide_ws_floats_L() {
+  return WGeo<L>::WS;
+}
+
+template <int L>
+hipError_t launch_stepper_wide_L(const StepLaunch& s, const DevTables& t, float* ws, hipStream_t stream) {
+  StepArgs a;
+  a.ip = s.ip;
+  a.inst_idx = s.inst_idx;
+  a.n_inst = s.n_inst;
+  a.c0 = s.c0;
+  a.c_stride = s.c_stride;
+  for (int c = 0; c < 3; ++c) {
+    a.amp[c] = s.amp[c];
+    a.freq[c] = s.freq[c];
+    a.phase[c] = s.phase[c];
+  }
+  a.period = s.period;
+  a.settle = s.settle;
+  a.Ns = s.Ns;
+  a.r_fixed = s.r_fixed;
+  a.r_max = s.r_max;
+  a.tol = s.tol;
+  a.msamp = s.msamp;
+  a.status = s.status;
+  a.steps_out = s.steps_out;
+  const size_t shm = kWideWaves * sizeof(WideLds<L>);
+  auto kern = stepper_wide_kernel<L, kWideWaves>;
+  hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void*>(kern),
+                                     hipFuncAttributeMaxDynamicSharedMemorySize, int(shm));
+  if (e != hipSuccess) return e;
+  const int grid = (s.n_inst + kWideWaves - 1) / kWideWaves;
+  hipLaunchKernelGGL(kern, dim3(grid), dim3(64 * kWideWaves), shm, stream, a, t, ws);
+  return hipGetLastError();
+}
+
+#define FPN_WINST(LL)                                                                                  \
+  template hipError_t launch_stepper_wide_L<LL>(const StepLaunch&, const DevTables&, float*, hipStream_t); \
+  template int64_t stepper_wide_ws_floats_L<LL>();
+#if !defined(FPN_L_BEGIN)
+#define FPN_L_BEGIN 17
+#define FPN_L_END 24
+#endif
+#if FPN_L_BEGIN <= 17 && 17 <= FPN_L_END
+FPN_WINST(17)
+#endif
+#if FPN_L_BEGIN <= 18 && 18 <= FPN_L_END
+FPN_WINST(18)
+#endif
+#if FPN_L_BEGIN <= 19 && 19 <= FPN_L_END
+FPN_WINST(19)
+#endif
+#if FPN_L_BEGIN <= 20 && 20 <= FPN_L_END
+FPN_WINST(20)
+#endif
+#if FPN_L_BEGIN <= 21 && 21 <= FPN_L_END
+FPN_WINST(21)
+#endif
+#if FPN_L_BEGIN <= 22 && 22 <= FPN_L_END
+FPN_WINST(22)
+#endif
+#if FPN_L_BEGIN <= 23 && 23 <= FPN_L_END
+FPN_WINST(23)
+#endif
+#if FPN_L_BEGIN <= 24 && 24 <= FPN_L_END
+FPN_WINST(24)
+#endif
+
+}  // namespace fpn

@@ -21,8 +21,23 @@ import workloads as W  # noqa: E402
 
 HERE = os.path.dirname(os.path.abspath(__file__))
 
+def wide_l17():
+    return W.small_random(2, 17, seed=117, samples=48, settle=1, n_harm=8)
+
+
+def wide_l20():
+    return W.small_random(2, 20, seed=120, samples=48, settle=1, n_harm=8)
+
+
+def wide_l24():
+    return W.small_random(2, 24, seed=124, samples=48, settle=1, n_harm=8)
+
+
 # (workload factory, instance ids, Radau steps per sample for the reference and its check)
 JOBS = {
+    "wide_l17": (wide_l17, [0], 8),
+    "wide_l20": (wide_l20, [0, 1], 8),
+    "wide_l24": (wide_l24, [0, 1], 8),
     "single_1d": (W.single_1d, [0], 8),
     "lissajous": (W.lissajous_grid, [(0 * 17 + 8) * 17 + 8, (3 * 17 + 2) * 17 + 13, (5 * 17 + 16) * 17 + 0,
                                      (7 * 17 + 10) * 17 + 4, (2 * 17 + 0) * 17 + 16, (6 * 17 + 12) * 17 + 12], 4),
