@@ -58,7 +58,9 @@ def test_wide_degrees_match_oracle(fpn, ctx, L):
     for f in files:
         g = np.load(f)
         i = int(g["idx"])
-        assert g["err_est"] < 1e-6
+        # change between 8 and 4 steps per sample; Radau IIA is order 5, so the error of the
+        # 8-step reference is about 1/31 of it
+        assert g["err_est"] < 5e-6
         em, eh = rel(m[i].T, g["m"]), rel(h[i].T, g["Phi"])
         print(f"L={L} inst {i}: m {em:.2e} Phi {eh:.2e}", flush=True)
         assert em < TOL and eh < TOL
