@@ -125,6 +125,56 @@ fpn_status fpn_solve(fpn_ctx ctx, const fpn_drive* drive, const fpn_solve_opts* 
                      const fpn_batch* batch, int64_t n,
                      float* m_out, float* harm_out, int32_t* status, void* stream);
 
+/* ---- parameter sensitivities (gradients) ----
+ * Derivatives of the outputs with respect to the five instance parameters, in this order:
+ *   0: D [1/m]   1: K [1/(J/m^3)]   2: alpha   3: polar angle of the easy axis   4: its azimuth
+ * (angles of n = (sin th cos ph, sin th sin ph, cos th) in radians; at the poles the azimuth
+ * derivative is zero and the polar one is taken along ph = atan2(n_y, n_x)).
+ * They are computed as tangents of the discrete solve (forward mode): every RODAS4 stage of the
+ * primal solve is differentiated with respect to the parameters and the five tangent systems are
+ * solved with the same factorisation, in FP32; the stationary initial state is differentiated in
+ * FP64 (same block inverses).  The result is the exact derivative of the computed outputs for the
+ * step sequence that the primal error control chose.  Available for L <= 16 (FPN_E_RANGE otherwise). */
+#define FPN_NPARAM 5
+
+/* As fpn_solve, plus dm_out [n][5][3][N_s] (FPN_OUT_M) and dharm_out [n][5][ch][K_h+1][2] (FPN_OUT_HARM),
+ * the parameter derivatives of m_out and harm_out.  Asynchronous. */
+fpn_status fpn_solve_tangent(fpn_ctx ctx, const fpn_drive* drive, const fpn_solve_opts* opts,
+                             const fpn_batch* batch, int64_t n, float* m_out, float* harm_out,
+                             float* dm_out, float* dharm_out, int32_t* status, void* stream);
+
+/* Gradient of a scalar loss through the harmonics: given dL_dharm [n][ch][K_h+1][2] (DEVICE FP32,
+ * same layout as harm_out), writes grad_out [n][5] (DEVICE FP64) = sum over channels, bins, re/im of
+ * dL/dPhi * dPhi/dp, accumulated in FP64 (NaN for failed instances).  harm_out may be NULL; opts->flags
+ * only selects FPN_HARM_Z.  Asynchronous. */
+fpn_status fpn_adjoint(fpn_ctx ctx, const fpn_drive* drive, const fpn_solve_opts* opts,
+                       const fpn_batch* batch, int64_t n, const float* dL_dharm, double* grad_out,
+                       float* harm_out, int32_t* status, void* stream);
+
+/* ---- solve plans: reusable schedules and graph capture ----
+ * A plan binds one solve to its inputs and outputs (device pointers that must stay valid and
+ * unchanged in shape for the plan's lifetime; their contents may change between launches) and fixes
+ * its schedule: instances are grouped by degree L, the groups are launched most expensive first on
+ * concurrent streams, and every stepper launch is persistent (each wavefront takes instances from a
+ * queue until it is drained), so uneven step counts do not idle whole workgroups.  Within a group
+ * instances start in order of decreasing cost_hint (HOST [n], e.g. the step counts of an earlier run
+ * from fpn_plan_steps; NULL keeps batch order).  Outputs do not depend on the schedule.
+ * The plan owns its workspace; plans are independent of fpn_solve's and of each other. */
+typedef struct fpn_plan_s* fpn_plan;
+
+/* Build a plan (synchronous).  Errors as fpn_solve; n >= 1. */
+fpn_status fpn_plan_create(fpn_ctx ctx, const fpn_drive* drive, const fpn_solve_opts* opts,
+                           const fpn_batch* batch, int64_t n, const float* cost_hint,
+                           float* m_out, float* harm_out, int32_t* status, fpn_plan* out);
+/* Run the plan on `stream` (asynchronous), as fpn_solve would. */
+fpn_status fpn_plan_launch(fpn_plan plan, void* stream);
+/* Run the plan as one HIP graph: the first call captures the launch sequence (on a stream of the
+ * plan's own) and instantiates it; every call launches the graph on `stream` (asynchronous). */
+fpn_status fpn_plan_graph_launch(fpn_plan plan, void* stream);
+/* Time steps taken per instance by the plan's last run (HOST int32 [n]; synchronises). */
+fpn_status fpn_plan_steps(fpn_plan plan, int32_t* steps_out);
+fpn_status fpn_plan_destroy(fpn_plan plan);
+
 /* Time steps taken by the last fpn_solve on this context, summed over its instances
  * (synchronises with that solve).  HOST output.  Errors: FPN_E_ARG, FPN_E_DEVICE. */
 fpn_status fpn_last_steps(fpn_ctx ctx, int64_t* total_steps);

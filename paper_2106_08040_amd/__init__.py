@@ -30,12 +30,14 @@ FPN_OK, FPN_E_ARG, FPN_E_RANGE, FPN_E_DEVICE, FPN_E_NOMEM, FPN_E_UNSUPPORTED = 0
 FPN_INST_OK, FPN_INST_BAD_PARAM, FPN_INST_NONFINITE, FPN_INST_SINGULAR = 0, 1, 2, 3
 FPN_OUT_M, FPN_OUT_HARM, FPN_HARM_Z = 1, 2, 4
 FPN_MAX_L = 24
+FPN_NPARAM = 5  # sensitivities: D, K, alpha, easy-axis polar angle, azimuth
 
 EXPORTED = ["fpn_status_string", "fpn_last_error", "fpn_create", "fpn_destroy", "fpn_solve",
             "fpn_stationary", "fpn_last_steps", "fpn_timing_enable", "fpn_timing_read", "fpn_host_operator", "fpn_host_frame",
             "fpn_host_table_nnz", "fpn_mlp_create", "fpn_mlp_destroy", "fpn_mlp_num_params", "fpn_mlp_params",
             "fpn_mlp_set_input_norm", "fpn_mlp_forward", "fpn_mlp_gradient", "fpn_mlp_train_step",
-            "fpn_surrogate_features", "fpn_surrogate_predict"]
+            "fpn_surrogate_features", "fpn_surrogate_predict", "fpn_plan_create", "fpn_plan_launch",
+            "fpn_plan_graph_launch", "fpn_plan_steps", "fpn_plan_destroy", "fpn_solve_tangent", "fpn_adjoint"]
 
 
 class fpn_drive(ctypes.Structure):
@@ -100,6 +102,26 @@ _lib.fpn_mlp_gradient.restype = ctypes.c_int32
 _lib.fpn_mlp_gradient.argtypes = [_vp, _vp, _vp, ctypes.c_int64, _vp, _vp, _vp]
 _lib.fpn_mlp_train_step.restype = ctypes.c_int32
 _lib.fpn_mlp_train_step.argtypes = [_vp, _vp, _vp, ctypes.c_int64, ctypes.c_float, _vp, _vp]
+
+
+_lib.fpn_solve_tangent.restype = ctypes.c_int32
+_lib.fpn_solve_tangent.argtypes = [_vp, ctypes.POINTER(fpn_drive), ctypes.POINTER(fpn_solve_opts),
+                                   ctypes.POINTER(fpn_batch), ctypes.c_int64, _vp, _vp, _vp, _vp, _vp, _vp]
+_lib.fpn_adjoint.restype = ctypes.c_int32
+_lib.fpn_adjoint.argtypes = [_vp, ctypes.POINTER(fpn_drive), ctypes.POINTER(fpn_solve_opts),
+                             ctypes.POINTER(fpn_batch), ctypes.c_int64, _vp, _vp, _vp, _vp, _vp]
+_lib.fpn_plan_create.restype = ctypes.c_int32
+_lib.fpn_plan_create.argtypes = [_vp, ctypes.POINTER(fpn_drive), ctypes.POINTER(fpn_solve_opts),
+                                 ctypes.POINTER(fpn_batch), ctypes.c_int64, ctypes.POINTER(ctypes.c_float), _vp, _vp,
+                                 _vp, ctypes.POINTER(_vp)]
+_lib.fpn_plan_launch.restype = ctypes.c_int32
+_lib.fpn_plan_launch.argtypes = [_vp, _vp]
+_lib.fpn_plan_graph_launch.restype = ctypes.c_int32
+_lib.fpn_plan_graph_launch.argtypes = [_vp, _vp]
+_lib.fpn_plan_steps.restype = ctypes.c_int32
+_lib.fpn_plan_steps.argtypes = [_vp, ctypes.POINTER(ctypes.c_int32)]
+_lib.fpn_plan_destroy.restype = ctypes.c_int32
+_lib.fpn_plan_destroy.argtypes = [_vp]
 
 
 class fpn_surrogate(ctypes.Structure):
@@ -265,6 +287,56 @@ class Context:
         _check(_lib.fpn_timing_read(self._h, ms, cnt), "fpn_timing_read")
         return {k: (ms[i], cnt[i]) for i, k in enumerate(self.TIMING_KERNELS)}
 
+    def solve_tangent(self, inst, L, drive, samples, settle, n_harm, substeps=0, want_m=True, want_harm=True,
+                      harm_z=False, tol=0.0):
+        """fpn_solve_tangent: (m, harm, dm [n,5,3,Ns], dharm [n,5,ch,Kh+1] complex, status)."""
+        torch = _torch()
+        dev = f"cuda:{self.device}"
+        b, keep, Lh = self._batch(inst, L)
+        n = keep["D"].numel()
+        ch = 3 if harm_z else 2
+        m = torch.empty((n, 3, samples), dtype=torch.float32, device=dev) if want_m else None
+        dm = torch.empty((n, FPN_NPARAM, 3, samples), dtype=torch.float32, device=dev) if want_m else None
+        hm = torch.empty((n, ch, n_harm + 1, 2), dtype=torch.float32, device=dev) if want_harm else None
+        dh = torch.empty((n, FPN_NPARAM, ch, n_harm + 1, 2), dtype=torch.float32, device=dev) if want_harm else None
+        st = torch.empty((n,), dtype=torch.int32, device=dev)
+        opts = fpn_solve_opts(samples, settle, n_harm, substeps,
+                              (FPN_OUT_M if want_m else 0) | (FPN_OUT_HARM if want_harm else 0) |
+                              (FPN_HARM_Z if harm_z else 0), float(tol))
+        s = torch.cuda.current_stream(self.device)
+        ptr = lambda t: t.data_ptr() if t is not None else None  # noqa: E731
+        _check(_lib.fpn_solve_tangent(self._h, ctypes.byref(drive), ctypes.byref(opts), ctypes.byref(b), n, ptr(m),
+                                      ptr(hm), ptr(dm), ptr(dh), st.data_ptr(), s.cuda_stream), "fpn_solve_tangent")
+        self._keep = (keep, Lh)
+        cv = torch.view_as_complex
+        return m, (cv(hm) if hm is not None else None), dm, (cv(dh) if dh is not None else None), st
+
+    def adjoint(self, inst, L, drive, samples, settle, n_harm, dL_dharm, substeps=0, harm_z=False, tol=0.0,
+                want_harm=True):
+        """fpn_adjoint: dL_dharm real [n, ch, Kh+1, 2] (d loss / d (Re, Im) Phi).  Returns (grad [n,5] float64,
+        harm [n,ch,Kh+1,2] float32 or None, status)."""
+        torch = _torch()
+        dev = f"cuda:{self.device}"
+        b, keep, Lh = self._batch(inst, L)
+        n = keep["D"].numel()
+        ch = 3 if harm_z else 2
+        g = _f32(dL_dharm, dev).reshape(n, ch, n_harm + 1, 2).contiguous()
+        grad = torch.empty((n, FPN_NPARAM), dtype=torch.float64, device=dev)
+        hm = torch.empty((n, ch, n_harm + 1, 2), dtype=torch.float32, device=dev) if want_harm else None
+        st = torch.empty((n,), dtype=torch.int32, device=dev)
+        opts = fpn_solve_opts(samples, settle, n_harm, substeps, FPN_HARM_Z if harm_z else 0, float(tol))
+        s = torch.cuda.current_stream(self.device)
+        _check(_lib.fpn_adjoint(self._h, ctypes.byref(drive), ctypes.byref(opts), ctypes.byref(b), n, g.data_ptr(),
+                                grad.data_ptr(), hm.data_ptr() if hm is not None else None, st.data_ptr(),
+                                s.cuda_stream), "fpn_adjoint")
+        self._keep = (keep, Lh, g)
+        return grad, hm, st
+
+    def plan(self, inst, L, drive, samples, settle, n_harm, substeps=0, want_m=True, want_harm=True, harm_z=False,
+             tol=0.0, cost_hint=None):
+        """A reusable solve schedule bound to these inputs and to freshly allocated outputs (fpn_plan_*)."""
+        return Plan(self, inst, L, drive, samples, settle, n_harm, substeps, want_m, want_harm, harm_z, tol, cost_hint)
+
     def surrogate_features(self, inst):
         """Network input features [n, 8] (float32, device) and status [n] (fpn_surrogate_features)."""
         torch = _torch()
@@ -409,3 +481,62 @@ class MLP:
         _check(_lib.fpn_mlp_train_step(self._h, x.data_ptr(), t.data_ptr(), x.shape[0], float(lr), loss.data_ptr(),
                                        self._stream()), "fpn_mlp_train_step")
         return loss
+
+
+class Plan:
+    """fpn_plan: one solve bound to its inputs and outputs, launched eagerly or as a HIP graph."""
+
+    def __init__(self, ctx, inst, L, drive, samples, settle, n_harm, substeps, want_m, want_harm, harm_z, tol,
+                 cost_hint):
+        torch = _torch()
+        dev = f"cuda:{ctx.device}"
+        self.ctx = ctx
+        self._b, self._keep, self._Lh = ctx._batch(inst, L)
+        n = self._keep["D"].numel()
+        self.n = n
+        ch = 3 if harm_z else 2
+        self.m = torch.empty((n, 3, samples), dtype=torch.float32, device=dev) if want_m else None
+        self._hm = torch.empty((n, ch, n_harm + 1, 2), dtype=torch.float32, device=dev) if want_harm else None
+        self.status = torch.empty((n,), dtype=torch.int32, device=dev)
+        self._drive = drive
+        self._opts = fpn_solve_opts(samples, settle, n_harm, substeps,
+                                    (FPN_OUT_M if want_m else 0) | (FPN_OUT_HARM if want_harm else 0) |
+                                    (FPN_HARM_Z if harm_z else 0), float(tol))
+        hint = None
+        if cost_hint is not None:
+            self._hint = np.ascontiguousarray(cost_hint, dtype=np.float32)
+            hint = self._hint.ctypes.data_as(ctypes.POINTER(ctypes.c_float))
+        self._h = _vp()
+        _check(_lib.fpn_plan_create(ctx._h, ctypes.byref(drive), ctypes.byref(self._opts), ctypes.byref(self._b), n,
+                                    hint, self.m.data_ptr() if self.m is not None else None,
+                                    self._hm.data_ptr() if self._hm is not None else None, self.status.data_ptr(),
+                                    ctypes.byref(self._h)), "fpn_plan_create")
+
+    @property
+    def harm(self):
+        return _torch().view_as_complex(self._hm) if self._hm is not None else None
+
+    def _stream(self, stream):
+        return (stream if stream is not None else _torch().cuda.current_stream(self.ctx.device)).cuda_stream
+
+    def launch(self, stream=None):
+        _check(_lib.fpn_plan_launch(self._h, self._stream(stream)), "fpn_plan_launch")
+
+    def graph_launch(self, stream=None):
+        _check(_lib.fpn_plan_graph_launch(self._h, self._stream(stream)), "fpn_plan_graph_launch")
+
+    def steps(self):
+        out = np.zeros(self.n, dtype=np.int32)
+        _check(_lib.fpn_plan_steps(self._h, out.ctypes.data_as(ctypes.POINTER(ctypes.c_int32))), "fpn_plan_steps")
+        return out
+
+    def close(self):
+        if self._h:
+            _lib.fpn_plan_destroy(self._h)
+            self._h = _vp()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass

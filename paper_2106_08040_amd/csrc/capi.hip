@@ -250,6 +250,21 @@ hipError_t launch_stepper(int L, const StepLaunch& s, const DevTables& t, float*
   }
 }
 
+hipError_t stepper_occupancy(int L, const DevTables& t, bool tangents, int* waves_per_block, int* blocks_per_cu) {
+  switch (L) {
+#define FPN_CASE(LL) \
+  case LL: return stepper_occupancy_L<LL>(t, tangents, waves_per_block, blocks_per_cu);
+    FPN_CASE(1) FPN_CASE(2) FPN_CASE(3) FPN_CASE(4) FPN_CASE(5) FPN_CASE(6) FPN_CASE(7) FPN_CASE(8)
+    FPN_CASE(9) FPN_CASE(10) FPN_CASE(11) FPN_CASE(12) FPN_CASE(13) FPN_CASE(14) FPN_CASE(15) FPN_CASE(16)
+#undef FPN_CASE
+#define FPN_WCASE(LL) \
+  case LL: return stepper_wide_occupancy_L<LL>(waves_per_block, blocks_per_cu);
+    FPN_WCASE(17) FPN_WCASE(18) FPN_WCASE(19) FPN_WCASE(20) FPN_WCASE(21) FPN_WCASE(22) FPN_WCASE(23) FPN_WCASE(24)
+#undef FPN_WCASE
+    default: return hipErrorInvalidValue;
+  }
+}
+
 int64_t stepper_ws_floats(int L) {
   switch (L) {
 #define FPN_WCASE(LL) \
@@ -303,6 +318,12 @@ fpn_status fpn_destroy(fpn_ctx ctx) {
   ctx->idx.release();
   ctx->steps.release();
   ctx->wide_ws.release();
+  for (fpn_plan_s* pl : {ctx->solve_plan, ctx->tangent_plan}) {
+    if (pl) {
+      plan_release(pl);
+      delete pl;
+    }
+  }
   for (auto* b : {&ctx->sur_x, &ctx->sur_ya, &ctx->sur_yb, &ctx->sur_h}) b->release();
   for (auto* b : {&ctx->sur_list, &ctx->sur_count, &ctx->sur_st}) b->release();
   ctx->sur_g.release();
@@ -314,11 +335,41 @@ fpn_status fpn_destroy(fpn_ctx ctx) {
   return FPN_OK;
 }
 
-fpn_status fpn_solve(fpn_ctx ctx, const fpn_drive* drive, const fpn_solve_opts* opts, const fpn_batch* batch,
-                     int64_t n, float* m_out, float* harm_out, int32_t* status, void* stream_) {
-  if (!ctx) return fail(FPN_E_ARG, "ctx is NULL");
+}  // extern "C"
+
+namespace fpn_internal {
+
+void plan_release(fpn_plan_s* p) {
+  if (p->exec) (void)hipGraphExecDestroy(p->exec);
+  if (p->graph) (void)hipGraphDestroy(p->graph);
+  p->exec = nullptr;
+  p->graph = nullptr;
+  for (hipStream_t s : p->side) (void)hipStreamDestroy(s);
+  for (hipEvent_t e : p->ev) (void)hipEventDestroy(e);
+  if (p->cap) (void)hipStreamDestroy(p->cap);
+  p->side.clear();
+  p->ev.clear();
+  p->cap = nullptr;
+  p->ip.release();
+  p->c0.release();
+  p->wsinv.release();
+  p->own_m.release();
+  p->wide_ws.release();
+  p->idx.release();
+  p->steps.release();
+  p->queue.release();
+  p->c0t.release();
+  p->own_mt.release();
+  p->own_dh.release();
+  p->tws.release();
+}
+
+}  // namespace fpn_internal
+
+namespace {
+
+fpn_status validate_opts(const fpn_drive* drive, const fpn_solve_opts* opts) {
   if (!opts) return fail(FPN_E_ARG, "opts is NULL");
-  if (n < 0) return fail(FPN_E_ARG, "n < 0");
   if (fpn_status s = validate_drive(drive)) return s;
   const int Ns = opts->samples_per_period, r = opts->substeps, Kh = opts->n_harm;
   if (Ns < 2) return fail(FPN_E_ARG, "samples_per_period must be >= 2");
@@ -329,83 +380,192 @@ fpn_status fpn_solve(fpn_ctx ctx, const fpn_drive* drive, const fpn_solve_opts* 
   if (int64_t(Ns) * std::max(r, 1) * (opts->settle_periods + 1) > (int64_t(1) << 30))
     return fail(FPN_E_ARG, "too many time steps");
   if (opts->flags & ~uint32_t(FPN_OUT_M | FPN_OUT_HARM | FPN_HARM_Z)) return fail(FPN_E_ARG, "unknown flag");
-  const bool want_m = opts->flags & FPN_OUT_M, want_h = opts->flags & FPN_OUT_HARM;
-  if (n == 0) return FPN_OK;  // nothing to do (empty outputs may be NULL)
-  if (want_m && !m_out) return fail(FPN_E_ARG, "FPN_OUT_M set but m_out is NULL");
-  if (want_h && !harm_out) return fail(FPN_E_ARG, "FPN_OUT_HARM set but harm_out is NULL");
-  if (!status) return fail(FPN_E_ARG, "status is NULL");
-  if (n > (int64_t(1) << 31) - 1) return fail(FPN_E_ARG, "n too large");
-  if (fpn_status s = validate_batch(batch, n)) return s;
-  std::lock_guard<std::mutex> lk(ctx->mu);
-  hipStream_t stream = reinterpret_cast<hipStream_t>(stream_);
-  FPN_HIP(hipSetDevice(ctx->device));
+  return FPN_OK;
+}
 
-  auto groups = group_by_L(batch->L, n);
-  int Lmax = 0;
-  for (auto& g : groups) Lmax = std::max(Lmax, g.first);
-  std::map<int, const fpn::DevTables*> tabs;
-  int64_t inv_max = 0, np_max = 0;
-  for (auto& g : groups) {
-    const fpn::DevTables* t = nullptr;
-    if (fpn_status s = get_tables(ctx, g.first, &t)) return s;
-    tabs[g.first] = t;
-    inv_max = std::max<int64_t>(inv_max, t->inv_doubles);
-    np_max = std::max<int64_t>(np_max, t->Np);
+fpn_status occupancy(fpn_ctx ctx, int L, const fpn::DevTables& t, bool tangents, int* waves, int* blocks) {
+  const int key = L + (tangents ? 1000 : 0);
+  auto it = ctx->occupancy.find(key);
+  if (it == ctx->occupancy.end()) {
+    int w = 0, b = 0;
+    FPN_HIP(fpn::stepper_occupancy(L, t, tangents, &w, &b));
+    if (b < 1) return fail(FPN_E_DEVICE, "stepper does not fit on a compute unit");
+    it = ctx->occupancy.emplace(key, std::make_pair(w, b)).first;
+  }
+  if (ctx->cus == 0) {
+    hipDeviceProp_t prop;
+    FPN_HIP(hipGetDeviceProperties(&prop, ctx->device));
+    ctx->cus = prop.multiProcessorCount;
+  }
+  *waves = it->second.first;
+  *blocks = it->second.second;
+  return FPN_OK;
+}
+
+// Groups the batch by degree, orders the groups (most expensive first) and the instances within each
+// group (by cost_hint, largest first, when given), and sizes every workspace.
+fpn_status plan_build(fpn_plan_s* p, fpn_ctx ctx, const fpn_drive* drive, const fpn_solve_opts* opts,
+                      const fpn_batch* batch, int64_t n, const float* cost_hint, float* m_out, float* harm_out,
+                      int32_t* status, hipStream_t stream, bool tangent = false, float* dm_out = nullptr,
+                      float* dharm_out = nullptr) {
+  const bool want_m = opts->flags & FPN_OUT_M, want_h = opts->flags & FPN_OUT_HARM;
+  const int Ns = opts->samples_per_period;
+  p->ctx = ctx;
+  p->drive = *drive;
+  p->opts = *opts;
+  p->batch = *batch;
+  p->batch.L = nullptr;
+  p->n = n;
+  p->m_out = want_m ? m_out : nullptr;
+  p->harm_out = want_h ? harm_out : nullptr;
+  p->status = status;
+  p->tangent = tangent;
+  std::map<int, std::vector<int32_t>> byL;
+  for (int64_t i = 0; i < n; ++i) {
+    if (tangent && batch->L[i] > 16)
+      return fail(FPN_E_RANGE, "parameter sensitivities are available for L <= 16");
+    byL[batch->L[i]].push_back(int32_t(i));
+  }
+  p->groups.clear();
+  p->order.clear();
+  p->order.reserve(n);
+  p->np_max = 0;
+  for (auto& kv : byL) {
+    fpn_internal::PlanGroup g;
+    g.L = kv.first;
+    if (fpn_status s = get_tables(ctx, g.L, &g.t)) return s;
+    p->np_max = std::max<int64_t>(p->np_max, g.t->Np);
+    auto& ids = kv.second;
+    double per = 0.0;  // per-step work of degree L: sum of cubed block sizes
+    for (int k = 0; k <= g.L; ++k) per += std::pow(double(k == 0 ? g.t->n0 : 2 * (g.L + 1 - k)), 3.0);
+    if (cost_hint) {
+      std::stable_sort(ids.begin(), ids.end(), [&](int32_t a, int32_t b) { return cost_hint[a] > cost_hint[b]; });
+      for (int32_t i : ids) g.cost += double(cost_hint[i]);
+    } else {
+      g.cost = per * double(ids.size());
+    }
+    g.cnt = int(ids.size());
+    p->groups.push_back(g);
+    byL[g.L] = ids;
+  }
+  std::stable_sort(p->groups.begin(), p->groups.end(),
+                   [](const fpn_internal::PlanGroup& a, const fpn_internal::PlanGroup& b) { return a.cost > b.cost; });
+  int64_t start = 0, ws_total = 0, inv_total = 0, tws_total = 0;
+  for (auto& g : p->groups) {
+    g.start = start;
+    auto& ids = byL[g.L];
+    p->order.insert(p->order.end(), ids.begin(), ids.end());
+    start += g.cnt;
+    int waves = 0, blocks = 0;
+    if (fpn_status s = occupancy(ctx, g.L, *g.t, tangent, &waves, &blocks)) return s;
+    g.grid = std::max(1, std::min((g.cnt + waves - 1) / waves, blocks * ctx->cus));
+    g.ws_off = ws_total;
+    ws_total += int64_t(g.grid) * waves * fpn::stepper_ws_floats(g.L);
+    g.tws_off = tws_total;
+    if (tangent) tws_total += int64_t(g.grid) * waves * fpn::stepper_tan_ws_floats(g.L);
+    g.inv_off = inv_total;
+    inv_total += int64_t(g.cnt) * g.t->inv_doubles;
   }
   if (want_h)
     if (fpn_status s = ensure_twiddle(ctx, Ns, stream)) return s;
-  FPN_HIP(ctx->ip.ensure(n));
-  FPN_HIP(ctx->c0.ensure(size_t(n) * np_max));
-  FPN_HIP(ctx->idx.ensure(n));
-  FPN_HIP(ctx->steps.ensure(n));
-  ctx->steps_n = n;
-  float* msamp = m_out;
+  FPN_HIP(p->ip.ensure(n));
+  FPN_HIP(p->c0.ensure(size_t(n) * p->np_max));
+  FPN_HIP(p->idx.ensure(n));
+  FPN_HIP(p->steps.ensure(n));
+  FPN_HIP(p->queue.ensure(std::max<size_t>(p->groups.size(), 1)));
+  FPN_HIP(p->wsinv.ensure(size_t(inv_total)));
+  if (ws_total) FPN_HIP(p->wide_ws.ensure(size_t(ws_total)));
+  p->msamp = m_out;
   if (!want_m) {
-    FPN_HIP(ctx->msamp.ensure(size_t(n) * 3 * Ns));
-    msamp = ctx->msamp.p;
+    FPN_HIP(p->own_m.ensure(size_t(n) * 3 * Ns));
+    p->msamp = p->own_m.p;
   }
-  // largest group bounds the stationary workspace; the wide-layout stepper needs its own
-  size_t maxg = 0, wide = 0;
-  for (auto& g : groups) {
-    maxg = std::max(maxg, g.second.size());
-    wide = std::max(wide, g.second.size() * size_t(fpn::stepper_ws_floats(g.first)));
+  if (tangent) {
+    const int nch = (opts->flags & FPN_HARM_Z) ? 3 : 2;
+    FPN_HIP(p->c0t.ensure(size_t(n) * fpn::kNTan * p->np_max));
+    FPN_HIP(p->tws.ensure(size_t(tws_total)));
+    p->mtan = dm_out;
+    if (!p->mtan) {
+      FPN_HIP(p->own_mt.ensure(size_t(n) * fpn::kNTan * 3 * Ns));
+      p->mtan = p->own_mt.p;
+    }
+    p->dharm = dharm_out;
+    if (!p->dharm) {
+      FPN_HIP(p->own_dh.ensure(size_t(n) * fpn::kNTan * nch * (opts->n_harm + 1) * 2));
+      p->dharm = p->own_dh.p;
+    }
+    if (!want_h)
+      if (fpn_status s = ensure_twiddle(ctx, Ns, stream)) return s;
   }
-  FPN_HIP(ctx->wsinv.ensure(maxg * size_t(inv_max)));
-  if (wide) FPN_HIP(ctx->wide_ws.ensure(wide));
-  std::vector<int32_t> order;
-  order.reserve(n);
-  for (auto& g : groups) order.insert(order.end(), g.second.begin(), g.second.end());
-  FPN_HIP(hipMemcpyAsync(ctx->idx.p, order.data(), n * sizeof(int32_t), hipMemcpyHostToDevice, stream));
+  FPN_HIP(hipMemcpyAsync(p->idx.p, p->order.data(), n * sizeof(int32_t), hipMemcpyHostToDevice, stream));
+  // side streams (default priority) and fork / join events for concurrent degree buckets
+  const size_t nside = std::min<size_t>(p->groups.size() > 1 ? p->groups.size() : 0, 4);
+  while (p->side.size() < nside) {
+    hipStream_t s = nullptr;
+    FPN_HIP(hipStreamCreateWithFlags(&s, hipStreamNonBlocking));
+    p->side.push_back(s);
+  }
+  while (p->ev.size() < 1 + p->side.size()) {
+    hipEvent_t e = nullptr;
+    FPN_HIP(hipEventCreateWithFlags(&e, hipEventDisableTiming));
+    p->ev.push_back(e);
+  }
+  return FPN_OK;
+}
 
-  if (fpn_status s = timed(ctx, 0, stream, [&]() -> fpn_status {
-        fpn::launch_instance_prep(n, batch->D, batch->Ms, batch->K, batch->alpha, batch->temp, batch->easy_axis,
-                                  batch->offset, ctx->ip.p, status, stream);
+// Launches the planned solve on `stream` (kernel launches, event records and stream waits only, so
+// the sequence can be captured into a graph).  Degree buckets run on side streams when there are
+// several of them.
+fpn_status plan_launch(fpn_plan_s* p, hipStream_t stream, bool timing) {
+  fpn_ctx ctx = p->ctx;
+  const fpn_solve_opts* opts = &p->opts;
+  const fpn_drive* drive = &p->drive;
+  const int64_t n = p->n;
+  const int Ns = opts->samples_per_period;
+  auto tm = [&](int which, hipStream_t s, auto&& f) -> fpn_status {
+    if (!timing) return f();
+    return timed(ctx, which, s, f);
+  };
+  fpn::launch_fill_i32(p->queue.p, int(p->groups.size()), 0, stream);
+  FPN_HIP(hipGetLastError());
+  if (fpn_status s = tm(0, stream, [&]() -> fpn_status {
+        fpn::launch_instance_prep(n, p->batch.D, p->batch.Ms, p->batch.K, p->batch.alpha, p->batch.temp,
+                                  p->batch.easy_axis, p->batch.offset, p->ip.p, p->status, stream);
         FPN_HIP(hipGetLastError());
         return FPN_OK;
       }))
     return s;
+  const bool fork = !p->side.empty();
+  if (fork) {
+    FPN_HIP(hipEventRecord(p->ev[0], stream));
+    for (hipStream_t s : p->side) FPN_HIP(hipStreamWaitEvent(s, p->ev[0], 0));
+  }
   double3 d0;
   d0.x = drive->amp[0] * std::cos(drive->phase[0]);
   d0.y = drive->amp[1] * std::cos(drive->phase[1]);
   d0.z = drive->amp[2] * std::cos(drive->phase[2]);
-  int64_t start = 0;
-  for (auto& g : groups) {
-    const fpn::DevTables& t = *tabs[g.first];
-    const int cnt = int(g.second.size());
-    const int32_t* idx = ctx->idx.p + start;
-    if (fpn_status s = timed(ctx, 1, stream, [&]() -> fpn_status {
-          fpn::launch_stationary(t, idx, cnt, ctx->ip.p, nullptr, d0, ctx->c0.p, np_max, ctx->wsinv.p, status,
-                                 stream);
+  for (size_t gi = 0; gi < p->groups.size(); ++gi) {
+    const auto& g = p->groups[gi];
+    hipStream_t gs = fork ? p->side[gi % p->side.size()] : stream;
+    const int32_t* idx = p->idx.p + g.start;
+    if (fpn_status s = tm(1, gs, [&]() -> fpn_status {
+          fpn::launch_stationary(*g.t, idx, g.cnt, p->ip.p, nullptr, d0, p->c0.p, p->np_max, p->wsinv.p + g.inv_off,
+                                 p->status, gs);
           FPN_HIP(hipGetLastError());
+          if (p->tangent) {
+            fpn::launch_stationary_tangent(*g.t, idx, g.cnt, p->ip.p, d0, p->c0.p, p->np_max,
+                                           p->wsinv.p + g.inv_off, p->c0t.p, p->status, gs);
+            FPN_HIP(hipGetLastError());
+          }
           return FPN_OK;
         }))
       return s;
     fpn::StepLaunch sl;
-    sl.ip = ctx->ip.p;
+    sl.ip = p->ip.p;
     sl.inst_idx = idx;
-    sl.n_inst = cnt;
-    sl.c0 = ctx->c0.p;
-    sl.c_stride = np_max;
+    sl.n_inst = g.cnt;
+    sl.c0 = p->c0.p;
+    sl.c_stride = p->np_max;
     for (int c = 0; c < 3; ++c) {
       sl.amp[c] = drive->amp[c];
       sl.freq[c] = drive->freq[c];
@@ -414,43 +574,210 @@ fpn_status fpn_solve(fpn_ctx ctx, const fpn_drive* drive, const fpn_solve_opts* 
     sl.period = drive->period;
     sl.settle = opts->settle_periods;
     sl.Ns = Ns;
-    sl.r_fixed = r;
+    sl.r_fixed = opts->substeps;
     sl.r_max = 64;
     sl.tol = float(opts->tol > 0.0 ? opts->tol : 5e-6);
-    sl.msamp = msamp;
-    sl.status = status;
-    sl.steps_out = ctx->steps.p;
-    if (fpn_status s = timed(ctx, 2, stream, [&]() -> fpn_status {
-          FPN_HIP(fpn::launch_stepper(g.first, sl, t, ctx->wide_ws.p, stream));
+    sl.msamp = p->msamp;
+    sl.status = p->status;
+    sl.steps_out = p->steps.p;
+    sl.queue = p->queue.p + gi;
+    sl.grid = g.grid;
+    if (p->tangent) {
+      sl.c0t = p->c0t.p;
+      sl.mtan = p->mtan;
+      sl.tws = p->tws.p + g.tws_off;
+    }
+    if (fpn_status s = tm(2, gs, [&]() -> fpn_status {
+          FPN_HIP(fpn::launch_stepper(g.L, sl, *g.t, p->wide_ws.p ? p->wide_ws.p + g.ws_off : nullptr, gs));
           return FPN_OK;
         }))
       return s;
-    start += cnt;
   }
-  if (want_h) {
+  if (fork) {
+    for (size_t k = 0; k < p->side.size(); ++k) {
+      FPN_HIP(hipEventRecord(p->ev[1 + k], p->side[k]));
+      FPN_HIP(hipStreamWaitEvent(stream, p->ev[1 + k], 0));
+    }
+  }
+  if (p->harm_out) {
     const int nch = (opts->flags & FPN_HARM_Z) ? 3 : 2;
-    if (fpn_status s = timed(ctx, 3, stream, [&]() -> fpn_status {
-          fpn::launch_harmonics(msamp, Ns, Kh, nch, drive->period, ctx->twiddle.p, harm_out, status, n, stream);
+    if (fpn_status s = tm(3, stream, [&]() -> fpn_status {
+          fpn::launch_harmonics(p->msamp, Ns, opts->n_harm, nch, drive->period, ctx->twiddle.p, p->harm_out,
+                                p->status, n, stream);
           FPN_HIP(hipGetLastError());
           return FPN_OK;
         }))
       return s;
   }
+  if (p->tangent) {
+    const int nch = (opts->flags & FPN_HARM_Z) ? 3 : 2;
+    fpn::launch_harmonics(p->mtan, Ns, opts->n_harm, nch, drive->period, ctx->twiddle.p, p->dharm, p->status,
+                          n * fpn::kNTan, stream, fpn::kNTan);
+    FPN_HIP(hipGetLastError());
+  }
   return FPN_OK;
+}
+
+fpn_status check_outputs(const fpn_solve_opts* opts, float* m_out, float* harm_out, int32_t* status, int64_t n) {
+  const bool want_m = opts->flags & FPN_OUT_M, want_h = opts->flags & FPN_OUT_HARM;
+  if (want_m && !m_out) return fail(FPN_E_ARG, "FPN_OUT_M set but m_out is NULL");
+  if (want_h && !harm_out) return fail(FPN_E_ARG, "FPN_OUT_HARM set but harm_out is NULL");
+  if (!status) return fail(FPN_E_ARG, "status is NULL");
+  if (n > (int64_t(1) << 31) - 1) return fail(FPN_E_ARG, "n too large");
+  return FPN_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+fpn_status fpn_solve(fpn_ctx ctx, const fpn_drive* drive, const fpn_solve_opts* opts, const fpn_batch* batch,
+                     int64_t n, float* m_out, float* harm_out, int32_t* status, void* stream_) {
+  if (!ctx) return fail(FPN_E_ARG, "ctx is NULL");
+  if (n < 0) return fail(FPN_E_ARG, "n < 0");
+  if (fpn_status s = validate_opts(drive, opts)) return s;
+  if (n == 0) return FPN_OK;  // nothing to do (empty outputs may be NULL)
+  if (fpn_status s = check_outputs(opts, m_out, harm_out, status, n)) return s;
+  if (fpn_status s = validate_batch(batch, n)) return s;
+  std::lock_guard<std::mutex> lk(ctx->mu);
+  hipStream_t stream = reinterpret_cast<hipStream_t>(stream_);
+  FPN_HIP(hipSetDevice(ctx->device));
+  if (!ctx->solve_plan) ctx->solve_plan = new fpn_plan_s();
+  fpn_plan_s* p = ctx->solve_plan;
+  if (fpn_status s = plan_build(p, ctx, drive, opts, batch, n, nullptr, m_out, harm_out, status, stream)) return s;
+  return plan_launch(p, stream, ctx->timing);
 }
 
 fpn_status fpn_last_steps(fpn_ctx ctx, int64_t* total_steps) {
   if (!ctx || !total_steps) return fail(FPN_E_ARG, "NULL argument");
   std::lock_guard<std::mutex> lk(ctx->mu);
   FPN_HIP(hipSetDevice(ctx->device));
-  std::vector<int32_t> h(ctx->steps_n);
-  if (ctx->steps_n > 0) {
+  const fpn_plan_s* p = ctx->solve_plan;
+  const int64_t n = p ? p->n : 0;
+  std::vector<int32_t> h(n);
+  if (n > 0) {
     FPN_HIP(hipDeviceSynchronize());
-    FPN_HIP(hipMemcpy(h.data(), ctx->steps.p, h.size() * sizeof(int32_t), hipMemcpyDeviceToHost));
+    FPN_HIP(hipMemcpy(h.data(), p->steps.p, h.size() * sizeof(int32_t), hipMemcpyDeviceToHost));
   }
   int64_t sum = 0;
   for (int32_t v : h) sum += v;
   *total_steps = sum;
+  return FPN_OK;
+}
+
+fpn_status fpn_solve_tangent(fpn_ctx ctx, const fpn_drive* drive, const fpn_solve_opts* opts, const fpn_batch* batch,
+                             int64_t n, float* m_out, float* harm_out, float* dm_out, float* dharm_out,
+                             int32_t* status, void* stream_) {
+  if (!ctx) return fail(FPN_E_ARG, "ctx is NULL");
+  if (n < 0) return fail(FPN_E_ARG, "n < 0");
+  if (fpn_status s = validate_opts(drive, opts)) return s;
+  if (n == 0) return FPN_OK;
+  if (fpn_status s = check_outputs(opts, m_out, harm_out, status, n)) return s;
+  if ((opts->flags & FPN_OUT_M) && !dm_out) return fail(FPN_E_ARG, "FPN_OUT_M set but dm_out is NULL");
+  if ((opts->flags & FPN_OUT_HARM) && !dharm_out) return fail(FPN_E_ARG, "FPN_OUT_HARM set but dharm_out is NULL");
+  if (fpn_status s = validate_batch(batch, n)) return s;
+  std::lock_guard<std::mutex> lk(ctx->mu);
+  hipStream_t stream = reinterpret_cast<hipStream_t>(stream_);
+  FPN_HIP(hipSetDevice(ctx->device));
+  if (!ctx->tangent_plan) ctx->tangent_plan = new fpn_plan_s();
+  fpn_plan_s* p = ctx->tangent_plan;
+  if (fpn_status s = plan_build(p, ctx, drive, opts, batch, n, nullptr, m_out, harm_out, status, stream, true,
+                                (opts->flags & FPN_OUT_M) ? dm_out : nullptr,
+                                (opts->flags & FPN_OUT_HARM) ? dharm_out : nullptr))
+    return s;
+  return plan_launch(p, stream, ctx->timing);
+}
+
+fpn_status fpn_adjoint(fpn_ctx ctx, const fpn_drive* drive, const fpn_solve_opts* opts, const fpn_batch* batch,
+                       int64_t n, const float* dL_dharm, double* grad_out, float* harm_out, int32_t* status,
+                       void* stream_) {
+  if (!ctx) return fail(FPN_E_ARG, "ctx is NULL");
+  if (n < 0) return fail(FPN_E_ARG, "n < 0");
+  if (fpn_status s = validate_opts(drive, opts)) return s;
+  if (n == 0) return FPN_OK;
+  if (!dL_dharm || !grad_out || !status) return fail(FPN_E_ARG, "dL_dharm, grad_out and status are required");
+  if (fpn_status s = validate_batch(batch, n)) return s;
+  fpn_solve_opts o = *opts;
+  o.flags = (opts->flags & FPN_HARM_Z) | (harm_out ? FPN_OUT_HARM : 0);
+  std::lock_guard<std::mutex> lk(ctx->mu);
+  hipStream_t stream = reinterpret_cast<hipStream_t>(stream_);
+  FPN_HIP(hipSetDevice(ctx->device));
+  if (!ctx->tangent_plan) ctx->tangent_plan = new fpn_plan_s();
+  fpn_plan_s* p = ctx->tangent_plan;
+  if (fpn_status s = plan_build(p, ctx, drive, &o, batch, n, nullptr, nullptr, harm_out, status, stream, true)) return s;
+  if (fpn_status s = plan_launch(p, stream, ctx->timing)) return s;
+  const int nch = (opts->flags & FPN_HARM_Z) ? 3 : 2;
+  fpn::launch_contract(dL_dharm, p->dharm, nch * (opts->n_harm + 1) * 2, grad_out, status, n, stream);
+  FPN_HIP(hipGetLastError());
+  return FPN_OK;
+}
+
+fpn_status fpn_plan_create(fpn_ctx ctx, const fpn_drive* drive, const fpn_solve_opts* opts, const fpn_batch* batch,
+                           int64_t n, const float* cost_hint, float* m_out, float* harm_out, int32_t* status,
+                           fpn_plan* out) {
+  if (!ctx || !out) return fail(FPN_E_ARG, "NULL argument");
+  *out = nullptr;
+  if (n < 1) return fail(FPN_E_ARG, "a plan needs n >= 1");
+  if (fpn_status s = validate_opts(drive, opts)) return s;
+  if (fpn_status s = check_outputs(opts, m_out, harm_out, status, n)) return s;
+  if (fpn_status s = validate_batch(batch, n)) return s;
+  std::lock_guard<std::mutex> lk(ctx->mu);
+  FPN_HIP(hipSetDevice(ctx->device));
+  auto* p = new fpn_plan_s();
+  if (fpn_status s = plan_build(p, ctx, drive, opts, batch, n, cost_hint, m_out, harm_out, status, nullptr)) {
+    plan_release(p);
+    delete p;
+    return s;
+  }
+  FPN_HIP(hipDeviceSynchronize());
+  *out = p;
+  return FPN_OK;
+}
+
+fpn_status fpn_plan_launch(fpn_plan p, void* stream) {
+  if (!p) return fail(FPN_E_ARG, "plan is NULL");
+  std::lock_guard<std::mutex> lk(p->ctx->mu);
+  FPN_HIP(hipSetDevice(p->ctx->device));
+  return plan_launch(p, reinterpret_cast<hipStream_t>(stream), p->ctx->timing);
+}
+
+fpn_status fpn_plan_graph_launch(fpn_plan p, void* stream) {
+  if (!p) return fail(FPN_E_ARG, "plan is NULL");
+  std::lock_guard<std::mutex> lk(p->ctx->mu);
+  FPN_HIP(hipSetDevice(p->ctx->device));
+  if (!p->exec) {
+    if (!p->cap) FPN_HIP(hipStreamCreateWithFlags(&p->cap, hipStreamNonBlocking));
+    FPN_HIP(hipStreamBeginCapture(p->cap, hipStreamCaptureModeRelaxed));
+    fpn_status s = plan_launch(p, p->cap, false);
+    hipGraph_t g = nullptr;
+    hipError_t e = hipStreamEndCapture(p->cap, &g);
+    if (s != FPN_OK) {
+      if (g) (void)hipGraphDestroy(g);
+      return s;
+    }
+    FPN_HIP(e);
+    p->graph = g;
+    FPN_HIP(hipGraphInstantiate(&p->exec, p->graph, nullptr, nullptr, 0));
+  }
+  FPN_HIP(hipGraphLaunch(p->exec, reinterpret_cast<hipStream_t>(stream)));
+  return FPN_OK;
+}
+
+fpn_status fpn_plan_steps(fpn_plan p, int32_t* steps_out) {
+  if (!p || !steps_out) return fail(FPN_E_ARG, "NULL argument");
+  std::lock_guard<std::mutex> lk(p->ctx->mu);
+  FPN_HIP(hipSetDevice(p->ctx->device));
+  FPN_HIP(hipDeviceSynchronize());
+  FPN_HIP(hipMemcpy(steps_out, p->steps.p, p->n * sizeof(int32_t), hipMemcpyDeviceToHost));
+  return FPN_OK;
+}
+
+fpn_status fpn_plan_destroy(fpn_plan p) {
+  if (!p) return fail(FPN_E_ARG, "plan is NULL");
+  (void)hipSetDevice(p->ctx->device);
+  (void)hipDeviceSynchronize();
+  plan_release(p);
+  delete p;
   return FPN_OK;
 }
 

@@ -51,6 +51,24 @@ struct TableSet {
 
 }  // namespace fpn_internal
 
+struct fpn_plan_s;
+
+namespace fpn_internal {
+// One |m|-degree bucket of a solve: instances [start, start + cnt) of the plan's order.
+struct PlanGroup {
+  int L = 0;
+  int64_t start = 0;
+  int cnt = 0;
+  const fpn::DevTables* t = nullptr;
+  int grid = 0;          // persistent workgroups of the stepper
+  int64_t ws_off = 0;    // floats into the wide-layout workspace
+  int64_t inv_off = 0;   // doubles into the stationary workspace
+  int64_t tws_off = 0;   // floats into the tangent workspace
+  double cost = 0.0;     // predicted work (for the launch order)
+};
+void plan_release(fpn_plan_s* p);
+}  // namespace fpn_internal
+
 struct fpn_ctx_s {
   int device = 0;
   std::mutex mu;
@@ -74,6 +92,42 @@ struct fpn_ctx_s {
   std::vector<std::pair<int, std::pair<hipEvent_t, hipEvent_t>>> events;
   double ms[4] = {0, 0, 0, 0};
   int64_t launches[4] = {0, 0, 0, 0};
+  fpn_plan_s* solve_plan = nullptr;   // reused by fpn_solve
+  fpn_plan_s* tangent_plan = nullptr; // reused by fpn_solve_tangent and fpn_adjoint
+  std::map<int, std::pair<int, int>> occupancy;  // L -> (waves per workgroup, workgroups per CU)
+  int cus = 0;
+};
+
+// A solve bound to its inputs and outputs: the degree buckets in launch order, the instance
+// order within them, and every workspace the launch needs.
+struct fpn_plan_s {
+  fpn_ctx ctx = nullptr;
+  fpn_drive drive{};
+  fpn_solve_opts opts{};
+  fpn_batch batch{};          // device pointers (the host L array is not kept)
+  int64_t n = 0;
+  float* m_out = nullptr;
+  float* harm_out = nullptr;
+  int32_t* status = nullptr;
+  float* msamp = nullptr;     // m_out or the plan's own sample buffer
+  int64_t np_max = 0;
+  std::vector<fpn_internal::PlanGroup> groups;
+  std::vector<int32_t> order;  // host copy of the instance order
+  fpn_internal::DevBuf<fpn::InstParams> ip;
+  fpn_internal::DevBuf<double> c0, wsinv;
+  fpn_internal::DevBuf<float> own_m, wide_ws;
+  fpn_internal::DevBuf<int32_t> idx, steps, queue;
+  std::vector<hipStream_t> side;
+  std::vector<hipEvent_t> ev;   // [0] fork, [1 + i] join of side stream i
+  hipStream_t cap = nullptr;    // capture stream for the graph
+  // tangents (parameter sensitivities), L <= 16
+  bool tangent = false;
+  float* mtan = nullptr;        // [n][kNTan][3][Ns]: caller's dm_out or own_mt
+  float* dharm = nullptr;       // [n][kNTan][ch][K_h+1][2]: caller's or own_dh
+  fpn_internal::DevBuf<double> c0t;
+  fpn_internal::DevBuf<float> own_mt, own_dh, tws;
+  hipGraph_t graph = nullptr;
+  hipGraphExec_t exec = nullptr;
 };
 
 struct fpn_mlp_s {

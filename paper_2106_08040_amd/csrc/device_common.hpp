@@ -1,6 +1,7 @@
 // Shared device-side definitions of the fpn kernels.
 #pragma once
 #include <hip/hip_runtime.h>
+#include <cmath>
 #include <cstdint>
 
 namespace fpn {
@@ -10,7 +11,51 @@ struct InstParams {
   double inv2tau, sigma, beta_T, alpha;  // particle scalars
   double R[9];                           // easy-axis frame, row-major, R e_z = n
   double off[3];                         // static offset mu0*H [T], lab frame
+  double D, sigK;                        // diameter [m] and d sigma / d K = V_C / (k_B T) (tangents)
 };
+
+// Tangent directions (parameter derivatives) carried by the sensitivity solves.
+enum : int { kNTan = 5 };  // D, K, alpha, easy-axis polar angle, easy-axis azimuth
+
+// Lab-frame rotation axis whose infinitesimal rotation moves the easy axis n = R e_z along the
+// polar (prm 3: e_phi) or azimuthal (prm 4: e_z) direction.  A rotation of n by e is the same as
+// rotating the field by -e and the result by +e, so the angle derivatives need no frame derivative.
+template <typename T>
+__host__ __device__ inline void tan_axis(int prm, const double* R, T e[3]) {
+  if (prm == 4) {
+    e[0] = 0; e[1] = 0; e[2] = 1;
+    return;
+  }
+  const double ph = atan2(R[5], R[2]);
+  e[0] = T(-sin(ph)); e[1] = T(cos(ph)); e[2] = 0;
+}
+
+// d/dp of kind multiplier `kind` (kind numbering of structure.hpp; multipliers as in kind_mult)
+// for the field h (easy frame) of the same time: prm 0..2 differentiate the particle scalars, prm 3, 4
+// rotate the field by h x e' with e' = R^T e.
+template <typename T>
+__host__ __device__ inline T tan_mult_t(int prm, int kind, T inv2tau, T sigma, T alpha, T beta, T D, T sigK,
+                                        const T h[3], const T ep[3]) {
+  const T s = inv2tau;
+  const T ia = T(1) / alpha;
+  const T m[9] = {s, s * sigma, s * T(2) * sigma * ia, s * beta * h[2], s * beta * h[2] * ia,
+                  s * beta * h[0], s * beta * h[1], s * beta * h[0] * ia, s * beta * h[1] * ia};
+  const bool over_alpha = (kind == 2 || kind == 4 || kind == 7 || kind == 8);
+  switch (prm) {
+    case 0: return kind == 0 ? T(-3) * m[0] / D : T(0);
+    case 1: return kind == 1 ? s * sigK : (kind == 2 ? s * T(2) * sigK * ia : T(0));
+    case 2: {
+      const T g = ia - T(2) * alpha / (T(1) + alpha * alpha);  // d ln(1/2tau) / d alpha
+      return m[kind] * (over_alpha ? g - ia : g);
+    }
+    default: {
+      if (kind < 3) return T(0);
+      const T d[3] = {h[1] * ep[2] - h[2] * ep[1], h[2] * ep[0] - h[0] * ep[2], h[0] * ep[1] - h[1] * ep[0]};
+      const T c = (kind == 3 || kind == 4) ? d[2] : ((kind == 5 || kind == 7) ? d[0] : d[1]);
+      return s * beta * c * (over_alpha ? ia : T(1));
+    }
+  }
+}
 
 // Device copies of the operator tables of one degree L (see structure.hpp).
 struct DevTables {

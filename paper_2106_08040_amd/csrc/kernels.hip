@@ -56,6 +56,8 @@ __global__ void instance_prep_kernel(int64_t n, const double* D, const double* M
   p.R[3] = u1; p.R[4] = v1; p.R[5] = z1;
   p.R[6] = u2; p.R[7] = v2; p.R[8] = z2;
   for (int c = 0; c < 3; ++c) p.off[c] = off[c];
+  p.D = ok ? d : 1e-8;
+  p.sigK = ok ? kPi * d * d * d / 6.0 / (kBoltzmann * T) : 0.0;
   ip[i] = p;
   status[i] = ok ? 0 : 1;
 }
@@ -266,18 +268,126 @@ stationary_kernel(DevTables t, const int32_t* inst_idx, int n_inst, const InstPa
   if (tid == 0 && !s_ok) status[inst] = 3;
 }
 
+// ------------------------------------------ a8: stationary-state tangents ---
+// d c0 / d p for the five instance parameters p (D, K, alpha, easy-axis polar and azimuth angle):
+// differentiating A'(p) c0(p) = c00 e_0 (row 0 of A' is the fixed normalisation) gives
+//   A' c0_p = -(dA/dp) c0  with row 0 (and the padding row) of the right-hand side zero,
+// solved with the block inverses the stationary kernel left in `wsinv` (same instance slot).
+// dA/dp is the operator with the parameter derivatives of the kind multipliers (tan_mult).
+__global__ void __launch_bounds__(kStatThreads)
+stationary_tangent_kernel(DevTables t, const int32_t* inst_idx, int n_inst, const InstParams* ip, double3 drive0,
+                          const double* c0, int64_t c_stride, const double* wsinv, double* ct, int32_t* status) {
+  const int w = blockIdx.x;
+  if (w >= n_inst) return;
+  const int inst = inst_idx[w];
+  const int tid = threadIdx.x;
+  const int Np = t.Np;
+  extern __shared__ double vec[];  // x [Np], tv [kMaxBlk]
+  double* x = vec;
+  __shared__ double tv[kMaxBlk];
+  __shared__ double dm[kNTan][9];
+  __shared__ double mult[9];
+  double* out = ct + int64_t(inst) * kNTan * c_stride;
+  if (status[inst] != 0) {
+    for (int e = tid; e < kNTan * Np; e += blockDim.x) out[(e / Np) * c_stride + e % Np] = __builtin_nan("");
+    return;
+  }
+  const InstParams P = ip[inst];
+  if (tid < kNTan * 9 + 9) {
+    const double B[3] = {drive0.x + P.off[0], drive0.y + P.off[1], drive0.z + P.off[2]};
+    double h[3];
+    for (int c = 0; c < 3; ++c) h[c] = P.R[0 * 3 + c] * B[0] + P.R[1 * 3 + c] * B[1] + P.R[2 * 3 + c] * B[2];
+    if (tid < kNTan * 9) {
+      const int prm = tid / 9;
+      double e[3], ep[3];
+      tan_axis(prm, P.R, e);
+      for (int c = 0; c < 3; ++c) ep[c] = P.R[0 * 3 + c] * e[0] + P.R[1 * 3 + c] * e[1] + P.R[2 * 3 + c] * e[2];
+      dm[prm][tid % 9] = tan_mult_t<double>(prm, tid % 9, P.inv2tau, P.sigma, P.alpha, P.beta_T, P.D, P.sigK, h, ep);
+    } else {
+      const double ia = 1.0 / P.alpha, b = P.beta_T, s2 = P.inv2tau;
+      const double m9[9] = {s2, s2 * P.sigma, s2 * 2.0 * P.sigma * ia, s2 * b * h[2], s2 * b * h[2] * ia,
+                            s2 * b * h[0], s2 * b * h[1], s2 * b * h[0] * ia, s2 * b * h[1] * ia};
+      mult[tid - kNTan * 9] = m9[tid - kNTan * 9];
+    }
+  }
+  __syncthreads();
+  const double* cin = c0 + int64_t(inst) * c_stride;
+  const int pad = (t.n0 != t.L + 1) ? t.n0 - 1 : -1;
+  const double* ws = wsinv + int64_t(w) * t.inv_doubles;
+  for (int prm = 0; prm < kNTan; ++prm) {
+    // forward: g_k = Sinv_k (b_k - B_k g_{k-1}), b = -(dA/dp) c0 (rows 0 and pad: 0)
+    int64_t invoff = 0;
+    for (int k = 0; k <= t.L; ++k) {
+      const int off = t.boff[k], n = t.bn[k];
+      for (int i = tid; i < n; i += blockDim.x) {
+        const int row = off + i;
+        double v = 0.0;
+        if (row != 0 && row != pad) {
+          for (int q = t.seg[4 * row]; q < t.seg[4 * row + 3]; ++q) {
+            const uint32_t ck = t.colkind[q];
+            v -= dm[prm][ck >> 16] * t.val64[q] * cin[int(ck & 0xffff)];
+          }
+          if (k > 0)
+            for (int q = t.seg[4 * row]; q < t.seg[4 * row + 1]; ++q) {
+              const uint32_t ck = t.colkind[q];
+              const int kind = ck >> 16;
+              v -= mult[kind] * t.val64[q] * x[int(ck & 0xffff)];
+            }
+        }
+        tv[i] = v;
+      }
+      __syncthreads();
+      for (int i = tid; i < n; i += blockDim.x) {
+        double acc = 0.0;
+        for (int j = 0; j < n; ++j) acc += ws[invoff + int64_t(i) * n + j] * tv[j];
+        x[off + i] = acc;
+      }
+      __syncthreads();
+      invoff += int64_t(n) * n;
+    }
+    // backward: x_k = g_k - Sinv_k C_k x_{k+1}
+    for (int k = t.L - 1; k >= 0; --k) {
+      const int off = t.boff[k], n = t.bn[k];
+      invoff -= int64_t(t.bn[k + 1]) * t.bn[k + 1];
+      const double* Sk = ws + invoff - int64_t(n) * n;
+      for (int i = tid; i < n; i += blockDim.x) {
+        const int row = off + i;
+        double v = 0.0;
+        if (row != 0 && row != pad)
+          for (int q = t.seg[4 * row + 2]; q < t.seg[4 * row + 3]; ++q) {
+            const uint32_t ck = t.colkind[q];
+            v += mult[ck >> 16] * t.val64[q] * x[int(ck & 0xffff)];
+          }
+        tv[i] = v;
+      }
+      __syncthreads();
+      double nv[2] = {0.0, 0.0};
+      for (int i = tid, r = 0; i < n; i += blockDim.x, ++r) {
+        double acc = 0.0;
+        for (int j = 0; j < n; ++j) acc += Sk[int64_t(i) * n + j] * tv[j];
+        nv[r] = x[off + i] - acc;
+      }
+      __syncthreads();
+      for (int i = tid, r = 0; i < n; i += blockDim.x, ++r) x[off + i] = nv[r];
+      __syncthreads();
+    }
+    for (int p = tid; p < Np; p += blockDim.x) out[int64_t(prm) * c_stride + p] = x[p];
+    __syncthreads();
+  }
+}
+
 // -------------------------------------------------------- a6: harmonics ---
 // Phi_k = (2 pi i k / T) (1/N_s) sum_j m(t_j) e^{-2 pi i j k / N_s}, FP64 accumulation.
 // One workgroup per instance; the twiddle index (j k) mod N_s is carried exactly in int32.
 __global__ void harmonics_kernel(const float* msamp, int Ns, int n_harm, int nch, double period,
-                                 const double2* tw, float* harm, const int32_t* status, int64_t n) {
+                                 const double2* tw, float* harm, const int32_t* status, int64_t n, int st_div) {
   const int64_t inst = blockIdx.x;
   if (inst >= n) return;
   extern __shared__ float ml[];  // [3][Ns]
   const float* src = msamp + inst * 3 * Ns;
   for (int e = threadIdx.x; e < 3 * Ns; e += blockDim.x) ml[e] = src[e];
   __syncthreads();
-  const bool bad = status[inst] != 0;
+  const bool bad = status[inst / st_div] != 0;  // st_div > 1: several sample sets per instance
   const int nk = n_harm + 1;
   for (int e = threadIdx.x; e < nch * nk; e += blockDim.x) {
     const int c = e / nk, k = e % nk;
@@ -303,7 +413,17 @@ __global__ void harmonics_kernel(const float* msamp, int Ns, int n_harm, int nch
   }
 }
 
+__global__ void fill_i32_kernel(int32_t* p, int n, int32_t v) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) p[i] = v;
+}
+
 // ------------------------------------------------------------- launchers ---
+
+void launch_fill_i32(int32_t* p, int n, int32_t v, hipStream_t stream) {
+  if (n <= 0) return;
+  hipLaunchKernelGGL(fill_i32_kernel, dim3((n + 255) / 256), dim3(256), 0, stream, p, n, v);
+}
 
 void launch_instance_prep(int64_t n, const double* D, const double* Ms, const double* K, const double* alpha,
                           const double* temp, const double* easy, const double* offset, InstParams* ip,
@@ -322,11 +442,48 @@ void launch_stationary(const DevTables& t, const int32_t* idx, int n_inst, const
                      field_lab, drive0, c_out, c_stride, wsinv, status);
 }
 
+void launch_stationary_tangent(const DevTables& t, const int32_t* idx, int n_inst, const InstParams* ip,
+                               double3 drive0, const double* c0, int64_t c_stride, const double* wsinv, double* ct,
+                               int32_t* status, hipStream_t stream) {
+  const size_t shm = size_t(t.Np) * sizeof(double);
+  hipLaunchKernelGGL(stationary_tangent_kernel, dim3(n_inst), dim3(kStatThreads), shm, stream, t, idx, n_inst, ip,
+                     drive0, c0, c_stride, wsinv, ct, status);
+}
+
 void launch_harmonics(const float* msamp, int Ns, int n_harm, int nch, double period, const double2* tw,
-                      float* harm, const int32_t* status, int64_t n, hipStream_t stream) {
+                      float* harm, const int32_t* status, int64_t n, hipStream_t stream, int st_div) {
   const size_t shm = size_t(3) * Ns * sizeof(float);
   hipLaunchKernelGGL(harmonics_kernel, dim3(n), dim3(256), shm, stream, msamp, Ns, n_harm, nch, period, tw, harm,
-                     status, n);
+                     status, n, st_div);
+}
+
+// grad[i][p] = sum over channels, bins and (re, im) of dL/dPhi[i] * dPhi/dp[i][p], FP64 accumulation;
+// one workgroup per instance.  NaN for instances with a non-zero status.
+__global__ void contract_kernel(const float* dL, const float* dharm, int per, double* grad, const int32_t* status,
+                                int64_t n) {
+  const int64_t i = blockIdx.x;
+  if (i >= n) return;
+  __shared__ double red[kNTan][256];
+  double acc[kNTan] = {0, 0, 0, 0, 0};
+  const float* g = dL + i * per;
+  for (int e = threadIdx.x; e < per; e += blockDim.x) {
+    const double w = g[e];
+    for (int p = 0; p < kNTan; ++p) acc[p] += w * double(dharm[(i * kNTan + p) * per + e]);
+  }
+  for (int p = 0; p < kNTan; ++p) red[p][threadIdx.x] = acc[p];
+  __syncthreads();
+  for (int o = blockDim.x / 2; o > 0; o >>= 1) {
+    if (int(threadIdx.x) < o)
+      for (int p = 0; p < kNTan; ++p) red[p][threadIdx.x] += red[p][threadIdx.x + o];
+    __syncthreads();
+  }
+  if (threadIdx.x < kNTan) grad[i * kNTan + threadIdx.x] = status[i] != 0 ? __builtin_nan("") : red[threadIdx.x][0];
+}
+
+void launch_contract(const float* dL, const float* dharm, int per, double* grad, const int32_t* status, int64_t n,
+                     hipStream_t stream) {
+  if (n <= 0) return;
+  hipLaunchKernelGGL(contract_kernel, dim3(n), dim3(256), 0, stream, dL, dharm, per, grad, status, n);
 }
 
 }  // namespace fpn

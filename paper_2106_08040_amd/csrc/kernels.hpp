@@ -23,6 +23,11 @@ struct StepLaunch {
   float* msamp;              // [n][3][Ns]
   int32_t* status;
   int32_t* steps_out;        // [n] steps taken, may be null
+  int32_t* queue;            // work counter, zero when the launch starts
+  int grid;                  // workgroups to launch (0: one wavefront per instance)
+  const double* c0t = nullptr;  // tangents (L <= 16): initial states [n][kNTan][c_stride]
+  float* mtan = nullptr;        // tangents: samples [n][kNTan][3][Ns]; null for a plain solve
+  float* tws = nullptr;         // tangents: workspace, stepper_tan_ws_floats(L) per resident wavefront
 };
 
 template <int L>
@@ -32,7 +37,14 @@ template <int L>
 hipError_t launch_stepper_wide_L(const StepLaunch& s, const DevTables& t, float* ws, hipStream_t stream);
 template <int L>
 int64_t stepper_wide_ws_floats_L();
-int64_t stepper_ws_floats(int L);  // 0 for the register layout (L <= 16)
+int64_t stepper_ws_floats(int L);  // 0 for the register layout (L <= 16); per resident wavefront
+template <int L>
+hipError_t stepper_occupancy_L(const DevTables& t, bool tangents, int* waves_per_block, int* blocks_per_cu);
+template <int L>
+hipError_t stepper_wide_occupancy_L(int* waves_per_block, int* blocks_per_cu);
+// wavefronts per workgroup and resident workgroups per CU of the stepper for degree L
+hipError_t stepper_occupancy(int L, const DevTables& t, bool tangents, int* waves_per_block, int* blocks_per_cu);
+inline int64_t stepper_tan_ws_floats(int L) { return int64_t(8 * kNTan) * (((L + 1) * (L + 1) + 1 + 3) & ~3); }
 
 void launch_instance_prep(int64_t n, const double* D, const double* Ms, const double* K, const double* alpha,
                           const double* temp, const double* easy, const double* offset, InstParams* ip,
@@ -41,7 +53,13 @@ void launch_stationary(const DevTables& t, const int32_t* idx, int n_inst, const
                        const double* field_lab, double3 drive0, double* c_out, int64_t c_stride, double* wsinv,
                        int32_t* status, hipStream_t stream);
 hipError_t launch_stepper(int L, const StepLaunch& s, const DevTables& t, float* ws, hipStream_t stream);
+void launch_stationary_tangent(const DevTables& t, const int32_t* idx, int n_inst, const InstParams* ip,
+                               double3 drive0, const double* c0, int64_t c_stride, const double* wsinv, double* ct,
+                               int32_t* status, hipStream_t stream);
+void launch_fill_i32(int32_t* p, int n, int32_t v, hipStream_t stream);
 void launch_harmonics(const float* msamp, int Ns, int n_harm, int nch, double period, const double2* tw,
-                      float* harm, const int32_t* status, int64_t n, hipStream_t stream);
+                      float* harm, const int32_t* status, int64_t n, hipStream_t stream, int st_div = 1);
+void launch_contract(const float* dL, const float* dharm, int per, double* grad, const int32_t* status, int64_t n,
+                     hipStream_t stream);
 
 }  // namespace fpn

@@ -12,6 +12,7 @@
 // h, h + 2, h + 4, ... (a[q] = S[i][h + 2q]).
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
 #include <cstdint>
 
 #include "device_common.hpp"
@@ -37,17 +38,24 @@ __device__ __forceinline__ auto& blk(Store<L, L>& s) {
   return static_cast<Store<L, K>&>(s).a.v;
 }
 
-// Per-wavefront LDS.  The factorisation scratch (X, Ub) and the stage vectors share `u`.
-template <int L>
+// Per-wavefront LDS.  The factorisation scratch (X, Ub) and the stage vectors share `u`.  With
+// tangents (NT > 0) three more vectors hold the step-start state, the tangent stage argument and the
+// current primal stage increment, and three multiplier tables hold the parameter derivatives.
+template <int L, int NT>
 struct WaveLds {
   static constexpr int NpA = Geo<L>::NpA;
   static constexpr int kUnion = (2048 > 9 * NpA) ? 2048 : 9 * NpA;
+  static constexpr int kTanV = NT > 0 ? 3 * NpA : 4;
   float u[kUnion];
   float T[32];     // block right-hand side [parity][16]
   float col[64];   // pivot columns [parity][32]
   float row[64];   // pivot rows [r][parity][16]
   float mk[16];    // -h g * multiplier(t_n) per kind
   float ms[16];    // multiplier at the current stage time per kind
+  float tv[kTanV];                     // y0 | xt | kc
+  float dmi[NT > 0 ? NT : 1][12];      // d multiplier / d p at the stage time
+  float dmn[NT > 0 ? NT : 1][12];      // ... at t_n
+  float ddm[NT > 0 ? NT : 1][12];      // d (time derivative of the multiplier) / d p at t_n
   __device__ float* X() { return u; }
   __device__ float* Ub() { return u + 1024; }
   __device__ float* xin() { return u; }
@@ -55,6 +63,9 @@ struct WaveLds {
   __device__ float* G() { return u + 2 * NpA; }
   __device__ float* Kv(int j) { return u + (3 + j) * NpA; }  // K1..K5
   __device__ float* ft() { return u + 8 * NpA; }
+  __device__ float* y0() { return tv; }
+  __device__ float* xt() { return tv + NpA; }
+  __device__ float* kc() { return tv + 2 * NpA; }
 };
 
 // In-place inverse of the lane-distributed block by Gauss-Jordan with 2x2 pivots.
@@ -103,11 +114,12 @@ __device__ __forceinline__ bool gj2_invert(float (&a)[Q], int i, int h, W& w) {
   return ok;
 }
 
-template <int L, int WAVES>
+template <int L, int WAVES, int NT>
 __global__ void __launch_bounds__(64 * WAVES)
 stepper_kernel(StepArgs A, DevTables t) {
   using Gm = Geo<L>;
-  using WL = WaveLds<L>;
+  using WL = WaveLds<L, NT>;
+  constexpr int NpA = Gm::NpA;
   constexpr int Np = Gm::Np;
   constexpr int S = Gm::S;
   extern __shared__ __align__(16) unsigned char smem[];
@@ -131,16 +143,30 @@ stepper_kernel(StepArgs A, DevTables t) {
 
   const int lane = threadIdx.x & 63;
   const int wid = threadIdx.x >> 6;
-  const int slot = blockIdx.x * WAVES + wid;
-  if (slot >= A.n_inst) return;
-  const int inst = A.inst_idx[slot];
+  // tangent workspace of this resident wavefront (lane-private rows): state, saved state,
+  // stage increments [5 stages][NT] and time-derivative terms, NpA floats each
+  float* tws = (NT > 0) ? A.tws + int64_t(blockIdx.x * WAVES + wid) * (8 * NT) * NpA : nullptr;
+  auto TY = [&](int p) { return tws + p * NpA; };
+  auto TYS = [&](int p) { return tws + (NT + p) * NpA; };
+  auto TK = [&](int j, int p) { return tws + (2 * NT + j * NT + p) * NpA; };
+  auto TF = [&](int p) { return tws + (7 * NT + p) * NpA; };
+  // persistent: every wavefront takes instances from the launch's queue until it is drained
+  for (;;) {
+  int qk = 0;
+  if (lane == 0) qk = atomicAdd(A.queue, 1);
+  qk = __builtin_amdgcn_readfirstlane(__shfl(qk, 0));
+  if (qk >= A.n_inst) break;
+  const int inst = A.inst_idx[qk];
   WL& w = wl[wid];
   const int i = lane & 31, h = lane >> 5;
   float* ms_out = A.msamp + int64_t(inst) * 3 * A.Ns;
+  float* mt_out = (NT > 0) ? A.mtan + int64_t(inst) * NT * 3 * A.Ns : nullptr;
   if (A.status[inst] != 0) {
     for (int j = lane; j < 3 * A.Ns; j += 64) ms_out[j] = __builtin_nanf("");
+    if constexpr (NT > 0)
+      for (int j = lane; j < NT * 3 * A.Ns; j += 64) mt_out[j] = __builtin_nanf("");
     if (A.steps_out && lane == 0) A.steps_out[inst] = 0;
-    return;
+    continue;
   }
   const InstParams P = A.ip[inst];
   const float inv2tau = float(P.inv2tau), sigma = float(P.sigma), alpha = float(P.alpha), beta = float(P.beta_T);
@@ -153,6 +179,17 @@ stepper_kernel(StepArgs A, DevTables t) {
   for (int s = 0; s < S; ++s) {
     const int p = lane + 64 * s;
     y[s] = (p < Np) ? float(A.c0[int64_t(inst) * A.c_stride + p]) : 0.0f;
+  }
+  float ep[3] = {0.0f, 0.0f, 0.0f};  // R^T e for the tangent direction of this lane (lane / 9)
+  if constexpr (NT > 0) {
+    for (int pp = 0; pp < NT; ++pp) {
+      const double* src = A.c0t + (int64_t(inst) * NT + pp) * A.c_stride;
+      float* dst = TY(pp);
+      for (int q = lane; q < Np; q += 64) dst[q] = float(src[q]);
+    }
+    double e[3];
+    tan_axis(lane < 9 * NT ? lane / 9 : 3, P.R, e);
+    for (int c = 0; c < 3; ++c) ep[c] = float(P.R[0 * 3 + c] * e[0] + P.R[1 * 3 + c] * e[1] + P.R[2 * 3 + c] * e[2]);
   }
   Store<L, L> st;
   const float rc = 2.0466534158929770f;  // sqrt(4 pi / 3)
@@ -192,9 +229,20 @@ stepper_kernel(StepArgs A, DevTables t) {
     const float hz = R[2] * bx + R[5] * by + R[8] * bz;
     return (lane < 3) ? 0.0f : kind_mult(lane < 9 ? lane : 0, inv2tau, sigma, alpha, beta, hx, hy, hz);
   };
-  // dst[p] = add * dst[p] + (A(ms) xin)[p] for the rows p = lane + 64 s (one row slot at a time)
-  auto matvec = [&](float* dst, bool add) {
-    const float* xin = w.xin();
+  // parameter derivative of multiplier kind (lane % 9) for direction lane / 9 (lanes < 9 NT), from the
+  // field (deriv = false) or its time derivative (deriv = true, constant kinds give 0)
+  auto tan_lane = [&](double tt, bool deriv) -> float {
+    float bx, by, bz;
+    field(tt, bx, by, bz, deriv);
+    if (!deriv) { bx += off[0]; by += off[1]; bz += off[2]; }
+    const float hh[3] = {R[0] * bx + R[3] * by + R[6] * bz, R[1] * bx + R[4] * by + R[7] * bz,
+                         R[2] * bx + R[5] * by + R[8] * bz};
+    const int kind = lane % 9, prm = lane / 9;
+    if (lane >= 9 * NT || (deriv && kind < 3)) return 0.0f;
+    return tan_mult_t<float>(prm, kind, inv2tau, sigma, alpha, beta, float(P.D), float(P.sigK), hh, ep);
+  };
+  // dst[p] = add * dst[p] + (A(ms) src)[p] for the rows p = lane + 64 s (one row slot at a time)
+  auto matvec = [&](float* dst, bool add, const float* xin) {
     float m[9];
 #pragma unroll
     for (int k = 0; k < 9; ++k) m[k] = w.ms[k];
@@ -210,6 +258,46 @@ stepper_kernel(StepArgs A, DevTables t) {
         for (int sl = 0; sl < kNSlRow; ++sl)
           acc = fmaf(m[kSlotKindRow[sl]] * ev[sl * Np + p], xin[ec[sl * Np + p]], acc);
         dst[p] = add ? dst[p] + acc : acc;
+      }
+    }
+  };
+  // tangent right-hand side of direction pp: V[p] += (A(t_i) xt + A_p(t_i) yt + A_p(t_n) K_i
+  //   + h gm_i dA_p/dt(t_n) y)[p], one pass over the table with four gathers
+  auto matvec_tan = [&](int pp, float hgm) {
+    float* V = w.V();
+    const float* xt = w.xt();
+    const float* yt = w.xin();
+    const float* kc = w.kc();
+    const float* y0 = w.y0();
+    float m[9], a1[9], a2[9], a3[9];
+#pragma unroll
+    for (int k = 0; k < 9; ++k) {
+      m[k] = w.ms[k];
+      a1[k] = w.dmi[pp][k];
+      a2[k] = w.dmn[pp][k];
+      a3[k] = hgm * w.ddm[pp][k];
+    }
+#pragma unroll 1
+    for (int s = 0; s < S; ++s) {
+      const int p = lane + 64 * s;
+      const int z = opaque_zero();
+      const uint16_t* ec = ecol + z;
+      const float* ev = eval + z;
+      if (p < Np) {
+        float acc = 0.0f;
+#pragma unroll
+        for (int sl = 0; sl < kNSlRow; ++sl) {
+          const int kd = kSlotKindRow[sl];
+          const int c = ec[sl * Np + p];
+          const float v = ev[sl * Np + p];
+          float g = m[kd] * xt[c];
+          g = fmaf(a1[kd], yt[c], g);
+          g = fmaf(a2[kd], kc[c], g);
+          g = fmaf(a3[kd], y0[c], g);
+          acc = fmaf(v, g, acc);
+          if ((sl % 7) == 6) __builtin_amdgcn_sched_barrier(0);
+        }
+        V[p] += acc;
       }
     }
   };
@@ -438,8 +526,34 @@ stepper_kernel(StepArgs A, DevTables t) {
       const float md = dmult_lane(tn);
       if (lane < 9) w.ms[lane] = md;
       wsync();
-      matvec(w.ft(), false);
+      matvec(w.ft(), false, w.xin());
       wsync();
+      if constexpr (NT > 0) {
+        // step-start state and the tangents' time-derivative terms dA/dt(t_n) y_p (same multipliers)
+        float* y0 = w.y0();
+#pragma unroll
+        for (int s = 0; s < S; ++s) {
+          const int p = lane + 64 * s;
+          if (p < Np) y0[p] = y[s];
+        }
+        const float dn = tan_lane(tn, false), dd = tan_lane(tn, true);
+        if (lane < 9 * NT) {
+          w.dmn[lane / 9][lane % 9] = dn;
+          w.ddm[lane / 9][lane % 9] = dd;
+        }
+        for (int pp = 0; pp < NT; ++pp) {
+          float* xt = w.xt();
+          const float* yp = TY(pp);
+#pragma unroll
+          for (int s = 0; s < S; ++s) {
+            const int p = lane + 64 * s;
+            if (p < Np) xt[p] = yp[p];
+          }
+          wsync();
+          matvec(TF(pp), false, w.xt());
+          wsync();
+        }
+      }
     }
     float yt[S], kr[S];
     for (int stg = 0; stg < 6; ++stg) {
@@ -472,7 +586,7 @@ stepper_kernel(StepArgs A, DevTables t) {
         }
       }
       wsync();
-      matvec(V, true);
+      matvec(V, true, w.xin());
       wsync();
       solve();
       const float* G = w.G();
@@ -482,6 +596,54 @@ stepper_kernel(StepArgs A, DevTables t) {
         const int p = lane + 64 * s;
         kr[s] = (p < Np) ? hg * G[p] : 0.0f;
         if (stg < 5 && p < Np) kd[p] = kr[s];
+      }
+      if constexpr (NT > 0) {
+        // tangents of this stage: same factorisation, right-hand sides from the primal stage
+        float* kc = w.kc();
+#pragma unroll
+        for (int s = 0; s < S; ++s) {
+          const int p = lane + 64 * s;
+          if (p < Np) kc[p] = hg * G[p];
+        }
+        const float tm = tan_lane(tn + double(kRodasAlpha[stg]) * hs, false);
+        if (lane < 9 * NT) w.dmi[lane / 9][lane % 9] = tm;
+        wsync();
+        for (int pp = 0; pp < NT; ++pp) {
+          float* xt = w.xt();
+          float* V = w.V();
+          const float* yp = TY(pp);
+          const float* fp = TF(pp);
+#pragma unroll
+          for (int s = 0; s < S; ++s) {
+            const int p = lane + 64 * s;
+            if (p < Np) {
+              float yv = yp[p];
+              float ev = hf * kRodasGamma[stg] * fp[p];
+              for (int j = 0; j < stg; ++j) {
+                const float kj = TK(j, pp)[p];
+                yv = fmaf(kRodasA[stg][j], kj, yv);
+                ev = fmaf(kRodasC[stg][j] * ih, kj, ev);
+              }
+              xt[p] = yv;
+              V[p] = ev;
+            }
+          }
+          wsync();
+          matvec_tan(pp, hf * kRodasGamma[stg]);
+          wsync();
+          solve();
+          const float* Gt = w.G();
+#pragma unroll
+          for (int s = 0; s < S; ++s) {
+            const int p = lane + 64 * s;
+            if (p < Np) {
+              const float kt = hg * Gt[p];
+              if (stg < 5) TK(stg, pp)[p] = kt;
+              else TY(pp)[p] = xt[p] + kt;
+            }
+          }
+          wsync();
+        }
       }
       wsync();
     }
@@ -513,6 +675,33 @@ stepper_kernel(StepArgs A, DevTables t) {
         ms_out[lane * A.Ns + js] = rc * (r0 * vx + r1 * vy + r2 * vz);
       }
       ok = ok && isfinite(vx) && isfinite(vy) && isfinite(vz);
+      if constexpr (NT > 0) {
+        // d m / d p = R d m' / d p, plus e x m for the axis angles (rotation of the frame)
+        const float mx = rc * (R[0] * vx + R[1] * vy + R[2] * vz);
+        const float my = rc * (R[3] * vx + R[4] * vy + R[5] * vz);
+        const float mz = rc * (R[6] * vx + R[7] * vy + R[8] * vz);
+        for (int pp = 0; pp < NT; ++pp) {
+          const float own = lane < Np ? TY(pp)[lane] : 0.0f;  // rows pX, pY, pZ lie in the first 64 for L <= 16
+          const float tx = __shfl(own, pX), ty = __shfl(own, pY), tz = __shfl(own, pZ);
+          if (lane < 3) {
+            const float r0 = lane == 0 ? R[0] : (lane == 1 ? R[3] : R[6]);
+            const float r1 = lane == 0 ? R[1] : (lane == 1 ? R[4] : R[7]);
+            const float r2 = lane == 0 ? R[2] : (lane == 1 ? R[5] : R[8]);
+            float v = rc * (r0 * tx + r1 * ty + r2 * tz);
+            if (pp >= 3) {
+              double e[3];
+              tan_axis(pp, P.R, e);
+              const float ex = float(e[0]), ey = float(e[1]), ez = float(e[2]);
+              v += (lane == 0) ? (ey * mz - ez * my) : ((lane == 1) ? (ez * mx - ex * mz) : (ex * my - ey * mx));
+            }
+            mt_out[(pp * 3 + lane) * A.Ns + js] = v;
+          }
+        }
+      }
+    }
+    if constexpr (NT > 0) {
+      for (int pp = 0; pp < NT; ++pp)
+        for (int q = lane; q < Np; q += 64) TYS(pp)[q] = TY(pp)[q];
     }
     float ysave[S];
 #pragma unroll
@@ -532,6 +721,10 @@ stepper_kernel(StepArgs A, DevTables t) {
       if (!(emax <= A.tol) && r < A.r_max && isfinite(emax)) {  // reject the interval, refine
 #pragma unroll
         for (int s = 0; s < S; ++s) y[s] = ysave[s];
+        if constexpr (NT > 0) {
+          for (int pp = 0; pp < NT; ++pp)
+            for (int q = lane; q < Np; q += 64) TY(pp)[q] = TYS(pp)[q];
+        }
         const int rn = int(ceilf(float(r) * 1.2f * sqrtf(sqrtf(emax / A.tol))));
         r = min(A.r_max, max(2 * r, rn));
         continue;
@@ -544,26 +737,31 @@ stepper_kernel(StepArgs A, DevTables t) {
   }
   if (!ok) {
     for (int j = lane; j < 3 * A.Ns; j += 64) ms_out[j] = __builtin_nanf("");
+    if constexpr (NT > 0)
+      for (int j = lane; j < NT * 3 * A.Ns; j += 64) mt_out[j] = __builtin_nanf("");
     if (lane == 0) A.status[inst] = 2;
   }
   if (A.steps_out && lane == 0) A.steps_out[inst] = steps;
+  }  // queue
 }
 
 #ifndef FPN_STEPPER_WAVES
 #define FPN_STEPPER_WAVES 8
 #endif
 constexpr int kWaves = FPN_STEPPER_WAVES;  // instances (wavefronts) per workgroup
+constexpr int kTanWaves = 4;               // with tangents (more LDS per wavefront)
 
-template <int L>
-size_t stepper_lds_bytes_L(const DevTables&) {
+template <int L, int NT>
+size_t stepper_lds_bytes_L() {
   constexpr int Np = Geo<L>::Np;
   constexpr size_t b16 = ((size_t(kNSlRow + kNSlCol) * Np * 2) + 15) & ~size_t(15);
   constexpr size_t tb = (b16 + size_t(kNSlRow + kNSlCol + 3 * kNWin) * Np * 4 + 15) & ~size_t(15);
-  return tb + kWaves * sizeof(WaveLds<L>);
+  return tb + (NT > 0 ? kTanWaves : kWaves) * sizeof(WaveLds<L, NT>);
 }
 
-template <int L>
-hipError_t launch_stepper_L(const StepLaunch& s, const DevTables& t, hipStream_t stream) {
+template <int L, int NT>
+hipError_t launch_stepper_NT(const StepLaunch& s, const DevTables& t, hipStream_t stream) {
+  constexpr int WV = NT > 0 ? kTanWaves : kWaves;
   StepArgs a;
   a.ip = s.ip;
   a.inst_idx = s.inst_idx;
@@ -584,17 +782,40 @@ hipError_t launch_stepper_L(const StepLaunch& s, const DevTables& t, hipStream_t
   a.msamp = s.msamp;
   a.status = s.status;
   a.steps_out = s.steps_out;
-  const size_t shm = stepper_lds_bytes_L<L>(t);
-  auto kern = stepper_kernel<L, kWaves>;
+  a.queue = s.queue;
+  a.c0t = s.c0t;
+  a.mtan = s.mtan;
+  a.tws = s.tws;
+  const size_t shm = stepper_lds_bytes_L<L, NT>();
+  auto kern = stepper_kernel<L, WV, NT>;
   hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void*>(kern),
                                      hipFuncAttributeMaxDynamicSharedMemorySize, int(shm));
   if (e != hipSuccess) return e;
-  const int grid = (s.n_inst + kWaves - 1) / kWaves;
-  hipLaunchKernelGGL(kern, dim3(grid), dim3(64 * kWaves), shm, stream, a, t);
+  int grid = (s.n_inst + WV - 1) / WV;
+  if (s.grid > 0) grid = std::min(grid, s.grid);
+  hipLaunchKernelGGL(kern, dim3(grid), dim3(64 * WV), shm, stream, a, t);
   return hipGetLastError();
 }
 
-#define FPN_INST(LL) template hipError_t launch_stepper_L<LL>(const StepLaunch&, const DevTables&, hipStream_t);
+template <int L>
+hipError_t launch_stepper_L(const StepLaunch& s, const DevTables& t, hipStream_t stream) {
+  return s.mtan ? launch_stepper_NT<L, kNTan>(s, t, stream) : launch_stepper_NT<L, 0>(s, t, stream);
+}
+
+template <int L>
+hipError_t stepper_occupancy_L(const DevTables&, bool tangents, int* waves_per_block, int* blocks_per_cu) {
+  const size_t shm = tangents ? stepper_lds_bytes_L<L, kNTan>() : stepper_lds_bytes_L<L, 0>();
+  const void* kern = tangents ? reinterpret_cast<const void*>(stepper_kernel<L, kTanWaves, kNTan>)
+                              : reinterpret_cast<const void*>(stepper_kernel<L, kWaves, 0>);
+  hipError_t e = hipFuncSetAttribute(kern, hipFuncAttributeMaxDynamicSharedMemorySize, int(shm));
+  if (e != hipSuccess) return e;
+  *waves_per_block = tangents ? kTanWaves : kWaves;
+  return hipOccupancyMaxActiveBlocksPerMultiprocessor(blocks_per_cu, kern, 64 * *waves_per_block, shm);
+}
+
+#define FPN_INST(LL)                                                                          \
+  template hipError_t launch_stepper_L<LL>(const StepLaunch&, const DevTables&, hipStream_t); \
+  template hipError_t stepper_occupancy_L<LL>(const DevTables&, bool, int*, int*);
 #if !defined(FPN_L_BEGIN)
 #define FPN_L_BEGIN 1
 #define FPN_L_END 16

@@ -94,6 +94,10 @@ struct StepArgs {
   float* msamp;  // [n_total][3][Ns]
   int32_t* status;
   int32_t* steps_out;  // [n_total] time steps taken (may be null)
+  int32_t* queue;      // work counter of this launch, zero at launch
+  const double* c0t;   // tangents: initial states [n_total][kNTan][c_stride] (FP64)
+  float* mtan;         // tangents: samples [n_total][kNTan][3][Ns]; null without tangents
+  float* tws;          // tangents: workspace per resident wavefront (8 kNTan NpA floats)
 };
 
 }  // namespace fpn

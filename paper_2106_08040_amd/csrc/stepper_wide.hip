@@ -11,6 +11,7 @@
 // shared by every wavefront and stay in L2).
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
 #include <cstdint>
 
 #include "device_common.hpp"
@@ -119,9 +120,14 @@ stepper_wide_kernel(StepArgs A, DevTables t, float* ws) {
 
   const int lane = threadIdx.x & 63;
   const int wid = __builtin_amdgcn_readfirstlane(int(threadIdx.x >> 6));  // uniform per wavefront
-  const int slot = blockIdx.x * WAVES + wid;
-  if (slot >= A.n_inst) return;
-  const int inst = A.inst_idx[slot];
+  const int slot = blockIdx.x * WAVES + wid;  // resident wavefront index
+  // persistent: every wavefront takes instances from the launch's queue until it is drained
+  for (;;) {
+  int qk = 0;
+  if (lane == 0) qk = atomicAdd(A.queue, 1);
+  qk = __builtin_amdgcn_readfirstlane(__shfl(qk, 0));
+  if (qk >= A.n_inst) break;
+  const int inst = A.inst_idx[qk];
   WL& w = wl[wid];
   float* inv = ws + int64_t(slot) * WG::WS;
   float* Kg = inv + WG::INV;  // K1..K5 at j * NpA, f_t at 5 * NpA, saved state at 6 * NpA
@@ -134,7 +140,7 @@ stepper_wide_kernel(StepArgs A, DevTables t, float* ws) {
   if (A.status[inst] != 0) {
     for (int j = lane; j < 3 * A.Ns; j += 64) ms_out[j] = __builtin_nanf("");
     if (A.steps_out && lane == 0) A.steps_out[inst] = 0;
-    return;
+    continue;
   }
   const InstParams P = A.ip[inst];
   const float inv2tau = float(P.inv2tau), sigma = float(P.sigma), alpha = float(P.alpha), beta = float(P.beta_T);
@@ -568,6 +574,7 @@ stepper_wide_kernel(StepArgs A, DevTables t, float* ws) {
     if (lane == 0) A.status[inst] = 2;
   }
   if (A.steps_out && lane == 0) A.steps_out[inst] = steps;
+  }  // queue
 }
 
 #ifndef FPN_WIDE_WAVES
@@ -602,19 +609,36 @@ hipError_t launch_stepper_wide_L(const StepLaunch& s, const DevTables& t, float*
   a.msamp = s.msamp;
   a.status = s.status;
   a.steps_out = s.steps_out;
+  a.queue = s.queue;
+  a.c0t = nullptr;  // tangents are carried by the register-layout stepper only
+  a.mtan = nullptr;
+  a.tws = nullptr;
   const size_t shm = kWideWaves * sizeof(WideLds<L>);
   auto kern = stepper_wide_kernel<L, kWideWaves>;
   hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void*>(kern),
                                      hipFuncAttributeMaxDynamicSharedMemorySize, int(shm));
   if (e != hipSuccess) return e;
-  const int grid = (s.n_inst + kWideWaves - 1) / kWideWaves;
+  int grid = (s.n_inst + kWideWaves - 1) / kWideWaves;
+  if (s.grid > 0) grid = std::min(grid, s.grid);
   hipLaunchKernelGGL(kern, dim3(grid), dim3(64 * kWideWaves), shm, stream, a, t, ws);
   return hipGetLastError();
 }
 
+template <int L>
+hipError_t stepper_wide_occupancy_L(int* waves_per_block, int* blocks_per_cu) {
+  const size_t shm = kWideWaves * sizeof(WideLds<L>);
+  auto kern = stepper_wide_kernel<L, kWideWaves>;
+  hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void*>(kern),
+                                     hipFuncAttributeMaxDynamicSharedMemorySize, int(shm));
+  if (e != hipSuccess) return e;
+  *waves_per_block = kWideWaves;
+  return hipOccupancyMaxActiveBlocksPerMultiprocessor(blocks_per_cu, kern, 64 * kWideWaves, shm);
+}
+
 #define FPN_WINST(LL)                                                                                  \
   template hipError_t launch_stepper_wide_L<LL>(const StepLaunch&, const DevTables&, float*, hipStream_t); \
-  template int64_t stepper_wide_ws_floats_L<LL>();
+  template int64_t stepper_wide_ws_floats_L<LL>();                                                     \
+  template hipError_t stepper_wide_occupancy_L<LL>(int*, int*);
 #if !defined(FPN_L_BEGIN)
 #define FPN_L_BEGIN 17
 #define FPN_L_END 24

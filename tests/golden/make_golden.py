@@ -21,6 +21,10 @@ import workloads as W  # noqa: E402
 
 HERE = os.path.dirname(os.path.abspath(__file__))
 
+def tangent_l10():
+    return W.small_random(2, 10, seed=510, samples=48, settle=1, n_harm=8)
+
+
 def wide_l17():
     return W.small_random(2, 17, seed=117, samples=48, settle=1, n_harm=8)
 
@@ -35,13 +39,45 @@ def wide_l24():
 
 # (workload factory, instance ids, Radau steps per sample for the reference and its check)
 JOBS = {
+    "tangent_l10": (tangent_l10, [0, 1], 8),
     "wide_l17": (wide_l17, [0], 8),
     "wide_l20": (wide_l20, [0, 1], 8),
-    "wide_l24": (wide_l24, [0, 1], 8),
+    "wide_l24": (wide_l24, [0, 1], 16),
     "single_1d": (W.single_1d, [0], 8),
     "lissajous": (W.lissajous_grid, [(0 * 17 + 8) * 17 + 8, (3 * 17 + 2) * 17 + 13, (5 * 17 + 16) * 17 + 0,
                                      (7 * 17 + 10) * 17 + 4, (2 * 17 + 0) * 17 + 16, (6 * 17 + 12) * 17 + 12], 4),
 }
+
+
+def fd_one(args):
+    """Central finite differences of the oracle's m and Phi with respect to D, K, alpha and the
+    easy-axis polar / azimuth angles (relative step 1e-6 for D, K, alpha; 1e-6 rad for the angles)."""
+    name, factory, idx, r = args
+    ws = factory()
+    inst = {k: v[idx] for k, v in ws["inst"].items()}
+    n = np.asarray(inst["easy_axis"], float)
+    th, ph = np.arccos(np.clip(n[2], -1, 1)), np.arctan2(n[1], n[0])
+    t0 = time.time()
+
+    def solve(D, K, alpha, th, ph):
+        p = dict(D=D, Ms=inst["Ms"], K=K, alpha=alpha, T=inst["T"])
+        ax = np.array([np.sin(th) * np.cos(ph), np.sin(th) * np.sin(ph), np.cos(th)])
+        return O.solve_instance(p, ax, int(inst["L"]), ws["drive"], ws["samples"], ws["settle"], ws["n_harm"], r=r,
+                                offset=inst["offset"])
+
+    base = [inst["D"], inst["K"], inst["alpha"], th, ph]
+    steps = [1e-6 * inst["D"], 1e-6 * inst["K"], 1e-6 * inst["alpha"], 1e-6, 1e-6]
+    dm, dPhi = [], []
+    for k in range(5):
+        up, dn = list(base), list(base)
+        up[k] += steps[k]
+        dn[k] -= steps[k]
+        a, b = solve(*up), solve(*dn)
+        dm.append((a["m"] - b["m"]) / (2 * steps[k]))
+        dPhi.append((a["Phi"] - b["Phi"]) / (2 * steps[k]))
+    out = os.path.join(HERE, f"{name}_{idx}.npz")
+    np.savez_compressed(out, dm=np.array(dm), dPhi=np.array(dPhi), r=r, idx=idx, theta=th, phi=ph)
+    return f"{out}: finite differences of the oracle, r={r} ({time.time() - t0:.0f}s)"
 
 
 def one(args):
@@ -62,6 +98,10 @@ def one(args):
     return f"{out}: r={r} change vs r/2 = {err:.2e} ({time.time() - t0:.0f}s)"
 
 
+def lambda_dispatch(args):
+    return fd_one(args) if args[0].startswith("tangent") else one(args)
+
+
 if __name__ == "__main__":
     names = sys.argv[1:] or list(JOBS)
     tasks = []
@@ -69,5 +109,5 @@ if __name__ == "__main__":
         factory, ids, r = JOBS[nm]
         tasks += [(nm, factory, i, r) for i in ids]
     with ProcessPoolExecutor(max_workers=min(7, len(tasks))) as ex:
-        for msg in ex.map(one, tasks):
+        for msg in ex.map(lambda_dispatch, tasks):
             print(msg, flush=True)

@@ -1,0 +1,152 @@
+"""GPU tests of the parameter sensitivities (fpn_solve_tangent, fpn_adjoint) and of the autograd
+Function built on them.
+
+* dPhi/dp and dm/dp for p = D, K, alpha, easy-axis polar and azimuth angles against central finite
+  differences of the FP64 oracle (tests/golden/make_golden.py): rel-L2 <= 1e-4 per parameter, the
+  tolerance proposed for an FP32 forward solve whose values match the oracle to ~1e-6.
+* For an isotropic particle (K = 0) the easy axis is irrelevant: both angle derivatives vanish, which
+  needs the field-rotation tangent and the frame term e x m to cancel.
+* fpn_adjoint equals the FP64 contraction of the tangents with dL/dPhi.
+* Gradients through torch.autograd (superposition weights and a data misfit in torch) match the chain
+  rule evaluated with the oracle's finite differences.
+"""
+import glob
+import os
+
+import numpy as np
+import pytest
+
+import workloads as W
+
+pytestmark = pytest.mark.gpu
+GOLDEN = os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden")
+
+
+def rel(a, b):
+    return float(np.linalg.norm(np.asarray(a) - np.asarray(b)) / np.linalg.norm(b))
+
+
+@pytest.fixture(scope="module")
+def fpn():
+    import paper_2106_08040_amd as fpn
+    return fpn
+
+
+@pytest.fixture(scope="module")
+def ctx(fpn):
+    c = fpn.Context(0)
+    yield c
+    c.close()
+
+
+def drive_of(fpn, ws):
+    d = ws["drive"]
+    return fpn.make_drive(d["amp"], d["freq"], d["period"], d["phase"])
+
+
+@pytest.fixture(scope="module")
+def tangent_run(fpn, ctx):
+    import torch
+    ws = W.small_random(2, 10, seed=510, samples=48, settle=1, n_harm=8)
+    m, h, dm, dh, st = ctx.solve_tangent(ws["inst"], ws["inst"]["L"], drive_of(fpn, ws), ws["samples"], ws["settle"],
+                                         ws["n_harm"], substeps=32, harm_z=True)
+    torch.cuda.synchronize()
+    return ws, m.cpu().numpy(), h.cpu().numpy(), dm.cpu().numpy(), dh.cpu().numpy(), st.cpu().numpy()
+
+
+def test_tangents_match_oracle_finite_differences(tangent_run):
+    ws, m, h, dm, dh, st = tangent_run
+    files = sorted(glob.glob(os.path.join(GOLDEN, "tangent_l10_*.npz")))
+    if not files:
+        pytest.skip("no golden files (run tests/golden/make_golden.py tangent_l10)")
+    assert (st == 0).all()
+    names = ["D", "K", "alpha", "theta", "phi"]
+    for f in files:
+        g = np.load(f)
+        i = int(g["idx"])
+        for p in range(5):
+            eh = rel(dh[i, p].T, g["dPhi"][p])
+            em = rel(dm[i, p].T, g["dm"][p])
+            print(f"inst {i} d/d{names[p]}: Phi {eh:.2e} m {em:.2e}", flush=True)
+            assert eh < 1e-4 and em < 1e-4
+
+
+def test_primal_outputs_of_the_tangent_solve(fpn, ctx, tangent_run):
+    import torch
+    ws, m, h, dm, dh, st = tangent_run
+    m0, h0, _ = ctx.solve(ws["inst"], ws["inst"]["L"], drive_of(fpn, ws), ws["samples"], ws["settle"], ws["n_harm"],
+                          substeps=32, harm_z=True)
+    torch.cuda.synchronize()
+    assert rel(m, m0.cpu().numpy()) < 1e-6 and rel(h, h0.cpu().numpy()) < 1e-6
+
+
+def test_isotropic_particle_has_no_axis_derivative(fpn, ctx):
+    import torch
+    ws = W.small_random(3, 8, seed=77, samples=32, settle=1, n_harm=6)
+    ws["inst"]["K"] = np.zeros(3)
+    m, h, dm, dh, st = ctx.solve_tangent(ws["inst"], ws["inst"]["L"], drive_of(fpn, ws), ws["samples"], ws["settle"],
+                                         ws["n_harm"], substeps=8, harm_z=True)
+    torch.cuda.synchronize()
+    dh, h = dh.cpu().numpy(), h.cpu().numpy()
+    assert (st.cpu().numpy() == 0).all()
+    for i in range(3):
+        scale = np.linalg.norm(h[i])  # per radian
+        print(f"inst {i}: |dPhi/dtheta| {np.linalg.norm(dh[i, 3]) / scale:.1e} |dPhi/dphi| "
+              f"{np.linalg.norm(dh[i, 4]) / scale:.1e} (relative)", flush=True)
+        assert np.linalg.norm(dh[i, 3]) < 1e-5 * scale and np.linalg.norm(dh[i, 4]) < 1e-5 * scale
+
+
+def test_adjoint_is_the_fp64_contraction(fpn, ctx, tangent_run):
+    import torch
+    ws, m, h, dm, dh, st = tangent_run
+    r = np.random.default_rng(3)
+    dL = r.normal(size=(2, 3, ws["n_harm"] + 1, 2)).astype(np.float32)
+    grad, hm, st2 = ctx.adjoint(ws["inst"], ws["inst"]["L"], drive_of(fpn, ws), ws["samples"], ws["settle"],
+                                ws["n_harm"], dL, substeps=32, harm_z=True)
+    torch.cuda.synchronize()
+    dhr = np.stack([dh.real, dh.imag], -1).astype(np.float64)  # [n, 5, ch, K+1, 2]
+    ref = np.einsum("ickr,ipckr->ip", dL.astype(np.float64), dhr)
+    assert rel(grad.cpu().numpy(), ref) < 1e-6
+
+
+def test_autograd_through_a_superposition_misfit(fpn, ctx):
+    """L = sum_k |w0 Phi_0 + w1 Phi_1 - S|^2 over the two tangent_l10 instances; gradients with respect to
+    every parameter and both weights against the chain rule with the oracle's finite differences."""
+    import torch
+
+    from paper_2106_08040_amd.autograd import Harmonics
+    files = sorted(glob.glob(os.path.join(GOLDEN, "tangent_l10_*.npz")))
+    if len(files) < 2:
+        pytest.skip("no golden files")
+    import oracle as O
+    ws = W.small_random(2, 10, seed=510, samples=48, settle=1, n_harm=8)
+    inst = ws["inst"]
+    g = [np.load(f) for f in files]
+    params = torch.tensor(np.stack([inst["D"], inst["K"], inst["alpha"], [x["theta"] for x in g],
+                                    [x["phi"] for x in g]], 1), dtype=torch.float64, device="cuda:0",
+                          requires_grad=True)
+    w = torch.tensor([0.7, 0.4], dtype=torch.float64, device="cuda:0", requires_grad=True)
+    S = torch.tensor(np.random.default_rng(1).normal(size=(2, 9, 2)) * 1e4, dtype=torch.float64, device="cuda:0")
+    fn = Harmonics(ctx, drive_of(fpn, ws), ws["samples"], ws["settle"], ws["n_harm"], L=10, substeps=32)
+    phi = fn(params, inst["Ms"], inst["T"], inst["offset"]).to(torch.float64)  # [2, 2, 9, 2]
+    res = w[0] * phi[0] + w[1] * phi[1] - S
+    loss = (res ** 2).sum()
+    loss.backward()
+    # reference: oracle Phi and its finite-difference derivatives (x and y channels)
+    ref_phi, ref_dphi = [], []
+    for i in range(2):
+        p = dict(D=inst["D"][i], Ms=inst["Ms"][i], K=inst["K"][i], alpha=inst["alpha"][i], T=inst["T"][i])
+        o = O.solve_instance(p, inst["easy_axis"][i], 10, ws["drive"], ws["samples"], ws["settle"], ws["n_harm"], r=8,
+                             offset=inst["offset"][i])
+        ref_phi.append(np.stack([o["Phi"][:, :2].T.real, o["Phi"][:, :2].T.imag], -1))
+        ref_dphi.append(np.stack([g[i]["dPhi"][:, :, :2].transpose(0, 2, 1).real,
+                                  g[i]["dPhi"][:, :, :2].transpose(0, 2, 1).imag], -1))
+    wn = w.detach().cpu().numpy()
+    r_ = wn[0] * ref_phi[0] + wn[1] * ref_phi[1] - S.cpu().numpy()
+    gp = np.stack([np.einsum("ckr,pckr->p", 2 * r_, wn[i] * ref_dphi[i]) for i in range(2)])
+    gw = np.array([np.sum(2 * r_ * ref_phi[i]) for i in range(2)])
+    gg = params.grad.cpu().numpy()
+    e1 = [rel(gg[:, p], gp[:, p]) for p in range(5)]  # per parameter (their units differ)
+    e2 = rel(w.grad.cpu().numpy(), gw)
+    print("params grad rel-L2 per parameter", ["%.1e" % e for e in e1], f"weights {e2:.2e}", flush=True)
+    assert max(e1) < 1e-4 and e2 < 1e-4

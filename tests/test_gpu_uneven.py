@@ -78,3 +78,53 @@ def test_mixed_degrees_one_call_equals_separate_calls(fpn, ctx):
         one = W.take(ws, [i])
         m1, h1, st1 = run(fpn, ctx, one, substeps=4)
         assert np.array_equal(m1[0], m[i]) and np.array_equal(h1[0], h[i]), (i, int(ws["inst"]["L"][i]))
+
+
+def _mixed(fpn):
+    parts = [W.small_random(3, L, seed=400 + L, samples=32, settle=1, n_harm=6) for L in (8, 16, 20, 24)]
+    ws = dict(parts[0])
+    ws["inst"] = {k: np.concatenate([p["inst"][k] for p in parts]) for k in parts[0]["inst"]}
+    d = ws["drive"]
+    return ws, fpn.make_drive(d["amp"], d["freq"], d["period"], d["phase"])
+
+
+def test_plan_graph_replays_match_eager_solve(fpn, ctx):
+    """The plan captured as one HIP graph reproduces the eager solve on every replay, with unrelated
+    eager work and synchronisations between the replays."""
+    import torch
+    ws, drive = _mixed(fpn)
+    m0, h0, st0 = run(fpn, ctx, ws, substeps=4)
+    plan = ctx.plan(ws["inst"], ws["inst"]["L"], drive, ws["samples"], ws["settle"], ws["n_harm"], substeps=4,
+                    harm_z=True)
+    other = W.small_random(5, 10, seed=9, samples=32, settle=1, n_harm=6)
+    for rep in range(3):
+        plan.m.fill_(float("nan"))
+        if rep == 0:
+            plan.launch()
+        else:
+            plan.graph_launch()
+        torch.cuda.synchronize()
+        assert np.array_equal(plan.m.cpu().numpy(), m0), rep
+        assert np.array_equal(plan.harm.cpu().numpy(), h0), rep
+        assert np.array_equal(plan.status.cpu().numpy(), st0), rep
+        run(fpn, ctx, other, substeps=2)  # unrelated eager work between replays
+    plan.close()
+
+
+def test_cost_ordered_plan_gives_the_same_outputs(fpn, ctx):
+    import torch
+    ws, drive = _mixed(fpn)
+    p1 = ctx.plan(ws["inst"], ws["inst"]["L"], drive, ws["samples"], ws["settle"], ws["n_harm"], harm_z=True)
+    p1.launch()
+    torch.cuda.synchronize()
+    steps = p1.steps()
+    assert (steps > 0).all()
+    p2 = ctx.plan(ws["inst"], ws["inst"]["L"], drive, ws["samples"], ws["settle"], ws["n_harm"], harm_z=True,
+                  cost_hint=steps.astype(np.float32))
+    p2.graph_launch()
+    torch.cuda.synchronize()
+    assert np.array_equal(p1.m.cpu().numpy(), p2.m.cpu().numpy())
+    assert np.array_equal(p1.harm.cpu().numpy(), p2.harm.cpu().numpy())
+    assert np.array_equal(p2.steps(), steps)
+    p1.close()
+    p2.close()

@@ -275,3 +275,44 @@ def test_exact_by_parts_route_agrees_with_rhs_route_when_resolved():
     res = O.solve_instance(p, [np.cos(0.5), np.sin(0.5), 0], 8, drive, 400, 1, 10, r=2)
     a, b = res["Phi"][1:, :2], res["Phi_rect"][1:, :2]
     assert np.linalg.norm(a - b) < 1e-6 * np.linalg.norm(b)
+
+
+# ------------------------------------------------- finite-difference derivatives ---
+# The sensitivity references are central differences of the oracle; these pins check that the
+# differencing recipe (step sizes, angle parametrisation) reproduces closed forms.
+
+def _stationary_m(D, K, n, B, L=16):
+    p = dict(D=D, Ms=474e3, K=K, alpha=0.1, T=295.0)
+    A0, Aa, _ = O.operator_parts(p, n, L)
+    return O.moment(O.stationary(A0 + sum(B[a] * Aa[a] for a in range(3))))
+
+
+def test_central_difference_in_D_matches_langevin_derivative():
+    """K = 0: m = L(x) H/|H| with x = beta |H| and beta proportional to D^3, so
+    dm/dD = L'(x) (3 x / D) H/|H|, L'(x) = 1/x^2 - 1/sinh(x)^2."""
+    B = np.array([4e-3, -2e-3, 3e-3])
+    D = 18e-9
+    n = np.array([0.0, 0.0, 1.0])
+    h = 1e-6 * D
+    fd = (_stationary_m(D + h, 0.0, n, B) - _stationary_m(D - h, 0.0, n, B)) / (2 * h)
+    x = O.particle_scalars(D, 474e3, 0.0, 0.1, 295.0)["beta_T"] * np.linalg.norm(B)
+    dL = 1 / x ** 2 - 1 / np.sinh(x) ** 2
+    exact = dL * 3 * x / D * B / np.linalg.norm(B)
+    assert np.abs(fd - exact).max() < 1e-6 * np.abs(exact).max()
+
+
+def test_isotropic_particle_has_no_axis_angle_derivative():
+    """K = 0 makes the easy axis irrelevant: central differences in both axis angles vanish."""
+    ws_drive = dict(amp=(10e-3, 8e-3, 3e-3), freq=(3 / 40e-6, 4 / 40e-6, 1 / 40e-6), phase=(0.0, 0.3, -0.7),
+                    period=40e-6)
+    p = dict(D=18e-9, Ms=474e3, K=0.0, alpha=0.1, T=295.0)
+    th, ph = 0.9, 0.4
+
+    def phi(th, ph):
+        n = np.array([np.sin(th) * np.cos(ph), np.sin(th) * np.sin(ph), np.cos(th)])
+        return O.solve_instance(p, n, 4, ws_drive, 16, 0, 4, r=2, offset=(1e-3, 0, 0))["Phi"]
+
+    base = np.linalg.norm(phi(th, ph))
+    for dth, dph in ((1e-6, 0.0), (0.0, 1e-6)):
+        d = (phi(th + dth, ph + dph) - phi(th - dth, ph - dph)) / 2e-6
+        assert np.linalg.norm(d) < 1e-6 * base

@@ -60,10 +60,16 @@ def lissajous_grid(n_off=17, n_ang=8, L=16, span=12e-3):
 
 
 def truncation_degree(D, K, T=ROOM_T, lo=8, hi=24):
-    """Galerkin degree rule of the uneven sweep: L = clamp(ceil(8 + 2 sqrt(sigma)), lo, hi),
-    sigma = K (pi D^3 / 6) / (k_B T); evaluated once here so every consumer reads the same integer."""
+    """Galerkin degree rule of the uneven sweep: L = clamp(ceil(sigma) + 4, lo, hi),
+    sigma = K (pi D^3 / 6) / (k_B T); evaluated once here so every consumer reads the same integer.
+
+    The truncated Galerkin operator acquires an eigenvalue with positive real part (a spurious
+    growing mode) once sigma exceeds about L - 1 (scanned for L = 12..24, fields up to 24 mT,
+    alpha 0.05..0.25), so the degree has to grow linearly with sigma; the margin of 4 keeps the
+    operator stable up to sigma = 20 at L = 24.  Beyond that no degree up to 24 resolves the particle
+    and the solve ends with a non-finite status."""
     sigma = np.asarray(K) * (np.pi * np.asarray(D) ** 3 / 6) / (1.380649e-23 * T)
-    return np.clip(np.ceil(8 + 2 * np.sqrt(sigma)), lo, hi).astype(np.int32)
+    return np.clip(np.ceil(sigma) + 4, lo, hi).astype(np.int32)
 
 
 def uneven_sweep(n=4096, seed=3, L_max=24):
