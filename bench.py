@@ -108,10 +108,12 @@ def wait_with_progress(torch, what, t0):
     """Block until the current stream's work is done, printing a progress line every 20 s."""
     ev = torch.cuda.Event()
     ev.record()
+    last = time.perf_counter()
     while not ev.query():
-        time.sleep(0.05 if time.perf_counter() - t0 < 20 else 20.0)
-        if not ev.query():
-            print(f"[bench] {what}: {time.perf_counter() - t0:.0f} s", file=sys.stderr, flush=True)
+        time.sleep(0.05)
+        if time.perf_counter() - last >= 20.0:
+            last = time.perf_counter()
+            print(f"[bench] {what}: {last - t0:.0f} s", file=sys.stderr, flush=True)
     torch.cuda.synchronize()
 
 
@@ -173,6 +175,104 @@ def bench_uneven(args):
     ctx.close()
 
 
+def surrogate_domain(n, seed, n_off=None, n_ang=None):
+    """The system-matrix family of the Lissajous workload (D = 20 nm, K = 2 kJ/m^3, alpha = 0.1, L = 16,
+    in-plane easy axes, offsets on +-12 mT): random draws, or a regular n_off x n_off x n_ang grid."""
+    import workloads as W
+    if n_off is None:
+        r = np.random.default_rng(seed)
+        th = r.uniform(0, np.pi, n)
+        off = np.stack([r.uniform(-12e-3, 12e-3, n), r.uniform(-12e-3, 12e-3, n), np.zeros(n)], 1)
+    else:
+        g = -12e-3 + 24e-3 * (np.arange(n_off) + 0.5) / n_off
+        a, iy, ix = np.meshgrid(np.arange(n_ang), np.arange(n_off), np.arange(n_off), indexing="ij")
+        th = (a.ravel() + 0.5) * np.pi / n_ang
+        off = np.stack([g[ix.ravel()], g[iy.ravel()], np.zeros(th.size)], 1)
+        n = th.size
+    easy = np.stack([np.cos(th), np.sin(th), np.zeros(n)], 1)
+    inst = dict(D=np.full(n, 20e-9), Ms=np.full(n, W.MAGNETITE_MS), K=np.full(n, 2e3), alpha=np.full(n, 0.1),
+                T=np.full(n, W.ROOM_T), easy_axis=easy, offset=off, L=np.full(n, 16, np.int32))
+    return dict(inst=inst, drive=W.lissajous_drive(), samples=1632, settle=1)
+
+
+def bench_surrogate(args):
+    """Surrogate of the Lissajous system-matrix family (harmonics 1..64 of x and y): two networks
+    (8 -> 512 x 4 -> 256, BF16 matrix cores) trained on solver output, evaluated on a 64 x 64 x 64 grid of
+    offsets and in-plane axes; accuracy and fallback measured on held-out instances against the solver."""
+    import torch
+    import paper_2106_08040_amd as fpn
+    from paper_2106_08040_amd.surrogate import Surrogate
+
+    KH = 64
+    ctx = fpn.Context(0)
+
+    def solve(ws):
+        d = ws["drive"]
+        drive = fpn.make_drive(d["amp"], d["freq"], d["period"], d["phase"])
+        t0 = time.perf_counter()
+        _, h, st = ctx.solve(ws["inst"], ws["inst"]["L"], drive, ws["samples"], ws["settle"], KH, want_m=False)
+        wait_with_progress(torch, "solver", t0)
+        return h, st, time.perf_counter() - t0, drive
+
+    tr, va, te = surrogate_domain(8192, 11), surrogate_domain(1024, 12), surrogate_domain(1024, 13)
+    htr, _, t_tr, drive = solve(tr)
+    hva, _, _, _ = solve(va)
+    hte, _, t_te, _ = solve(te)
+    print(f"[bench] training targets: {len(tr['inst']['D'])} solves in {t_tr:.1f} s", file=sys.stderr, flush=True)
+    sur = Surrogate(ctx, KH)
+    sur.fit(tr["inst"], htr, steps=4000, batch=4096, lr=2e-3)
+    true_va, _ = sur.calibrate(va["inst"], hva)
+    ev = surrogate_domain(0, 0, n_off=64, n_ang=64)
+    n_ev = ev["inst"]["D"].size
+    x, _ = ctx.surrogate_features(ev["inst"])
+    ya = torch.empty((n_ev, 4 * KH), dtype=torch.float32, device="cuda:0")
+    yb = torch.empty_like(ya)
+    for net, y in zip(sur.nets, (ya, yb)):  # warm-up
+        net.forward(x, out=y)
+    torch.cuda.synchronize()
+    reps = 5
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record()
+    for _ in range(reps):
+        for net, y in zip(sur.nets, (ya, yb)):
+            net.forward(x, out=y)
+    e1.record()
+    torch.cuda.synchronize()
+    t_inf = e0.elapsed_time(e1) / reps * 1e-3  # both members, all evaluations
+    flops = 2.0 * 2 * n_ev * sum(a * b for a, b in zip(sur.nets[0].widths[:-1], sur.nets[0].widths[1:]))
+    solver_rate = len(te["inst"]["D"]) / t_te
+    res_tol = {}
+    for tol in (1e-3, 1e-2, 3e-2):
+        h, err, used, st, nf = sur.predict(te["inst"], te["inst"]["L"], drive, te["samples"], te["settle"], tol)
+        ref = hte[:, :2]
+        e = (torch.linalg.vector_norm((h - ref).reshape(h.shape[0], -1), dim=1) /
+             torch.linalg.vector_norm(ref.reshape(h.shape[0], -1), dim=1)).cpu().numpy()
+        frac = nf / h.shape[0]
+        eff = n_ev / (t_inf + frac * n_ev / solver_rate)
+        res_tol[f"{tol:g}"] = {"fallback_fraction": frac, "max_rel_l2": float(e.max()),
+                               "p99_rel_l2": float(np.quantile(e, 0.99)), "effective_evals_per_s": eff}
+    achieved = flops / t_inf / 1e12
+    out = {
+        "metric": "FP solves/sec & surrogate evals/sec at \u22641e-3 rel-L2 vs FP64 oracle",
+        "value": res_tol["0.001"]["effective_evals_per_s"], "unit": "evals/s", "n_gpus": 1, "steps": reps,
+        "warmup": 1, "ms_per_step": t_inf * 1e3, "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+        "dtype": "bf16", "data": "synthetic",
+        "config": {"workload": "surrogate_lissajous_family_64x64x64", "evaluations": n_ev, "harmonics": KH,
+                   "network": sur.nets[0].widths, "ensemble": 2, "train_instances": len(tr["inst"]["D"]),
+                   "train_steps": 4000, "train_seconds": sur.train_seconds,
+                   "validation_rel_l2_median": float(np.median(true_va)),
+                   "validation_rel_l2_p99": float(np.quantile(true_va, 0.99)), "err_calibration": sur.err_calib,
+                   "inference_evals_per_s": n_ev / t_inf, "solver_solves_per_s": solver_rate,
+                   "by_tolerance": res_tol},
+        "roofline": {"bound": "mfma", "kernel": "gemm_nt_kernel (all layers, both members)", "achieved": achieved,
+                     "peak": 2500.0, "unit": "TFLOP/s", "frac": achieved / 2500.0, "traffic": None,
+                     "flops_per_forward": flops / 2},
+    }
+    print(json.dumps(out), flush=True)
+    sur.close()
+    ctx.close()
+
+
 def main():
     ap = argparse.ArgumentParser(description=__doc__.split("\n")[0])
     ap.add_argument("--gpus", type=int, default=1)
@@ -182,9 +282,10 @@ def main():
     ap.add_argument("--tol", type=float, default=0.0, help="adaptive error bound (0 = library default)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-budget", type=float, default=15.0)
-    ap.add_argument("--workload", choices=("lissajous", "uneven"), default="lissajous",
+    ap.add_argument("--workload", choices=("lissajous", "uneven", "surrogate"), default="lissajous",
                     help="lissajous: 2312-instance system matrix, L = 16 (headline); "
-                         "uneven: 4096 instances with L = 8..24 in one graph launch")
+                         "uneven: 4096 instances with L = 8..24 in one graph launch; "
+                         "surrogate: network ensemble trained on solver output, 262144 evaluations")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py measures one GPU only: this build has no multi-GPU path "
@@ -197,6 +298,8 @@ def main():
 
     if args.workload == "uneven":
         return bench_uneven(args)
+    if args.workload == "surrogate":
+        return bench_surrogate(args)
     ws = W.lissajous_grid()
     n = ws["inst"]["D"].size
     dev = "cuda:0"

@@ -41,10 +41,15 @@ __device__ __forceinline__ auto& blk(Store<L, L>& s) {
 // Per-wavefront LDS.  The factorisation scratch (X, Ub) and the stage vectors share `u`.  With
 // tangents (NT > 0) three more vectors hold the step-start state, the tangent stage argument and the
 // current primal stage increment, and three multiplier tables hold the parameter derivatives.
+// Row stride of the factorisation scratch: 33 floats, so the 32 rows of a half-wave fall in different
+// LDS banks (a stride of 32 put every row of a column access in one bank).
+constexpr int kXS = 33;
+constexpr int kUbOff = 1224;  // X: rows 0..36 (window overhang included), then Ub: 32 rows
+
 template <int L, int NT>
 struct WaveLds {
   static constexpr int NpA = Geo<L>::NpA;
-  static constexpr int kUnion = (2048 > 9 * NpA) ? 2048 : 9 * NpA;
+  static constexpr int kUnion = (kUbOff + 32 * kXS > 9 * NpA) ? kUbOff + 32 * kXS : 9 * NpA;
   static constexpr int kTanV = NT > 0 ? 3 * NpA : 4;
   float u[kUnion];
   float T[32];     // block right-hand side [parity][16]
@@ -57,7 +62,7 @@ struct WaveLds {
   float dmn[NT > 0 ? NT : 1][12];      // ... at t_n
   float ddm[NT > 0 ? NT : 1][12];      // d (time derivative of the multiplier) / d p at t_n
   __device__ float* X() { return u; }
-  __device__ float* Ub() { return u + 1024; }
+  __device__ float* Ub() { return u + kUbOff; }
   __device__ float* xin() { return u; }
   __device__ float* V() { return u + NpA; }
   __device__ float* G() { return u + 2 * NpA; }
@@ -394,7 +399,7 @@ stepper_kernel(StepArgs A, DevTables t) {
         auto& ap = blk<K - 1>(st);
         if (i < np) {
 #pragma unroll
-          for (int q = 0; q < Qp; ++q) X[i * 32 + h * 16 + q] = ap[q];
+          for (int q = 0; q < Qp; ++q) X[i * kXS + h * 16 + q] = ap[q];
         }
         wsync();
 #pragma unroll
@@ -406,21 +411,21 @@ stepper_kernel(StepArgs A, DevTables t) {
 #pragma unroll
             for (int sl = kSlB; sl < kSlB + kNSlB; ++sl) {
               const float me = mk[kSlotKindRow[sl]] * eval[z + sl * Np + row];
-              const float* xr = X + (int(ecol[z + sl * Np + row]) - offp) * 32 + h * 16;
+              const float* xr = X + (int(ecol[z + sl * Np + row]) - offp) * kXS + h * 16;
 #pragma unroll
               for (int q = 0; q < Qp; ++q) u[q] = fmaf(me, xr[q], u[q]);
               __builtin_amdgcn_sched_barrier(0);
             }
           } else {
             const int t = i & 1;
-            const float* xs = X + i * 32 + h * 16;                // rows i + 2d
-            const float* xo = X + (i + 1 - 2 * t) * 32 + h * 16;  // rows i + 1 - 2t + 2d
+            const float* xs = X + i * kXS + h * 16;                // rows i + 2d
+            const float* xo = X + (i + 1 - 2 * t) * kXS + h * 16;  // rows i + 1 - 2t + 2d
 #pragma unroll
             for (int d = 0; d < 3; ++d) {
               const float ms_ = (d == 1 ? mk[8] : mk[5]) * wB[z + d * Np + row];
               const float mo_ = (d == 1 ? mk[7] : mk[6]) * wB[z + (3 + d) * Np + row];
 #pragma unroll
-              for (int q = 0; q < Qp; ++q) u[q] = fmaf(mo_, xo[64 * d + q], fmaf(ms_, xs[64 * d + q], u[q]));
+              for (int q = 0; q < Qp; ++q) u[q] = fmaf(mo_, xo[2 * kXS * d + q], fmaf(ms_, xs[2 * kXS * d + q], u[q]));
               __builtin_amdgcn_sched_barrier(0);
             }
           }
@@ -428,7 +433,7 @@ stepper_kernel(StepArgs A, DevTables t) {
         if constexpr (K == 1) {
           if (act) {
 #pragma unroll
-            for (int q = 0; q < Qp; ++q) Ub[i * 32 + h * 16 + q] = u[q];
+            for (int q = 0; q < Qp; ++q) Ub[i * kXS + h * 16 + q] = u[q];
           }
           wsync();
         } else {
@@ -441,7 +446,7 @@ stepper_kernel(StepArgs A, DevTables t) {
       }
       if (act) {
 #pragma unroll
-        for (int q = 0; q < Q; ++q) X[i * 32 + h * 16 + q] = 0.0f;
+        for (int q = 0; q < Q; ++q) X[i * kXS + h * 16 + q] = 0.0f;
       }
       wsync();
       if (act) {
@@ -450,15 +455,15 @@ stepper_kernel(StepArgs A, DevTables t) {
 #pragma unroll
         for (int sl = kSlD; sl < kSlD + kNSlD; ++sl) {
           const int cl = int(ecol[z + sl * Np + row]) - off0;
-          if ((cl & 1) == h) X[i * 32 + h * 16 + (cl >> 1)] += mk[kSlotKindRow[sl]] * eval[z + sl * Np + row];
+          if ((cl & 1) == h) X[i * kXS + h * 16 + (cl >> 1)] += mk[kSlotKindRow[sl]] * eval[z + sl * Np + row];
         }
-        if ((i & 1) == h) X[i * 32 + h * 16 + (i >> 1)] += 1.0f;
+        if ((i & 1) == h) X[i * kXS + h * 16 + (i >> 1)] += 1.0f;
       }
       wsync();
       // work on a local copy: the indexed pivot-column access must not touch the store itself
       float a[Q];
 #pragma unroll
-      for (int q = 0; q < Q; ++q) a[q] = act ? X[i * 32 + h * 16 + q] : 0.0f;
+      for (int q = 0; q < Q; ++q) a[q] = act ? X[i * kXS + h * 16 + q] : 0.0f;
       if constexpr (K == 1) {
         constexpr int offp = Gm::off(K - 1);
         if (act) {
@@ -470,7 +475,7 @@ stepper_kernel(StepArgs A, DevTables t) {
 #pragma unroll
             for (int sl = 0; sl < kNSlCol; ++sl) {
               const int rl = int(crow[z + sl * Np + c]) - offp;
-              acc = fmaf(mk[kSlotKindCol[sl]] * cvl[z + sl * Np + c], Ub[i * 32 + (rl & 1) * 16 + (rl >> 1)], acc);
+              acc = fmaf(mk[kSlotKindCol[sl]] * cvl[z + sl * Np + c], Ub[i * kXS + (rl & 1) * 16 + (rl >> 1)], acc);
             }
             a[q] -= acc;
             if ((q & 3) == 3) __builtin_amdgcn_sched_barrier(0);  // bound the gathers in flight

