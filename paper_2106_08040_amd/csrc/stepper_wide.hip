@@ -42,8 +42,8 @@ template <int L>
 struct WideLds {
   static constexpr int NpA = Geo<L>::NpA;
   static constexpr int kX = WGeo<L>::XR * WGeo<L>::XS;
-  static constexpr int kA = (((kX > 3 * NpA) ? kX : 3 * NpA) + 3) & ~3;  // keeps T 16-byte aligned
-  float a[kA];        // X (factorisation) | xin, V, Gs (stages)
+  static constexpr int kA = (((kX > 2 * NpA) ? kX : 2 * NpA) + 3) & ~3;  // keeps T 16-byte aligned
+  float a[kA];        // X (factorisation) | xin, V (stages)
   float g[NpA];       // G (block-solve result)
   float T[64];        // block right-hand side
   float prow[2][64];  // pivot rows
@@ -54,7 +54,6 @@ struct WideLds {
   __device__ float* xin() { return a; }
   __device__ float* V() { return a + NpA; }
   __device__ float* G() { return g; }
-  __device__ float* Gs() { return a + 2 * NpA; }
 };
 
 // In-place inverse of an n x n block, row `lane` in a[0..n-1], by Gauss-Jordan with 2 x 2 pivots.
@@ -296,29 +295,6 @@ stepper_wide_kernel(StepArgs A, DevTables t, float* ws) {
   // M = I - h g A span several thousand in scale and their FP32 inverses carry relative errors up to
   // ~1e-4; the residual V - M G is formed with exact products and FP64 sums (the multipliers are the
   // FP32 values the factorisation used), and one more solve with the same inverses removes that error.
-  // residual V <- V - M G (exact products, FP64 sums); G saved in Gs
-  auto residual = [&]() {
-    float* V = w.V();
-    float* G = w.G();
-    float* Gs = w.Gs();
-    float mkv[9];
-#pragma unroll
-    for (int k = 0; k < 9; ++k) mkv[k] = w.mk[k];
-#pragma unroll 1
-    for (int s = 0; s < S; ++s) {
-      const int p = lane + 64 * s;
-      if (p < Np) {
-        const float gp = G[p];
-        double acc = double(V[p]) - double(gp);
-#pragma unroll
-        for (int sl = 0; sl < kNSlRow; ++sl)
-          acc -= double(mkv[kSlotKindRow[sl]] * eval[sl * Np + p]) * double(G[ecol[sl * Np + p]]);
-        Gs[p] = gp;
-        V[p] = float(acc);
-      }
-    }
-    wsync();
-  };
   // factor M = I - h g A(t_n) (multipliers in w.mk): Schur-complement inverses into the workspace.
   // X holds the previous block's inverse (rows) on entry to each block.
   auto factor = [&]() {
@@ -517,22 +493,7 @@ stepper_wide_kernel(StepArgs A, DevTables t, float* ws) {
       wsync();
       matvec(V, true);
       wsync();
-      // the solve and one step of refinement share one call site (the solver body is inlined once)
-#pragma unroll 1
-      for (int pass = 0; pass < 2; ++pass) {
-        if (pass == 1) residual();
-        solve();
-        if (pass == 1) {
-          float* G = w.G();
-          const float* Gs = w.Gs();
-#pragma unroll
-          for (int s = 0; s < S; ++s) {
-            const int p = lane + 64 * s;
-            if (p < Np) G[p] += Gs[p];
-          }
-          wsync();
-        }
-      }
+      solve();
       if (stg < 5) {
         const float* G = w.G();
         float* kd = Kv + stg * NpA;
