@@ -23,6 +23,31 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 FP32_VECTOR_PEAK_TFLOPS = 157.3   # MI355X: 256 CU x 2.4 GHz x 256 FP32 flop/clk/CU
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "stepper_lissajous_2312_L16_traffic.json")
+STEPPER_SOURCES = ("stepper.hip", "stepper_common.hpp", "device_common.hpp", "device_util.hpp")
+
+
+def stepper_source_digest():
+    """SHA-256 over the sources of the time-stepper kernel (the measured counters belong to one build)."""
+    import hashlib
+    h = hashlib.sha256()
+    for f in STEPPER_SOURCES:
+        with open(os.path.join(ROOT, "paper_2106_08040_amd", "csrc", f), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()
+
+
+def measured_traffic():
+    """HBM bytes per stepper launch from the committed FETCH_SIZE / WRITE_SIZE counter summary, or None
+    when that summary was taken on different kernel sources."""
+    try:
+        with open(TRAFFIC_FILE) as fh:
+            t = json.load(fh)
+    except (OSError, ValueError):
+        return None
+    if t.get("stepper_source_sha256") != stepper_source_digest():
+        return None
+    return float(t["hbm_bytes_per_launch"])
 
 
 def block_structure(L):
@@ -282,6 +307,9 @@ def main():
     ap.add_argument("--tol", type=float, default=0.0, help="adaptive error bound (0 = library default)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-budget", type=float, default=15.0)
+    ap.add_argument("--copy-calibration", action="store_true",
+                    help="run only a plain 256 MiB device copy three times (reference for the FETCH_SIZE / "
+                         "WRITE_SIZE counters) and exit")
     ap.add_argument("--workload", choices=("lissajous", "uneven", "surrogate"), default="lissajous",
                     help="lissajous: 2312-instance system matrix, L = 16 (headline); "
                          "uneven: 4096 instances with L = 8..24 in one graph launch; "
@@ -296,6 +324,14 @@ def main():
     import paper_2106_08040_amd as fpn
     import workloads as W
 
+    if args.copy_calibration:
+        a = torch.ones(64 * 1024 * 1024, device="cuda:0")
+        b = torch.empty_like(a)
+        for _ in range(3):
+            b.copy_(a)
+        torch.cuda.synchronize()
+        print(json.dumps({"copy_bytes": a.numel() * 4, "copies": 3}), flush=True)
+        return
     if args.workload == "uneven":
         return bench_uneven(args)
     if args.workload == "surrogate":
@@ -360,7 +396,7 @@ def main():
                    "substeps": args.substeps if args.substeps else "adaptive", "avg_substeps": avg_sub,
                    "integrator": "RODAS4", "failed_instances": bad},
         "roofline": {"bound": "alu", "kernel": "stepper", "achieved": achieved, "peak": FP32_VECTOR_PEAK_TFLOPS,
-                     "unit": "TFLOP/s", "frac": achieved / FP32_VECTOR_PEAK_TFLOPS, "traffic": None,
+                     "unit": "TFLOP/s", "frac": achieved / FP32_VECTOR_PEAK_TFLOPS, "traffic": measured_traffic(),
                      "avg_launch_ms": avg_ms, "flops_per_launch": flops_launch,
                      "kernel_ms": {k: v[0] / max(v[1], 1) for k, v in timing.items()}},
     }

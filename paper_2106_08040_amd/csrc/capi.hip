@@ -462,7 +462,7 @@ fpn_status plan_build(fpn_plan_s* p, fpn_ctx ctx, const fpn_drive* drive, const 
     g.ws_off = ws_total;
     ws_total += int64_t(g.grid) * waves * fpn::stepper_ws_floats(g.L);
     g.tws_off = tws_total;
-    if (tangent) tws_total += int64_t(g.grid) * waves * fpn::stepper_tan_ws_floats(g.L);
+    if (g.L <= 16) tws_total += int64_t(g.grid) * waves * fpn::stepper_reg_ws_floats(g.L, tangent);
     g.inv_off = inv_total;
     inv_total += int64_t(g.cnt) * g.t->inv_doubles;
   }
@@ -480,10 +480,10 @@ fpn_status plan_build(fpn_plan_s* p, fpn_ctx ctx, const fpn_drive* drive, const 
     FPN_HIP(p->own_m.ensure(size_t(n) * 3 * Ns));
     p->msamp = p->own_m.p;
   }
+  if (tws_total) FPN_HIP(p->tws.ensure(size_t(tws_total)));
   if (tangent) {
     const int nch = (opts->flags & FPN_HARM_Z) ? 3 : 2;
     FPN_HIP(p->c0t.ensure(size_t(n) * fpn::kNTan * p->np_max));
-    FPN_HIP(p->tws.ensure(size_t(tws_total)));
     p->mtan = dm_out;
     if (!p->mtan) {
       FPN_HIP(p->own_mt.ensure(size_t(n) * fpn::kNTan * 3 * Ns));
@@ -582,10 +582,10 @@ fpn_status plan_launch(fpn_plan_s* p, hipStream_t stream, bool timing) {
     sl.steps_out = p->steps.p;
     sl.queue = p->queue.p + gi;
     sl.grid = g.grid;
+    if (g.L <= 16 && p->tws.p) sl.tws = p->tws.p + g.tws_off;
     if (p->tangent) {
       sl.c0t = p->c0t.p;
       sl.mtan = p->mtan;
-      sl.tws = p->tws.p + g.tws_off;
     }
     if (fpn_status s = tm(2, gs, [&]() -> fpn_status {
           FPN_HIP(fpn::launch_stepper(g.L, sl, *g.t, p->wide_ws.p ? p->wide_ws.p + g.ws_off : nullptr, gs));

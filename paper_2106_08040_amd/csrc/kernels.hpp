@@ -27,7 +27,7 @@ struct StepLaunch {
   int grid;                  // workgroups to launch (0: one wavefront per instance)
   const double* c0t = nullptr;  // tangents (L <= 16): initial states [n][kNTan][c_stride]
   float* mtan = nullptr;        // tangents: samples [n][kNTan][3][Ns]; null for a plain solve
-  float* tws = nullptr;         // tangents: workspace, stepper_tan_ws_floats(L) per resident wavefront
+  float* tws = nullptr;         // L <= 16: workspace, stepper_reg_ws_floats(L, tangents) per resident wavefront
 };
 
 template <int L>
@@ -44,7 +44,11 @@ template <int L>
 hipError_t stepper_wide_occupancy_L(int* waves_per_block, int* blocks_per_cu);
 // wavefronts per workgroup and resident workgroups per CU of the stepper for degree L
 hipError_t stepper_occupancy(int L, const DevTables& t, bool tangents, int* waves_per_block, int* blocks_per_cu);
-inline int64_t stepper_tan_ws_floats(int L) { return int64_t(8 * kNTan) * (((L + 1) * (L + 1) + 1 + 3) & ~3); }
+// register-layout stepper workspace per resident wavefront (floats): the tangent vectors (none without
+// tangents)
+inline int64_t stepper_reg_ws_floats(int L, bool tangents) {
+  return tangents ? int64_t(8 * kNTan) * (((L + 1) * (L + 1) + 1 + 3) & ~3) : 0;
+}
 
 void launch_instance_prep(int64_t n, const double* D, const double* Ms, const double* K, const double* alpha,
                           const double* temp, const double* easy, const double* offset, InstParams* ip,

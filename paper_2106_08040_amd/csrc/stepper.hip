@@ -560,34 +560,25 @@ stepper_kernel(StepArgs A, DevTables t) {
         }
       }
     }
-    float yt[S], kr[S];
     for (int stg = 0; stg < 6; ++stg) {
       const float mt = mult_lane(tn + double(kRodasAlpha[stg]) * hs);
       if (lane < 9) w.ms[lane] = mt;
-      // stage argument and the extra right-hand-side terms
-      float ex[S];
-#pragma unroll
-      for (int s = 0; s < S; ++s) {
-        const int p = lane + 64 * s;
-        float yv = y[s];
-        float ev = (p < Np) ? hf * kRodasGamma[stg] * w.ft()[p] : 0.0f;
-        for (int j = 0; j < stg; ++j) {
-          const float kj = (p < Np) ? w.Kv(j)[p] : 0.0f;
-          yv = fmaf(kRodasA[stg][j], kj, yv);
-          ev = fmaf(kRodasC[stg][j] * ih, kj, ev);
-        }
-        yt[s] = yv;
-        ex[s] = ev;
-      }
-      // V = A(ms) yt + ex; solve; K = h g M^{-1} V
+      // stage argument -> xin, extra right-hand-side terms -> V (no per-lane copies kept: registers)
       float* xin = w.xin();
       float* V = w.V();
 #pragma unroll
       for (int s = 0; s < S; ++s) {
         const int p = lane + 64 * s;
         if (p < Np) {
-          xin[p] = yt[s];
-          V[p] = ex[s];
+          float yv = y[s];
+          float ev = hf * kRodasGamma[stg] * w.ft()[p];
+          for (int j = 0; j < stg; ++j) {
+            const float kj = w.Kv(j)[p];
+            yv = fmaf(kRodasA[stg][j], kj, yv);
+            ev = fmaf(kRodasC[stg][j] * ih, kj, ev);
+          }
+          xin[p] = yv;
+          V[p] = ev;
         }
       }
       wsync();
@@ -595,12 +586,13 @@ stepper_kernel(StepArgs A, DevTables t) {
       wsync();
       solve();
       const float* G = w.G();
-      float* kd = w.Kv(stg < 5 ? stg : 4);
+      if (stg < 5) {
+        float* kd = w.Kv(stg);
 #pragma unroll
-      for (int s = 0; s < S; ++s) {
-        const int p = lane + 64 * s;
-        kr[s] = (p < Np) ? hg * G[p] : 0.0f;
-        if (stg < 5 && p < Np) kd[p] = kr[s];
+        for (int s = 0; s < S; ++s) {
+          const int p = lane + 64 * s;
+          if (p < Np) kd[p] = hg * G[p];
+        }
       }
       if constexpr (NT > 0) {
         // tangents of this stage: same factorisation, right-hand sides from the primal stage
@@ -652,12 +644,20 @@ stepper_kernel(StepArgs A, DevTables t) {
       }
       wsync();
     }
-    // y_{n+1} = (y + sum_{j<6} a6j K_j) + K6 ; embedded error K6
+    // y_{n+1} = (stage-6 argument, in xin) + K6 ; embedded error K6 (with tangents K6 was kept in kc,
+    // G holds the last tangent solve)
     float emax = 0.0f;
+    {
+      const float* xin = w.xin();
+      const float* k6 = (NT > 0) ? w.kc() : w.G();
+      const float sc = (NT > 0) ? 1.0f : hg;
 #pragma unroll
-    for (int s = 0; s < S; ++s) {
-      y[s] = yt[s] + kr[s];
-      emax = fmaxf(emax, fabsf(kr[s]));
+      for (int s = 0; s < S; ++s) {
+        const int p = lane + 64 * s;
+        const float kv = (p < Np) ? sc * k6[p] : 0.0f;
+        y[s] = (p < Np) ? xin[p] + kv : 0.0f;
+        emax = fmaxf(emax, fabsf(kv));
+      }
     }
     return wave_max(emax);
   };
@@ -665,7 +665,8 @@ stepper_kernel(StepArgs A, DevTables t) {
   const double dt = A.period / A.Ns;
   const int n_int = (A.settle + 1) * A.Ns;
   const int first_rec = A.settle * A.Ns;
-  int r = (A.r_fixed > 0) ? A.r_fixed : 1;
+  double hstep = dt;                         // adaptive step size, kept across sample intervals
+  const double hmin = dt / (A.r_max > 0 ? A.r_max : 64);
   int steps = 0;
   for (int j = 0; j < n_int && ok; ++j) {
     const double tj = j * dt;
@@ -704,40 +705,47 @@ stepper_kernel(StepArgs A, DevTables t) {
         }
       }
     }
-    if constexpr (NT > 0) {
-      for (int pp = 0; pp < NT; ++pp)
-        for (int q = lane; q < Np; q += 64) TYS(pp)[q] = TY(pp)[q];
-    }
-    float ysave[S];
-#pragma unroll
-    for (int s = 0; s < S; ++s) ysave[s] = y[s];
-    while (true) {
-      const double hs = dt / r;
-      float emax = 0.0f;
-      for (int sub = 0; sub < r; ++sub) {
-        emax = fmaxf(emax, rodas_step(tj + sub * hs, hs));
-        ++steps;
+    // fixed: r_fixed equal steps per sample interval.  adaptive: steps of any size up to the sample
+    // spacing, each accepted (max |K6| <= tol) or redone on its own.  The last step of an interval
+    // lands on the next sample time.  (One call site of the stage routine keeps it inlined.)
+    const bool fixedr = A.r_fixed > 0;
+    double t = tj;
+    const double tend = tj + dt;
+    while (t < tend - 1e-9 * dt) {
+      double hs = fixedr ? dt / A.r_fixed : hstep;
+      bool landed = false;
+      if (hs >= (tend - t) * (fixedr ? 0.75 : 0.95)) {
+        hs = tend - t;
+        landed = true;
       }
-      if (!isfinite(emax)) {
+      float ysave[S];
+#pragma unroll
+      for (int s = 0; s < S; ++s) ysave[s] = y[s];
+      if constexpr (NT > 0) {
+        if (!fixedr)
+          for (int pp = 0; pp < NT; ++pp)
+            for (int q = lane; q < Np; q += 64) TYS(pp)[q] = TY(pp)[q];
+      }
+      const float e = rodas_step(t, hs);
+      ++steps;
+      if (!isfinite(e)) {
         ok = false;
         break;
       }
-      if (A.r_fixed > 0) break;
-      if (!(emax <= A.tol) && r < A.r_max && isfinite(emax)) {  // reject the interval, refine
+      const float fac = 0.9f * sqrtf(sqrtf(A.tol / fmaxf(e, 1e-30f)));
+      if (!fixedr && e > A.tol && hs > hmin * 1.0001) {  // reject this step only
 #pragma unroll
         for (int s = 0; s < S; ++s) y[s] = ysave[s];
         if constexpr (NT > 0) {
           for (int pp = 0; pp < NT; ++pp)
             for (int q = lane; q < Np; q += 64) TY(pp)[q] = TYS(pp)[q];
         }
-        const int rn = int(ceilf(float(r) * 1.2f * sqrtf(sqrtf(emax / A.tol))));
-        r = min(A.r_max, max(2 * r, rn));
+        hstep = fmax(hmin, hs * double(fmaxf(0.2f, fac)));
         continue;
       }
-      // accept; shrink the next interval's substeps when the estimate allows
-      const int rn = int(ceilf(float(r) * 1.2f * sqrtf(sqrtf(fmaxf(emax, 1e-30f) / A.tol))));
-      r = max(1, min(r, rn));
-      break;
+      t = landed ? tend : t + hs;
+      const double hn = hs * double(fminf(4.0f, fmaxf(0.2f, fac)));
+      hstep = fmin(dt, fmax(hmin, landed ? fmax(hn, hstep) : hn));
     }
   }
   if (!ok) {

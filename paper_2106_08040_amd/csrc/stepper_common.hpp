@@ -47,7 +47,8 @@ __device__ __forceinline__ float half_sum(float v) {
   return __uint_as_float(r[0]) + __uint_as_float(r[1]);
 }
 
-// Largest absolute value over the wavefront.
+// Largest absolute value over the wavefront, returned as a wavefront-uniform (scalar) value so that
+// control flow that depends on it stays uniform.
 __device__ __forceinline__ float wave_max(float v) {
   v = fmaxf(v, __shfl_xor(v, 16));
   v = fmaxf(v, __shfl_xor(v, 8));
@@ -55,7 +56,8 @@ __device__ __forceinline__ float wave_max(float v) {
   v = fmaxf(v, __shfl_xor(v, 2));
   v = fmaxf(v, __shfl_xor(v, 1));
   auto r = __builtin_amdgcn_permlane32_swap(__float_as_uint(v), __float_as_uint(v), false, false);
-  return fmaxf(__uint_as_float(r[0]), __uint_as_float(r[1]));
+  const float m = fmaxf(__uint_as_float(r[0]), __uint_as_float(r[1]));
+  return __int_as_float(__builtin_amdgcn_readfirstlane(__float_as_int(m)));
 }
 
 // RODAS4 (Hairer & Wanner) in the form
@@ -97,7 +99,7 @@ struct StepArgs {
   int32_t* queue;      // work counter of this launch, zero at launch
   const double* c0t;   // tangents: initial states [n_total][kNTan][c_stride] (FP64)
   float* mtan;         // tangents: samples [n_total][kNTan][3][Ns]; null without tangents
-  float* tws;          // tangents: workspace per resident wavefront (8 kNTan NpA floats)
+  float* tws;          // register layout with tangents: workspace per resident wavefront (8 NT NpA floats)
 };
 
 }  // namespace fpn

@@ -524,7 +524,8 @@ stepper_wide_kernel(StepArgs A, DevTables t, float* ws) {
   const double dt = A.period / A.Ns;
   const int n_int = (A.settle + 1) * A.Ns;
   const int first_rec = A.settle * A.Ns;
-  int r = (A.r_fixed > 0) ? A.r_fixed : 1;
+  double hstep = dt;                         // adaptive step size, kept across sample intervals
+  const double hmin = dt / (A.r_max > 0 ? A.r_max : 64);
   int steps = 0;
   for (int j = 0; j < n_int && ok; ++j) {
     const double tj = j * dt;
@@ -540,37 +541,46 @@ stepper_wide_kernel(StepArgs A, DevTables t, float* ws) {
       }
       ok = ok && isfinite(vx) && isfinite(vy) && isfinite(vz);
     }
-    float* ysave = Kg + 6 * NpA;
-#pragma unroll
-    for (int s = 0; s < S; ++s) {
-      const int p = lane + 64 * s;
-      if (p < Np) ysave[p] = y[s];
-    }
-    while (true) {
-      const double hs = dt / r;
-      float emax = 0.0f;
-      for (int sub = 0; sub < r; ++sub) {
-        emax = fmaxf(emax, rodas_step(tj + sub * hs, hs));
-        ++steps;
+    // fixed: r_fixed equal steps per sample interval.  adaptive: steps of any size up to the sample
+    // spacing, each accepted (max |K6| <= tol) or redone on its own.  The last step of an interval
+    // lands on the next sample time.  (One call site of the stage routine keeps it inlined.)
+    const bool fixedr = A.r_fixed > 0;
+    double t = tj;
+    const double tend = tj + dt;
+    while (t < tend - 1e-9 * dt) {
+      double hs = fixedr ? dt / A.r_fixed : hstep;
+      bool landed = false;
+      if (hs >= (tend - t) * (fixedr ? 0.75 : 0.95)) {
+        hs = tend - t;
+        landed = true;
       }
-      if (!isfinite(emax)) {
+      float* ysave = Kg + 6 * NpA;  // each lane saves and restores its own rows
+      if (!fixedr) {
+#pragma unroll
+        for (int s = 0; s < S; ++s) {
+          const int p = lane + 64 * s;
+          if (p < Np) ysave[p] = y[s];
+        }
+      }
+      const float e = rodas_step(t, hs);
+      ++steps;
+      if (!isfinite(e)) {
         ok = false;
         break;
       }
-      if (A.r_fixed > 0) break;
-      if (!(emax <= A.tol) && r < A.r_max) {
+      const float fac = 0.9f * sqrtf(sqrtf(A.tol / fmaxf(e, 1e-30f)));
+      if (!fixedr && e > A.tol && hs > hmin * 1.0001) {  // reject this step only
 #pragma unroll
         for (int s = 0; s < S; ++s) {
           const int p = lane + 64 * s;
           y[s] = (p < Np) ? ysave[p] : 0.0f;
         }
-        const int rn = int(ceilf(float(r) * 1.2f * sqrtf(sqrtf(emax / A.tol))));
-        r = min(A.r_max, max(2 * r, rn));
+        hstep = fmax(hmin, hs * double(fmaxf(0.2f, fac)));
         continue;
       }
-      const int rn = int(ceilf(float(r) * 1.2f * sqrtf(sqrtf(fmaxf(emax, 1e-30f) / A.tol))));
-      r = max(1, min(r, rn));
-      break;
+      t = landed ? tend : t + hs;
+      const double hn = hs * double(fminf(4.0f, fmaxf(0.2f, fac)));
+      hstep = fmin(dt, fmax(hmin, landed ? fmax(hn, hstep) : hn));
     }
   }
   if (!ok) {
