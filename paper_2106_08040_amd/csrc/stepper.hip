@@ -91,14 +91,22 @@ __device__ __forceinline__ bool gj2_invert(float (&a)[Q], int i, int h, W& w) {
       for (int q = 0; q < Q; ++q) w.row[(r * 2 + h) * 16 + q] = a[q];
     }
     wsync();
+    // every read of this elimination step is issued before the first use (one LDS wait)
     const float P00 = w.col[r0], P01 = w.col[32 + r0];
     const float P10 = w.col[r0 + 1], P11 = w.col[32 + r0 + 1];
+    const float g0r = w.col[i], g1r = w.col[32 + i];  // i < 32: in bounds for every lane
+    float w0[Q], w1[Q];
+#pragma unroll
+    for (int q = 0; q < Q; ++q) {
+      w0[q] = w.row[(0 * 2 + h) * 16 + q];
+      w1[q] = w.row[(1 * 2 + h) * 16 + q];
+    }
+    __builtin_amdgcn_sched_barrier(0);
     const float det = P00 * P11 - P01 * P10;
     ok = ok && (det != 0.0f) && isfinite(det);
-    const float id = 1.0f / det;
+    const float id = __builtin_amdgcn_rcpf(det);  // hardware reciprocal (1 ulp)
     const float Pi00 = P11 * id, Pi01 = -P01 * id, Pi10 = -P10 * id, Pi11 = P00 * id;
-    const float g0 = act ? w.col[i] : 0.0f;
-    const float g1 = act ? w.col[32 + i] : 0.0f;
+    const float g0 = act ? g0r : 0.0f, g1 = act ? g1r : 0.0f;
     float G0 = g0 * Pi00 + g1 * Pi10;
     float G1 = g0 * Pi01 + g1 * Pi11;
     float s = 1.0f;
@@ -109,8 +117,6 @@ __device__ __forceinline__ bool gj2_invert(float (&a)[Q], int i, int h, W& w) {
       G1 = (r == 0) ? -Pi01 : -Pi11;
       newc = (r == 0) ? ((h == 0) ? Pi00 : Pi01) : ((h == 0) ? Pi10 : Pi11);
     }
-    const float* w0 = w.row + (0 * 2 + h) * 16;
-    const float* w1 = w.row + (1 * 2 + h) * 16;
 #pragma unroll
     for (int q = 0; q < Q; ++q) a[q] = fmaf(-G1, w1[q], fmaf(-G0, w0[q], s * a[q]));
     a[qq] = act ? newc : 0.0f;
@@ -258,10 +264,27 @@ stepper_kernel(StepArgs A, DevTables t) {
       const uint16_t* ec = ecol + z;
       const float* ev = eval + z;
       if (p < Np) {
+        // table reads, then gathers, then the sum, seven couplings at a time: the LDS latency is paid
+        // twice per group rather than twice per coupling (the scheduler otherwise waits after every load)
+        constexpr int kG = 7;
+        static_assert(kNSlRow % kG == 0, "row slots come in whole groups");
         float acc = 0.0f;
 #pragma unroll
-        for (int sl = 0; sl < kNSlRow; ++sl)
-          acc = fmaf(m[kSlotKindRow[sl]] * ev[sl * Np + p], xin[ec[sl * Np + p]], acc);
+        for (int g0 = 0; g0 < kNSlRow; g0 += kG) {
+          int ci[kG];
+          float cv[kG], xv[kG];
+#pragma unroll
+          for (int u = 0; u < kG; ++u) {
+            ci[u] = ec[(g0 + u) * Np + p];
+            cv[u] = ev[(g0 + u) * Np + p];
+          }
+          __builtin_amdgcn_sched_barrier(0);
+#pragma unroll
+          for (int u = 0; u < kG; ++u) xv[u] = xin[ci[u]];
+          __builtin_amdgcn_sched_barrier(0);
+#pragma unroll
+          for (int u = 0; u < kG; ++u) acc = fmaf(m[kSlotKindRow[g0 + u]] * cv[u], xv[u], acc);
+        }
         dst[p] = add ? dst[p] + acc : acc;
       }
     }
@@ -320,21 +343,41 @@ stepper_kernel(StepArgs A, DevTables t) {
       if (h == 0 && i < n) {
         const int row = off0 + i;
         float tv = V[row];
+        // (loads first, then the sums: one LDS wait per phase instead of one per coupling)
         if constexpr (K == 1) {
           const int z = opaque_zero();
+          int ci[kNSlB];
+          float cv[kNSlB], gv[kNSlB];
 #pragma unroll
-          for (int sl = kSlB; sl < kSlB + kNSlB; ++sl)
-            tv = fmaf(-mk[kSlotKindRow[sl]] * eval[z + sl * Np + row], G[ecol[z + sl * Np + row]], tv);
+          for (int u = 0; u < kNSlB; ++u) {
+            ci[u] = ecol[z + (kSlB + u) * Np + row];
+            cv[u] = eval[z + (kSlB + u) * Np + row];
+          }
+          __builtin_amdgcn_sched_barrier(0);
+#pragma unroll
+          for (int u = 0; u < kNSlB; ++u) gv[u] = G[ci[u]];
+          __builtin_amdgcn_sched_barrier(0);
+#pragma unroll
+          for (int u = 0; u < kNSlB; ++u) tv = fmaf(-mk[kSlotKindRow[kSlB + u]] * cv[u], gv[u], tv);
         } else if constexpr (K >= 2) {
           constexpr int offp = Gm::off(K - 1);
           const int z = opaque_zero();
           const int t = i & 1;
           const float* gs = G + offp + i;
           const float* go = G + offp + i + 1 - 2 * t;
+          float wv[6], gsv[3], gov[3];
 #pragma unroll
           for (int d = 0; d < 3; ++d) {
-            tv = fmaf(-(d == 1 ? mRY : mFX) * wB[z + d * Np + row], gs[2 * d], tv);
-            tv = fmaf(-(d == 1 ? mRX : mFY) * wB[z + (3 + d) * Np + row], go[2 * d], tv);
+            wv[d] = wB[z + d * Np + row];
+            wv[3 + d] = wB[z + (3 + d) * Np + row];
+            gsv[d] = gs[2 * d];
+            gov[d] = go[2 * d];
+          }
+          __builtin_amdgcn_sched_barrier(0);
+#pragma unroll
+          for (int d = 0; d < 3; ++d) {
+            tv = fmaf(-(d == 1 ? mRY : mFX) * wv[d], gsv[d], tv);
+            tv = fmaf(-(d == 1 ? mRX : mFY) * wv[3 + d], gov[d], tv);
           }
         }
         w.T[(i & 1) * 16 + (i >> 1)] = tv;
@@ -361,10 +404,19 @@ stepper_kernel(StepArgs A, DevTables t) {
           const int t = (K > 0) ? (i & 1) : 0;
           const float* gs = G + offn + ((K > 0) ? i - 4 : 2 * i - 4);
           const float* go = G + offn + ((K > 0) ? i - 3 - 2 * t : 2 * i - 3);
+          float wv[6], gsv[3], gov[3];
 #pragma unroll
           for (int d = 0; d < 3; ++d) {
-            tv = fmaf((d == 1 ? mRY : mFX) * wC[z + d * Np + row], gs[2 * d], tv);
-            tv = fmaf((d == 1 ? mRX : mFY) * wC[z + (3 + d) * Np + row], go[2 * d], tv);
+            wv[d] = wC[z + d * Np + row];
+            wv[3 + d] = wC[z + (3 + d) * Np + row];
+            gsv[d] = gs[2 * d];
+            gov[d] = go[2 * d];
+          }
+          __builtin_amdgcn_sched_barrier(0);
+#pragma unroll
+          for (int d = 0; d < 3; ++d) {
+            tv = fmaf((d == 1 ? mRY : mFX) * wv[d], gsv[d], tv);
+            tv = fmaf((d == 1 ? mRX : mFY) * wv[3 + d], gov[d], tv);
           }
         }
         w.T[(i & 1) * 16 + (i >> 1)] = tv;
@@ -407,26 +459,47 @@ stepper_kernel(StepArgs A, DevTables t) {
         if (act) {
           const int row = off0 + i;
           const int z = opaque_zero();
+          // table entries first (one LDS wait), then each coupling's row of the inverse
           if constexpr (K == 1) {
+            int ci[kNSlB];
+            float cv[kNSlB];
 #pragma unroll
-            for (int sl = kSlB; sl < kSlB + kNSlB; ++sl) {
-              const float me = mk[kSlotKindRow[sl]] * eval[z + sl * Np + row];
-              const float* xr = X + (int(ecol[z + sl * Np + row]) - offp) * kXS + h * 16;
+            for (int u2 = 0; u2 < kNSlB; ++u2) {
+              ci[u2] = ecol[z + (kSlB + u2) * Np + row];
+              cv[u2] = eval[z + (kSlB + u2) * Np + row];
+            }
+            __builtin_amdgcn_sched_barrier(0);
 #pragma unroll
-              for (int q = 0; q < Qp; ++q) u[q] = fmaf(me, xr[q], u[q]);
+            for (int u2 = 0; u2 < kNSlB; ++u2) {
+              const float me = mk[kSlotKindRow[kSlB + u2]] * cv[u2];
+              const float* xr = X + (ci[u2] - offp) * kXS + h * 16;
+              float xv[Qp];
+#pragma unroll
+              for (int q = 0; q < Qp; ++q) xv[q] = xr[q];
               __builtin_amdgcn_sched_barrier(0);
+#pragma unroll
+              for (int q = 0; q < Qp; ++q) u[q] = fmaf(me, xv[q], u[q]);
             }
           } else {
             const int t = i & 1;
             const float* xs = X + i * kXS + h * 16;                // rows i + 2d
             const float* xo = X + (i + 1 - 2 * t) * kXS + h * 16;  // rows i + 1 - 2t + 2d
+            float wv[6];
+#pragma unroll
+            for (int d = 0; d < 6; ++d) wv[d] = wB[z + d * Np + row];
 #pragma unroll
             for (int d = 0; d < 3; ++d) {
-              const float ms_ = (d == 1 ? mk[8] : mk[5]) * wB[z + d * Np + row];
-              const float mo_ = (d == 1 ? mk[7] : mk[6]) * wB[z + (3 + d) * Np + row];
+              const float ms_ = (d == 1 ? mk[8] : mk[5]) * wv[d];
+              const float mo_ = (d == 1 ? mk[7] : mk[6]) * wv[3 + d];
+              float xsv[Qp], xov[Qp];
 #pragma unroll
-              for (int q = 0; q < Qp; ++q) u[q] = fmaf(mo_, xo[2 * kXS * d + q], fmaf(ms_, xs[2 * kXS * d + q], u[q]));
+              for (int q = 0; q < Qp; ++q) {
+                xsv[q] = xs[2 * kXS * d + q];
+                xov[q] = xo[2 * kXS * d + q];
+              }
               __builtin_amdgcn_sched_barrier(0);
+#pragma unroll
+              for (int q = 0; q < Qp; ++q) u[q] = fmaf(mo_, xov[q], fmaf(ms_, xsv[q], u[q]));
             }
           }
         }
@@ -450,20 +523,35 @@ stepper_kernel(StepArgs A, DevTables t) {
       }
       wsync();
       if (act) {
+        // diagonal-block entries of M: table reads first, then LDS atomic adds (entries of several
+        // slots can share a column; the adds need no wait in between)
         const int row = off0 + i;
         const int z = opaque_zero();
+        int cl[kNSlD];
+        float cv[kNSlD];
 #pragma unroll
-        for (int sl = kSlD; sl < kSlD + kNSlD; ++sl) {
-          const int cl = int(ecol[z + sl * Np + row]) - off0;
-          if ((cl & 1) == h) X[i * kXS + h * 16 + (cl >> 1)] += mk[kSlotKindRow[sl]] * eval[z + sl * Np + row];
+        for (int u2 = 0; u2 < kNSlD; ++u2) {
+          cl[u2] = int(ecol[z + (kSlD + u2) * Np + row]) - off0;
+          cv[u2] = eval[z + (kSlD + u2) * Np + row];
         }
-        if ((i & 1) == h) X[i * kXS + h * 16 + (i >> 1)] += 1.0f;
+        __builtin_amdgcn_sched_barrier(0);
+#pragma unroll
+        for (int u2 = 0; u2 < kNSlD; ++u2) {
+          if ((cl[u2] & 1) == h)
+            __hip_atomic_fetch_add(X + i * kXS + h * 16 + (cl[u2] >> 1), mk[kSlotKindRow[kSlD + u2]] * cv[u2],
+                                   __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WAVEFRONT);
+        }
+        if ((i & 1) == h)
+          __hip_atomic_fetch_add(X + i * kXS + h * 16 + (i >> 1), 1.0f, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WAVEFRONT);
       }
       wsync();
-      // work on a local copy: the indexed pivot-column access must not touch the store itself
+      // work on a local copy: the indexed pivot-column access must not touch the store itself.  Rows
+      // i >= n lie inside the scratch (rows 0..36) and are read unconditionally, then masked.
       float a[Q];
 #pragma unroll
-      for (int q = 0; q < Q; ++q) a[q] = act ? X[i * kXS + h * 16 + q] : 0.0f;
+      for (int q = 0; q < Q; ++q) a[q] = X[i * kXS + h * 16 + q];
+#pragma unroll
+      for (int q = 0; q < Q; ++q) a[q] = act ? a[q] : 0.0f;
       if constexpr (K == 1) {
         constexpr int offp = Gm::off(K - 1);
         if (act) {
@@ -472,13 +560,20 @@ stepper_kernel(StepArgs A, DevTables t) {
             const int c = off0 + h + 2 * q;
             float acc = 0.0f;
             const int z = opaque_zero();
+            int rl[kNSlCol];
+            float cv[kNSlCol], uv[kNSlCol];
 #pragma unroll
             for (int sl = 0; sl < kNSlCol; ++sl) {
-              const int rl = int(crow[z + sl * Np + c]) - offp;
-              acc = fmaf(mk[kSlotKindCol[sl]] * cvl[z + sl * Np + c], Ub[i * kXS + (rl & 1) * 16 + (rl >> 1)], acc);
+              rl[sl] = int(crow[z + sl * Np + c]) - offp;
+              cv[sl] = cvl[z + sl * Np + c];
             }
+            __builtin_amdgcn_sched_barrier(0);
+#pragma unroll
+            for (int sl = 0; sl < kNSlCol; ++sl) uv[sl] = Ub[i * kXS + (rl[sl] & 1) * 16 + (rl[sl] >> 1)];
+            __builtin_amdgcn_sched_barrier(0);
+#pragma unroll
+            for (int sl = 0; sl < kNSlCol; ++sl) acc = fmaf(mk[kSlotKindCol[sl]] * cv[sl], uv[sl], acc);
             a[q] -= acc;
-            if ((q & 3) == 3) __builtin_amdgcn_sched_barrier(0);  // bound the gathers in flight
           }
         }
       } else if constexpr (K >= 2) {
@@ -487,18 +582,32 @@ stepper_kernel(StepArgs A, DevTables t) {
         constexpr int Qp = Gm::nb(K - 1) / 2;
         if (act) {
           const int z = opaque_zero();
+          // window weights of two columns per LDS wait
 #pragma unroll
-          for (int q = 0; q < Q; ++q) {
-            const int c = off0 + h + 2 * q;
-            float acc = 0.0f;
+          for (int q0 = 0; q0 < Q; q0 += 2) {
+            float wv[2][6];
 #pragma unroll
-            for (int d = 0; d < 3; ++d) {
-              if (q + d < Qp) {
-                acc = fmaf((d == 1 ? mk[8] : mk[5]) * wS[z + d * Np + c], u[q + d], acc);
-                acc = fmaf((d == 1 ? mk[7] : mk[6]) * wS[z + (3 + d) * Np + c], uo[q + d], acc);
+            for (int qq = 0; qq < 2; ++qq) {
+              const int c = off0 + h + 2 * (q0 + qq);
+#pragma unroll
+              for (int d = 0; d < 6; ++d) wv[qq][d] = (q0 + qq < Q) ? wS[z + d * Np + c] : 0.0f;
+            }
+            __builtin_amdgcn_sched_barrier(0);
+#pragma unroll
+            for (int qq = 0; qq < 2; ++qq) {
+              const int q = q0 + qq;
+              if (q < Q) {
+                float acc = 0.0f;
+#pragma unroll
+                for (int d = 0; d < 3; ++d) {
+                  if (q + d < Qp) {
+                    acc = fmaf((d == 1 ? mk[8] : mk[5]) * wv[qq][d], u[q + d], acc);
+                    acc = fmaf((d == 1 ? mk[7] : mk[6]) * wv[qq][3 + d], uo[q + d], acc);
+                  }
+                }
+                a[q] -= acc;
               }
             }
-            a[q] -= acc;
           }
         }
       }
