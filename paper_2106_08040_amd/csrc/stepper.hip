@@ -147,7 +147,14 @@ stepper_kernel(StepArgs A, DevTables t) {
   WL* wl = reinterpret_cast<WL*>(smem + tb);
   for (int e = threadIdx.x; e < kNSlRow * Np; e += blockDim.x) { ecol[e] = t.ell_col[e]; eval[e] = t.ell_val[e]; }
   for (int e = threadIdx.x; e < kNSlCol * Np; e += blockDim.x) { crow[e] = t.ecol_row[e]; cvl[e] = t.ecol_val[e]; }
-  for (int e = threadIdx.x; e < kNWin * Np; e += blockDim.x) { wB[e] = t.win_b[e]; wC[e] = t.win_c[e]; wS[e] = t.win_s[e]; }
+  // wB, wC slot-major like the global tables; wS column-major ([column][6]): the Schur update reads
+  // the six weights of one column together (three 8-byte broadcast reads)
+  for (int e = threadIdx.x; e < kNWin * Np; e += blockDim.x) {
+    wB[e] = t.win_b[e];
+    wC[e] = t.win_c[e];
+    const int d = e / Np, c = e - d * Np;
+    wS[c * kNWin + d] = t.win_s[e];
+  }
   // per-wave scratch starts zeroed: window reads past a block edge (weight 0) then see finite data
   for (int e = threadIdx.x; e < int(WAVES * sizeof(WL) / 4); e += blockDim.x) reinterpret_cast<float*>(wl)[e] = 0.0f;
   __syncthreads();
@@ -582,19 +589,26 @@ stepper_kernel(StepArgs A, DevTables t) {
         constexpr int Qp = Gm::nb(K - 1) / 2;
         if (act) {
           const int z = opaque_zero();
-          // window weights of two columns per LDS wait
+          // window weights of four columns per LDS wait
+          constexpr int kC = 4;
 #pragma unroll
-          for (int q0 = 0; q0 < Q; q0 += 2) {
-            float wv[2][6];
+          for (int q0 = 0; q0 < Q; q0 += kC) {
+            float wv[kC][6];
 #pragma unroll
-            for (int qq = 0; qq < 2; ++qq) {
-              const int c = off0 + h + 2 * (q0 + qq);
+            for (int qq = 0; qq < kC; ++qq) {
+              if (q0 + qq < Q) {
+                const float2* src = reinterpret_cast<const float2*>(wS + z + (off0 + h + 2 * (q0 + qq)) * kNWin);
 #pragma unroll
-              for (int d = 0; d < 6; ++d) wv[qq][d] = (q0 + qq < Q) ? wS[z + d * Np + c] : 0.0f;
+                for (int d2 = 0; d2 < 3; ++d2) {
+                  const float2 v = src[d2];
+                  wv[qq][2 * d2] = v.x;
+                  wv[qq][2 * d2 + 1] = v.y;
+                }
+              }
             }
             __builtin_amdgcn_sched_barrier(0);
 #pragma unroll
-            for (int qq = 0; qq < 2; ++qq) {
+            for (int qq = 0; qq < kC; ++qq) {
               const int q = q0 + qq;
               if (q < Q) {
                 float acc = 0.0f;

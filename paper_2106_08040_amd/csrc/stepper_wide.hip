@@ -201,10 +201,26 @@ stepper_wide_kernel(StepArgs A, DevTables t, float* ws) {
       const float* ev = opaque_ptr(eval);
       const uint16_t* ec = opaque_ptr(ecol);
       if (p < Np) {
+        // table reads, then gathers, then the sum, seven couplings at a time (one wait per phase)
+        constexpr int kG = 7;
+        static_assert(kNSlRow % kG == 0, "row slots come in whole groups");
         float acc = 0.0f;
 #pragma unroll
-        for (int sl = 0; sl < kNSlRow; ++sl)
-          acc = fmaf(m[kSlotKindRow[sl]] * ev[sl * Np + p], xin[ec[sl * Np + p]], acc);
+        for (int g0 = 0; g0 < kNSlRow; g0 += kG) {
+          int ci[kG];
+          float cv[kG], xv[kG];
+#pragma unroll
+          for (int u = 0; u < kG; ++u) {
+            ci[u] = ec[(g0 + u) * Np + p];
+            cv[u] = ev[(g0 + u) * Np + p];
+          }
+          __builtin_amdgcn_sched_barrier(0);
+#pragma unroll
+          for (int u = 0; u < kG; ++u) xv[u] = xin[ci[u]];
+          __builtin_amdgcn_sched_barrier(0);
+#pragma unroll
+          for (int u = 0; u < kG; ++u) acc = fmaf(m[kSlotKindRow[g0 + u]] * cv[u], xv[u], acc);
+        }
         dst[p] = add ? dst[p] + acc : acc;
       }
     }
@@ -216,15 +232,19 @@ stepper_wide_kernel(StepArgs A, DevTables t, float* ws) {
     const float4* iv = reinterpret_cast<const float4*>(opaque_ptr(inv) + WG::ioff(K));
     float part = 0.0f;
     if (lane < n) {
+      // every column quad of this row is requested before the first use (one memory wait)
+      float4 cq[nq];
+#pragma unroll
+      for (int q = 0; q < nq; ++q) cq[q] = iv[q * n + lane];
+      __builtin_amdgcn_sched_barrier(0);
 #pragma unroll
       for (int q = 0; q < nq; ++q) {
-        const float4 c = iv[q * n + lane];
+        const float4 c = cq[q];
         const float4 tv = *reinterpret_cast<const float4*>(&w.T[4 * q]);
         part = fmaf(c.x, tv.x, part);
         part = fmaf(c.y, tv.y, part);
         part = fmaf(c.z, tv.z, part);
         part = fmaf(c.w, tv.w, part);
-        if ((q & 3) == 3) __builtin_amdgcn_sched_barrier(0);  // bound the loads in flight
       }
       if (subtract) G[off0 + lane] -= part;
       else G[off0 + lane] = part;
@@ -247,19 +267,39 @@ stepper_wide_kernel(StepArgs A, DevTables t, float* ws) {
       if (lane < n) {
         const int row = off0 + lane;
         float tv = V[row];
+        // (loads first, then the sums: one wait per phase instead of one per coupling)
         if constexpr (K == 1) {
+          int ci[kNSlB];
+          float cv[kNSlB], gv[kNSlB];
 #pragma unroll
-          for (int sl = kSlB; sl < kSlB + kNSlB; ++sl)
-            tv = fmaf(-mk[kSlotKindRow[sl]] * ev[sl * Np + row], G[ec[sl * Np + row]], tv);
+          for (int u = 0; u < kNSlB; ++u) {
+            ci[u] = ec[(kSlB + u) * Np + row];
+            cv[u] = ev[(kSlB + u) * Np + row];
+          }
+          __builtin_amdgcn_sched_barrier(0);
+#pragma unroll
+          for (int u = 0; u < kNSlB; ++u) gv[u] = G[ci[u]];
+          __builtin_amdgcn_sched_barrier(0);
+#pragma unroll
+          for (int u = 0; u < kNSlB; ++u) tv = fmaf(-mk[kSlotKindRow[kSlB + u]] * cv[u], gv[u], tv);
         } else if constexpr (K >= 2) {
           constexpr int offp = Gm::off(K - 1);
           const int tt = lane & 1;
           const float* gs = G + offp + lane;
           const float* go = G + offp + lane + 1 - 2 * tt;
+          float wv[6], gsv[3], gov[3];
 #pragma unroll
           for (int d = 0; d < 3; ++d) {
-            tv = fmaf(-(d == 1 ? mRY : mFX) * wb[d * Np + row], gs[2 * d], tv);
-            tv = fmaf(-(d == 1 ? mRX : mFY) * wb[(3 + d) * Np + row], go[2 * d], tv);
+            wv[d] = wb[d * Np + row];
+            wv[3 + d] = wb[(3 + d) * Np + row];
+            gsv[d] = gs[2 * d];
+            gov[d] = go[2 * d];
+          }
+          __builtin_amdgcn_sched_barrier(0);
+#pragma unroll
+          for (int d = 0; d < 3; ++d) {
+            tv = fmaf(-(d == 1 ? mRY : mFX) * wv[d], gsv[d], tv);
+            tv = fmaf(-(d == 1 ? mRX : mFY) * wv[3 + d], gov[d], tv);
           }
         }
         w.T[lane] = tv;
@@ -279,10 +319,19 @@ stepper_wide_kernel(StepArgs A, DevTables t, float* ws) {
         const int tt = (K > 0) ? (lane & 1) : 0;
         const float* gs = G + offn + ((K > 0) ? lane - 4 : 2 * lane - 4);
         const float* go = G + offn + ((K > 0) ? lane - 3 - 2 * tt : 2 * lane - 3);
+        float wv[6], gsv[3], gov[3];
 #pragma unroll
         for (int d = 0; d < 3; ++d) {
-          tv = fmaf((d == 1 ? mRY : mFX) * wc[d * Np + row], gs[2 * d], tv);
-          tv = fmaf((d == 1 ? mRX : mFY) * wc[(3 + d) * Np + row], go[2 * d], tv);
+          wv[d] = wc[d * Np + row];
+          wv[3 + d] = wc[(3 + d) * Np + row];
+          gsv[d] = gs[2 * d];
+          gov[d] = go[2 * d];
+        }
+        __builtin_amdgcn_sched_barrier(0);
+#pragma unroll
+        for (int d = 0; d < 3; ++d) {
+          tv = fmaf((d == 1 ? mRY : mFX) * wv[d], gsv[d], tv);
+          tv = fmaf((d == 1 ? mRX : mFY) * wv[3 + d], gov[d], tv);
         }
         w.T[lane] = tv;
       }
@@ -291,10 +340,6 @@ stepper_wide_kernel(StepArgs A, DevTables t, float* ws) {
       __builtin_amdgcn_sched_barrier(0);
     });
   };
-  // One step of iterative refinement of G = M^{-1} V.  At these degrees the Schur blocks of
-  // M = I - h g A span several thousand in scale and their FP32 inverses carry relative errors up to
-  // ~1e-4; the residual V - M G is formed with exact products and FP64 sums (the multipliers are the
-  // FP32 values the factorisation used), and one more solve with the same inverses removes that error.
   // factor M = I - h g A(t_n) (multipliers in w.mk): Schur-complement inverses into the workspace.
   // X holds the previous block's inverse (rows) on entry to each block.
   auto factor = [&]() {
@@ -317,10 +362,18 @@ stepper_wide_kernel(StepArgs A, DevTables t, float* ws) {
           if constexpr (K == 1) {
             const float* ev = opaque_ptr(eval);
             const uint16_t* ec = opaque_ptr(ecol);
+            int ci[kNSlB];
+            float cv[kNSlB];
+#pragma unroll
+            for (int u2 = 0; u2 < kNSlB; ++u2) {
+              ci[u2] = ec[(kSlB + u2) * Np + row];
+              cv[u2] = ev[(kSlB + u2) * Np + row];
+            }
+            __builtin_amdgcn_sched_barrier(0);
 #pragma unroll
             for (int sl = kSlB; sl < kSlB + kNSlB; ++sl) {
-              const float me = mk[kSlotKindRow[sl]] * ev[sl * Np + row];
-              const float* xr = X + (int(ec[sl * Np + row]) - offp) * XS;
+              const float me = mk[kSlotKindRow[sl]] * cv[sl - kSlB];
+              const float* xr = X + (ci[sl - kSlB] - offp) * XS;
 #pragma unroll
               for (int q = 0; q < np; ++q) {
                 u[q] = fmaf(me, xr[q], u[q]);
@@ -333,10 +386,14 @@ stepper_wide_kernel(StepArgs A, DevTables t, float* ws) {
             const float* xs = X + lane * XS;                // rows lane + 2d
             const float* xo = X + (lane + 1 - 2 * tt) * XS;  // rows lane + 1 - 2t + 2d
             const float* wb = opaque_ptr(wB);
+            float wv[6];
+#pragma unroll
+            for (int d = 0; d < 6; ++d) wv[d] = wb[d * Np + row];
+            __builtin_amdgcn_sched_barrier(0);
 #pragma unroll
             for (int d = 0; d < 3; ++d) {
-              const float ms_ = (d == 1 ? mk[8] : mk[5]) * wb[d * Np + row];
-              const float mo_ = (d == 1 ? mk[7] : mk[6]) * wb[(3 + d) * Np + row];
+              const float ms_ = (d == 1 ? mk[8] : mk[5]) * wv[d];
+              const float mo_ = (d == 1 ? mk[7] : mk[6]) * wv[3 + d];
 #pragma unroll
               for (int q = 0; q < np; ++q) {
                 u[q] = fmaf(mo_, xo[2 * d * XS + q], fmaf(ms_, xs[2 * d * XS + q], u[q]));
@@ -358,12 +415,20 @@ stepper_wide_kernel(StepArgs A, DevTables t, float* ws) {
         const int row = off0 + lane;
         const float* ev = opaque_ptr(eval);
         const uint16_t* ec = opaque_ptr(ecol);
+        // table reads first, then LDS atomic adds (several slots can share a column)
+        int cl[kNSlD];
+        float cv[kNSlD];
 #pragma unroll
-        for (int sl = kSlD; sl < kSlD + kNSlD; ++sl) {
-          const int cl = int(ec[sl * Np + row]) - off0;
-          X[lane * XS + cl] += mk[kSlotKindRow[sl]] * ev[sl * Np + row];
+        for (int u2 = 0; u2 < kNSlD; ++u2) {
+          cl[u2] = int(ec[(kSlD + u2) * Np + row]) - off0;
+          cv[u2] = ev[(kSlD + u2) * Np + row];
         }
-        X[lane * XS + lane] += 1.0f;
+        __builtin_amdgcn_sched_barrier(0);
+#pragma unroll
+        for (int u2 = 0; u2 < kNSlD; ++u2)
+          __hip_atomic_fetch_add(X + lane * XS + cl[u2], mk[kSlotKindRow[kSlD + u2]] * cv[u2], __ATOMIC_RELAXED,
+                                 __HIP_MEMORY_SCOPE_WAVEFRONT);
+        __hip_atomic_fetch_add(X + lane * XS + lane, 1.0f, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WAVEFRONT);
       }
       wsync();
       if constexpr (K >= 1) {
