@@ -686,51 +686,35 @@ stepper_kernel(StepArgs A, DevTables t) {
     for (int stg = 0; stg < 6; ++stg) {
       const float mt = mult_lane(tn + double(kRodasAlpha[stg]) * hs);
       if (lane < 9) w.ms[lane] = mt;
-      // stage argument -> xin, extra right-hand-side terms -> V (no per-lane copies kept: registers)
-      float* xin = w.xin();
-      float* V = w.V();
+      // r = 0: the primal stage; r = 1..NT: the tangent directions of the same stage (same
+      // factorisation, right-hand sides from the primal stage).  One call site of the block solve keeps
+      // it inlined, so the inverses stay in registers.
+#pragma unroll 1
+      for (int r = 0; r <= NT; ++r) {
+        float* V = w.V();
+        const int pp = r - 1;
+        if (r == 0) {
+          // stage argument -> xin, extra right-hand-side terms -> V (no per-lane copies kept: registers)
+          float* xin = w.xin();
 #pragma unroll
-      for (int s = 0; s < S; ++s) {
-        const int p = lane + 64 * s;
-        if (p < Np) {
-          float yv = y[s];
-          float ev = hf * kRodasGamma[stg] * w.ft()[p];
-          for (int j = 0; j < stg; ++j) {
-            const float kj = w.Kv(j)[p];
-            yv = fmaf(kRodasA[stg][j], kj, yv);
-            ev = fmaf(kRodasC[stg][j] * ih, kj, ev);
+          for (int s = 0; s < S; ++s) {
+            const int p = lane + 64 * s;
+            if (p < Np) {
+              float yv = y[s];
+              float ev = hf * kRodasGamma[stg] * w.ft()[p];
+              for (int j = 0; j < stg; ++j) {
+                const float kj = w.Kv(j)[p];
+                yv = fmaf(kRodasA[stg][j], kj, yv);
+                ev = fmaf(kRodasC[stg][j] * ih, kj, ev);
+              }
+              xin[p] = yv;
+              V[p] = ev;
+            }
           }
-          xin[p] = yv;
-          V[p] = ev;
-        }
-      }
-      wsync();
-      matvec(V, true, w.xin());
-      wsync();
-      solve();
-      const float* G = w.G();
-      if (stg < 5) {
-        float* kd = w.Kv(stg);
-#pragma unroll
-        for (int s = 0; s < S; ++s) {
-          const int p = lane + 64 * s;
-          if (p < Np) kd[p] = hg * G[p];
-        }
-      }
-      if constexpr (NT > 0) {
-        // tangents of this stage: same factorisation, right-hand sides from the primal stage
-        float* kc = w.kc();
-#pragma unroll
-        for (int s = 0; s < S; ++s) {
-          const int p = lane + 64 * s;
-          if (p < Np) kc[p] = hg * G[p];
-        }
-        const float tm = tan_lane(tn + double(kRodasAlpha[stg]) * hs, false);
-        if (lane < 9 * NT) w.dmi[lane / 9][lane % 9] = tm;
-        wsync();
-        for (int pp = 0; pp < NT; ++pp) {
+          wsync();
+          matvec(V, true, w.xin());
+        } else if constexpr (NT > 0) {
           float* xt = w.xt();
-          float* V = w.V();
           const float* yp = TY(pp);
           const float* fp = TF(pp);
 #pragma unroll
@@ -750,22 +734,43 @@ stepper_kernel(StepArgs A, DevTables t) {
           }
           wsync();
           matvec_tan(pp, hf * kRodasGamma[stg]);
-          wsync();
-          solve();
-          const float* Gt = w.G();
+        }
+        wsync();
+        solve();
+        const float* G = w.G();
+        if (r == 0) {
+          if (stg < 5) {
+            float* kd = w.Kv(stg);
+#pragma unroll
+            for (int s = 0; s < S; ++s) {
+              const int p = lane + 64 * s;
+              if (p < Np) kd[p] = hg * G[p];
+            }
+          }
+          if constexpr (NT > 0) {
+            float* kc = w.kc();
+#pragma unroll
+            for (int s = 0; s < S; ++s) {
+              const int p = lane + 64 * s;
+              if (p < Np) kc[p] = hg * G[p];
+            }
+            const float tm = tan_lane(tn + double(kRodasAlpha[stg]) * hs, false);
+            if (lane < 9 * NT) w.dmi[lane / 9][lane % 9] = tm;
+          }
+        } else if constexpr (NT > 0) {
+          const float* xt = w.xt();
 #pragma unroll
           for (int s = 0; s < S; ++s) {
             const int p = lane + 64 * s;
             if (p < Np) {
-              const float kt = hg * Gt[p];
+              const float kt = hg * G[p];
               if (stg < 5) TK(stg, pp)[p] = kt;
               else TY(pp)[p] = xt[p] + kt;
             }
           }
-          wsync();
         }
+        wsync();
       }
-      wsync();
     }
     // y_{n+1} = (stage-6 argument, in xin) + K6 ; embedded error K6 (with tangents K6 was kept in kc,
     // G holds the last tangent solve)
