@@ -61,6 +61,7 @@ struct WaveLds {
   float dmi[NT > 0 ? NT : 1][12];      // d multiplier / d p at the stage time
   float dmn[NT > 0 ? NT : 1][12];      // ... at t_n
   float ddm[NT > 0 ? NT : 1][12];      // d (time derivative of the multiplier) / d p at t_n
+  double ctl[4];                       // step controller: time, next step size, this step size, landed
   __device__ float* X() { return u; }
   __device__ float* Ub() { return u + kUbOff; }
   __device__ float* xin() { return u; }
@@ -639,8 +640,14 @@ stepper_kernel(StepArgs A, DevTables t) {
     const float hg = hf * 0.25f;
     const float ih = 1.0f / hf;
     {
+      // both multiplier sets of t_n before the factorisation (their shared sin/cos work is not kept
+      // live across it): M's in mk, the time derivatives for f_t in ms
       const float mt = mult_lane(tn);
-      if (lane < 9) { w.mk[lane] = -hg * mt; }
+      const float md = dmult_lane(tn);
+      if (lane < 9) {
+        w.mk[lane] = -hg * mt;
+        w.ms[lane] = md;
+      }
       wsync();
     }
     factor();
@@ -651,8 +658,6 @@ stepper_kernel(StepArgs A, DevTables t) {
         const int p = lane + 64 * s;
         if (p < Np) xin[p] = y[s];
       }
-      const float md = dmult_lane(tn);
-      if (lane < 9) w.ms[lane] = md;
       wsync();
       matvec(w.ft(), false, w.xin());
       wsync();
@@ -772,29 +777,38 @@ stepper_kernel(StepArgs A, DevTables t) {
         wsync();
       }
     }
-    // y_{n+1} = (stage-6 argument, in xin) + K6 ; embedded error K6 (with tangents K6 was kept in kc,
-    // G holds the last tangent solve)
+    // embedded error estimate max |K6|.  The candidate y_{n+1} = (stage-6 argument, in xin) + K6 stays in
+    // LDS (with tangents K6 was kept in kc, G holds the last tangent solve) until the step is accepted.
     float emax = 0.0f;
     {
-      const float* xin = w.xin();
       const float* k6 = (NT > 0) ? w.kc() : w.G();
       const float sc = (NT > 0) ? 1.0f : hg;
 #pragma unroll
       for (int s = 0; s < S; ++s) {
         const int p = lane + 64 * s;
-        const float kv = (p < Np) ? sc * k6[p] : 0.0f;
-        y[s] = (p < Np) ? xin[p] + kv : 0.0f;
-        emax = fmaxf(emax, fabsf(kv));
+        emax = fmaxf(emax, (p < Np) ? fabsf(sc * k6[p]) : 0.0f);
       }
     }
     return wave_max(emax);
+  };
+  // y <- y_{n+1} of the step just taken
+  auto accept = [&](float hg) {
+    const float* xin = w.xin();
+    const float* k6 = (NT > 0) ? w.kc() : w.G();
+    const float sc = (NT > 0) ? 1.0f : hg;
+#pragma unroll
+    for (int s = 0; s < S; ++s) {
+      const int p = lane + 64 * s;
+      y[s] = (p < Np) ? xin[p] + sc * k6[p] : 0.0f;
+    }
   };
 
   const double dt = A.period / A.Ns;
   const int n_int = (A.settle + 1) * A.Ns;
   const int first_rec = A.settle * A.Ns;
-  double hstep = dt;                         // adaptive step size, kept across sample intervals
-  const double hmin = dt / (A.r_max > 0 ? A.r_max : 64);
+  // The controller's FP64 scalars live in LDS across a step (re-read after it), so they take no
+  // registers while the step runs.
+  if (lane == 0) w.ctl[1] = dt;  // step size, kept across sample intervals
   int steps = 0;
   for (int j = 0; j < n_int && ok; ++j) {
     const double tj = j * dt;
@@ -837,18 +851,23 @@ stepper_kernel(StepArgs A, DevTables t) {
     // spacing, each accepted (max |K6| <= tol) or redone on its own.  The last step of an interval
     // lands on the next sample time.  (One call site of the stage routine keeps it inlined.)
     const bool fixedr = A.r_fixed > 0;
-    double t = tj;
-    const double tend = tj + dt;
-    while (t < tend - 1e-9 * dt) {
-      double hs = fixedr ? dt / A.r_fixed : hstep;
+    if (lane == 0) w.ctl[0] = tj;
+    wsync();
+    for (;;) {
+      const double dtv = A.period / A.Ns;
+      const double tend = j * dtv + dtv;
+      const double t = w.ctl[0];
+      if (!(t < tend - 1e-9 * dtv)) break;
+      double hs = fixedr ? dtv / A.r_fixed : w.ctl[1];
       bool landed = false;
       if (hs >= (tend - t) * (fixedr ? 0.75 : 0.95)) {
         hs = tend - t;
         landed = true;
       }
-      float ysave[S];
-#pragma unroll
-      for (int s = 0; s < S; ++s) ysave[s] = y[s];
+      if (lane == 0) {
+        w.ctl[2] = hs;
+        w.ctl[3] = landed ? 1.0 : 0.0;
+      }
       if constexpr (NT > 0) {
         if (!fixedr)
           for (int pp = 0; pp < NT; ++pp)
@@ -860,20 +879,28 @@ stepper_kernel(StepArgs A, DevTables t) {
         ok = false;
         break;
       }
+      const double dt2 = A.period / A.Ns;
+      const double hmin = dt2 / (A.r_max > 0 ? A.r_max : 64);
+      const double t2 = w.ctl[0], hst = w.ctl[1], hs2 = w.ctl[2];
+      const bool landed2 = w.ctl[3] != 0.0;
+      const double tend2 = j * dt2 + dt2;
       const float fac = 0.9f * sqrtf(sqrtf(A.tol / fmaxf(e, 1e-30f)));
-      if (!fixedr && e > A.tol && hs > hmin * 1.0001) {  // reject this step only
-#pragma unroll
-        for (int s = 0; s < S; ++s) y[s] = ysave[s];
+      if (!fixedr && e > A.tol && hs2 > hmin * 1.0001) {  // reject this step only: y is unchanged
         if constexpr (NT > 0) {
           for (int pp = 0; pp < NT; ++pp)
             for (int q = lane; q < Np; q += 64) TY(pp)[q] = TYS(pp)[q];
         }
-        hstep = fmax(hmin, hs * double(fmaxf(0.2f, fac)));
+        if (lane == 0) w.ctl[1] = fmax(hmin, hs2 * double(fmaxf(0.2f, fac)));
+        wsync();
         continue;
       }
-      t = landed ? tend : t + hs;
-      const double hn = hs * double(fminf(4.0f, fmaxf(0.2f, fac)));
-      hstep = fmin(dt, fmax(hmin, landed ? fmax(hn, hstep) : hn));
+      accept(float(hs2) * 0.25f);
+      const double hn = hs2 * double(fminf(4.0f, fmaxf(0.2f, fac)));
+      if (lane == 0) {
+        w.ctl[0] = landed2 ? tend2 : t2 + hs2;
+        w.ctl[1] = fmin(dt2, fmax(hmin, landed2 ? fmax(hn, hst) : hn));
+      }
+      wsync();
     }
   }
   if (!ok) {

@@ -35,7 +35,7 @@ struct WGeo {
     return o;
   }
   static constexpr int INV = ioff(L + 1);        // floats of all block inverses
-  static constexpr int WS = INV + 7 * G::NpA;    // + K1..K5, f_t and the saved state
+  static constexpr int WS = INV + 6 * G::NpA;    // + K1..K5 and f_t
 };
 
 template <int L>
@@ -50,6 +50,7 @@ struct WideLds {
   float cw[6][64];    // Schur coefficients of one block, multiplier included
   float mk[16];
   float ms[16];
+  double ctl[4];      // step controller: time, next step size, this step size, landed
   __device__ float* X() { return a; }
   __device__ float* xin() { return a; }
   __device__ float* V() { return a + NpA; }
@@ -130,7 +131,7 @@ stepper_wide_kernel(StepArgs A, DevTables t, float* ws) {
   const int inst = A.inst_idx[qk];
   WL& w = wl[wid];
   float* inv = ws + int64_t(slot) * WG::WS;
-  float* Kg = inv + WG::INV;  // K1..K5 at j * NpA, f_t at 5 * NpA, saved state at 6 * NpA
+  float* Kg = inv + WG::INV;  // K1..K5 at j * NpA, f_t at 5 * NpA
   const uint16_t* ecol = t.ell_col;
   const float* eval = t.ell_val;
   const float* wB = t.win_b;
@@ -516,8 +517,14 @@ stepper_wide_kernel(StepArgs A, DevTables t, float* ws) {
     const float hg = hf * 0.25f;
     const float ih = 1.0f / hf;
     {
+      // both multiplier sets of t_n before the factorisation (their shared sin/cos work is not kept
+      // live across it): M's in mk, the time derivatives for f_t in ms
       const float mt = mult_lane(tn);
-      if (lane < 9) w.mk[lane] = -hg * mt;
+      const float md = dmult_lane(tn);
+      if (lane < 9) {
+        w.mk[lane] = -hg * mt;
+        w.ms[lane] = md;
+      }
       wsync();
     }
     factor();
@@ -528,8 +535,6 @@ stepper_wide_kernel(StepArgs A, DevTables t, float* ws) {
         const int p = lane + 64 * s;
         if (p < Np) xin[p] = y[s];
       }
-      const float md = dmult_lane(tn);
-      if (lane < 9) w.ms[lane] = md;
       wsync();
       matvec(ft, false);
       wsync();
@@ -571,26 +576,35 @@ stepper_wide_kernel(StepArgs A, DevTables t, float* ws) {
       wsync();
     }
     // y_{n+1} = (stage-6 argument) + K6 ; embedded error K6
+    // embedded error estimate max |K6|; the candidate (stage-6 argument in xin) + K6 stays in LDS until
+    // the step is accepted
     float emax = 0.0f;
     {
-      const float* xin = w.xin();
       const float* G = w.G();
 #pragma unroll
       for (int s = 0; s < S; ++s) {
         const int p = lane + 64 * s;
-        const float k6 = (p < Np) ? hg * G[p] : 0.0f;
-        y[s] = (p < Np) ? xin[p] + k6 : 0.0f;
-        emax = fmaxf(emax, fabsf(k6));
+        emax = fmaxf(emax, (p < Np) ? fabsf(hg * G[p]) : 0.0f);
       }
     }
     return wave_max(emax);
+  };
+  // y <- y_{n+1} of the step just taken
+  auto accept = [&](float hg) {
+    const float* xin = w.xin();
+    const float* G = w.G();
+#pragma unroll
+    for (int s = 0; s < S; ++s) {
+      const int p = lane + 64 * s;
+      y[s] = (p < Np) ? xin[p] + hg * G[p] : 0.0f;
+    }
   };
 
   const double dt = A.period / A.Ns;
   const int n_int = (A.settle + 1) * A.Ns;
   const int first_rec = A.settle * A.Ns;
-  double hstep = dt;                         // adaptive step size, kept across sample intervals
-  const double hmin = dt / (A.r_max > 0 ? A.r_max : 64);
+  // The controller's FP64 scalars live in LDS across a step (re-read after it).
+  if (lane == 0) w.ctl[1] = dt;  // step size, kept across sample intervals
   int steps = 0;
   for (int j = 0; j < n_int && ok; ++j) {
     const double tj = j * dt;
@@ -610,22 +624,22 @@ stepper_wide_kernel(StepArgs A, DevTables t, float* ws) {
     // spacing, each accepted (max |K6| <= tol) or redone on its own.  The last step of an interval
     // lands on the next sample time.  (One call site of the stage routine keeps it inlined.)
     const bool fixedr = A.r_fixed > 0;
-    double t = tj;
-    const double tend = tj + dt;
-    while (t < tend - 1e-9 * dt) {
-      double hs = fixedr ? dt / A.r_fixed : hstep;
+    if (lane == 0) w.ctl[0] = tj;
+    wsync();
+    for (;;) {
+      const double dtv = A.period / A.Ns;
+      const double tend = j * dtv + dtv;
+      const double t = w.ctl[0];
+      if (!(t < tend - 1e-9 * dtv)) break;
+      double hs = fixedr ? dtv / A.r_fixed : w.ctl[1];
       bool landed = false;
       if (hs >= (tend - t) * (fixedr ? 0.75 : 0.95)) {
         hs = tend - t;
         landed = true;
       }
-      float* ysave = Kg + 6 * NpA;  // each lane saves and restores its own rows
-      if (!fixedr) {
-#pragma unroll
-        for (int s = 0; s < S; ++s) {
-          const int p = lane + 64 * s;
-          if (p < Np) ysave[p] = y[s];
-        }
+      if (lane == 0) {
+        w.ctl[2] = hs;
+        w.ctl[3] = landed ? 1.0 : 0.0;
       }
       const float e = rodas_step(t, hs);
       ++steps;
@@ -633,19 +647,24 @@ stepper_wide_kernel(StepArgs A, DevTables t, float* ws) {
         ok = false;
         break;
       }
+      const double dt2 = A.period / A.Ns;
+      const double hmin = dt2 / (A.r_max > 0 ? A.r_max : 64);
+      const double t2 = w.ctl[0], hst = w.ctl[1], hs2 = w.ctl[2];
+      const bool landed2 = w.ctl[3] != 0.0;
+      const double tend2 = j * dt2 + dt2;
       const float fac = 0.9f * sqrtf(sqrtf(A.tol / fmaxf(e, 1e-30f)));
-      if (!fixedr && e > A.tol && hs > hmin * 1.0001) {  // reject this step only
-#pragma unroll
-        for (int s = 0; s < S; ++s) {
-          const int p = lane + 64 * s;
-          y[s] = (p < Np) ? ysave[p] : 0.0f;
-        }
-        hstep = fmax(hmin, hs * double(fmaxf(0.2f, fac)));
+      if (!fixedr && e > A.tol && hs2 > hmin * 1.0001) {  // reject this step only: y is unchanged
+        if (lane == 0) w.ctl[1] = fmax(hmin, hs2 * double(fmaxf(0.2f, fac)));
+        wsync();
         continue;
       }
-      t = landed ? tend : t + hs;
-      const double hn = hs * double(fminf(4.0f, fmaxf(0.2f, fac)));
-      hstep = fmin(dt, fmax(hmin, landed ? fmax(hn, hstep) : hn));
+      accept(float(hs2) * 0.25f);
+      const double hn = hs2 * double(fminf(4.0f, fmaxf(0.2f, fac)));
+      if (lane == 0) {
+        w.ctl[0] = landed2 ? tend2 : t2 + hs2;
+        w.ctl[1] = fmin(dt2, fmax(hmin, landed2 ? fmax(hn, hst) : hn));
+      }
+      wsync();
     }
   }
   if (!ok) {
