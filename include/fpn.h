@@ -89,7 +89,10 @@ typedef struct {
   int32_t settle_periods;      /* >= 0; the period with index settle_periods is recorded */
   int32_t n_harm;              /* K_h: harmonic bins 0..K_h, 0 <= K_h < N_s/2 */
   int32_t substeps;            /* 1..64: fixed time steps per sample interval;
-                                  0: adaptive per interval (1..64 steps) from the embedded error */
+                                  0: adaptive: every RODAS4 step is accepted or redone on its own
+                                  embedded error, step sizes between 1/64 of the sample spacing and
+                                  the sample spacing, the last step of each interval ending on the
+                                  sample time */
   uint32_t flags;              /* FPN_OUT_* */
   double tol;                  /* adaptive: bound on the embedded error max|K6| of every step,
                                   0 selects the default 5e-6; ignored when substeps > 0 */

@@ -18,7 +18,7 @@ struct StepLaunch {
   int settle;
   int Ns;
   int r_fixed;               // > 0 fixed substeps per sample interval, 0 adaptive
-  int r_max;
+  int r_max;                 // adaptive: smallest step = sample spacing / r_max
   float tol;
   float* msamp;              // [n][3][Ns]
   int32_t* status;

@@ -1,5 +1,5 @@
 // FP32 time stepper (rows a4/a5): one wavefront per instance, linearly implicit
-// L-stable RODAS4 with adaptive substeps per sample interval.
+// L-stable RODAS4 with per-step error control.
 //
 // The Galerkin ODE dc/dt = A(t) c (paper: Eq. FP-general with the drift of
 // Eq. convection, easy-axis frame) is integrated over (settle + 1) drive periods.

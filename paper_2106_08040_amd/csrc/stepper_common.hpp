@@ -91,7 +91,7 @@ struct StepArgs {
   int settle;
   int Ns;
   int r_fixed;   // > 0: fixed substeps per sample interval; 0: adaptive
-  int r_max;
+  int r_max;     // adaptive: smallest step = sample spacing / r_max
   float tol;     // adaptive: bound on max |K6| (embedded RODAS4 error) per step
   float* msamp;  // [n_total][3][Ns]
   int32_t* status;
