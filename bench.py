@@ -144,7 +144,8 @@ def wait_with_progress(torch, what, t0):
 
 def bench_uneven(args):
     """4096 instances with D, K, alpha, axis and offset drawn at random and L = 8..24 from the
-    anisotropy: one plan, cost-ordered by the step counts of the warm-up run, launched as one graph."""
+    anisotropy: workgroup size per degree from the autotuner, one plan, cost-ordered by the step counts
+    of the warm-up run, launched as one graph."""
     import torch
     import paper_2106_08040_amd as fpn
     import workloads as W
@@ -155,6 +156,15 @@ def bench_uneven(args):
     L = ws["inst"]["L"]
     d = ws["drive"]
     drive = fpn.make_drive(d["amp"], d["freq"], d["period"], d["phase"])
+    # autotuner: per degree, the fastest compiled workgroup size on a synthetic probe (untimed)
+    t_tune = time.perf_counter()
+    tuned = {}
+    for l in np.unique(L):
+        w, ns = ctx.autotune(int(l))
+        tuned[int(l)] = {"waves": w, "ns_per_step": {str(k): v for k, v in ns.items()}}
+    t_tune = time.perf_counter() - t_tune
+    print(f"[bench] autotune {t_tune:.1f} s: " + ", ".join(f"L{l}:{v['waves']}" for l, v in tuned.items()),
+          file=sys.stderr, flush=True)
     t0 = time.perf_counter()
     warm = ctx.plan(ws["inst"], L, drive, ws["samples"], ws["settle"], ws["n_harm"], want_m=False,
                     substeps=args.substeps, tol=args.tol)
@@ -188,6 +198,7 @@ def bench_uneven(args):
                    "samples": ws["samples"], "settle_periods": ws["settle"], "n_harm": ws["n_harm"],
                    "schedule": "one graph launch, degree buckets on concurrent streams, persistent queues, "
                                "cost order from the warm-up step counts",
+                   "autotune_s": t_tune, "autotuned_waves": {str(k): v["waves"] for k, v in tuned.items()},
                    "warmup_batch_order_s": t_warm, "avg_steps_per_interval": float(steps.mean()) /
                    ((ws["settle"] + 1) * ws["samples"]), "failed_instances": int((st != 0).sum()),
                    "failed_status_counts": np.bincount(st).tolist()},

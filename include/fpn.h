@@ -178,6 +178,35 @@ fpn_status fpn_plan_graph_launch(fpn_plan plan, void* stream);
 fpn_status fpn_plan_steps(fpn_plan plan, int32_t* steps_out);
 fpn_status fpn_plan_destroy(fpn_plan plan);
 
+/* ---- Launch configuration and autotuner (batching of uneven degrees) ----
+ * The register-layout stepper (L <= 16) is compiled for several workgroup sizes: 8 instances per
+ * workgroup for every degree, and 12 and 16 for L <= 13.  A larger workgroup shares the per-degree
+ * operator tables in LDS among more instances, so more instances fit on a compute unit, at a smaller
+ * register budget per instance.  Which is fastest depends on L; results are bitwise identical for
+ * every size (each instance is integrated by one wavefront in the same order).  The context keeps
+ * one size per degree, used by fpn_solve and fpn_plan_create (a plan keeps the size it was built
+ * with); the tangent stepper of fpn_solve_tangent and fpn_adjoint has a size of its own. */
+
+/* Workgroup sizes compiled for degree L: *count (1..3) sizes written to waves (capacity >= 3).
+ * For L = 17..24 (one configuration) the single entry is 0.  Errors: FPN_E_ARG. */
+fpn_status fpn_stepper_wave_options(int32_t L, int32_t* waves, int32_t* count);
+
+/* Use workgroup size `waves` (one of fpn_stepper_wave_options(L), or 0 for the default) for degree L
+ * in this context.  Errors: FPN_E_ARG (size not compiled for L), FPN_E_DEVICE (the configuration
+ * does not fit on a compute unit of this device). */
+fpn_status fpn_set_stepper_waves(fpn_ctx ctx, int32_t L, int32_t waves);
+
+/* Autotuner: time every workgroup size of degree L that fits on this device on a fixed synthetic
+ * probe batch (one particle, D = 20 nm, K = 2 kJ/m^3, alpha = 0.1, 295 K, easy axes on a spiral,
+ * 6 mT offsets on a ring; a 40 us drive with 3 and 4 cycles on x and y, 64 samples, 2 fixed steps
+ * per sample; twice as many instances as the largest configuration keeps resident, at most 16384)
+ * and keep the fastest for this context.  waves_out (may be NULL): the chosen size.
+ * ns_per_step_out (may be NULL, capacity >= 3): measured time per instance-step of each size, in
+ * the order of fpn_stepper_wave_options, +inf for a size that does not fit.  Allocates and frees
+ * its probe buffers and synchronises the device; the chosen size persists until changed.
+ * Errors: FPN_E_ARG, FPN_E_DEVICE. */
+fpn_status fpn_autotune(fpn_ctx ctx, int32_t L, int32_t* waves_out, double* ns_per_step_out);
+
 /* Time steps taken by the last fpn_solve on this context, summed over its instances
  * (synchronises with that solve).  HOST output.  Errors: FPN_E_ARG, FPN_E_DEVICE. */
 fpn_status fpn_last_steps(fpn_ctx ctx, int64_t* total_steps);

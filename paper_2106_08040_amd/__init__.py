@@ -37,7 +37,8 @@ EXPORTED = ["fpn_status_string", "fpn_last_error", "fpn_create", "fpn_destroy", 
             "fpn_host_table_nnz", "fpn_mlp_create", "fpn_mlp_destroy", "fpn_mlp_num_params", "fpn_mlp_params",
             "fpn_mlp_set_input_norm", "fpn_mlp_forward", "fpn_mlp_gradient", "fpn_mlp_train_step",
             "fpn_surrogate_features", "fpn_surrogate_predict", "fpn_plan_create", "fpn_plan_launch",
-            "fpn_plan_graph_launch", "fpn_plan_steps", "fpn_plan_destroy", "fpn_solve_tangent", "fpn_adjoint"]
+            "fpn_plan_graph_launch", "fpn_plan_steps", "fpn_plan_destroy", "fpn_solve_tangent", "fpn_adjoint",
+            "fpn_stepper_wave_options", "fpn_set_stepper_waves", "fpn_autotune"]
 
 
 class fpn_drive(ctypes.Structure):
@@ -110,6 +111,12 @@ _lib.fpn_solve_tangent.argtypes = [_vp, ctypes.POINTER(fpn_drive), ctypes.POINTE
 _lib.fpn_adjoint.restype = ctypes.c_int32
 _lib.fpn_adjoint.argtypes = [_vp, ctypes.POINTER(fpn_drive), ctypes.POINTER(fpn_solve_opts),
                              ctypes.POINTER(fpn_batch), ctypes.c_int64, _vp, _vp, _vp, _vp, _vp]
+_lib.fpn_stepper_wave_options.restype = ctypes.c_int32
+_lib.fpn_stepper_wave_options.argtypes = [ctypes.c_int32, ctypes.POINTER(ctypes.c_int32), ctypes.POINTER(ctypes.c_int32)]
+_lib.fpn_set_stepper_waves.restype = ctypes.c_int32
+_lib.fpn_set_stepper_waves.argtypes = [_vp, ctypes.c_int32, ctypes.c_int32]
+_lib.fpn_autotune.restype = ctypes.c_int32
+_lib.fpn_autotune.argtypes = [_vp, ctypes.c_int32, ctypes.POINTER(ctypes.c_int32), ctypes.POINTER(ctypes.c_double)]
 _lib.fpn_plan_create.restype = ctypes.c_int32
 _lib.fpn_plan_create.argtypes = [_vp, ctypes.POINTER(fpn_drive), ctypes.POINTER(fpn_solve_opts),
                                  ctypes.POINTER(fpn_batch), ctypes.c_int64, ctypes.POINTER(ctypes.c_float), _vp, _vp,
@@ -181,6 +188,14 @@ def fpn_host_table_nnz(L):
 
 
 # ------------------------------------------------------------------ device calls ---
+
+def fpn_stepper_wave_options(L):
+    """Workgroup sizes (instances per workgroup) compiled for degree L (fpn_stepper_wave_options)."""
+    w = (ctypes.c_int32 * 3)()
+    c = ctypes.c_int32()
+    _check(_lib.fpn_stepper_wave_options(int(L), w, ctypes.byref(c)), "fpn_stepper_wave_options")
+    return [int(w[k]) for k in range(c.value)]
+
 
 def _torch():
     import torch
@@ -268,6 +283,19 @@ class Context:
         self._keep = (keep, Lh)  # inputs alive until the next call on this context
         harm = torch.view_as_complex(hm) if hm is not None else None
         return m, harm, st
+
+    def set_stepper_waves(self, L, waves):
+        """fpn_set_stepper_waves: workgroup size of degree L for this context (0: the default)."""
+        _check(_lib.fpn_set_stepper_waves(self._h, int(L), int(waves)), "fpn_set_stepper_waves")
+
+    def autotune(self, L):
+        """fpn_autotune: time every workgroup size of degree L, keep the fastest.
+        Returns (chosen size, {size: ns per instance-step})."""
+        w = ctypes.c_int32()
+        ns = (ctypes.c_double * 3)()
+        _check(_lib.fpn_autotune(self._h, int(L), ctypes.byref(w), ns), "fpn_autotune")
+        opts = fpn_stepper_wave_options(L)
+        return int(w.value), {opts[k]: float(ns[k]) for k in range(len(opts))}
 
     def last_steps(self):
         """Time steps taken by the last solve, summed over instances."""

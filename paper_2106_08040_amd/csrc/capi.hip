@@ -5,6 +5,7 @@
 #include <cmath>
 #include <cstdio>
 #include <cstring>
+#include <limits>
 #include <map>
 #include <memory>
 #include <mutex>
@@ -250,10 +251,11 @@ hipError_t launch_stepper(int L, const StepLaunch& s, const DevTables& t, float*
   }
 }
 
-hipError_t stepper_occupancy(int L, const DevTables& t, bool tangents, int* waves_per_block, int* blocks_per_cu) {
+hipError_t stepper_occupancy(int L, const DevTables& t, bool tangents, int waves, int* waves_per_block,
+                             int* blocks_per_cu) {
   switch (L) {
 #define FPN_CASE(LL) \
-  case LL: return stepper_occupancy_L<LL>(t, tangents, waves_per_block, blocks_per_cu);
+  case LL: return stepper_occupancy_L<LL>(t, tangents, waves, waves_per_block, blocks_per_cu);
     FPN_CASE(1) FPN_CASE(2) FPN_CASE(3) FPN_CASE(4) FPN_CASE(5) FPN_CASE(6) FPN_CASE(7) FPN_CASE(8)
     FPN_CASE(9) FPN_CASE(10) FPN_CASE(11) FPN_CASE(12) FPN_CASE(13) FPN_CASE(14) FPN_CASE(15) FPN_CASE(16)
 #undef FPN_CASE
@@ -383,15 +385,15 @@ fpn_status validate_opts(const fpn_drive* drive, const fpn_solve_opts* opts) {
   return FPN_OK;
 }
 
-fpn_status occupancy(fpn_ctx ctx, int L, const fpn::DevTables& t, bool tangents, int* waves, int* blocks) {
-  const int key = L + (tangents ? 1000 : 0);
+fpn_status occupancy(fpn_ctx ctx, int L, const fpn::DevTables& t, bool tangents, int wg, int* waves, int* blocks) {
+  const int key = L + (tangents ? 1000 : 0) + 10000 * wg;
   auto it = ctx->occupancy.find(key);
   if (it == ctx->occupancy.end()) {
     int w = 0, b = 0;
-    FPN_HIP(fpn::stepper_occupancy(L, t, tangents, &w, &b));
-    if (b < 1) return fail(FPN_E_DEVICE, "stepper does not fit on a compute unit");
+    FPN_HIP(fpn::stepper_occupancy(L, t, tangents, wg, &w, &b));
     it = ctx->occupancy.emplace(key, std::make_pair(w, b)).first;
   }
+  if (it->second.second < 1) return fail(FPN_E_DEVICE, "stepper configuration does not fit on a compute unit");
   if (ctx->cus == 0) {
     hipDeviceProp_t prop;
     FPN_HIP(hipGetDeviceProperties(&prop, ctx->device));
@@ -457,7 +459,8 @@ fpn_status plan_build(fpn_plan_s* p, fpn_ctx ctx, const fpn_drive* drive, const 
     p->order.insert(p->order.end(), ids.begin(), ids.end());
     start += g.cnt;
     int waves = 0, blocks = 0;
-    if (fpn_status s = occupancy(ctx, g.L, *g.t, tangent, &waves, &blocks)) return s;
+    g.waves = (!tangent && g.L <= 16) ? ctx->stepper_waves[g.L] : 0;
+    if (fpn_status s = occupancy(ctx, g.L, *g.t, tangent, g.waves, &waves, &blocks)) return s;
     g.grid = std::max(1, std::min((g.cnt + waves - 1) / waves, blocks * ctx->cus));
     g.ws_off = ws_total;
     ws_total += int64_t(g.grid) * waves * fpn::stepper_ws_floats(g.L);
@@ -582,6 +585,7 @@ fpn_status plan_launch(fpn_plan_s* p, hipStream_t stream, bool timing) {
     sl.steps_out = p->steps.p;
     sl.queue = p->queue.p + gi;
     sl.grid = g.grid;
+    sl.waves = g.waves;
     if (g.L <= 16 && p->tws.p) sl.tws = p->tws.p + g.tws_off;
     if (p->tangent) {
       sl.c0t = p->c0t.p;
@@ -778,6 +782,154 @@ fpn_status fpn_plan_destroy(fpn_plan p) {
   (void)hipDeviceSynchronize();
   plan_release(p);
   delete p;
+  return FPN_OK;
+}
+
+fpn_status fpn_stepper_wave_options(int32_t L, int32_t* waves, int32_t* count) {
+  if (!waves || !count) return fail(FPN_E_ARG, "NULL argument");
+  if (L < 1 || L > FPN_MAX_L) return fail(FPN_E_ARG, "L out of range");
+  int tmp[3];
+  const int c = fpn::stepper_wave_options(L, tmp);
+  for (int k = 0; k < c; ++k) waves[k] = tmp[k];
+  *count = c;
+  return FPN_OK;
+}
+
+namespace {
+// the context's workgroup size for degree L after checking it is compiled and fits (lock held)
+fpn_status set_waves_locked(fpn_ctx ctx, int L, int waves) {
+  int opts[3];
+  const int c = fpn::stepper_wave_options(L, opts);
+  bool known = false;
+  for (int k = 0; k < c; ++k) known = known || opts[k] == waves;
+  if (waves != 0 && !known) return fail(FPN_E_ARG, "workgroup size not compiled for this degree");
+  if (waves != 0 && L <= 16) {
+    const fpn::DevTables* t = nullptr;
+    if (fpn_status s = get_tables(ctx, L, &t)) return s;
+    int w = 0, b = 0;
+    if (fpn_status s = occupancy(ctx, L, *t, false, waves, &w, &b)) return s;
+  }
+  ctx->stepper_waves[L] = (L <= 16) ? waves : 0;
+  return FPN_OK;
+}
+}  // namespace
+
+fpn_status fpn_set_stepper_waves(fpn_ctx ctx, int32_t L, int32_t waves) {
+  if (!ctx) return fail(FPN_E_ARG, "ctx is NULL");
+  if (L < 1 || L > FPN_MAX_L) return fail(FPN_E_ARG, "L out of range");
+  std::lock_guard<std::mutex> lk(ctx->mu);
+  FPN_HIP(hipSetDevice(ctx->device));
+  return set_waves_locked(ctx, L, waves);
+}
+
+fpn_status fpn_autotune(fpn_ctx ctx, int32_t L, int32_t* waves_out, double* ns_per_step_out) {
+  if (!ctx) return fail(FPN_E_ARG, "ctx is NULL");
+  if (L < 1 || L > FPN_MAX_L) return fail(FPN_E_ARG, "L out of range");
+  int opts[3];
+  const int nopt = fpn::stepper_wave_options(L, opts);
+  std::lock_guard<std::mutex> lk(ctx->mu);
+  FPN_HIP(hipSetDevice(ctx->device));
+  const fpn::DevTables* t = nullptr;
+  if (fpn_status s = get_tables(ctx, L, &t)) return s;
+  // probe size: twice the resident instances of the largest configuration that fits
+  int64_t slots = 1;
+  bool fits[3] = {false, false, false};
+  for (int k = 0; k < nopt; ++k) {
+    int w = 0, b = 0;
+    const int key_waves = (L <= 16) ? opts[k] : 0;
+    if (occupancy(ctx, L, *t, false, key_waves, &w, &b) != FPN_OK) continue;
+    fits[k] = true;
+    slots = std::max<int64_t>(slots, int64_t(w) * b * ctx->cus);
+  }
+  const int64_t n = std::min<int64_t>(2 * slots, 16384);
+  // probe batch: one magnetite-like particle (D 20 nm, K 2 kJ/m^3, alpha 0.1, 295 K), easy axes on a
+  // golden-angle spiral, offsets on a ring of 6 mT; a 40 us drive with 3 and 4 cycles on x and y,
+  // 64 samples, no settling, two fixed steps per sample (the step count does not depend on the
+  // configuration, so times compare directly)
+  std::vector<double> hD(n, 20e-9), hMs(n, 474e3), hK(n, 2e3), hA(n, 0.1), hT(n, 295.0), hE(3 * n), hO(3 * n);
+  for (int64_t i = 0; i < n; ++i) {
+    const double z = 1.0 - (2.0 * double(i) + 1.0) / double(n);
+    const double r = std::sqrt(std::max(0.0, 1.0 - z * z)), ph = 2.399963229728653 * double(i);
+    hE[3 * i] = r * std::cos(ph);
+    hE[3 * i + 1] = r * std::sin(ph);
+    hE[3 * i + 2] = z;
+    const double a = 0.6180339887498949 * double(i) * 6.283185307179586;
+    hO[3 * i] = 6e-3 * std::cos(a);
+    hO[3 * i + 1] = 6e-3 * std::sin(a);
+    hO[3 * i + 2] = 0.0;
+  }
+  std::vector<int32_t> hL(n, L);
+  fpn_internal::DevBuf<double> dD, dMs, dK, dA, dT, dE, dO;
+  fpn_internal::DevBuf<float> dm;
+  fpn_internal::DevBuf<int32_t> dst;
+  auto release = [&]() {
+    dD.release(); dMs.release(); dK.release(); dA.release(); dT.release(); dE.release(); dO.release();
+    dm.release(); dst.release();
+  };
+  const int Ns = 64;
+  hipError_t he = hipSuccess;
+  for (auto* b : {&dD, &dMs, &dK, &dA, &dT}) he = (he == hipSuccess) ? b->ensure(n) : he;
+  if (he == hipSuccess) he = dE.ensure(3 * n);
+  if (he == hipSuccess) he = dO.ensure(3 * n);
+  if (he == hipSuccess) he = dm.ensure(size_t(n) * 3 * Ns);
+  if (he == hipSuccess) he = dst.ensure(n);
+  const std::pair<fpn_internal::DevBuf<double>*, const std::vector<double>*> ups[] = {
+      {&dD, &hD}, {&dMs, &hMs}, {&dK, &hK}, {&dA, &hA}, {&dT, &hT}, {&dE, &hE}, {&dO, &hO}};
+  for (const auto& u : ups)
+    if (he == hipSuccess)
+      he = hipMemcpy(u.first->p, u.second->data(), u.second->size() * sizeof(double), hipMemcpyHostToDevice);
+  if (he != hipSuccess) {
+    release();
+    return fail(FPN_E_DEVICE, hipGetErrorString(he));
+  }
+  fpn_batch b{dD.p, dMs.p, dK.p, dA.p, dT.p, dE.p, dO.p, hL.data()};
+  const double T = 40e-6;
+  fpn_drive dr{{10e-3, 8e-3, 0.0}, {3.0 / T, 4.0 / T, 0.0}, {0.0, 0.3, 0.0}, T};
+  fpn_solve_opts o{Ns, 0, 0, 2, FPN_OUT_M, 0.0};
+  hipEvent_t e0 = nullptr, e1 = nullptr;
+  fpn_status status = FPN_OK;
+  double best = 0.0;
+  int best_k = -1;
+  const int saved = ctx->stepper_waves[L];
+  if (hipEventCreate(&e0) != hipSuccess || hipEventCreate(&e1) != hipSuccess) status = fail(FPN_E_DEVICE, "event");
+  for (int k = 0; k < nopt && status == FPN_OK; ++k) {
+    double ns = std::numeric_limits<double>::infinity();
+    if (fits[k]) {
+      ctx->stepper_waves[L] = (L <= 16) ? opts[k] : 0;
+      fpn_plan_s p;
+      status = plan_build(&p, ctx, &dr, &o, &b, n, nullptr, dm.p, nullptr, dst.p, nullptr);
+      float ms = 0.0f;
+      if (status == FPN_OK) status = plan_launch(&p, nullptr, false);  // first run: code and caches warm
+      if (status == FPN_OK && (hipEventRecord(e0, nullptr) != hipSuccess)) status = fail(FPN_E_DEVICE, "event");
+      if (status == FPN_OK) status = plan_launch(&p, nullptr, false);
+      if (status == FPN_OK && (hipEventRecord(e1, nullptr) != hipSuccess || hipEventSynchronize(e1) != hipSuccess ||
+                               hipEventElapsedTime(&ms, e0, e1) != hipSuccess))
+        status = fail(FPN_E_DEVICE, "timing");
+      std::vector<int32_t> steps(n);
+      if (status == FPN_OK &&
+          hipMemcpy(steps.data(), p.steps.p, n * sizeof(int32_t), hipMemcpyDeviceToHost) != hipSuccess)
+        status = fail(FPN_E_DEVICE, "steps");
+      (void)hipDeviceSynchronize();
+      plan_release(&p);
+      int64_t tot = 0;
+      for (int32_t v : steps) tot += v;
+      if (status == FPN_OK && tot > 0) ns = double(ms) * 1e6 / double(tot);
+    }
+    if (ns_per_step_out) ns_per_step_out[k] = ns;
+    if (ns < std::numeric_limits<double>::infinity() && (best_k < 0 || ns < best)) {
+      best = ns;
+      best_k = k;
+    }
+  }
+  if (e0) (void)hipEventDestroy(e0);
+  if (e1) (void)hipEventDestroy(e1);
+  release();
+  if (status != FPN_OK || best_k < 0) {
+    ctx->stepper_waves[L] = saved;
+    return status != FPN_OK ? status : fail(FPN_E_DEVICE, "no stepper configuration fits");
+  }
+  ctx->stepper_waves[L] = (L <= 16) ? opts[best_k] : 0;
+  if (waves_out) *waves_out = opts[best_k];
   return FPN_OK;
 }
 

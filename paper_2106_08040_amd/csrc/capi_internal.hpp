@@ -61,6 +61,7 @@ struct PlanGroup {
   int cnt = 0;
   const fpn::DevTables* t = nullptr;
   int grid = 0;          // persistent workgroups of the stepper
+  int waves = 0;         // instances per workgroup (0: the default for L)
   int64_t ws_off = 0;    // floats into the wide-layout workspace
   int64_t inv_off = 0;   // doubles into the stationary workspace
   int64_t tws_off = 0;   // floats into the tangent workspace
@@ -94,8 +95,10 @@ struct fpn_ctx_s {
   int64_t launches[4] = {0, 0, 0, 0};
   fpn_plan_s* solve_plan = nullptr;   // reused by fpn_solve
   fpn_plan_s* tangent_plan = nullptr; // reused by fpn_solve_tangent and fpn_adjoint
-  std::map<int, std::pair<int, int>> occupancy;  // L -> (waves per workgroup, workgroups per CU)
+  // (L, tangents, workgroup size) -> (waves per workgroup, workgroups per CU)
+  std::map<int, std::pair<int, int>> occupancy;
   int cus = 0;
+  int stepper_waves[25] = {0};  // workgroup size per degree (0: default), set by fpn_autotune
 };
 
 // A solve bound to its inputs and outputs: the degree buckets in launch order, the instance

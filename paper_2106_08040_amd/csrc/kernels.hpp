@@ -28,6 +28,8 @@ struct StepLaunch {
   const double* c0t = nullptr;  // tangents (L <= 16): initial states [n][kNTan][c_stride]
   float* mtan = nullptr;        // tangents: samples [n][kNTan][3][Ns]; null for a plain solve
   float* tws = nullptr;         // L <= 16: workspace, stepper_reg_ws_floats(L, tangents) per resident wavefront
+  int waves = 0;                // L <= 16 without tangents: instances per workgroup (0: the default, 8;
+                                // stepper_wave_options lists the others compiled for L)
 };
 
 template <int L>
@@ -39,11 +41,32 @@ template <int L>
 int64_t stepper_wide_ws_floats_L();
 int64_t stepper_ws_floats(int L);  // 0 for the register layout (L <= 16); per resident wavefront
 template <int L>
-hipError_t stepper_occupancy_L(const DevTables& t, bool tangents, int* waves_per_block, int* blocks_per_cu);
+hipError_t stepper_occupancy_L(const DevTables& t, bool tangents, int waves, int* waves_per_block,
+                               int* blocks_per_cu);
 template <int L>
 hipError_t stepper_wide_occupancy_L(int* waves_per_block, int* blocks_per_cu);
-// wavefronts per workgroup and resident workgroups per CU of the stepper for degree L
-hipError_t stepper_occupancy(int L, const DevTables& t, bool tangents, int* waves_per_block, int* blocks_per_cu);
+// wavefronts per workgroup and resident workgroups per CU of the stepper for degree L, for the
+// workgroup size `waves` (0: the default); blocks_per_cu = 0 when that configuration does not fit
+hipError_t stepper_occupancy(int L, const DevTables& t, bool tangents, int waves, int* waves_per_block,
+                             int* blocks_per_cu);
+// Instances (wavefronts) per workgroup of the primal register-layout stepper: 8 for every degree, and
+// 12 and 16 as well for L <= kStepperMultiWavesMaxL.
+constexpr int kStepperWaves = 8;
+constexpr int kStepperMultiWavesMaxL = 13;
+// workgroup sizes compiled for the primal stepper of degree L (at most 3 written to out); the wide
+// layout (L = 17..24) has one size, reported as 0 (its default)
+inline int stepper_wave_options(int L, int* out) {
+  if (L < 1 || L > 24) return 0;
+  if (L > 16) {
+    out[0] = 0;
+    return 1;
+  }
+  out[0] = kStepperWaves;
+  if (L > kStepperMultiWavesMaxL) return 1;
+  out[1] = 12;
+  out[2] = 16;
+  return 3;
+}
 // register-layout stepper workspace per resident wavefront (floats): the tangent vectors (none without
 // tangents)
 inline int64_t stepper_reg_ws_floats(int L, bool tangents) {

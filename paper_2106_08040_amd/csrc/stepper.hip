@@ -38,25 +38,30 @@ __device__ __forceinline__ auto& blk(Store<L, L>& s) {
   return static_cast<Store<L, K>&>(s).a.v;
 }
 
-// Per-wavefront LDS.  The factorisation scratch (X, Ub) and the stage vectors share `u`.  With
-// tangents (NT > 0) three more vectors hold the step-start state, the tangent stage argument and the
-// current primal stage increment, and three multiplier tables hold the parameter derivatives.
-// Row stride of the factorisation scratch: 33 floats, so the 32 rows of a half-wave fall in different
-// LDS banks (a stride of 32 put every row of a column access in one bank).
-constexpr int kXS = 33;
-constexpr int kUbOff = 1224;  // X: rows 0..36 (window overhang included), then Ub: 32 rows
-
+// Per-wavefront LDS, sized by the degree.  The factorisation scratch (X, Ub) and the stage vectors
+// share `u`.  A scratch row holds the two column parities of a block row side by side, kH slots each
+// (kH = the longest half row of any block), with a row stride kXS = 2 kH + 1 (odd, so the rows of a
+// half-wave fall in different LDS banks).  X has 2 kH + 5 rows (window reads overhang a block by up
+// to five rows), Ub 2 kH rows.  With tangents (NT > 0) three more vectors hold the step-start state,
+// the tangent stage argument and the current primal stage increment, and three multiplier tables
+// hold the parameter derivatives.
 template <int L, int NT>
 struct WaveLds {
   static constexpr int NpA = Geo<L>::NpA;
-  static constexpr int kUnion = (kUbOff + 32 * kXS > 9 * NpA) ? kUbOff + 32 * kXS : 9 * NpA;
+  static constexpr int kH = Geo<L>::qmax;
+  static constexpr int kXS = 2 * kH + 1;
+  static constexpr int kUbOff = (2 * kH + 5) * kXS;
+  static constexpr int kFac = kUbOff + 2 * kH * kXS;
+  // every lane reads a scratch row i < 32 (masked when i is past the block): keep 32 rows in bounds
+  static constexpr int kUnion0 = (kFac > 9 * NpA) ? kFac : 9 * NpA;
+  static constexpr int kUnion = (kUnion0 > 32 * kXS) ? kUnion0 : 32 * kXS;
   static constexpr int kTanV = NT > 0 ? 3 * NpA : 4;
   float u[kUnion];
-  float T[32];     // block right-hand side [parity][16]
-  float col[64];   // pivot columns [parity][32]
-  float row[64];   // pivot rows [r][parity][16]
-  float mk[16];    // -h g * multiplier(t_n) per kind
-  float ms[16];    // multiplier at the current stage time per kind
+  float T[2 * kH];     // block right-hand side [parity][kH]
+  float col[64];       // pivot columns [parity][32]
+  float row[4 * kH];   // pivot rows [r][parity][kH]
+  float mk[16];        // -h g * multiplier(t_n) per kind
+  float ms[16];        // multiplier at the current stage time per kind
   float tv[kTanV];                     // y0 | xt | kc
   float dmi[NT > 0 ? NT : 1][12];      // d multiplier / d p at the stage time
   float dmn[NT > 0 ? NT : 1][12];      // ... at t_n
@@ -89,7 +94,7 @@ __device__ __forceinline__ bool gj2_invert(float (&a)[Q], int i, int h, W& w) {
     const bool inR = act && (r == 0 || r == 1);
     if (inR) {
 #pragma unroll
-      for (int q = 0; q < Q; ++q) w.row[(r * 2 + h) * 16 + q] = a[q];
+      for (int q = 0; q < Q; ++q) w.row[(r * 2 + h) * W::kH + q] = a[q];
     }
     wsync();
     // every read of this elimination step is issued before the first use (one LDS wait)
@@ -99,8 +104,8 @@ __device__ __forceinline__ bool gj2_invert(float (&a)[Q], int i, int h, W& w) {
     float w0[Q], w1[Q];
 #pragma unroll
     for (int q = 0; q < Q; ++q) {
-      w0[q] = w.row[(0 * 2 + h) * 16 + q];
-      w1[q] = w.row[(1 * 2 + h) * 16 + q];
+      w0[q] = w.row[(0 * 2 + h) * W::kH + q];
+      w1[q] = w.row[(1 * 2 + h) * W::kH + q];
     }
     __builtin_amdgcn_sched_barrier(0);
     const float det = P00 * P11 - P01 * P10;
@@ -131,6 +136,8 @@ __global__ void __launch_bounds__(64 * WAVES)
 stepper_kernel(StepArgs A, DevTables t) {
   using Gm = Geo<L>;
   using WL = WaveLds<L, NT>;
+  constexpr int kH = WL::kH;    // half-row slots of the factorisation scratch
+  constexpr int kXS = WL::kXS;  // its row stride
   constexpr int NpA = Gm::NpA;
   constexpr int Np = Gm::Np;
   constexpr int S = Gm::S;
@@ -320,18 +327,36 @@ stepper_kernel(StepArgs A, DevTables t) {
       const uint16_t* ec = ecol + z;
       const float* ev = eval + z;
       if (p < Np) {
+        // table reads, then the four gathers, then the sums, seven couplings at a time
+        constexpr int kG = 7;
         float acc = 0.0f;
 #pragma unroll
-        for (int sl = 0; sl < kNSlRow; ++sl) {
-          const int kd = kSlotKindRow[sl];
-          const int c = ec[sl * Np + p];
-          const float v = ev[sl * Np + p];
-          float g = m[kd] * xt[c];
-          g = fmaf(a1[kd], yt[c], g);
-          g = fmaf(a2[kd], kc[c], g);
-          g = fmaf(a3[kd], y0[c], g);
-          acc = fmaf(v, g, acc);
-          if ((sl % 7) == 6) __builtin_amdgcn_sched_barrier(0);
+        for (int g0 = 0; g0 < kNSlRow; g0 += kG) {
+          int ci[kG];
+          float cv[kG], gx[kG], gy[kG], gk[kG], g0v[kG];
+#pragma unroll
+          for (int u = 0; u < kG; ++u) {
+            ci[u] = ec[(g0 + u) * Np + p];
+            cv[u] = ev[(g0 + u) * Np + p];
+          }
+          __builtin_amdgcn_sched_barrier(0);
+#pragma unroll
+          for (int u = 0; u < kG; ++u) {
+            gx[u] = xt[ci[u]];
+            gy[u] = yt[ci[u]];
+            gk[u] = kc[ci[u]];
+            g0v[u] = y0[ci[u]];
+          }
+          __builtin_amdgcn_sched_barrier(0);
+#pragma unroll
+          for (int u = 0; u < kG; ++u) {
+            const int kd = kSlotKindRow[g0 + u];
+            float g = m[kd] * gx[u];
+            g = fmaf(a1[kd], gy[u], g);
+            g = fmaf(a2[kd], gk[u], g);
+            g = fmaf(a3[kd], g0v[u], g);
+            acc = fmaf(cv[u], g, acc);
+          }
         }
         V[p] += acc;
       }
@@ -388,13 +413,13 @@ stepper_kernel(StepArgs A, DevTables t) {
             tv = fmaf(-(d == 1 ? mRX : mFY) * wv[3 + d], gov[d], tv);
           }
         }
-        w.T[(i & 1) * 16 + (i >> 1)] = tv;
+        w.T[(i & 1) * kH + (i >> 1)] = tv;
       }
       wsync();
       auto& a = blk<K>(st);
       float part = 0.0f;
 #pragma unroll
-      for (int q = 0; q < Q; ++q) part = fmaf(a[q], w.T[h * 16 + q], part);
+      for (int q = 0; q < Q; ++q) part = fmaf(a[q], w.T[h * kH + q], part);
       part = half_sum(part);
       if (h == 0 && i < n) G[off0 + i] = part;
       wsync();
@@ -427,13 +452,13 @@ stepper_kernel(StepArgs A, DevTables t) {
             tv = fmaf((d == 1 ? mRX : mFY) * wv[3 + d], gov[d], tv);
           }
         }
-        w.T[(i & 1) * 16 + (i >> 1)] = tv;
+        w.T[(i & 1) * kH + (i >> 1)] = tv;
       }
       wsync();
       auto& a = blk<K>(st);
       float part = 0.0f;
 #pragma unroll
-      for (int q = 0; q < Q; ++q) part = fmaf(a[q], w.T[h * 16 + q], part);
+      for (int q = 0; q < Q; ++q) part = fmaf(a[q], w.T[h * kH + q], part);
       part = half_sum(part);
       if (h == 0 && i < n) G[off0 + i] -= part;
       wsync();
@@ -459,7 +484,7 @@ stepper_kernel(StepArgs A, DevTables t) {
         auto& ap = blk<K - 1>(st);
         if (i < np) {
 #pragma unroll
-          for (int q = 0; q < Qp; ++q) X[i * kXS + h * 16 + q] = ap[q];
+          for (int q = 0; q < Qp; ++q) X[i * kXS + h * kH + q] = ap[q];
         }
         wsync();
 #pragma unroll
@@ -480,7 +505,7 @@ stepper_kernel(StepArgs A, DevTables t) {
 #pragma unroll
             for (int u2 = 0; u2 < kNSlB; ++u2) {
               const float me = mk[kSlotKindRow[kSlB + u2]] * cv[u2];
-              const float* xr = X + (ci[u2] - offp) * kXS + h * 16;
+              const float* xr = X + (ci[u2] - offp) * kXS + h * kH;
               float xv[Qp];
 #pragma unroll
               for (int q = 0; q < Qp; ++q) xv[q] = xr[q];
@@ -490,8 +515,8 @@ stepper_kernel(StepArgs A, DevTables t) {
             }
           } else {
             const int t = i & 1;
-            const float* xs = X + i * kXS + h * 16;                // rows i + 2d
-            const float* xo = X + (i + 1 - 2 * t) * kXS + h * 16;  // rows i + 1 - 2t + 2d
+            const float* xs = X + i * kXS + h * kH;                // rows i + 2d
+            const float* xo = X + (i + 1 - 2 * t) * kXS + h * kH;  // rows i + 1 - 2t + 2d
             float wv[6];
 #pragma unroll
             for (int d = 0; d < 6; ++d) wv[d] = wB[z + d * Np + row];
@@ -514,7 +539,7 @@ stepper_kernel(StepArgs A, DevTables t) {
         if constexpr (K == 1) {
           if (act) {
 #pragma unroll
-            for (int q = 0; q < Qp; ++q) Ub[i * kXS + h * 16 + q] = u[q];
+            for (int q = 0; q < Qp; ++q) Ub[i * kXS + h * kH + q] = u[q];
           }
           wsync();
         } else {
@@ -527,7 +552,7 @@ stepper_kernel(StepArgs A, DevTables t) {
       }
       if (act) {
 #pragma unroll
-        for (int q = 0; q < Q; ++q) X[i * kXS + h * 16 + q] = 0.0f;
+        for (int q = 0; q < Q; ++q) X[i * kXS + h * kH + q] = 0.0f;
       }
       wsync();
       if (act) {
@@ -546,18 +571,18 @@ stepper_kernel(StepArgs A, DevTables t) {
 #pragma unroll
         for (int u2 = 0; u2 < kNSlD; ++u2) {
           if ((cl[u2] & 1) == h)
-            __hip_atomic_fetch_add(X + i * kXS + h * 16 + (cl[u2] >> 1), mk[kSlotKindRow[kSlD + u2]] * cv[u2],
+            __hip_atomic_fetch_add(X + i * kXS + h * kH + (cl[u2] >> 1), mk[kSlotKindRow[kSlD + u2]] * cv[u2],
                                    __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WAVEFRONT);
         }
         if ((i & 1) == h)
-          __hip_atomic_fetch_add(X + i * kXS + h * 16 + (i >> 1), 1.0f, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WAVEFRONT);
+          __hip_atomic_fetch_add(X + i * kXS + h * kH + (i >> 1), 1.0f, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WAVEFRONT);
       }
       wsync();
       // work on a local copy: the indexed pivot-column access must not touch the store itself.  Rows
       // i >= n lie inside the scratch (rows 0..36) and are read unconditionally, then masked.
       float a[Q];
 #pragma unroll
-      for (int q = 0; q < Q; ++q) a[q] = X[i * kXS + h * 16 + q];
+      for (int q = 0; q < Q; ++q) a[q] = X[i * kXS + h * kH + q];
 #pragma unroll
       for (int q = 0; q < Q; ++q) a[q] = act ? a[q] : 0.0f;
       if constexpr (K == 1) {
@@ -577,7 +602,7 @@ stepper_kernel(StepArgs A, DevTables t) {
             }
             __builtin_amdgcn_sched_barrier(0);
 #pragma unroll
-            for (int sl = 0; sl < kNSlCol; ++sl) uv[sl] = Ub[i * kXS + (rl[sl] & 1) * 16 + (rl[sl] >> 1)];
+            for (int sl = 0; sl < kNSlCol; ++sl) uv[sl] = Ub[i * kXS + (rl[sl] & 1) * kH + (rl[sl] >> 1)];
             __builtin_amdgcn_sched_barrier(0);
 #pragma unroll
             for (int sl = 0; sl < kNSlCol; ++sl) acc = fmaf(mk[kSlotKindCol[sl]] * cv[sl], uv[sl], acc);
@@ -913,23 +938,28 @@ stepper_kernel(StepArgs A, DevTables t) {
   }  // queue
 }
 
-#ifndef FPN_STEPPER_WAVES
-#define FPN_STEPPER_WAVES 8
-#endif
-constexpr int kWaves = FPN_STEPPER_WAVES;  // instances (wavefronts) per workgroup
-constexpr int kTanWaves = 4;               // with tangents (more LDS per wavefront)
+// Instances (wavefronts) per workgroup.  Every degree has the 8-wavefront kernel; degrees up to
+// kMultiWavesMaxL also have 12- and 16-wavefront kernels, which share the operator tables in LDS
+// among more instances at a smaller register budget per wavefront (a workgroup of 64 w threads
+// needs w / 4 wavefronts per SIMD).  The fastest one per degree is picked by measurement
+// (fpn_autotune).  With tangents the workgroup has 4 wavefronts (more LDS per wavefront).
+constexpr int kWaves = kStepperWaves;
+constexpr int kTanWaves = 4;
+constexpr int kMultiWavesMaxL = kStepperMultiWavesMaxL;
+constexpr size_t kMaxLdsBytes = 160 * 1024;  // LDS of one compute unit
 
-template <int L, int NT>
-size_t stepper_lds_bytes_L() {
+template <int L, int WV, int NT>
+constexpr size_t stepper_lds_bytes() {
   constexpr int Np = Geo<L>::Np;
   constexpr size_t b16 = ((size_t(kNSlRow + kNSlCol) * Np * 2) + 15) & ~size_t(15);
   constexpr size_t tb = (b16 + size_t(kNSlRow + kNSlCol + 3 * kNWin) * Np * 4 + 15) & ~size_t(15);
-  return tb + (NT > 0 ? kTanWaves : kWaves) * sizeof(WaveLds<L, NT>);
+  return tb + WV * sizeof(WaveLds<L, NT>);
 }
 
-template <int L, int NT>
-hipError_t launch_stepper_NT(const StepLaunch& s, const DevTables& t, hipStream_t stream) {
-  constexpr int WV = NT > 0 ? kTanWaves : kWaves;
+template <int L, int WV, int NT>
+hipError_t launch_stepper_cfg(const StepLaunch& s, const DevTables& t, hipStream_t stream) {
+  constexpr size_t shm = stepper_lds_bytes<L, WV, NT>();
+  if (shm > kMaxLdsBytes) return hipErrorInvalidConfiguration;
   StepArgs a;
   a.ip = s.ip;
   a.inst_idx = s.inst_idx;
@@ -954,7 +984,6 @@ hipError_t launch_stepper_NT(const StepLaunch& s, const DevTables& t, hipStream_
   a.c0t = s.c0t;
   a.mtan = s.mtan;
   a.tws = s.tws;
-  const size_t shm = stepper_lds_bytes_L<L, NT>();
   auto kern = stepper_kernel<L, WV, NT>;
   hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void*>(kern),
                                      hipFuncAttributeMaxDynamicSharedMemorySize, int(shm));
@@ -967,23 +996,41 @@ hipError_t launch_stepper_NT(const StepLaunch& s, const DevTables& t, hipStream_
 
 template <int L>
 hipError_t launch_stepper_L(const StepLaunch& s, const DevTables& t, hipStream_t stream) {
-  return s.mtan ? launch_stepper_NT<L, kNTan>(s, t, stream) : launch_stepper_NT<L, 0>(s, t, stream);
+  if (s.mtan) return launch_stepper_cfg<L, kTanWaves, kNTan>(s, t, stream);
+  if constexpr (L <= kMultiWavesMaxL) {
+    if (s.waves == 12) return launch_stepper_cfg<L, 12, 0>(s, t, stream);
+    if (s.waves == 16) return launch_stepper_cfg<L, 16, 0>(s, t, stream);
+  }
+  if (s.waves != 0 && s.waves != kWaves) return hipErrorInvalidValue;
+  return launch_stepper_cfg<L, kWaves, 0>(s, t, stream);
+}
+
+template <int L, int WV, int NT>
+hipError_t stepper_occupancy_cfg(int* waves_per_block, int* blocks_per_cu) {
+  constexpr size_t shm = stepper_lds_bytes<L, WV, NT>();
+  *waves_per_block = WV;
+  *blocks_per_cu = 0;
+  if (shm > kMaxLdsBytes) return hipSuccess;  // does not fit: reported as zero workgroups per CU
+  const void* kern = reinterpret_cast<const void*>(stepper_kernel<L, WV, NT>);
+  hipError_t e = hipFuncSetAttribute(kern, hipFuncAttributeMaxDynamicSharedMemorySize, int(shm));
+  if (e != hipSuccess) return e;
+  return hipOccupancyMaxActiveBlocksPerMultiprocessor(blocks_per_cu, kern, 64 * WV, shm);
 }
 
 template <int L>
-hipError_t stepper_occupancy_L(const DevTables&, bool tangents, int* waves_per_block, int* blocks_per_cu) {
-  const size_t shm = tangents ? stepper_lds_bytes_L<L, kNTan>() : stepper_lds_bytes_L<L, 0>();
-  const void* kern = tangents ? reinterpret_cast<const void*>(stepper_kernel<L, kTanWaves, kNTan>)
-                              : reinterpret_cast<const void*>(stepper_kernel<L, kWaves, 0>);
-  hipError_t e = hipFuncSetAttribute(kern, hipFuncAttributeMaxDynamicSharedMemorySize, int(shm));
-  if (e != hipSuccess) return e;
-  *waves_per_block = tangents ? kTanWaves : kWaves;
-  return hipOccupancyMaxActiveBlocksPerMultiprocessor(blocks_per_cu, kern, 64 * *waves_per_block, shm);
+hipError_t stepper_occupancy_L(const DevTables&, bool tangents, int waves, int* waves_per_block, int* blocks_per_cu) {
+  if (tangents) return stepper_occupancy_cfg<L, kTanWaves, kNTan>(waves_per_block, blocks_per_cu);
+  if constexpr (L <= kMultiWavesMaxL) {
+    if (waves == 12) return stepper_occupancy_cfg<L, 12, 0>(waves_per_block, blocks_per_cu);
+    if (waves == 16) return stepper_occupancy_cfg<L, 16, 0>(waves_per_block, blocks_per_cu);
+  }
+  if (waves != 0 && waves != kWaves) return hipErrorInvalidValue;
+  return stepper_occupancy_cfg<L, kWaves, 0>(waves_per_block, blocks_per_cu);
 }
 
 #define FPN_INST(LL)                                                                          \
   template hipError_t launch_stepper_L<LL>(const StepLaunch&, const DevTables&, hipStream_t); \
-  template hipError_t stepper_occupancy_L<LL>(const DevTables&, bool, int*, int*);
+  template hipError_t stepper_occupancy_L<LL>(const DevTables&, bool, int, int*, int*);
 #if !defined(FPN_L_BEGIN)
 #define FPN_L_BEGIN 1
 #define FPN_L_END 16

@@ -21,6 +21,7 @@ struct Geo {
     for (int j = 0; j < k; ++j) o += nb(j);
     return o;
   }
+  static constexpr int qmax = (n0 / 2 > L) ? n0 / 2 : L;  // largest block row length per half-wave
   static constexpr int S = (Np + 63) / 64;    // vector slots per lane
   static constexpr int NpA = (Np + 3) & ~3;   // padded vector length in LDS
 };

@@ -1,0 +1,76 @@
+"""GPU tests of the launch-configuration autotuner (batching): every compiled workgroup size of the
+register-layout stepper integrates each instance with one wavefront in the same order, so outputs do
+not depend on the size; the autotuner picks a compiled size and the context then uses it."""
+import numpy as np
+import pytest
+
+import workloads as W
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def fpn():
+    import paper_2106_08040_amd as fpn
+    return fpn
+
+
+@pytest.fixture(scope="module")
+def ctx(fpn):
+    c = fpn.Context(0)
+    yield c
+    c.close()
+
+
+def _solve(fpn, ctx, ws):
+    import torch
+    d = ws["drive"]
+    m, h, st = ctx.solve(ws["inst"], ws["inst"]["L"], fpn.make_drive(d["amp"], d["freq"], d["period"], d["phase"]),
+                         ws["samples"], ws["settle"], ws["n_harm"], harm_z=True)
+    torch.cuda.synchronize()
+    return m.cpu().numpy(), h.cpu().numpy(), st.cpu().numpy()
+
+
+@pytest.mark.parametrize("L", [8, 12])
+def test_every_workgroup_size_gives_the_same_outputs(fpn, ctx, L):
+    ws = W.small_random(40, L, seed=900 + L, samples=48, settle=1, n_harm=6)
+    ref = None
+    for w in fpn.fpn_stepper_wave_options(L):
+        ctx.set_stepper_waves(L, w)
+        m, h, st = _solve(fpn, ctx, ws)
+        assert (st == 0).all()
+        if ref is None:
+            ref = (m, h)
+            continue
+        dm = np.abs(m - ref[0]).max() / np.abs(ref[0]).max()
+        dh = np.abs(h - ref[1]).max() / np.abs(ref[1]).max()
+        print(f"L={L} waves={w}: max |dm| {dm:.1e}, max |dPhi| {dh:.1e} (relative to the largest entry)", flush=True)
+        assert dm <= 1e-6 and dh <= 1e-6
+    ctx.set_stepper_waves(L, 0)
+
+
+def test_autotune_picks_a_compiled_size(fpn, ctx):
+    L = 10
+    w, ns = ctx.autotune(L)
+    opts = fpn.fpn_stepper_wave_options(L)
+    print("autotune L=10:", w, ns, flush=True)
+    assert w in opts and set(ns) == set(opts)
+    assert np.isfinite(ns[w]) and ns[w] > 0 and ns[w] == min(ns.values())
+    ws = W.small_random(16, L, seed=77, samples=32, settle=1, n_harm=4)
+    m, h, st = _solve(fpn, ctx, ws)  # the tuned size is the one in use
+    ctx.set_stepper_waves(L, 0)
+    m0, h0, st0 = _solve(fpn, ctx, ws)
+    assert (st == 0).all() and (st0 == 0).all()
+    assert np.abs(m - m0).max() <= 1e-6 * np.abs(m0).max()
+
+
+def test_wide_degree_autotune_has_one_configuration(fpn, ctx):
+    w, ns = ctx.autotune(17)
+    assert w == 0 and list(ns) == [0] and np.isfinite(ns[0])
+
+
+def test_unknown_workgroup_size_is_rejected(fpn, ctx):
+    with pytest.raises(fpn.FpnError):
+        ctx.set_stepper_waves(16, 12)   # 12 is compiled for L <= 13 only
+    with pytest.raises(fpn.FpnError):
+        ctx.set_stepper_waves(8, 5)

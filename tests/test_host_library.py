@@ -84,3 +84,17 @@ def test_table_sizes_and_selection_rules():
         ls = O.sh_degrees(L)
         far = np.abs(ls[:, None] - ls[None, :]) > 2
         assert np.abs(A[far]).max() == 0.0
+
+
+def test_stepper_wave_options():
+    """Workgroup sizes compiled per degree: 8, 12, 16 up to L = 13, 8 up to 16, one wide layout above."""
+    import paper_2106_08040_amd as fpn
+    for L in range(1, 14):
+        assert fpn.fpn_stepper_wave_options(L) == [8, 12, 16]
+    for L in (14, 15, 16):
+        assert fpn.fpn_stepper_wave_options(L) == [8]
+    for L in range(17, 25):
+        assert fpn.fpn_stepper_wave_options(L) == [0]
+    for L in (0, 25):
+        with pytest.raises(fpn.FpnError):
+            fpn.fpn_stepper_wave_options(L)

@@ -68,16 +68,29 @@ def truncation_degree(D, K, T=ROOM_T, lo=8, hi=24):
     alpha 0.05..0.25), so the degree has to grow linearly with sigma; the margin of 4 keeps the
     operator stable up to sigma = 20 at L = 24.  Beyond that no degree up to 24 resolves the particle
     and the solve ends with a non-finite status."""
-    sigma = np.asarray(K) * (np.pi * np.asarray(D) ** 3 / 6) / (1.380649e-23 * T)
+    sigma = anisotropy_ratio(D, K, T)
     return np.clip(np.ceil(sigma) + 4, lo, hi).astype(np.int32)
 
 
-def uneven_sweep(n=4096, seed=3, L_max=24):
+def anisotropy_ratio(D, K, T=ROOM_T):
+    """sigma = K V / (k_B T) with V = pi D^3 / 6."""
+    return np.asarray(K) * (np.pi * np.asarray(D) ** 3 / 6) / (1.380649e-23 * T)
+
+
+def uneven_sweep(n=4096, seed=3, L_max=24, sigma_max=20.0):
     """Batched uneven sweep: D ~ U[15, 30] nm, K log-uniform in [0.5, 20] kJ/m^3, alpha ~ U[0.05, 0.3],
-    easy axes uniform on the sphere, offsets U[-12, 12] mT in x and y, L by truncation_degree."""
+    easy axes uniform on the sphere, offsets U[-12, 12] mT in x and y, L by truncation_degree.
+    (D, K) pairs with sigma > sigma_max are drawn again (in order, from the same generator), so every
+    particle is resolvable at L <= 24 under the degree rule (sigma_max = 20 gives L = 24)."""
     r = np.random.default_rng(seed)
     D = r.uniform(15e-9, 30e-9, n)
     K = np.exp(r.uniform(np.log(500.0), np.log(2e4), n))
+    while True:
+        bad = np.nonzero(anisotropy_ratio(D, K) > sigma_max)[0]
+        if bad.size == 0:
+            break
+        D[bad] = r.uniform(15e-9, 30e-9, bad.size)
+        K[bad] = np.exp(r.uniform(np.log(500.0), np.log(2e4), bad.size))
     alpha = r.uniform(0.05, 0.3, n)
     z = r.uniform(-1, 1, n)
     ph = r.uniform(0, 2 * np.pi, n)
