@@ -66,7 +66,8 @@ struct WaveLds {
   float dmi[NT > 0 ? NT : 1][12];      // d multiplier / d p at the stage time
   float dmn[NT > 0 ? NT : 1][12];      // ... at t_n
   float ddm[NT > 0 ? NT : 1][12];      // d (time derivative of the multiplier) / d p at t_n
-  double ctl[4];                       // step controller: time, next step size, this step size, landed
+  double ctl[6];                       // step controller: time, next step size, this step size, landed,
+                                       // last attempt rejected
   __device__ float* X() { return u; }
   __device__ float* Ub() { return u + kUbOff; }
   __device__ float* xin() { return u; }
@@ -833,7 +834,10 @@ stepper_kernel(StepArgs A, DevTables t) {
   const int first_rec = A.settle * A.Ns;
   // The controller's FP64 scalars live in LDS across a step (re-read after it), so they take no
   // registers while the step runs.
-  if (lane == 0) w.ctl[1] = dt;  // step size, kept across sample intervals
+  if (lane == 0) {
+    w.ctl[1] = dt;  // step size, kept across sample intervals
+    w.ctl[4] = 0.0;
+  }
   int steps = 0;
   for (int j = 0; j < n_int && ok; ++j) {
     const double tj = j * dt;
@@ -907,23 +911,30 @@ stepper_kernel(StepArgs A, DevTables t) {
       const double dt2 = A.period / A.Ns;
       const double hmin = dt2 / (A.r_max > 0 ? A.r_max : 64);
       const double t2 = w.ctl[0], hst = w.ctl[1], hs2 = w.ctl[2];
-      const bool landed2 = w.ctl[3] != 0.0;
+      const bool landed2 = w.ctl[3] != 0.0, after_reject = w.ctl[4] != 0.0;
       const double tend2 = j * dt2 + dt2;
       const float fac = 0.9f * sqrtf(sqrtf(A.tol / fmaxf(e, 1e-30f)));
-      if (!fixedr && e > A.tol && hs2 > hmin * 1.0001) {  // reject this step only: y is unchanged
+      // reject this step only (y is unchanged).  A step no longer than hmin / 0.95 is always accepted:
+      // the landing rule could stretch its retry back to the same length.
+      if (!fixedr && e > A.tol && hs2 > hmin * 1.06) {
         if constexpr (NT > 0) {
           for (int pp = 0; pp < NT; ++pp)
             for (int q = lane; q < Np; q += 64) TY(pp)[q] = TYS(pp)[q];
         }
-        if (lane == 0) w.ctl[1] = fmax(hmin, hs2 * double(fmaxf(0.2f, fac)));
+        if (lane == 0) {
+          w.ctl[1] = fmax(hmin, hs2 * double(fmaxf(0.2f, fac)));
+          w.ctl[4] = 1.0;
+        }
         wsync();
         continue;
       }
       accept(float(hs2) * 0.25f);
-      const double hn = hs2 * double(fminf(4.0f, fmaxf(0.2f, fac)));
+      // no growth right after a rejected attempt (avoids grow / reject cycles)
+      const double hn = hs2 * double(fminf(after_reject ? 1.0f : 4.0f, fmaxf(0.2f, fac)));
       if (lane == 0) {
         w.ctl[0] = landed2 ? tend2 : t2 + hs2;
         w.ctl[1] = fmin(dt2, fmax(hmin, landed2 ? fmax(hn, hst) : hn));
+        w.ctl[4] = 0.0;
       }
       wsync();
     }

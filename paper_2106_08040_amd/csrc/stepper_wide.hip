@@ -50,7 +50,7 @@ struct WideLds {
   float cw[6][64];    // Schur coefficients of one block, multiplier included
   float mk[16];
   float ms[16];
-  double ctl[4];      // step controller: time, next step size, this step size, landed
+  double ctl[6];      // step controller: time, next step size, this step size, landed, last attempt rejected
   __device__ float* X() { return a; }
   __device__ float* xin() { return a; }
   __device__ float* V() { return a + NpA; }
@@ -227,17 +227,24 @@ stepper_wide_kernel(StepArgs A, DevTables t, float* ws) {
     }
   };
   // x = M^{-1} V with the stored block inverses; result in G
-  auto block_apply = [&](auto KK, float* G, bool subtract) {
+  // Block solves read the inverses from the workspace.  The column quads of the next block are
+  // requested before the current block's right-hand side is formed (two alternating register
+  // buffers), so the memory latency overlaps the LDS work of the current block.
+  constexpr int kNQ = WG::q4(0) > WG::q4(1) ? WG::q4(0) : WG::q4(1);  // largest quad count of a block
+  auto load_quads = [&](auto KK, float4 (&cq)[kNQ]) {
     constexpr int K = decltype(KK)::value;
-    constexpr int n = Gm::nb(K), off0 = Gm::off(K), nq = WG::q4(K);
+    constexpr int n = Gm::nb(K), nq = WG::q4(K);
     const float4* iv = reinterpret_cast<const float4*>(opaque_ptr(inv) + WG::ioff(K));
-    float part = 0.0f;
     if (lane < n) {
-      // every column quad of this row is requested before the first use (one memory wait)
-      float4 cq[nq];
 #pragma unroll
       for (int q = 0; q < nq; ++q) cq[q] = iv[q * n + lane];
-      __builtin_amdgcn_sched_barrier(0);
+    }
+  };
+  auto block_apply = [&](auto KK, float* G, bool subtract, const float4 (&cq)[kNQ]) {
+    constexpr int K = decltype(KK)::value;
+    constexpr int n = Gm::nb(K), off0 = Gm::off(K), nq = WG::q4(K);
+    float part = 0.0f;
+    if (lane < n) {
 #pragma unroll
       for (int q = 0; q < nq; ++q) {
         const float4 c = cq[q];
@@ -259,9 +266,12 @@ stepper_wide_kernel(StepArgs A, DevTables t, float* ws) {
 #pragma unroll
     for (int k = 0; k < 9; ++k) mk[k] = w.mk[k];
     const float mFX = mk[5], mFY = mk[6], mRX = mk[7], mRY = mk[8];
+    float4 qa[kNQ], qb[kNQ];
+    load_quads(std::integral_constant<int, 0>{}, qa);
     static_for<0, L + 1>([&](auto KK) {
       constexpr int K = decltype(KK)::value;
       constexpr int n = Gm::nb(K), off0 = Gm::off(K);
+      if constexpr (K + 1 <= L) load_quads(std::integral_constant<int, K + 1>{}, (K % 2 == 0) ? qb : qa);
       const float* ev = opaque_ptr(eval);
       const uint16_t* ec = opaque_ptr(ecol);
       const float* wb = opaque_ptr(wB);
@@ -306,12 +316,14 @@ stepper_wide_kernel(StepArgs A, DevTables t, float* ws) {
         w.T[lane] = tv;
       }
       wsync();
-      block_apply(KK, G, false);
+      block_apply(KK, G, false, (K % 2 == 0) ? qa : qb);
       __builtin_amdgcn_sched_barrier(0);
     });
+    load_quads(std::integral_constant<int, L - 1>{}, ((L - 1) % 2 == 0) ? qa : qb);
     static_for_down<L - 1, 0>([&](auto KK) {
       constexpr int K = decltype(KK)::value;
       constexpr int n = Gm::nb(K), off0 = Gm::off(K);
+      if constexpr (K >= 1) load_quads(std::integral_constant<int, K - 1>{}, (K % 2 == 0) ? qb : qa);
       const float* wc = opaque_ptr(wC);
       if (lane < n) {
         const int row = off0 + lane;
@@ -337,7 +349,7 @@ stepper_wide_kernel(StepArgs A, DevTables t, float* ws) {
         w.T[lane] = tv;
       }
       wsync();
-      block_apply(KK, G, true);
+      block_apply(KK, G, true, (K % 2 == 0) ? qa : qb);
       __builtin_amdgcn_sched_barrier(0);
     });
   };
@@ -604,7 +616,10 @@ stepper_wide_kernel(StepArgs A, DevTables t, float* ws) {
   const int n_int = (A.settle + 1) * A.Ns;
   const int first_rec = A.settle * A.Ns;
   // The controller's FP64 scalars live in LDS across a step (re-read after it).
-  if (lane == 0) w.ctl[1] = dt;  // step size, kept across sample intervals
+  if (lane == 0) {
+    w.ctl[1] = dt;  // step size, kept across sample intervals
+    w.ctl[4] = 0.0;
+  }
   int steps = 0;
   for (int j = 0; j < n_int && ok; ++j) {
     const double tj = j * dt;
@@ -650,19 +665,26 @@ stepper_wide_kernel(StepArgs A, DevTables t, float* ws) {
       const double dt2 = A.period / A.Ns;
       const double hmin = dt2 / (A.r_max > 0 ? A.r_max : 64);
       const double t2 = w.ctl[0], hst = w.ctl[1], hs2 = w.ctl[2];
-      const bool landed2 = w.ctl[3] != 0.0;
+      const bool landed2 = w.ctl[3] != 0.0, after_reject = w.ctl[4] != 0.0;
       const double tend2 = j * dt2 + dt2;
       const float fac = 0.9f * sqrtf(sqrtf(A.tol / fmaxf(e, 1e-30f)));
-      if (!fixedr && e > A.tol && hs2 > hmin * 1.0001) {  // reject this step only: y is unchanged
-        if (lane == 0) w.ctl[1] = fmax(hmin, hs2 * double(fmaxf(0.2f, fac)));
+      // reject this step only (y is unchanged).  A step no longer than hmin / 0.95 is always accepted:
+      // the landing rule could stretch its retry back to the same length.
+      if (!fixedr && e > A.tol && hs2 > hmin * 1.06) {
+        if (lane == 0) {
+          w.ctl[1] = fmax(hmin, hs2 * double(fmaxf(0.2f, fac)));
+          w.ctl[4] = 1.0;
+        }
         wsync();
         continue;
       }
       accept(float(hs2) * 0.25f);
-      const double hn = hs2 * double(fminf(4.0f, fmaxf(0.2f, fac)));
+      // no growth right after a rejected attempt (avoids grow / reject cycles)
+      const double hn = hs2 * double(fminf(after_reject ? 1.0f : 4.0f, fmaxf(0.2f, fac)));
       if (lane == 0) {
         w.ctl[0] = landed2 ? tend2 : t2 + hs2;
         w.ctl[1] = fmin(dt2, fmax(hmin, landed2 ? fmax(hn, hst) : hn));
+        w.ctl[4] = 0.0;
       }
       wsync();
     }
