@@ -1,0 +1,38 @@
+"""GPU regression test of the per-step error control on particles at the edge of resolution
+(the L = 24 particles of the uneven sweep, sigma up to 20): every sample interval must finish in a
+bounded number of RODAS4 steps.  A rejected step that the landing rule stretched back to the same
+length was once retried until the error estimate happened to fall below the tolerance."""
+import numpy as np
+import pytest
+
+import workloads as W
+
+pytestmark = pytest.mark.gpu
+
+
+def test_hard_particles_finish_in_bounded_steps():
+    import torch
+
+    import paper_2106_08040_amd as fpn
+    ws = W.uneven_sweep(4096, seed=3)
+    sub = W.take(ws, np.nonzero(ws["inst"]["L"] == 24)[0])
+    ctx = fpn.Context(0)
+    try:
+        T = 40e-6
+        drive = fpn.make_drive((10e-3, 8e-3, 0.0), (3 / T, 4 / T, 0.0), T, (0.0, 0.3, 0.0))
+        Ns = 64
+        p = ctx.plan(sub["inst"], sub["inst"]["L"], drive, Ns, 1, 8, want_m=True)
+        p.launch()
+        torch.cuda.synchronize()
+        per_interval = p.steps() / (2 * Ns)
+        status = p.status.cpu().numpy()
+        m = p.m.cpu().numpy()
+        p.close()
+    finally:
+        ctx.close()
+    print(f"{len(per_interval)} particles: steps per sample interval mean {per_interval.mean():.1f}, "
+          f"max {per_interval.max():.1f}", flush=True)
+    assert (status == 0).all()
+    assert np.isfinite(m).all() and (np.linalg.norm(m, axis=1) <= 1.0 + 1e-5).all()
+    # the smallest step is 1/64 of the sample spacing; rejections may add to that, not multiply it
+    assert per_interval.max() <= 128 and per_interval.mean() <= 64
