@@ -250,13 +250,13 @@ def bench_surrogate(args):
         wait_with_progress(torch, "solver", t0)
         return h, st, time.perf_counter() - t0, drive
 
-    tr, va, te = surrogate_domain(8192, 11), surrogate_domain(1024, 12), surrogate_domain(1024, 13)
+    tr, va, te = surrogate_domain(args.sur_train, 11), surrogate_domain(1024, 12), surrogate_domain(1024, 13)
     htr, _, t_tr, drive = solve(tr)
     hva, _, _, _ = solve(va)
     hte, _, t_te, _ = solve(te)
     print(f"[bench] training targets: {len(tr['inst']['D'])} solves in {t_tr:.1f} s", file=sys.stderr, flush=True)
     sur = Surrogate(ctx, KH)
-    sur.fit(tr["inst"], htr, steps=4000, batch=4096, lr=2e-3)
+    sur.fit(tr["inst"], htr, steps=args.sur_steps, batch=4096, lr=2e-3)
     true_va, _ = sur.calibrate(va["inst"], hva)
     ev = surrogate_domain(0, 0, n_off=64, n_ang=64)
     n_ev = ev["inst"]["D"].size
@@ -295,7 +295,7 @@ def bench_surrogate(args):
         "dtype": "bf16", "data": "synthetic",
         "config": {"workload": "surrogate_lissajous_family_64x64x64", "evaluations": n_ev, "harmonics": KH,
                    "network": sur.nets[0].widths, "ensemble": 2, "train_instances": len(tr["inst"]["D"]),
-                   "train_steps": 4000, "train_seconds": sur.train_seconds,
+                   "train_steps": args.sur_steps, "train_seconds": sur.train_seconds,
                    "validation_rel_l2_median": float(np.median(true_va)),
                    "validation_rel_l2_p99": float(np.quantile(true_va, 0.99)), "err_calibration": sur.err_calib,
                    "inference_evals_per_s": n_ev / t_inf, "solver_solves_per_s": solver_rate,
@@ -318,6 +318,8 @@ def main():
     ap.add_argument("--tol", type=float, default=0.0, help="adaptive error bound (0 = library default)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-budget", type=float, default=15.0)
+    ap.add_argument("--sur-train", type=int, default=32768, help="surrogate workload: solver-generated training instances")
+    ap.add_argument("--sur-steps", type=int, default=16000, help="surrogate workload: Adam steps per member")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="run only a plain 256 MiB device copy three times (reference for the FETCH_SIZE / "
                          "WRITE_SIZE counters) and exit")
