@@ -329,8 +329,8 @@ def main():
                          "surrogate: network ensemble trained on solver output, 262144 evaluations")
     args = ap.parse_args()
     if args.gpus != 1:
-        print("bench.py measures one GPU only: this build has no multi-GPU path "
-              "(instances are independent; see DESIGN.md for how the batch would shard).", file=sys.stderr)
+        print("bench.py measures one GPU only: there is no multi-GPU path (instances are independent; a "
+              "batch would be split across GPUs by predicted cost, each GPU writing its own slice).", file=sys.stderr)
         sys.exit(2)
 
     import torch
