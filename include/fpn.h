@@ -41,7 +41,7 @@ enum {
   FPN_E_RANGE = -2,        /* value out of the supported range (e.g. L) */
   FPN_E_DEVICE = -3,       /* HIP runtime error */
   FPN_E_NOMEM = -4,        /* device allocation failed */
-  FPN_E_UNSUPPORTED = -7   /* valid request this build does not implement */
+  FPN_E_UNSUPPORTED = -7   /* valid request the library does not implement */
 };
 
 /* per-instance status codes written to `status[i]` */
