@@ -67,7 +67,7 @@ struct WaveLds {
   float dmn[NT > 0 ? NT : 1][12];      // ... at t_n
   float ddm[NT > 0 ? NT : 1][12];      // d (time derivative of the multiplier) / d p at t_n
   double ctl[6];                       // step controller: time, next step size, this step size, landed,
-                                       // last attempt rejected
+                                       // last attempt rejected, steps taken (accepted and rejected)
   __device__ float* X() { return u; }
   __device__ float* Ub() { return u + kUbOff; }
   __device__ float* xin() { return u; }
@@ -837,8 +837,8 @@ stepper_kernel(StepArgs A, DevTables t) {
   if (lane == 0) {
     w.ctl[1] = dt;  // step size, kept across sample intervals
     w.ctl[4] = 0.0;
+    w.ctl[5] = 0.0;
   }
-  int steps = 0;
   for (int j = 0; j < n_int && ok; ++j) {
     const double tj = j * dt;
     if (j >= first_rec) {
@@ -903,14 +903,14 @@ stepper_kernel(StepArgs A, DevTables t) {
             for (int q = lane; q < Np; q += 64) TYS(pp)[q] = TY(pp)[q];
       }
       const float e = rodas_step(t, hs);
-      ++steps;
       if (!isfinite(e)) {
+        if (lane == 0) w.ctl[5] += 1.0;
         ok = false;
         break;
       }
       const double dt2 = A.period / A.Ns;
       const double hmin = dt2 / (A.r_max > 0 ? A.r_max : 64);
-      const double t2 = w.ctl[0], hst = w.ctl[1], hs2 = w.ctl[2];
+      const double t2 = w.ctl[0], hst = w.ctl[1], hs2 = w.ctl[2], nst = w.ctl[5];
       const bool landed2 = w.ctl[3] != 0.0, after_reject = w.ctl[4] != 0.0;
       const double tend2 = j * dt2 + dt2;
       const float fac = 0.9f * sqrtf(sqrtf(A.tol / fmaxf(e, 1e-30f)));
@@ -924,6 +924,7 @@ stepper_kernel(StepArgs A, DevTables t) {
         if (lane == 0) {
           w.ctl[1] = fmax(hmin, hs2 * double(fmaxf(0.2f, fac)));
           w.ctl[4] = 1.0;
+          w.ctl[5] = nst + 1.0;
         }
         wsync();
         continue;
@@ -935,6 +936,7 @@ stepper_kernel(StepArgs A, DevTables t) {
         w.ctl[0] = landed2 ? tend2 : t2 + hs2;
         w.ctl[1] = fmin(dt2, fmax(hmin, landed2 ? fmax(hn, hst) : hn));
         w.ctl[4] = 0.0;
+        w.ctl[5] = nst + 1.0;
       }
       wsync();
     }
@@ -945,7 +947,8 @@ stepper_kernel(StepArgs A, DevTables t) {
       for (int j = lane; j < NT * 3 * A.Ns; j += 64) mt_out[j] = __builtin_nanf("");
     if (lane == 0) A.status[inst] = 2;
   }
-  if (A.steps_out && lane == 0) A.steps_out[inst] = steps;
+  wsync();
+  if (A.steps_out && lane == 0) A.steps_out[inst] = int(w.ctl[5]);
   }  // queue
 }
 
