@@ -75,13 +75,16 @@ def coupling_counts(fpn, L):
     return nD, nB, nC, int(nz.sum())
 
 
-def flops_per_step(fpn, L):
+def flops_per_step(fpn, L, tangents=0):
     """Algorithmic FP32 flops of one RODAS4 step of one instance (6 stages, one factorisation):
       factorisation: sum_k 2 n_k^3 (block inverse) + 2 nnz(B_k) n_{k-1} + 2 nnz(C_{k-1}) n_k (Schur)
                      + 2 nnz(D) (assembly)
       per stage:     2 nnz (matvec) + sum_k [4 n_k^2 + 2 nnz(B_k) + 2 nnz(C_k)] (block solve)
                      + 13 N (stage combinations, on average)
-      plus one matvec for the time derivative of the field term."""
+      plus one matvec for the time derivative of the field term.
+    Each parameter tangent adds per stage four products with the operator's sparsity (A and dA/dp on
+    the tangent and primal stage vectors, 8 nnz), one block solve and the stage combinations, and per
+    step one more matvec for its time-derivative term."""
     n = block_structure(L)
     N = (L + 1) ** 2
     nD, nB, nC, nnz = coupling_counts(fpn, L)
@@ -89,7 +92,8 @@ def flops_per_step(fpn, L):
     fac += sum(2 * nB[k] * n[k - 1] + 2 * nC[k - 1] * n[k] for k in range(1, L + 1))
     solve = sum(4 * nk ** 2 for nk in n) + 2 * int(nB.sum()) + 2 * int(nC.sum())
     stage = 2 * nnz + solve + 13 * N
-    return fac + 6 * stage + 2 * nnz
+    tan = 6 * (8 * nnz + solve + 13 * N) + 2 * nnz
+    return fac + 6 * stage + 2 * nnz + tangents * tan
 
 
 def cpu_baseline(ws, budget_s=15.0):
@@ -211,6 +215,127 @@ def bench_uneven(args):
     ctx.close()
 
 
+def bench_gradient(args):
+    """Parameter identification gradient: 32 x 32 offsets on +-12 mT x 16 in-plane easy-axis angles x 4
+    particle components (D, K, alpha and a superposition weight each), L = 16, harmonics 1..300 of x and
+    y.  Loss = sum over angles, offsets, channels and harmonics of |sum_c w_c Phi_c - S|^2, S synthesised
+    from seeded ground-truth parameters plus 1 % Gaussian noise.  One step = the loss and its gradient
+    with respect to every component's D, K, alpha and weight and every angle, through the autograd
+    Function (forward fpn_solve, backward fpn_adjoint: five parameter tangents per instance and the FP64
+    contraction), one angle (4096 instances) per forward/backward pair."""
+    import torch
+    import paper_2106_08040_amd as fpn
+    from paper_2106_08040_amd.autograd import Harmonics
+    import workloads as W
+
+    ws = W.identification_problem(n_ang=args.grad_angles)
+    dev = "cuda:0"
+    torch.cuda.set_device(0)
+    ctx = fpn.Context(0)
+    d = ws["drive"]
+    drive = fpn.make_drive(d["amp"], d["freq"], d["period"], d["phase"])
+    Kh, L = ws["n_harm"], ws["L"]
+    fn = Harmonics(ctx, drive, ws["samples"], ws["settle"], Kh, L=L)
+    off = ws["offsets"]
+    nO, nC, nA = off.shape[0], ws["truth"]["D"].size, ws["angles"].size
+    nch = nO * nC                      # instances per angle: instance = offset * nC + component
+    f64 = dict(dtype=torch.float64, device=dev)
+    off_t = torch.as_tensor(np.repeat(off, nC, 0), **f64)
+    comp = torch.arange(nch, device=dev) % nC
+    Ms_t, T_t = torch.full((nch,), ws["Ms"], **f64), torch.full((nch,), ws["T"], **f64)
+    polar = torch.full((nch,), np.pi / 2, **f64)
+
+    def chunk_phi(p, az):
+        params = torch.stack([p["D"][comp], p["K"][comp], p["alpha"][comp], polar, az.expand(nch)], 1)
+        phi = fn(params, Ms_t, T_t, off_t)             # [nch, 2, Kh + 1, 2]
+        return phi[:, :, 1:, :].to(torch.float64).reshape(nO, nC, 2, Kh, 2)
+
+    def superpose(p, phi):
+        return (p["w"][None, :, None, None, None] * phi).sum(1)
+
+    # measured signal: the ground truth's superposition plus 1 % noise per channel
+    t0 = time.perf_counter()
+    truth = {k: torch.as_tensor(v, **f64) for k, v in ws["truth"].items()}
+    with torch.no_grad():
+        S = torch.stack([superpose(truth, chunk_phi(truth, torch.tensor(a, **f64))) for a in ws["angles"]])
+    wait_with_progress(torch, "signal synthesis", t0)
+    rms = torch.sqrt((S ** 2).mean(dim=(0, 1, 3, 4)))      # per channel
+    noise = torch.as_tensor(ws["noise_rng"]().normal(size=tuple(S.shape)), **f64)
+    S = S + noise * (ws["noise_frac"] * rms)[None, None, :, None, None]
+    print(f"[bench] signal: {nA * nch} solves in {time.perf_counter() - t0:.1f} s", file=sys.stderr, flush=True)
+
+    def gradient(timed):
+        p = {k: torch.tensor(v, requires_grad=True, **f64) for k, v in ws["guess"].items()}
+        az = torch.tensor(ws["angles_guess"], requires_grad=True, **f64)
+        total = torch.zeros((), **f64)
+        acc = {"primal_ms": 0.0, "tangent_ms": 0.0, "primal_steps": 0, "tangent_steps": 0, "nonfinite": 0}
+        for j in range(nA):
+            tc = time.perf_counter()
+            if timed:
+                r0 = ctx.timing_read()["stepper"][0]
+            phi = chunk_phi(p, az[j])
+            if timed:
+                r1 = ctx.timing_read()["stepper"][0]
+                acc["primal_ms"] += r1 - r0
+                acc["primal_steps"] += ctx.last_steps()
+                acc["nonfinite"] += int((~torch.isfinite(phi.reshape(nO * nC, -1)).all(1)).sum().item())
+            res = superpose(p, phi) - S[j]
+            loss = (res ** 2).sum()
+            loss.backward()
+            total = total + loss.detach()
+            wait_with_progress(torch, f"angle {j + 1}/{nA}", tc)
+            if timed:
+                acc["tangent_ms"] += ctx.timing_read()["stepper"][0] - r1
+                acc["tangent_steps"] += ctx.last_steps()
+                print(f"[bench] angle {j + 1}/{nA}: {time.perf_counter() - tc:.1f} s", file=sys.stderr, flush=True)
+        grad = {k: v.grad.cpu().numpy().tolist() for k, v in p.items()}
+        grad["angle"] = az.grad.cpu().numpy().tolist()
+        return float(total.item()), grad, acc
+
+    for _ in range(args.warmup):
+        gradient(False)
+    torch.cuda.synchronize()
+    ctx.timing_enable(True)
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        loss, grad, acc = gradient(True)
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    ctx.timing_enable(False)
+    n = nA * nch
+    fl_t = float(flops_per_step(fpn, L, tangents=5))
+    achieved = fl_t * acc["tangent_steps"] / (acc["tangent_ms"] * 1e-3) / 1e12
+    res = {
+        "metric": "FP solves/sec & surrogate evals/sec at \u22641e-3 rel-L2 vs FP64 oracle",
+        "value": n * args.steps / wall, "unit": "solves/s (with gradient)", "n_gpus": 1, "steps": args.steps,
+        "warmup": args.warmup, "ms_per_step": wall / args.steps * 1e3, "higher_is_better": True,
+        "scaling": "weak", "vs_baseline": None, "dtype": "f32", "data": "synthetic",
+        "config": {"workload": ws["name"], "instances": n, "L": L, "samples": ws["samples"],
+                   "settle_periods": ws["settle"], "harmonics": f"1..{Kh}", "parameters_per_instance": 5,
+                   "loss": loss, "gradient": grad, "nonfinite_instances": acc["nonfinite"],
+                   "primal_steps": acc["primal_steps"], "tangent_steps": acc["tangent_steps"]},
+        "roofline": {"bound": "alu", "kernel": "stepper (five tangents)", "achieved": achieved,
+                     "peak": FP32_VECTOR_PEAK_TFLOPS, "unit": "TFLOP/s", "frac": achieved / FP32_VECTOR_PEAK_TFLOPS,
+                     "traffic": None, "avg_launch_ms": acc["tangent_ms"] / nA,
+                     "flops_per_step": fl_t, "primal_stepper_ms": acc["primal_ms"] / nA},
+    }
+    if not args.no_cpu_baseline:
+        one = dict(inst=dict(D=np.array([ws["guess"]["D"][0]]), Ms=np.array([ws["Ms"]]),
+                             K=np.array([ws["guess"]["K"][0]]), alpha=np.array([ws["guess"]["alpha"][0]]),
+                             T=np.array([ws["T"]]),
+                             easy_axis=np.array([[np.cos(ws["angles_guess"][0]), np.sin(ws["angles_guess"][0]), 0.0]]),
+                             offset=off[:1], L=np.array([L], np.int32)),
+                   drive=ws["drive"], samples=ws["samples"], settle=ws["settle"])
+        cb = cpu_baseline(one, args.cpu_budget)
+        cb["value"] /= 11.0
+        cb["unit"] = "solves/s (with gradient)"
+        cb["sample"] += ("; the oracle's gradient is central differences in D, K, alpha and the two axis angles, "
+                         "11 solves per instance, so the rate is the solve rate / 11")
+        res["cpu_baseline"] = cb
+    print(json.dumps(res), flush=True)
+    ctx.close()
+
+
 def surrogate_domain(n, seed, n_off=None, n_ang=None):
     """The system-matrix family of the Lissajous workload (D = 20 nm, K = 2 kJ/m^3, alpha = 0.1, L = 16,
     in-plane easy axes, offsets on +-12 mT): random draws, or a regular n_off x n_off x n_ang grid."""
@@ -323,10 +448,12 @@ def main():
     ap.add_argument("--copy-calibration", action="store_true",
                     help="run only a plain 256 MiB device copy three times (reference for the FETCH_SIZE / "
                          "WRITE_SIZE counters) and exit")
-    ap.add_argument("--workload", choices=("lissajous", "uneven", "surrogate"), default="lissajous",
+    ap.add_argument("--grad-angles", type=int, default=16, help="gradient workload: easy-axis angles")
+    ap.add_argument("--workload", choices=("lissajous", "uneven", "surrogate", "gradient"), default="lissajous",
                     help="lissajous: 2312-instance system matrix, L = 16 (headline); "
                          "uneven: 4096 instances with L = 8..24 in one graph launch; "
-                         "surrogate: network ensemble trained on solver output, 262144 evaluations")
+                         "surrogate: network ensemble trained on solver output, 262144 evaluations; "
+                         "gradient: identification loss and its gradient over 65536 instances")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py measures one GPU only: there is no multi-GPU path (instances are independent; a "
@@ -349,6 +476,8 @@ def main():
         return bench_uneven(args)
     if args.workload == "surrogate":
         return bench_surrogate(args)
+    if args.workload == "gradient":
+        return bench_gradient(args)
     ws = W.lissajous_grid()
     n = ws["inst"]["D"].size
     dev = "cuda:0"

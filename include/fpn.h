@@ -207,8 +207,11 @@ fpn_status fpn_set_stepper_waves(fpn_ctx ctx, int32_t L, int32_t waves);
  * Errors: FPN_E_ARG, FPN_E_DEVICE. */
 fpn_status fpn_autotune(fpn_ctx ctx, int32_t L, int32_t* waves_out, double* ns_per_step_out);
 
-/* Time steps taken by the last fpn_solve on this context, summed over its instances
- * (synchronises with that solve).  HOST output.  Errors: FPN_E_ARG, FPN_E_DEVICE. */
+/* Time steps taken by the most recent fpn_solve, fpn_solve_tangent or fpn_adjoint on this context,
+ * summed over its instances (synchronises with that call).  0 before the first such call and after
+ * one that failed while setting up or launching; a call rejected for its arguments leaves the previous
+ * count.  Plans (fpn_plan_*) report theirs through fpn_plan_steps.  HOST output.
+ * Errors: FPN_E_ARG, FPN_E_DEVICE. */
 fpn_status fpn_last_steps(fpn_ctx ctx, int64_t* total_steps);
 
 /* Stationary mean moment under a static field (FP64 on the device):

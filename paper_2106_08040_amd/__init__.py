@@ -298,7 +298,7 @@ class Context:
         return int(w.value), {opts[k]: float(ns[k]) for k in range(len(opts))}
 
     def last_steps(self):
-        """Time steps taken by the last solve, summed over instances."""
+        """Time steps taken by the most recent solve, tangent solve or adjoint, summed over instances."""
         v = ctypes.c_int64()
         _check(_lib.fpn_last_steps(self._h, ctypes.byref(v)), "fpn_last_steps")
         return int(v.value)

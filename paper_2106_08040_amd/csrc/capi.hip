@@ -648,15 +648,18 @@ fpn_status fpn_solve(fpn_ctx ctx, const fpn_drive* drive, const fpn_solve_opts* 
   FPN_HIP(hipSetDevice(ctx->device));
   if (!ctx->solve_plan) ctx->solve_plan = new fpn_plan_s();
   fpn_plan_s* p = ctx->solve_plan;
+  ctx->last_plan = nullptr;
   if (fpn_status s = plan_build(p, ctx, drive, opts, batch, n, nullptr, m_out, harm_out, status, stream)) return s;
-  return plan_launch(p, stream, ctx->timing);
+  if (fpn_status s = plan_launch(p, stream, ctx->timing)) return s;
+  ctx->last_plan = p;
+  return FPN_OK;
 }
 
 fpn_status fpn_last_steps(fpn_ctx ctx, int64_t* total_steps) {
   if (!ctx || !total_steps) return fail(FPN_E_ARG, "NULL argument");
   std::lock_guard<std::mutex> lk(ctx->mu);
   FPN_HIP(hipSetDevice(ctx->device));
-  const fpn_plan_s* p = ctx->solve_plan;
+  const fpn_plan_s* p = ctx->last_plan;
   const int64_t n = p ? p->n : 0;
   std::vector<int32_t> h(n);
   if (n > 0) {
@@ -685,11 +688,14 @@ fpn_status fpn_solve_tangent(fpn_ctx ctx, const fpn_drive* drive, const fpn_solv
   FPN_HIP(hipSetDevice(ctx->device));
   if (!ctx->tangent_plan) ctx->tangent_plan = new fpn_plan_s();
   fpn_plan_s* p = ctx->tangent_plan;
+  ctx->last_plan = nullptr;
   if (fpn_status s = plan_build(p, ctx, drive, opts, batch, n, nullptr, m_out, harm_out, status, stream, true,
                                 (opts->flags & FPN_OUT_M) ? dm_out : nullptr,
                                 (opts->flags & FPN_OUT_HARM) ? dharm_out : nullptr))
     return s;
-  return plan_launch(p, stream, ctx->timing);
+  if (fpn_status s = plan_launch(p, stream, ctx->timing)) return s;
+  ctx->last_plan = p;
+  return FPN_OK;
 }
 
 fpn_status fpn_adjoint(fpn_ctx ctx, const fpn_drive* drive, const fpn_solve_opts* opts, const fpn_batch* batch,
@@ -708,8 +714,10 @@ fpn_status fpn_adjoint(fpn_ctx ctx, const fpn_drive* drive, const fpn_solve_opts
   FPN_HIP(hipSetDevice(ctx->device));
   if (!ctx->tangent_plan) ctx->tangent_plan = new fpn_plan_s();
   fpn_plan_s* p = ctx->tangent_plan;
+  ctx->last_plan = nullptr;
   if (fpn_status s = plan_build(p, ctx, drive, &o, batch, n, nullptr, nullptr, harm_out, status, stream, true)) return s;
   if (fpn_status s = plan_launch(p, stream, ctx->timing)) return s;
+  ctx->last_plan = p;
   const int nch = (opts->flags & FPN_HARM_Z) ? 3 : 2;
   fpn::launch_contract(dL_dharm, p->dharm, nch * (opts->n_harm + 1) * 2, grad_out, status, n, stream);
   FPN_HIP(hipGetLastError());

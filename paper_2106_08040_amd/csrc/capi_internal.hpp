@@ -95,6 +95,7 @@ struct fpn_ctx_s {
   int64_t launches[4] = {0, 0, 0, 0};
   fpn_plan_s* solve_plan = nullptr;   // reused by fpn_solve
   fpn_plan_s* tangent_plan = nullptr; // reused by fpn_solve_tangent and fpn_adjoint
+  fpn_plan_s* last_plan = nullptr;    // the one of the two used by the most recent call (fpn_last_steps)
   // (L, tangents, workgroup size) -> (waves per workgroup, workgroups per CU)
   std::map<int, std::pair<int, int>> occupancy;
   int cus = 0;

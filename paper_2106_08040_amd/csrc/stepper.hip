@@ -164,8 +164,6 @@ stepper_kernel(StepArgs A, DevTables t) {
     const int d = e / Np, c = e - d * Np;
     wS[c * kNWin + d] = t.win_s[e];
   }
-  // per-wave scratch starts zeroed: window reads past a block edge (weight 0) then see finite data
-  for (int e = threadIdx.x; e < int(WAVES * sizeof(WL) / 4); e += blockDim.x) reinterpret_cast<float*>(wl)[e] = 0.0f;
   __syncthreads();
 
   const int lane = threadIdx.x & 63;
@@ -185,6 +183,8 @@ stepper_kernel(StepArgs A, DevTables t) {
   if (qk >= A.n_inst) break;
   const int inst = A.inst_idx[qk];
   WL& w = wl[wid];
+  clear_wave_scratch(w, lane);
+  wsync();
   const int i = lane & 31, h = lane >> 5;
   float* ms_out = A.msamp + int64_t(inst) * 3 * A.Ns;
   float* mt_out = (NT > 0) ? A.mtan + int64_t(inst) * NT * 3 * A.Ns : nullptr;
@@ -812,7 +812,7 @@ stepper_kernel(StepArgs A, DevTables t) {
 #pragma unroll
       for (int s = 0; s < S; ++s) {
         const int p = lane + 64 * s;
-        emax = fmaxf(emax, (p < Np) ? fabsf(sc * k6[p]) : 0.0f);
+        emax = fmaxf(emax, (p < Np) ? err_abs(sc * k6[p]) : 0.0f);
       }
     }
     return wave_max(emax);
@@ -903,16 +903,18 @@ stepper_kernel(StepArgs A, DevTables t) {
             for (int q = lane; q < Np; q += 64) TYS(pp)[q] = TY(pp)[q];
       }
       const float e = rodas_step(t, hs);
-      if (!isfinite(e)) {
-        if (lane == 0) w.ctl[5] += 1.0;
-        ok = false;
-        break;
-      }
       const double dt2 = A.period / A.Ns;
       const double hmin = dt2 / (A.r_max > 0 ? A.r_max : 64);
       const double t2 = w.ctl[0], hst = w.ctl[1], hs2 = w.ctl[2], nst = w.ctl[5];
       const bool landed2 = w.ctl[3] != 0.0, after_reject = w.ctl[4] != 0.0;
       const double tend2 = j * dt2 + dt2;
+      // e = +inf for a non-finite attempt (an overflow of the FP32 factorisation, which a long step can
+      // cause): rejected like any other (5x shorter, on cleared scratch) unless it is the smallest step
+      if (!isfinite(e) && (fixedr || hs2 <= hmin * 1.06)) {
+        if (lane == 0) w.ctl[5] = nst + 1.0;
+        ok = false;
+        break;
+      }
       const float fac = 0.9f * sqrtf(sqrtf(A.tol / fmaxf(e, 1e-30f)));
       // reject this step only (y is unchanged).  A step no longer than hmin / 0.95 is always accepted:
       // the landing rule could stretch its retry back to the same length.
@@ -920,6 +922,10 @@ stepper_kernel(StepArgs A, DevTables t) {
         if constexpr (NT > 0) {
           for (int pp = 0; pp < NT; ++pp)
             for (int q = lane; q < Np; q += 64) TY(pp)[q] = TYS(pp)[q];
+        }
+        if (!isfinite(e) || !ok) {
+          clear_wave_scratch(w, lane);
+          ok = true;
         }
         if (lane == 0) {
           w.ctl[1] = fmax(hmin, hs2 * double(fmaxf(0.2f, fac)));

@@ -42,6 +42,23 @@ __device__ __forceinline__ T* opaque_ptr(T* p) {
   return p;
 }
 
+// |v| for the step-error maximum, with NaN mapped to +inf: fmaxf ignores a NaN operand, an infinity
+// survives the maximum and marks the attempt as non-finite.
+__device__ __forceinline__ float err_abs(float v) {
+  const float a = fabsf(v);
+  return a == a ? a : __builtin_inff();
+}
+
+// Zeroes a wavefront's LDS scratch up to its step-controller scalars `ctl` (the struct's last
+// member), before each instance and after a non-finite attempt: window reads past a block edge
+// carry weight 0 and need finite data there.
+template <typename WL>
+__device__ __forceinline__ void clear_wave_scratch(WL& w, int lane) {
+  float* f = reinterpret_cast<float*>(&w);
+  const int nf = int((reinterpret_cast<const char*>(w.ctl) - reinterpret_cast<const char*>(&w)) / 4);
+  for (int e = lane; e < nf; e += 64) f[e] = 0.0f;
+}
+
 // Sum of a value over the two 32-lane halves (lane and lane ^ 32).
 __device__ __forceinline__ float half_sum(float v) {
   auto r = __builtin_amdgcn_permlane32_swap(__float_as_uint(v), __float_as_uint(v), false, false);

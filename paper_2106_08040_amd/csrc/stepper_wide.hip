@@ -115,8 +115,6 @@ stepper_wide_kernel(StepArgs A, DevTables t, float* ws) {
   constexpr int XS = WG::XS;
   extern __shared__ __align__(16) unsigned char smem[];
   WL* wl = reinterpret_cast<WL*>(smem);
-  // per-wave scratch starts zeroed: window reads past a block edge (weight 0) then see finite data
-  for (int e = threadIdx.x; e < int(WAVES * sizeof(WL) / 4); e += blockDim.x) reinterpret_cast<float*>(wl)[e] = 0.0f;
   __syncthreads();
 
   const int lane = threadIdx.x & 63;
@@ -130,6 +128,8 @@ stepper_wide_kernel(StepArgs A, DevTables t, float* ws) {
   if (qk >= A.n_inst) break;
   const int inst = A.inst_idx[qk];
   WL& w = wl[wid];
+  clear_wave_scratch(w, lane);
+  wsync();
   float* inv = ws + int64_t(slot) * WG::WS;
   float* Kg = inv + WG::INV;  // K1..K5 at j * NpA, f_t at 5 * NpA
   const uint16_t* ecol = t.ell_col;
@@ -596,7 +596,7 @@ stepper_wide_kernel(StepArgs A, DevTables t, float* ws) {
 #pragma unroll
       for (int s = 0; s < S; ++s) {
         const int p = lane + 64 * s;
-        emax = fmaxf(emax, (p < Np) ? fabsf(hg * G[p]) : 0.0f);
+        emax = fmaxf(emax, (p < Np) ? err_abs(hg * G[p]) : 0.0f);
       }
     }
     return wave_max(emax);
@@ -658,19 +658,25 @@ stepper_wide_kernel(StepArgs A, DevTables t, float* ws) {
       }
       const float e = rodas_step(t, hs);
       ++steps;
-      if (!isfinite(e)) {
-        ok = false;
-        break;
-      }
       const double dt2 = A.period / A.Ns;
       const double hmin = dt2 / (A.r_max > 0 ? A.r_max : 64);
       const double t2 = w.ctl[0], hst = w.ctl[1], hs2 = w.ctl[2];
       const bool landed2 = w.ctl[3] != 0.0, after_reject = w.ctl[4] != 0.0;
       const double tend2 = j * dt2 + dt2;
+      // e = +inf for a non-finite attempt (an overflow of the FP32 factorisation, which a long step can
+      // cause): rejected like any other (5x shorter, on cleared scratch) unless it is the smallest step
+      if (!isfinite(e) && (fixedr || hs2 <= hmin * 1.06)) {
+        ok = false;
+        break;
+      }
       const float fac = 0.9f * sqrtf(sqrtf(A.tol / fmaxf(e, 1e-30f)));
       // reject this step only (y is unchanged).  A step no longer than hmin / 0.95 is always accepted:
       // the landing rule could stretch its retry back to the same length.
       if (!fixedr && e > A.tol && hs2 > hmin * 1.06) {
+        if (!isfinite(e) || !ok) {
+          clear_wave_scratch(w, lane);
+          ok = true;
+        }
         if (lane == 0) {
           w.ctl[1] = fmax(hmin, hs2 * double(fmaxf(0.2f, fac)));
           w.ctl[4] = 1.0;

@@ -37,6 +37,15 @@ def wide_l24():
     return W.small_random(2, 24, seed=124, samples=48, settle=1, n_harm=8)
 
 
+def identification_a0():
+    """Angle 0 of the identification problem at the guess parameters, 64 harmonics (the first attempted
+    step of these instances, one sample spacing long, overflows the FP32 factorisation)."""
+    ws = W.identification_problem()
+    out = W.identification_instances(ws, 0)
+    out["n_harm"] = 64
+    return out
+
+
 # (workload factory, instance ids, Radau steps per sample for the reference and its check)
 JOBS = {
     "tangent_l10": (tangent_l10, [0, 1], 8),
@@ -44,6 +53,8 @@ JOBS = {
     "wide_l20": (wide_l20, [0, 1], 8),
     "wide_l24": (wide_l24, [0, 1], 16),
     "single_1d": (W.single_1d, [0], 8),
+    # offset (3.5, 6.6) mT components 0 and 2, offset (12, 12) mT component 2
+    "identification_a0": (identification_a0, [(24 * 32 + 20) * 4 + 0, (24 * 32 + 20) * 4 + 2, (31 * 32 + 31) * 4 + 2], 4),
     "lissajous": (W.lissajous_grid, [(0 * 17 + 8) * 17 + 8, (3 * 17 + 2) * 17 + 13, (5 * 17 + 16) * 17 + 0,
                                      (7 * 17 + 10) * 17 + 4, (2 * 17 + 0) * 17 + 16, (6 * 17 + 12) * 17 + 12], 4),
 }

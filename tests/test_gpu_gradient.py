@@ -87,6 +87,23 @@ def test_primal_outputs_of_the_tangent_solve(fpn, ctx, tangent_run):
     assert rel(m, m0.cpu().numpy()) < 1e-6 and rel(h, h0.cpu().numpy()) < 1e-6
 
 
+def test_tangent_solve_takes_the_primal_steps(fpn, ctx):
+    """The step-size control of the tangent solve uses the primal error estimate only, so an adaptive
+    tangent solve takes the plain solve's steps (up to rounding differences between the two kernels)."""
+    import torch
+    ws = W.small_random(4, 10, seed=91, samples=48, settle=1, n_harm=8)
+    args = (ws["inst"], ws["inst"]["L"], drive_of(fpn, ws), ws["samples"], ws["settle"], ws["n_harm"])
+    ctx.solve(*args, want_m=False)
+    s0 = ctx.last_steps()
+    _, _, _, _, st = ctx.solve_tangent(*args, want_m=False)
+    s1 = ctx.last_steps()
+    torch.cuda.synchronize()
+    print(f"steps: plain {s0}, tangent {s1}", flush=True)
+    assert (st.cpu().numpy() == 0).all()
+    assert s0 >= 4 * ws["samples"] * (ws["settle"] + 1)
+    assert abs(s1 - s0) <= 0.02 * s0
+
+
 def test_isotropic_particle_has_no_axis_derivative(fpn, ctx):
     import torch
     ws = W.small_random(3, 8, seed=77, samples=32, settle=1, n_harm=6)

@@ -1,0 +1,47 @@
+"""CPU tests of the seeded input generators: sizes, index maps, ranges and determinism."""
+import numpy as np
+import pytest
+
+import workloads as W
+
+
+def test_lissajous_grid_layout():
+    ws = W.lissajous_grid()
+    inst = ws["inst"]
+    assert inst["D"].size == 2312 and (inst["L"] == 16).all()
+    offs = np.linspace(-12e-3, 12e-3, 17)
+    for j, iy, ix in ((0, 0, 0), (3, 5, 16), (7, 16, 16)):
+        i = (j * 17 + iy) * 17 + ix
+        assert np.allclose(inst["offset"][i], [offs[ix], offs[iy], 0.0], rtol=0, atol=1e-15)
+        assert np.allclose(inst["easy_axis"][i], [np.cos(j * np.pi / 8), np.sin(j * np.pi / 8), 0.0])
+    # 16 and 17 drive cycles per repetition time (the mixing orders of the Lissajous trajectory)
+    assert ws["drive"]["period"] * np.array(ws["drive"]["freq"][:2]) == pytest.approx([16, 17], rel=1e-12)
+
+
+def test_uneven_sweep_is_resolvable_and_seeded():
+    a, b = W.uneven_sweep(4096, seed=3), W.uneven_sweep(4096, seed=3)
+    for k in a["inst"]:
+        assert np.array_equal(a["inst"][k], b["inst"][k])
+    inst = a["inst"]
+    sigma = W.anisotropy_ratio(inst["D"], inst["K"])
+    assert sigma.max() <= 20.0
+    assert inst["L"].min() == 8 and inst["L"].max() == 24
+    assert (inst["L"] >= np.minimum(np.ceil(sigma) + 4, 24)).all()
+    assert np.allclose(np.linalg.norm(inst["easy_axis"], axis=1), 1.0)
+
+
+def test_identification_problem_layout():
+    ws = W.identification_problem()
+    off, ang = ws["offsets"], ws["angles"]
+    assert off.shape == (1024, 3) and ang.size == 16
+    assert off[:, 0].min() == -12e-3 and np.isclose(off[:, 0].max(), 12e-3)
+    assert np.allclose(off[33], [off[1, 0], off[32, 1], 0.0])      # offset index = iy * 32 + ix
+    assert np.allclose(ang, np.arange(16) * np.pi / 16)
+    t, g = ws["truth"], ws["guess"]
+    assert ((t["D"] >= 16e-9) & (t["D"] <= 28e-9)).all() and ((t["K"] >= 500) & (t["K"] <= 5e3)).all()
+    assert ((t["alpha"] >= 0.05) & (t["alpha"] <= 0.3)).all() and ((t["w"] >= 0.1) & (t["w"] <= 1)).all()
+    # L = 16 meets the degree rule for the truth and for the point where the gradient is taken
+    for p in (t, g):
+        assert (np.ceil(W.anisotropy_ratio(p["D"], p["K"])) + 4 <= ws["L"]).all()
+    n1, n2 = ws["noise_rng"]().normal(size=5), W.identification_problem()["noise_rng"]().normal(size=5)
+    assert np.array_equal(n1, n2)

@@ -103,6 +103,44 @@ def uneven_sweep(n=4096, seed=3, L_max=24, sigma_max=20.0):
                 n_harm=200, harm_z=False)
 
 
+def identification_problem(n_off=32, n_ang=16, n_comp=4, L=16, span=12e-3, n_harm=300, seed=4, noise_seed=40):
+    """Parameter identification by gradient (the adjoint workload): an n_off x n_off grid of offsets on
+    +-span (endpoints included) x n_ang in-plane easy-axis angles j pi / n_ang (from x) x n_comp particle
+    components, each with its own D, K, alpha and superposition weight; L fixed, the Lissajous drive,
+    harmonics 1..n_harm of x and y.  Ground truth (seed): D ~ U[16, 28] nm, K log-uniform in
+    [0.5, 5] kJ/m^3, alpha ~ U[0.05, 0.3], w ~ U[0.1, 1].  The gradient is taken at a fixed guess away
+    from the truth (D x 1.05, K x 1.1, alpha x 0.9, w x 0.95, angles + 0.02 rad).  The measured signal is
+    the truth's superposition plus Gaussian noise (noise_seed) of 1 % of each channel's RMS, drawn by
+    the consumer with noise_rng() since it needs the clean signal."""
+    r = np.random.default_rng(seed)
+    truth = dict(D=r.uniform(16e-9, 28e-9, n_comp), K=np.exp(r.uniform(np.log(500.0), np.log(5e3), n_comp)),
+                 alpha=r.uniform(0.05, 0.3, n_comp), w=r.uniform(0.1, 1.0, n_comp))
+    guess = dict(D=truth["D"] * 1.05, K=truth["K"] * 1.1, alpha=truth["alpha"] * 0.9, w=truth["w"] * 0.95)
+    g = -span + (2 * span / (n_off - 1)) * np.arange(n_off)
+    iy, ix = np.meshgrid(np.arange(n_off), np.arange(n_off), indexing="ij")
+    off = np.stack([g[ix.ravel()], g[iy.ravel()], np.zeros(n_off * n_off)], 1)
+    angles = np.arange(n_ang) * np.pi / n_ang
+    return dict(name=f"identification_{n_off}x{n_off}x{n_ang}x{n_comp}_L{L}", offsets=off, angles=angles,
+                angles_guess=angles + 0.02, truth=truth, guess=guess, Ms=MAGNETITE_MS, T=ROOM_T, L=L,
+                drive=lissajous_drive(), samples=1632, settle=1, n_harm=n_harm, noise_frac=0.01,
+                noise_rng=lambda: np.random.default_rng(noise_seed))
+
+
+def identification_instances(ws, angle_index, which="guess"):
+    """The instances of one easy-axis angle of an identification problem as an instance set
+    (instance = offset index * n_comp + component), with the guess or the truth parameters."""
+    p = ws[which]
+    nC = p["D"].size
+    nO = ws["offsets"].shape[0]
+    a = (ws["angles_guess"] if which == "guess" else ws["angles"])[angle_index]
+    n = nO * nC
+    inst = _instances(np.tile(p["D"], nO), np.full(n, ws["Ms"]), np.tile(p["K"], nO), np.tile(p["alpha"], nO),
+                      np.full(n, ws["T"]), np.tile([np.cos(a), np.sin(a), 0.0], (n, 1)),
+                      np.repeat(ws["offsets"], nC, 0), np.full(n, ws["L"]))
+    return dict(name=f"{ws['name']}_{which}_angle{angle_index}", inst=inst, drive=ws["drive"], samples=ws["samples"],
+                settle=ws["settle"], n_harm=ws["n_harm"], harm_z=False)
+
+
 def small_random(n, L, seed, samples=64, settle=1, n_harm=10, freq_scale=1.0):
     """Small random instances for parity tests (short synthetic drive with 3 and 4 cycles per period)."""
     r = np.random.default_rng(seed)
