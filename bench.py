@@ -10,6 +10,11 @@ harmonic reduction.  Inputs are resident in device memory before timing starts.
 Prints one JSON line with the contract fields plus "roofline" (time stepper,
 algorithmic FP32 flops per launch over its HIP-event-measured launch duration)
 and "cpu_baseline" (the FP64 oracle timed on a bounded sample on the host).
+
+Other workloads (--workload): "uneven" (4096 instances, L = 8..24, one graph launch),
+"surrogate" (network ensemble trained on solver output, BF16 inference) and
+"gradient" (identification loss over 65536 instances and its gradient through the
+autograd Function; one step takes minutes, run it with --steps 1 --warmup 0).
 """
 import argparse
 import json

@@ -78,6 +78,38 @@ def test_tangents_match_oracle_finite_differences(tangent_run):
                 assert err <= bound
 
 
+def test_tangents_at_production_size_match_oracle(fpn, ctx):
+    """Two instances of the identification problem (L = 16, the Lissajous drive, 1632 samples, adaptive
+    steps: the configuration of the gradient workload) against central differences of the oracle
+    (Radau IIA, 4 steps per sample), same bound as above.  Measured: the GPU tangents of D, K and the
+    azimuth within 1.2e-5 of the oracle's differences on m, alpha 3.8e-5; with a 100x tighter step
+    tolerance they move by less than 7e-5, and the oracle's differences with 2 steps per sample are
+    2.6e-4 away from these."""
+    import torch
+    files = sorted(glob.glob(os.path.join(GOLDEN, "tangent_ident_*.npz")))
+    if not files:
+        pytest.skip("no golden files (run tests/golden/make_golden.py tangent_ident)")
+    full = W.identification_instances(W.identification_problem(), 0)
+    ids = [int(np.load(f)["idx"]) for f in files]
+    sub = W.take(full, ids)
+    m, h, dm, dh, st = ctx.solve_tangent(sub["inst"], sub["inst"]["L"], drive_of(fpn, sub), sub["samples"],
+                                         sub["settle"], 64)
+    torch.cuda.synchronize()
+    m, h, dm, dh = m.cpu().numpy(), h.cpu().numpy(), dm.cpu().numpy(), dh.cpu().numpy()
+    assert (st.cpu().numpy() == 0).all()
+    names = ["D", "K", "alpha", "theta", "phi"]
+    for k, f in enumerate(files):
+        g = np.load(f)
+        scale = [sub["inst"]["D"][k], sub["inst"]["K"][k], sub["inst"]["alpha"][k], 1.0, 1.0]
+        for p in range(5):
+            for got, ref, y in ((dh[k, p].T, g["dPhi"][p][:, :2], h[k]), (dm[k, p].T, g["dm"][p], m[k])):
+                err = np.linalg.norm(got - ref)
+                bound = 1e-4 * np.linalg.norm(ref) + 1e-5 * np.linalg.norm(y) / scale[p]
+                print(f"identification inst {ids[k]} d/d{names[p]}: rel {err / np.linalg.norm(ref):.2e}, "
+                      f"error / bound {err / bound:.2f}", flush=True)
+                assert err <= bound
+
+
 def test_primal_outputs_of_the_tangent_solve(fpn, ctx, tangent_run):
     import torch
     ws, m, h, dm, dh, st = tangent_run
