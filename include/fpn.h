@@ -80,7 +80,8 @@ typedef struct {
 enum {
   FPN_OUT_M = 1u,          /* write m_out */
   FPN_OUT_HARM = 2u,       /* write harm_out */
-  FPN_HARM_Z = 4u          /* harm_out has 3 channels (x, y, z) instead of 2 (x, y) */
+  FPN_HARM_Z = 4u,         /* harm_out has 3 channels (x, y, z) instead of 2 (x, y) */
+  FPN_OUT_DMDT = 8u        /* write dmdt_out (fpn_solve only) */
 };
 
 /* Host memory. */
@@ -123,12 +124,16 @@ typedef struct {
  * at t_j = settle_periods*T + j T / N_s.
  * Outputs (DEVICE, may be NULL when the matching flag is off):
  *   m_out    [n][3][N_s]          float, dimensionless <m> (lab frame)
+ *   dmdt_out [n][3][N_s]          float, d<m>/dt [1/s] at the same samples (lab frame): the rows
+ *                                 l = 1 of the ODE's right-hand side A(t_j) c(t_j) (the derivative of
+ *                                 the mean moment of the averaged equation of motion, model section)
  *   harm_out [n][ch][K_h+1][2]    float, (re, im) of Phi_k [1/s], ch = 2 or 3
  *   status   [n]                  int32, FPN_INST_* (required)
+ * Instances with a non-zero status get NaN in every output.
  * Errors: FPN_E_ARG, FPN_E_RANGE (L), FPN_E_DEVICE, FPN_E_NOMEM. */
 fpn_status fpn_solve(fpn_ctx ctx, const fpn_drive* drive, const fpn_solve_opts* opts,
                      const fpn_batch* batch, int64_t n,
-                     float* m_out, float* harm_out, int32_t* status, void* stream);
+                     float* m_out, float* dmdt_out, float* harm_out, int32_t* status, void* stream);
 
 /* ---- parameter sensitivities (gradients) ----
  * Derivatives of the outputs with respect to the five instance parameters, in this order:

@@ -28,7 +28,7 @@ _lib = ctypes.CDLL(LIB_PATH)
 
 FPN_OK, FPN_E_ARG, FPN_E_RANGE, FPN_E_DEVICE, FPN_E_NOMEM, FPN_E_UNSUPPORTED = 0, -1, -2, -3, -4, -7
 FPN_INST_OK, FPN_INST_BAD_PARAM, FPN_INST_NONFINITE, FPN_INST_SINGULAR = 0, 1, 2, 3
-FPN_OUT_M, FPN_OUT_HARM, FPN_HARM_Z = 1, 2, 4
+FPN_OUT_M, FPN_OUT_HARM, FPN_HARM_Z, FPN_OUT_DMDT = 1, 2, 4, 8
 FPN_MAX_L = 24
 FPN_NPARAM = 5  # sensitivities: D, K, alpha, easy-axis polar angle, azimuth
 
@@ -69,7 +69,7 @@ _lib.fpn_destroy.restype = ctypes.c_int32
 _lib.fpn_destroy.argtypes = [_vp]
 _lib.fpn_solve.restype = ctypes.c_int32
 _lib.fpn_solve.argtypes = [_vp, ctypes.POINTER(fpn_drive), ctypes.POINTER(fpn_solve_opts),
-                           ctypes.POINTER(fpn_batch), ctypes.c_int64, _vp, _vp, _vp, _vp]
+                           ctypes.POINTER(fpn_batch), ctypes.c_int64, _vp, _vp, _vp, _vp, _vp]
 _lib.fpn_stationary.restype = ctypes.c_int32
 _lib.fpn_stationary.argtypes = [_vp, ctypes.POINTER(fpn_batch), ctypes.c_int64, _vp, _vp, _vp, _vp]
 _lib.fpn_last_steps.restype = ctypes.c_int32
@@ -253,9 +253,10 @@ class Context:
         return b, t, Lh
 
     def solve(self, inst, L, drive, samples, settle, n_harm, substeps=0, want_m=True, want_harm=True,
-              harm_z=False, stream=None, out=None, tol=0.0):
+              harm_z=False, stream=None, out=None, tol=0.0, want_dmdt=False):
         """Run fpn_solve.  Returns (m [n,3,Ns] float32, harm [n,ch,Kh+1] complex64, status [n] int32)
-        as torch tensors on the device (None for outputs not requested)."""
+        as torch tensors on the device (None for outputs not requested), and dm/dt [n,3,Ns] float32
+        as a fourth element when want_dmdt is set."""
         torch = _torch()
         dev = f"cuda:{self.device}"
         b, keep, Lh = self._batch(inst, L)
@@ -272,17 +273,20 @@ class Context:
         st = out.get("status")
         if st is None:
             st = torch.empty((n,), dtype=torch.int32, device=dev)
+        dd = out.get("dmdt") if want_dmdt else None
+        if want_dmdt and dd is None:
+            dd = torch.empty((n, 3, samples), dtype=torch.float32, device=dev)
         opts = fpn_solve_opts(samples, settle, n_harm, substeps,
                               (FPN_OUT_M if want_m else 0) | (FPN_OUT_HARM if want_harm else 0) |
-                              (FPN_HARM_Z if harm_z else 0), float(tol))
+                              (FPN_HARM_Z if harm_z else 0) | (FPN_OUT_DMDT if want_dmdt else 0), float(tol))
         s = stream if stream is not None else torch.cuda.current_stream(self.device)
         code = _lib.fpn_solve(self._h, ctypes.byref(drive), ctypes.byref(opts), ctypes.byref(b), n,
-                              m.data_ptr() if m is not None else None,
+                              m.data_ptr() if m is not None else None, dd.data_ptr() if dd is not None else None,
                               hm.data_ptr() if hm is not None else None, st.data_ptr(), s.cuda_stream)
         _check(code, "fpn_solve")
         self._keep = (keep, Lh)  # inputs alive until the next call on this context
         harm = torch.view_as_complex(hm) if hm is not None else None
-        return m, harm, st
+        return (m, harm, st, dd) if want_dmdt else (m, harm, st)
 
     def set_stepper_waves(self, L, waves):
         """fpn_set_stepper_waves: workgroup size of degree L for this context (0: the default)."""

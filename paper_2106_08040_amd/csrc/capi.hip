@@ -381,7 +381,7 @@ fpn_status validate_opts(const fpn_drive* drive, const fpn_solve_opts* opts) {
   if (Kh < 0 || 2 * Kh >= Ns) return fail(FPN_E_ARG, "n_harm must satisfy 0 <= n_harm < samples_per_period/2");
   if (int64_t(Ns) * std::max(r, 1) * (opts->settle_periods + 1) > (int64_t(1) << 30))
     return fail(FPN_E_ARG, "too many time steps");
-  if (opts->flags & ~uint32_t(FPN_OUT_M | FPN_OUT_HARM | FPN_HARM_Z)) return fail(FPN_E_ARG, "unknown flag");
+  if (opts->flags & ~uint32_t(FPN_OUT_M | FPN_OUT_HARM | FPN_HARM_Z | FPN_OUT_DMDT)) return fail(FPN_E_ARG, "unknown flag");
   return FPN_OK;
 }
 
@@ -413,6 +413,7 @@ fpn_status plan_build(fpn_plan_s* p, fpn_ctx ctx, const fpn_drive* drive, const 
   const bool want_m = opts->flags & FPN_OUT_M, want_h = opts->flags & FPN_OUT_HARM;
   const int Ns = opts->samples_per_period;
   p->ctx = ctx;
+  p->dmdt = nullptr;
   p->drive = *drive;
   p->opts = *opts;
   p->batch = *batch;
@@ -581,6 +582,7 @@ fpn_status plan_launch(fpn_plan_s* p, hipStream_t stream, bool timing) {
     sl.r_max = 64;
     sl.tol = float(opts->tol > 0.0 ? opts->tol : 5e-6);
     sl.msamp = p->msamp;
+    sl.dmdt = p->dmdt;
     sl.status = p->status;
     sl.steps_out = p->steps.p;
     sl.queue = p->queue.p + gi;
@@ -636,12 +638,14 @@ fpn_status check_outputs(const fpn_solve_opts* opts, float* m_out, float* harm_o
 extern "C" {
 
 fpn_status fpn_solve(fpn_ctx ctx, const fpn_drive* drive, const fpn_solve_opts* opts, const fpn_batch* batch,
-                     int64_t n, float* m_out, float* harm_out, int32_t* status, void* stream_) {
+                     int64_t n, float* m_out, float* dmdt_out, float* harm_out, int32_t* status, void* stream_) {
   if (!ctx) return fail(FPN_E_ARG, "ctx is NULL");
   if (n < 0) return fail(FPN_E_ARG, "n < 0");
   if (fpn_status s = validate_opts(drive, opts)) return s;
   if (n == 0) return FPN_OK;  // nothing to do (empty outputs may be NULL)
   if (fpn_status s = check_outputs(opts, m_out, harm_out, status, n)) return s;
+  const bool want_dmdt = opts->flags & FPN_OUT_DMDT;
+  if (want_dmdt && !dmdt_out) return fail(FPN_E_ARG, "FPN_OUT_DMDT set but dmdt_out is NULL");
   if (fpn_status s = validate_batch(batch, n)) return s;
   std::lock_guard<std::mutex> lk(ctx->mu);
   hipStream_t stream = reinterpret_cast<hipStream_t>(stream_);
@@ -650,6 +654,7 @@ fpn_status fpn_solve(fpn_ctx ctx, const fpn_drive* drive, const fpn_solve_opts* 
   fpn_plan_s* p = ctx->solve_plan;
   ctx->last_plan = nullptr;
   if (fpn_status s = plan_build(p, ctx, drive, opts, batch, n, nullptr, m_out, harm_out, status, stream)) return s;
+  p->dmdt = want_dmdt ? dmdt_out : nullptr;
   if (fpn_status s = plan_launch(p, stream, ctx->timing)) return s;
   ctx->last_plan = p;
   return FPN_OK;
@@ -680,6 +685,7 @@ fpn_status fpn_solve_tangent(fpn_ctx ctx, const fpn_drive* drive, const fpn_solv
   if (fpn_status s = validate_opts(drive, opts)) return s;
   if (n == 0) return FPN_OK;
   if (fpn_status s = check_outputs(opts, m_out, harm_out, status, n)) return s;
+  if (opts->flags & FPN_OUT_DMDT) return fail(FPN_E_ARG, "FPN_OUT_DMDT is written by fpn_solve only");
   if ((opts->flags & FPN_OUT_M) && !dm_out) return fail(FPN_E_ARG, "FPN_OUT_M set but dm_out is NULL");
   if ((opts->flags & FPN_OUT_HARM) && !dharm_out) return fail(FPN_E_ARG, "FPN_OUT_HARM set but dharm_out is NULL");
   if (fpn_status s = validate_batch(batch, n)) return s;
@@ -731,6 +737,7 @@ fpn_status fpn_plan_create(fpn_ctx ctx, const fpn_drive* drive, const fpn_solve_
   *out = nullptr;
   if (n < 1) return fail(FPN_E_ARG, "a plan needs n >= 1");
   if (fpn_status s = validate_opts(drive, opts)) return s;
+  if (opts->flags & FPN_OUT_DMDT) return fail(FPN_E_ARG, "FPN_OUT_DMDT is written by fpn_solve only");
   if (fpn_status s = check_outputs(opts, m_out, harm_out, status, n)) return s;
   if (fpn_status s = validate_batch(batch, n)) return s;
   std::lock_guard<std::mutex> lk(ctx->mu);

@@ -114,6 +114,7 @@ struct fpn_plan_s {
   float* harm_out = nullptr;
   int32_t* status = nullptr;
   float* msamp = nullptr;     // m_out or the plan's own sample buffer
+  float* dmdt = nullptr;      // dmdt_out of fpn_solve (null for plans and tangent solves)
   int64_t np_max = 0;
   std::vector<fpn_internal::PlanGroup> groups;
   std::vector<int32_t> order;  // host copy of the instance order

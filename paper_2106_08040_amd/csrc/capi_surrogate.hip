@@ -91,7 +91,7 @@ fpn_status fpn_surrogate_predict(fpn_ctx ctx, const fpn_surrogate* sur, double t
   sub.L = Lsub.data();
   fpn_solve_opts o = *opts;
   o.flags = FPN_OUT_HARM;
-  if (fpn_status e = fpn_solve(ctx, drive, &o, &sub, cnt, nullptr, ctx->sur_h.p, ctx->sur_st.p, stream)) return e;
+  if (fpn_status e = fpn_solve(ctx, drive, &o, &sub, cnt, nullptr, nullptr, ctx->sur_h.p, ctx->sur_st.p, stream)) return e;
   FPN_HIP(fpn::sur::scatter(cnt, per, ctx->sur_list.p, ctx->sur_h.p, ctx->sur_st.p, harm_out, status, err_out, s));
   // the call is synchronous as a whole (the fallback count had to be read)
   FPN_HIP(hipStreamSynchronize(s));

@@ -21,6 +21,7 @@ struct StepLaunch {
   int r_max;                 // adaptive: smallest step = sample spacing / r_max
   float tol;
   float* msamp;              // [n][3][Ns]
+  float* dmdt = nullptr;      // [n][3][Ns] dm/dt at the samples, may be null
   int32_t* status;
   int32_t* steps_out;        // [n] steps taken, may be null
   int32_t* queue;            // work counter, zero when the launch starts

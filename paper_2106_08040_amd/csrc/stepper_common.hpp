@@ -112,6 +112,7 @@ struct StepArgs {
   int r_max;     // adaptive: smallest step = sample spacing / r_max
   float tol;     // adaptive: bound on max |K6| (embedded RODAS4 error) per step
   float* msamp;  // [n_total][3][Ns]
+  float* dmdt;   // [n_total][3][Ns] dm/dt at the samples (right-hand side of the ODE), may be null
   int32_t* status;
   int32_t* steps_out;  // [n_total] time steps taken (may be null)
   int32_t* queue;      // work counter of this launch, zero at launch

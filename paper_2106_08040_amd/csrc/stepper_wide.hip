@@ -138,8 +138,11 @@ stepper_wide_kernel(StepArgs A, DevTables t, float* ws) {
   const float* wC = t.win_c;
   const float* wS = t.win_s;
   float* ms_out = A.msamp + int64_t(inst) * 3 * A.Ns;
+  float* dd_out = A.dmdt ? A.dmdt + int64_t(inst) * 3 * A.Ns : nullptr;
   if (A.status[inst] != 0) {
     for (int j = lane; j < 3 * A.Ns; j += 64) ms_out[j] = __builtin_nanf("");
+    if (dd_out)
+      for (int j = lane; j < 3 * A.Ns; j += 64) dd_out[j] = __builtin_nanf("");
     if (A.steps_out && lane == 0) A.steps_out[inst] = 0;
     continue;
   }
@@ -634,6 +637,32 @@ stepper_wide_kernel(StepArgs A, DevTables t, float* ws) {
         ms_out[lane * A.Ns + js] = rc * (r0 * vx + r1 * vy + r2 * vz);
       }
       ok = ok && isfinite(vx) && isfinite(vy) && isfinite(vz);
+      if (dd_out) {
+        // dm/dt at the sample: rows l = 1 of A(t_j) y (the ODE's right-hand side), rotated like m
+        const float mt = mult_lane(tj);
+        if (lane < 9) w.ms[lane] = mt;
+        float* xs = w.xin();
+#pragma unroll
+        for (int s = 0; s < S; ++s) {
+          const int p = lane + 64 * s;
+          if (p < Np) xs[p] = y[s];
+        }
+        wsync();
+        float acc = 0.0f;
+        if (lane < 3) {
+          const int row = lane == 0 ? pX : (lane == 1 ? pY : pZ);  // rows < 64
+          for (int g = 0; g < kNSlRow; ++g)
+            acc = fmaf(w.ms[kSlotKindRow[g]] * eval[g * Np + row], xs[ecol[g * Np + row]], acc);
+        }
+        const float ax = __shfl(acc, 0), ay = __shfl(acc, 1), az = __shfl(acc, 2);
+        if (lane < 3) {
+          const float r0 = lane == 0 ? R[0] : (lane == 1 ? R[3] : R[6]);
+          const float r1 = lane == 0 ? R[1] : (lane == 1 ? R[4] : R[7]);
+          const float r2 = lane == 0 ? R[2] : (lane == 1 ? R[5] : R[8]);
+          dd_out[lane * A.Ns + js] = rc * (r0 * ax + r1 * ay + r2 * az);
+        }
+        wsync();
+      }
     }
     // fixed: r_fixed equal steps per sample interval.  adaptive: steps of any size up to the sample
     // spacing, each accepted (max |K6| <= tol) or redone on its own.  The last step of an interval
@@ -697,6 +726,8 @@ stepper_wide_kernel(StepArgs A, DevTables t, float* ws) {
   }
   if (!ok) {
     for (int j = lane; j < 3 * A.Ns; j += 64) ms_out[j] = __builtin_nanf("");
+    if (dd_out)
+      for (int j = lane; j < 3 * A.Ns; j += 64) dd_out[j] = __builtin_nanf("");
     if (lane == 0) A.status[inst] = 2;
   }
   if (A.steps_out && lane == 0) A.steps_out[inst] = steps;
@@ -733,6 +764,7 @@ hipError_t launch_stepper_wide_L(const StepLaunch& s, const DevTables& t, float*
   a.r_max = s.r_max;
   a.tol = s.tol;
   a.msamp = s.msamp;
+  a.dmdt = s.dmdt;
   a.status = s.status;
   a.steps_out = s.steps_out;
   a.queue = s.queue;

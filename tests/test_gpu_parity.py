@@ -69,6 +69,48 @@ def test_small_random_instances_match_oracle(fpn, ctx, L):
         assert rel(h[i].T, ref["Phi"][:, :ch]) < TOL
 
 
+@pytest.mark.parametrize("L", [10, 20])
+def test_dmdt_matches_oracle(fpn, ctx, L):
+    """dm/dt at the samples (rows l = 1 of the right-hand side A(t_j) c(t_j), rotated to the lab
+    frame) against the oracle's, register (L = 10) and wide (L = 20) layouts; requesting it leaves
+    m and Phi bitwise unchanged.  Bound: a state error of 1e-5 relative (the solver's bar) moves
+    dm/dt by at most 1e-5 ||A_(l=1)(t_j)||_2 ||c_j|| per sample (the operator rows are stiff, so
+    this is looser than 1e-5 of |dm/dt|); the test takes that, summed over the samples, from the
+    oracle's own states and operator."""
+    import torch
+    ws = W.small_random(3, L, seed=140 + L, samples=48, settle=1, n_harm=8)
+    d = ws["drive"]
+    drive = fpn.make_drive(d["amp"], d["freq"], d["period"], d["phase"])
+    args = (ws["inst"], ws["inst"]["L"], drive, ws["samples"], ws["settle"], ws["n_harm"])
+    m, h, st, dd = ctx.solve(*args, substeps=32, harm_z=True, want_dmdt=True)
+    m0, h0, st0 = ctx.solve(*args, substeps=32, harm_z=True)
+    torch.cuda.synchronize()
+    m, h, dd, m0, h0 = (x.cpu().numpy() for x in (m, h, dd, m0, h0))
+    assert (st.cpu().numpy() == 0).all()
+    assert np.array_equal(m, m0) and np.array_equal(h, h0)
+    rows = [O.sh_index(1, 1), O.sh_index(1, -1), O.sh_index(1, 0)]
+    T, Ns = d["period"], ws["samples"]
+    for i in range(3):
+        inst = {k: v[i] for k, v in ws["inst"].items()}
+        p = dict(D=inst["D"], Ms=inst["Ms"], K=inst["K"], alpha=inst["alpha"], T=inst["T"])
+        A0, Aa, _ = O.operator_parts(p, inst["easy_axis"], L)
+
+        def Afun(t):
+            B = O.drive_field(d, np.asarray(inst["offset"], float), t)
+            return A0 + B[0] * Aa[0] + B[1] * Aa[1] + B[2] * Aa[2]
+
+        cs = O.integrate_samples(Afun, O.stationary(Afun(0.0)), T, Ns, ws["settle"], 8)
+        ts = ws["settle"] * T + np.arange(Ns) * T / Ns
+        ref = np.array([O.moment(Afun(t) @ c) for t, c in zip(ts, cs)])
+        scale = np.sqrt(4 * np.pi / 3) * np.array([np.linalg.norm(Afun(t)[rows], 2) * np.linalg.norm(c)
+                                                   for t, c in zip(ts, cs)])
+        err = np.linalg.norm(dd[i].T - ref)
+        bound = 1e-5 * np.linalg.norm(scale)
+        print(f"L={L} inst={i}: dm/dt rel {err / np.linalg.norm(ref):.2e}, error / bound {err / bound:.2f}, "
+              f"bound / |dm/dt| {bound / np.linalg.norm(ref):.1e}", flush=True)
+        assert err <= bound
+
+
 @pytest.mark.parametrize("L", [10, 16])
 def test_stationary_matches_oracle(fpn, ctx, L):
     r = np.random.default_rng(7 + L)
@@ -182,6 +224,21 @@ def test_argument_errors(fpn, ctx):
     with pytest.raises(fpn.FpnError) as e:
         ctx.solve(ws["inst"], ws["inst"]["L"], good, 16, 0, 8)  # n_harm must be < N_s / 2
     assert e.value.code == fpn.FPN_E_ARG
+    # dm/dt: requested without a buffer, or from a plan (an output of fpn_solve only)
+    import ctypes
+
+    import torch
+    b, keep, Lh = ctx._batch(ws["inst"], ws["inst"]["L"])
+    opts = fpn.fpn_solve_opts(16, 0, 4, 0, fpn.FPN_OUT_M | fpn.FPN_OUT_DMDT, 0.0)
+    mm = torch.empty((2, 3, 16), dtype=torch.float32, device="cuda:0")
+    st = torch.empty((2,), dtype=torch.int32, device="cuda:0")
+    code = fpn._lib.fpn_solve(ctx._h, ctypes.byref(good), ctypes.byref(opts), ctypes.byref(b), 2, mm.data_ptr(),
+                              None, None, st.data_ptr(), torch.cuda.current_stream().cuda_stream)
+    assert code == fpn.FPN_E_ARG
+    hdl = ctypes.c_void_p()
+    code = fpn._lib.fpn_plan_create(ctx._h, ctypes.byref(good), ctypes.byref(opts), ctypes.byref(b), 2, None,
+                                    mm.data_ptr(), None, st.data_ptr(), ctypes.byref(hdl))
+    assert code == fpn.FPN_E_ARG and not hdl.value
 
 
 def test_empty_batch(fpn, ctx):
