@@ -300,6 +300,23 @@ def langevin(x):
     return np.where(small, x / 3 - x ** 3 / 45, 1 / np.tanh(xs) - 1 / xs)
 
 
+def equilibrium_instance(p, drive, n_samples, settle, n_harm, offset=(0, 0, 0)):
+    """Equilibrium model (model M0 of the data-driven models section, Eq. Langevin): the moment follows
+    the field without delay and without anisotropy, m(t) = L(beta |H(t)|) H(t) / |H(t)| with
+    L(x) = coth(x) - 1/x, dimensionless like the FP moment; sampled at the same times as
+    solve_instance (the settling periods change nothing: the model has no memory) and reduced to the
+    same harmonics.  Returns dict with m [N_s, 3] and Phi [n_harm+1, 3]."""
+    sc = particle_scalars(p["D"], p["Ms"], p["K"], p["alpha"], p["T"])
+    T = drive["period"]
+    ts = settle * T + np.arange(n_samples) * T / n_samples
+    B = drive_field(drive, offset, ts)                     # [N_s, 3], mu0 H in T
+    bn = np.linalg.norm(B, axis=1)
+    x = sc["beta_T"] * bn
+    safe = np.where(bn > 0, bn, 1.0)
+    m = np.where(bn[:, None] > 0, (langevin(x) / safe)[:, None] * B, 0.0)
+    return dict(m=m, Phi=harmonics_from_samples(m, T, n_harm))
+
+
 def boltzmann_mean(bH, sigma, n, nq=80):
     """<m> under f ~ exp(bH . m + sigma (n.m)^2) by product quadrature (bH = beta * H vector)."""
     th, ph, W = quadrature(nq, 2 * nq)

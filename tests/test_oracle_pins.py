@@ -316,3 +316,33 @@ def test_isotropic_particle_has_no_axis_angle_derivative():
     for dth, dph in ((1e-6, 0.0), (0.0, 1e-6)):
         d = (phi(th + dth, ph + dph) - phi(th - dth, ph - dph)) / 2e-6
         assert np.linalg.norm(d) < 1e-6 * base
+
+
+def test_equilibrium_model_is_the_isotropic_stationary_moment_of_each_instant():
+    """Model M0 (Eq. Langevin): at every sample the equilibrium moment equals the stationary moment of
+    the Fokker-Planck operator with K = 0 for the instantaneous field (an independent construction:
+    Galerkin null vector at L = 24)."""
+    p = dict(P_CFG1, D=14e-9, K=0.0)
+    d = dict(amp=(12e-3, 12e-3, 0.0), freq=(2.5e6 / 102, 2.5e6 / 96, 0.0), phase=(0.0, 0.0, 0.0),
+             period=652.8e-6)
+    off = np.array([3e-3, -5e-3, 1e-3])
+    eq = O.equilibrium_instance(p, d, 32, 1, 4, offset=off)
+    A0, Aa, _ = O.operator_parts(p, np.array([0.0, 0.0, 1.0]), 24)
+    for j in (0, 5, 11, 26):
+        t = d["period"] * (1 + j / 32)
+        B = O.drive_field(d, off, t)
+        m = O.moment(O.stationary(A0 + sum(B[a] * Aa[a] for a in range(3))))
+        assert np.abs(eq["m"][j] - m).max() < 1e-9
+
+
+def test_equilibrium_model_symmetry_and_zero_field():
+    """1D drive along x without offset: m stays on x and m(t + T/2) = -m(t), so the even harmonics
+    vanish; at a zero field the moment is zero."""
+    d = dict(amp=(12e-3, 0.0, 0.0), freq=(25e3, 0.0, 0.0), phase=(0.0, 0.0, 0.0), period=40e-6)
+    eq = O.equilibrium_instance(P_CFG1, d, 64, 0, 10)
+    assert np.abs(eq["m"][:, 1:]).max() == 0.0
+    assert np.allclose(eq["m"][32:], -eq["m"][:32], rtol=0, atol=1e-13)
+    scale = np.abs(eq["Phi"][1, 0])
+    assert np.abs(eq["Phi"][0::2]).max() < 1e-12 * scale and np.abs(eq["Phi"][3, 0]) > 1e-3 * scale
+    z = O.equilibrium_instance(P_CFG1, dict(d, amp=(0.0, 0.0, 0.0)), 8, 0, 2)
+    assert np.array_equal(z["m"], np.zeros((8, 3)))
