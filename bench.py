@@ -341,6 +341,71 @@ def bench_gradient(args):
     ctx.close()
 
 
+def bench_equilibrium(args):
+    """Equilibrium-model (model M0, Eq. Langevin) system matrix of the Lissajous workload: 2312 instances,
+    1632 samples, harmonics 0..200 of x and y; one step = one fpn_equilibrium call (closed-form moments
+    and the harmonic reduction).  Roofline of the dominant kernel, the FP64 harmonic sums: 4 flops per
+    sample, bin and channel."""
+    import torch
+    import paper_2106_08040_amd as fpn
+    import oracle as O
+    import workloads as W
+
+    ws = W.lissajous_grid()
+    n, Ns, Kh = ws["inst"]["D"].size, ws["samples"], ws["n_harm"]
+    dev = "cuda:0"
+    torch.cuda.set_device(0)
+    ctx = fpn.Context(0)
+    inst = {k: torch.as_tensor(v, dtype=torch.float64, device=dev) for k, v in ws["inst"].items() if k != "L"}
+    d = ws["drive"]
+    drive = fpn.make_drive(d["amp"], d["freq"], d["period"], d["phase"])
+    for _ in range(args.warmup):
+        m, h, st = ctx.equilibrium(inst, drive, Ns, ws["settle"], Kh)
+    torch.cuda.synchronize()
+    ctx.timing_enable(True)
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        m, h, st = ctx.equilibrium(inst, drive, Ns, ws["settle"], Kh)
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    harm_ms, launches = ctx.timing_read()["harmonics"]
+    ctx.timing_enable(False)
+    bad = int((st != 0).sum().item())
+    avg_ms = harm_ms / max(launches, 1)
+    flops = 4.0 * n * 2 * (Kh + 1) * Ns
+    achieved = flops / (avg_ms * 1e-3) / 1e12
+    res = {
+        "metric": "FP solves/sec & surrogate evals/sec at \u22641e-3 rel-L2 vs FP64 oracle",
+        "value": n * args.steps / wall, "unit": "system-matrix columns/s (equilibrium model)", "n_gpus": 1,
+        "steps": args.steps, "warmup": args.warmup, "ms_per_step": wall / args.steps * 1e3,
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f64", "data": "synthetic",
+        "config": {"workload": ws["name"] + "_equilibrium_M0", "instances": n, "samples": Ns,
+                   "n_harm": Kh, "failed_instances": bad},
+        "roofline": {"bound": "alu", "kernel": "harmonics_kernel (FP64 sums)", "achieved": achieved, "peak": 78.6,
+                     "unit": "TFLOP/s", "frac": achieved / 78.6, "traffic": None, "avg_launch_ms": avg_ms,
+                     "flops_per_launch": flops},
+    }
+    if not args.no_cpu_baseline:
+        t0 = time.perf_counter()
+        k = 0
+        while time.perf_counter() - t0 < args.cpu_budget and k < n:
+            i = k
+            p = dict(D=ws["inst"]["D"][i], Ms=ws["inst"]["Ms"][i], K=ws["inst"]["K"][i],
+                     alpha=ws["inst"]["alpha"][i], T=ws["inst"]["T"][i])
+            O.equilibrium_instance(p, d, Ns, ws["settle"], Kh, offset=ws["inst"]["offset"][i])
+            k += 1
+        try:
+            from threadpoolctl import threadpool_info
+            threads = max([x.get("num_threads", 1) for x in threadpool_info()] or [1])
+        except Exception:
+            threads = os.cpu_count()
+        res["cpu_baseline"] = {"value": k / (time.perf_counter() - t0), "unit": "system-matrix columns/s",
+                               "cores": int(threads), "kind": "oracle",
+                               "sample": f"the first {k} instances of the batch, oracle equilibrium model"}
+    print(json.dumps(res), flush=True)
+    ctx.close()
+
+
 def surrogate_domain(n, seed, n_off=None, n_ang=None):
     """The system-matrix family of the Lissajous workload (D = 20 nm, K = 2 kJ/m^3, alpha = 0.1, L = 16,
     in-plane easy axes, offsets on +-12 mT): random draws, or a regular n_off x n_off x n_ang grid."""
@@ -454,11 +519,13 @@ def main():
                     help="run only a plain 256 MiB device copy three times (reference for the FETCH_SIZE / "
                          "WRITE_SIZE counters) and exit")
     ap.add_argument("--grad-angles", type=int, default=16, help="gradient workload: easy-axis angles")
-    ap.add_argument("--workload", choices=("lissajous", "uneven", "surrogate", "gradient"), default="lissajous",
+    ap.add_argument("--workload", choices=("lissajous", "uneven", "surrogate", "gradient", "equilibrium"),
+                    default="lissajous",
                     help="lissajous: 2312-instance system matrix, L = 16 (headline); "
                          "uneven: 4096 instances with L = 8..24 in one graph launch; "
                          "surrogate: network ensemble trained on solver output, 262144 evaluations; "
-                         "gradient: identification loss and its gradient over 65536 instances")
+                         "gradient: identification loss and its gradient over 65536 instances; "
+                         "equilibrium: the Lissajous system matrix of the equilibrium model (M0)")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py measures one GPU only: there is no multi-GPU path (instances are independent; a "
@@ -483,6 +550,8 @@ def main():
         return bench_surrogate(args)
     if args.workload == "gradient":
         return bench_gradient(args)
+    if args.workload == "equilibrium":
+        return bench_equilibrium(args)
     ws = W.lissajous_grid()
     n = ws["inst"]["D"].size
     dev = "cuda:0"

@@ -135,6 +135,17 @@ fpn_status fpn_solve(fpn_ctx ctx, const fpn_drive* drive, const fpn_solve_opts* 
                      const fpn_batch* batch, int64_t n,
                      float* m_out, float* dmdt_out, float* harm_out, int32_t* status, void* stream);
 
+/* Equilibrium-model columns (paper: model M0 of the data-driven models section, Eq. Langevin):
+ * the moment follows the field at once and ignores the anisotropy and the easy axis,
+ * m(t) = L(beta |B(t)|) B(t) / |B(t)| with L(x) = coth(x) - 1/x, beta = V_C M_S / (k_B T) per tesla,
+ * B = drive + offset.  Sampled at the same times as fpn_solve and reduced to the same harmonics, so the
+ * outputs are directly comparable with the Fokker-Planck ones.  Arguments, layouts and errors as
+ * fpn_solve (K, alpha, easy_axis are checked but do not enter; batch->L must be valid and is unused;
+ * FPN_OUT_DMDT is rejected); FP64 evaluation, FP32 outputs.  Asynchronous. */
+fpn_status fpn_equilibrium(fpn_ctx ctx, const fpn_drive* drive, const fpn_solve_opts* opts,
+                           const fpn_batch* batch, int64_t n,
+                           float* m_out, float* harm_out, int32_t* status, void* stream);
+
 /* ---- parameter sensitivities (gradients) ----
  * Derivatives of the outputs with respect to the five instance parameters, in this order:
  *   0: D [1/m]   1: K [1/(J/m^3)]   2: alpha   3: polar angle of the easy axis   4: its azimuth

@@ -38,7 +38,7 @@ EXPORTED = ["fpn_status_string", "fpn_last_error", "fpn_create", "fpn_destroy", 
             "fpn_mlp_set_input_norm", "fpn_mlp_forward", "fpn_mlp_gradient", "fpn_mlp_train_step",
             "fpn_surrogate_features", "fpn_surrogate_predict", "fpn_plan_create", "fpn_plan_launch",
             "fpn_plan_graph_launch", "fpn_plan_steps", "fpn_plan_destroy", "fpn_solve_tangent", "fpn_adjoint",
-            "fpn_stepper_wave_options", "fpn_set_stepper_waves", "fpn_autotune"]
+            "fpn_stepper_wave_options", "fpn_set_stepper_waves", "fpn_autotune", "fpn_equilibrium"]
 
 
 class fpn_drive(ctypes.Structure):
@@ -70,6 +70,9 @@ _lib.fpn_destroy.argtypes = [_vp]
 _lib.fpn_solve.restype = ctypes.c_int32
 _lib.fpn_solve.argtypes = [_vp, ctypes.POINTER(fpn_drive), ctypes.POINTER(fpn_solve_opts),
                            ctypes.POINTER(fpn_batch), ctypes.c_int64, _vp, _vp, _vp, _vp, _vp]
+_lib.fpn_equilibrium.restype = ctypes.c_int32
+_lib.fpn_equilibrium.argtypes = [_vp, ctypes.POINTER(fpn_drive), ctypes.POINTER(fpn_solve_opts),
+                                 ctypes.POINTER(fpn_batch), ctypes.c_int64, _vp, _vp, _vp, _vp]
 _lib.fpn_stationary.restype = ctypes.c_int32
 _lib.fpn_stationary.argtypes = [_vp, ctypes.POINTER(fpn_batch), ctypes.c_int64, _vp, _vp, _vp, _vp]
 _lib.fpn_last_steps.restype = ctypes.c_int32
@@ -287,6 +290,25 @@ class Context:
         self._keep = (keep, Lh)  # inputs alive until the next call on this context
         harm = torch.view_as_complex(hm) if hm is not None else None
         return (m, harm, st, dd) if want_dmdt else (m, harm, st)
+
+    def equilibrium(self, inst, drive, samples, settle, n_harm, want_m=True, harm_z=False, stream=None):
+        """fpn_equilibrium (model M0): (m [n,3,Ns] float32 or None, harm [n,ch,Kh+1] complex64, status)."""
+        torch = _torch()
+        dev = f"cuda:{self.device}"
+        n = np.asarray(inst["D"]).shape[0] if not hasattr(inst["D"], "numel") else inst["D"].numel()
+        b, keep, Lh = self._batch(inst, np.ones(n, np.int32))
+        ch = 3 if harm_z else 2
+        m = torch.empty((n, 3, samples), dtype=torch.float32, device=dev) if want_m else None
+        hm = torch.empty((n, ch, n_harm + 1, 2), dtype=torch.float32, device=dev)
+        st = torch.empty((n,), dtype=torch.int32, device=dev)
+        opts = fpn_solve_opts(samples, settle, n_harm, 0, (FPN_OUT_M if want_m else 0) | FPN_OUT_HARM |
+                              (FPN_HARM_Z if harm_z else 0), 0.0)
+        s = stream if stream is not None else torch.cuda.current_stream(self.device)
+        _check(_lib.fpn_equilibrium(self._h, ctypes.byref(drive), ctypes.byref(opts), ctypes.byref(b), n,
+                                    m.data_ptr() if m is not None else None, hm.data_ptr(), st.data_ptr(),
+                                    s.cuda_stream), "fpn_equilibrium")
+        self._keep = (keep, Lh)
+        return m, torch.view_as_complex(hm), st
 
     def set_stepper_waves(self, L, waves):
         """fpn_set_stepper_waves: workgroup size of degree L for this context (0: the default)."""

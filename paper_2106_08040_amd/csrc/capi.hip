@@ -317,6 +317,7 @@ fpn_status fpn_destroy(fpn_ctx ctx) {
   ctx->c0.release();
   ctx->wsinv.release();
   ctx->msamp.release();
+  ctx->eq_m.release();
   ctx->idx.release();
   ctx->steps.release();
   ctx->wide_ws.release();
@@ -979,6 +980,53 @@ fpn_status fpn_timing_read(fpn_ctx ctx, double* ms_out, int64_t* launches_out) {
   for (int k = 0; k < 4; ++k) {
     ms_out[k] = ctx->ms[k];
     launches_out[k] = ctx->launches[k];
+  }
+  return FPN_OK;
+}
+
+fpn_status fpn_equilibrium(fpn_ctx ctx, const fpn_drive* drive, const fpn_solve_opts* opts, const fpn_batch* batch,
+                           int64_t n, float* m_out, float* harm_out, int32_t* status, void* stream_) {
+  if (!ctx) return fail(FPN_E_ARG, "ctx is NULL");
+  if (n < 0) return fail(FPN_E_ARG, "n < 0");
+  if (fpn_status s = validate_opts(drive, opts)) return s;
+  if (n == 0) return FPN_OK;
+  if (opts->flags & FPN_OUT_DMDT) return fail(FPN_E_ARG, "FPN_OUT_DMDT is written by fpn_solve only");
+  if (fpn_status s = check_outputs(opts, m_out, harm_out, status, n)) return s;
+  if (fpn_status s = validate_batch(batch, n)) return s;
+  const int Ns = opts->samples_per_period;
+  if (int64_t(n) * Ns > (int64_t(1) << 40)) return fail(FPN_E_ARG, "n * samples_per_period too large");
+  const bool want_m = opts->flags & FPN_OUT_M, want_h = opts->flags & FPN_OUT_HARM;
+  std::lock_guard<std::mutex> lk(ctx->mu);
+  hipStream_t stream = reinterpret_cast<hipStream_t>(stream_);
+  FPN_HIP(hipSetDevice(ctx->device));
+  float* m = m_out;
+  if (!want_m) {
+    FPN_HIP(ctx->eq_m.ensure(size_t(n) * 3 * Ns));
+    m = ctx->eq_m.p;
+  }
+  if (want_h)
+    if (fpn_status s = ensure_twiddle(ctx, Ns, stream)) return s;
+  FPN_HIP(ctx->ip.ensure(n));
+  fpn::launch_instance_prep(n, batch->D, batch->Ms, batch->K, batch->alpha, batch->temp, batch->easy_axis,
+                            batch->offset, ctx->ip.p, status, stream);
+  FPN_HIP(hipGetLastError());
+  fpn::EqDrive d;
+  for (int c = 0; c < 3; ++c) {
+    d.amp[c] = drive->amp[c];
+    d.freq[c] = drive->freq[c];
+    d.phase[c] = drive->phase[c];
+  }
+  d.period = drive->period;
+  fpn::launch_equilibrium(n, Ns, opts->settle_periods, d, ctx->ip.p, status, m, stream);
+  FPN_HIP(hipGetLastError());
+  if (want_h) {
+    const int nch = (opts->flags & FPN_HARM_Z) ? 3 : 2;
+    // timed like the solver's harmonics (fpn_timing_enable / fpn_timing_read, slot 3)
+    return timed(ctx, 3, stream, [&]() -> fpn_status {
+      fpn::launch_harmonics(m, Ns, opts->n_harm, nch, drive->period, ctx->twiddle.p, harm_out, status, n, stream);
+      FPN_HIP(hipGetLastError());
+      return FPN_OK;
+    });
   }
   return FPN_OK;
 }

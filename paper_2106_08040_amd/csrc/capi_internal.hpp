@@ -80,6 +80,7 @@ struct fpn_ctx_s {
   fpn_internal::DevBuf<double> c0;
   fpn_internal::DevBuf<double> wsinv;
   fpn_internal::DevBuf<float> msamp;
+  fpn_internal::DevBuf<float> eq_m;     // equilibrium model: samples when the caller wants none
   fpn_internal::DevBuf<int32_t> idx;
   fpn_internal::DevBuf<int32_t> steps;
   fpn_internal::DevBuf<float> wide_ws;  // wide-layout stepper: block inverses and stage vectors

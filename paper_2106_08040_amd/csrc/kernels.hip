@@ -413,12 +413,56 @@ __global__ void harmonics_kernel(const float* msamp, int Ns, int n_harm, int nch
   }
 }
 
+// Equilibrium model (model M0, Eq. Langevin): the moment follows the field without delay or
+// anisotropy, m(t_j) = L(beta |B(t_j)|) B(t_j) / |B(t_j)|, L(x) = coth(x) - 1/x, at the samples
+// t_j = settle T + j T / N_s of the recorded period.  One thread per (instance, sample), FP64,
+// stored as FP32 in the stepper's sample layout [n][3][N_s].
+__global__ void equilibrium_kernel(int64_t n, int Ns, int settle, EqDrive d, const InstParams* ip,
+                                   const int32_t* status, float* m) {
+  const int64_t e = blockIdx.x * int64_t(blockDim.x) + threadIdx.x;
+  if (e >= n * Ns) return;
+  const int64_t i = e / Ns;
+  const int j = int(e - i * Ns);
+  float* out = m + i * 3 * Ns + j;
+  if (status[i] != 0) {
+    for (int c = 0; c < 3; ++c) out[c * Ns] = __builtin_nanf("");
+    return;
+  }
+  const InstParams p = ip[i];
+  double b[3];
+  for (int c = 0; c < 3; ++c) {
+    // drive phase in cycles, reduced to [0, 1) before the cosine: t is up to a few periods long
+    double cyc = d.freq[c] * (double(settle) * d.period) + d.freq[c] * d.period * double(j) / double(Ns);
+    cyc -= floor(cyc);
+    b[c] = p.off[c] + d.amp[c] * cos(2.0 * kPi * cyc + d.phase[c]);
+  }
+  const double bn = sqrt(b[0] * b[0] + b[1] * b[1] + b[2] * b[2]);
+  const double x = p.beta_T * bn;
+  double Lx;
+  if (x < 1e-2) {
+    const double x2 = x * x;  // Taylor series of coth(x) - 1/x
+    Lx = x * (1.0 / 3.0 - x2 * (1.0 / 45.0 - x2 * (2.0 / 945.0)));
+  } else {
+    Lx = 1.0 / tanh(x) - 1.0 / x;
+  }
+  const double s = bn > 0.0 ? Lx / bn : 0.0;
+  for (int c = 0; c < 3; ++c) out[c * Ns] = float(s * b[c]);
+}
+
 __global__ void fill_i32_kernel(int32_t* p, int n, int32_t v) {
   const int i = blockIdx.x * blockDim.x + threadIdx.x;
   if (i < n) p[i] = v;
 }
 
 // ------------------------------------------------------------- launchers ---
+
+void launch_equilibrium(int64_t n, int Ns, int settle, const EqDrive& d, const InstParams* ip,
+                        const int32_t* status, float* m, hipStream_t stream) {
+  const int64_t total = n * Ns;
+  if (total <= 0) return;
+  hipLaunchKernelGGL(equilibrium_kernel, dim3(unsigned((total + 255) / 256)), dim3(256), 0, stream, n, Ns, settle, d,
+                     ip, status, m);
+}
 
 void launch_fill_i32(int32_t* p, int n, int32_t v, hipStream_t stream) {
   if (n <= 0) return;

@@ -84,6 +84,13 @@ hipError_t launch_stepper(int L, const StepLaunch& s, const DevTables& t, float*
 void launch_stationary_tangent(const DevTables& t, const int32_t* idx, int n_inst, const InstParams* ip,
                                double3 drive0, const double* c0, int64_t c_stride, const double* wsinv, double* ct,
                                int32_t* status, hipStream_t stream);
+// drive of the equilibrium model: mu0 H_a(t) = amp_a cos(2 pi freq_a t + phase_a) + offset_a
+struct EqDrive {
+  double amp[3], freq[3], phase[3], period;
+};
+// m [n][3][Ns] of the equilibrium model (NaN for instances with a non-zero status)
+void launch_equilibrium(int64_t n, int Ns, int settle, const EqDrive& d, const InstParams* ip,
+                        const int32_t* status, float* m, hipStream_t stream);
 void launch_fill_i32(int32_t* p, int n, int32_t v, hipStream_t stream);
 void launch_harmonics(const float* msamp, int Ns, int n_harm, int nch, double period, const double2* tw,
                       float* harm, const int32_t* status, int64_t n, hipStream_t stream, int st_div = 1);
