@@ -9,6 +9,8 @@
 // Eq. MPI_model_fourier / phi-hat of model M1 (harmonics).
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
+
 #include <cstdint>
 #include <type_traits>
 
@@ -378,29 +380,50 @@ stationary_tangent_kernel(DevTables t, const int32_t* inst_idx, int n_inst, cons
 
 // -------------------------------------------------------- a6: harmonics ---
 // Phi_k = (2 pi i k / T) (1/N_s) sum_j m(t_j) e^{-2 pi i j k / N_s}, FP64 accumulation.
-// One workgroup per instance; the twiddle index (j k) mod N_s is carried exactly in int32.
+// One workgroup per instance: its samples (and the twiddle table, when both fit in 64 KiB) are staged
+// in LDS; each thread owns one (channel, bin) and keeps two partial sums (even and odd j) so that
+// consecutive multiply-adds do not wait on each other.  The twiddle index (j k) mod N_s is carried
+// exactly in int32 (k < N_s / 2, so 2k < N_s and one subtraction keeps it reduced).
+template <bool kTwLds>
 __global__ void harmonics_kernel(const float* msamp, int Ns, int n_harm, int nch, double period,
                                  const double2* tw, float* harm, const int32_t* status, int64_t n, int st_div) {
   const int64_t inst = blockIdx.x;
   if (inst >= n) return;
-  extern __shared__ float ml[];  // [3][Ns]
+  extern __shared__ double2 hsm[];  // [N_s] twiddles (kTwLds), then [nch][N_s] samples
+  float* ml = reinterpret_cast<float*>(kTwLds ? hsm + Ns : hsm);
+  const double2* twl = kTwLds ? hsm : tw;
+  if (kTwLds)
+    for (int e = threadIdx.x; e < Ns; e += blockDim.x) hsm[e] = tw[e];
   const float* src = msamp + inst * 3 * Ns;
-  for (int e = threadIdx.x; e < 3 * Ns; e += blockDim.x) ml[e] = src[e];
+  for (int e = threadIdx.x; e < nch * Ns; e += blockDim.x) ml[e] = src[e];
   __syncthreads();
   const bool bad = status[inst / st_div] != 0;  // st_div > 1: several sample sets per instance
   const int nk = n_harm + 1;
   for (int e = threadIdx.x; e < nch * nk; e += blockDim.x) {
     const int c = e / nk, k = e % nk;
-    double re = 0.0, im = 0.0;
-    int r = 0;
     const float* mc = ml + c * Ns;
-    for (int j = 0; j < Ns; ++j) {
-      const double2 t = tw[r];  // (cos, sin)(2 pi r / N_s)
-      re += double(mc[j]) * t.x;
-      im -= double(mc[j]) * t.y;
-      r += k;
-      if (r >= Ns) r -= Ns;
+    const int k2 = 2 * k;
+    double re0 = 0.0, im0 = 0.0, re1 = 0.0, im1 = 0.0;
+    int r0 = 0, r1 = k;  // (j k) mod N_s for the even and the odd sample of a pair
+    int j = 0;
+    for (; j + 1 < Ns; j += 2) {
+      const double2 t0 = twl[r0], t1 = twl[r1];  // (cos, sin)(2 pi r / N_s)
+      const double a0 = double(mc[j]), a1 = double(mc[j + 1]);
+      re0 += a0 * t0.x;
+      im0 -= a0 * t0.y;
+      re1 += a1 * t1.x;
+      im1 -= a1 * t1.y;
+      r0 += k2;
+      if (r0 >= Ns) r0 -= Ns;
+      r1 += k2;
+      if (r1 >= Ns) r1 -= Ns;
     }
+    if (j < Ns) {
+      const double2 t0 = twl[r0];
+      re0 += double(mc[j]) * t0.x;
+      im0 -= double(mc[j]) * t0.y;
+    }
+    const double re = re0 + re1, im = im0 + im1;
     const double sc = 2.0 * kPi * k / period / Ns;
     float* out = harm + ((inst * nch + c) * nk + k) * 2;
     if (bad) {
@@ -496,9 +519,17 @@ void launch_stationary_tangent(const DevTables& t, const int32_t* idx, int n_ins
 
 void launch_harmonics(const float* msamp, int Ns, int n_harm, int nch, double period, const double2* tw,
                       float* harm, const int32_t* status, int64_t n, hipStream_t stream, int st_div) {
-  const size_t shm = size_t(3) * Ns * sizeof(float);
-  hipLaunchKernelGGL(harmonics_kernel, dim3(n), dim3(256), shm, stream, msamp, Ns, n_harm, nch, period, tw, harm,
-                     status, n, st_div);
+  if (n <= 0) return;
+  const int items = nch * (n_harm + 1);
+  const int threads = std::min(512, std::max(64, (items + 63) / 64 * 64));  // one (channel, bin) per thread
+  const size_t samples = size_t(nch) * Ns * sizeof(float);
+  const size_t with_tw = size_t(Ns) * sizeof(double2) + samples;
+  if (with_tw <= 64 * 1024)
+    hipLaunchKernelGGL(harmonics_kernel<true>, dim3(n), dim3(threads), with_tw, stream, msamp, Ns, n_harm, nch,
+                       period, tw, harm, status, n, st_div);
+  else
+    hipLaunchKernelGGL(harmonics_kernel<false>, dim3(n), dim3(threads), samples, stream, msamp, Ns, n_harm, nch,
+                       period, tw, harm, status, n, st_div);
 }
 
 // grad[i][p] = sum over channels, bins and (re, im) of dL/dPhi[i] * dPhi/dp[i][p], FP64 accumulation;
