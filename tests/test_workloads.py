@@ -45,3 +45,14 @@ def test_identification_problem_layout():
         assert (np.ceil(W.anisotropy_ratio(p["D"], p["K"])) + 4 <= ws["L"]).all()
     n1, n2 = ws["noise_rng"]().normal(size=5), W.identification_problem()["noise_rng"]().normal(size=5)
     assert np.array_equal(n1, n2)
+
+
+def test_bench_refuses_several_gpus():
+    """bench.py measures one GPU: --gpus N > 1 exits with status 2 and says why, before touching a device."""
+    import os
+    import subprocess
+    import sys
+    root = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+    r = subprocess.run([sys.executable, os.path.join(root, "bench.py"), "--gpus", "2"], capture_output=True,
+                       text=True, timeout=120)
+    assert r.returncode == 2 and "one GPU" in r.stderr and r.stdout == ""
