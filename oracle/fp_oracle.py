@@ -37,6 +37,9 @@ to the same PDE solution):
   (m is T-periodic) and the remaining integral of m by the rectangle rule.
   The rectangle rule applied to sampled dm/dt (RHS evaluation) is also
   returned as a diagnostic (``Phi_rect``).
+* Equilibrium model (model M0, Eq. Langevin), the paper's baseline: the Langevin
+  moment of the instantaneous field on the same samples and harmonics
+  (``equilibrium_instance``).
 
 Parity pins for every function live in ``tests/test_oracle_pins.py``.
 """
