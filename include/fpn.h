@@ -141,7 +141,8 @@ fpn_status fpn_solve(fpn_ctx ctx, const fpn_drive* drive, const fpn_solve_opts* 
  * B = drive + offset.  Sampled at the same times as fpn_solve and reduced to the same harmonics, so the
  * outputs are directly comparable with the Fokker-Planck ones.  Arguments, layouts and errors as
  * fpn_solve (K, alpha, easy_axis are checked but do not enter; batch->L must be valid and is unused;
- * FPN_OUT_DMDT is rejected); FP64 evaluation, FP32 outputs.  Asynchronous. */
+ * FPN_OUT_DMDT is rejected; n * samples_per_period < 2^31); FP64 evaluation, FP32 outputs.
+ * Asynchronous. */
 fpn_status fpn_equilibrium(fpn_ctx ctx, const fpn_drive* drive, const fpn_solve_opts* opts,
                            const fpn_batch* batch, int64_t n,
                            float* m_out, float* harm_out, int32_t* status, void* stream);

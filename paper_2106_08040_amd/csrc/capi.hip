@@ -994,7 +994,7 @@ fpn_status fpn_equilibrium(fpn_ctx ctx, const fpn_drive* drive, const fpn_solve_
   if (fpn_status s = check_outputs(opts, m_out, harm_out, status, n)) return s;
   if (fpn_status s = validate_batch(batch, n)) return s;
   const int Ns = opts->samples_per_period;
-  if (int64_t(n) * Ns > (int64_t(1) << 40)) return fail(FPN_E_ARG, "n * samples_per_period too large");
+  if (int64_t(n) * Ns >= (int64_t(1) << 31)) return fail(FPN_E_ARG, "n * samples_per_period must be < 2^31");
   const bool want_m = opts->flags & FPN_OUT_M, want_h = opts->flags & FPN_OUT_HARM;
   std::lock_guard<std::mutex> lk(ctx->mu);
   hipStream_t stream = reinterpret_cast<hipStream_t>(stream_);
