@@ -49,7 +49,14 @@ enum {
   FPN_INST_OK = 0,
   FPN_INST_BAD_PARAM = 1,  /* non-finite or non-positive parameter, |n| != 1 */
   FPN_INST_NONFINITE = 2,  /* non-finite state during stepping */
-  FPN_INST_SINGULAR = 3    /* zero pivot in a block inversion */
+  FPN_INST_SINGULAR = 3,   /* zero pivot in a block inversion */
+  FPN_INST_UNRESOLVED = 4, /* the Galerkin degree does not resolve the particle: at some sample time
+                              (settling included) the state is not a probability density, |m| > 1 + 1e-3
+                              or c_00 (total probability, conserved exactly by the solver) changed;
+                              the solve stops there */
+  FPN_INST_TOL_UNMET = 5   /* outputs ARE written (finite), but some step at the smallest step size
+                              (sample spacing / 64) was accepted with its error estimate above `tol`:
+                              their accuracy is not certified */
 };
 
 /* Static description of a status code (never NULL). */
@@ -117,6 +124,9 @@ typedef struct {
 } fpn_batch;
 
 #define FPN_MAX_L 24
+/* channels * samples_per_period * 4 bytes must not exceed this (one instance's samples are staged in
+ * LDS by the harmonics reduction): N_s <= 8192 with 2 channels, <= 5461 with 3; else FPN_E_RANGE */
+#define FPN_MAX_HARM_LDS 65536
 
 /* Periodic response of every instance to drive + offset (the system-matrix columns).
  * Procedure: stationary density of the field at t = 0 (FP64), then
@@ -126,11 +136,15 @@ typedef struct {
  *   m_out    [n][3][N_s]          float, dimensionless <m> (lab frame)
  *   dmdt_out [n][3][N_s]          float, d<m>/dt [1/s] at the same samples (lab frame): the rows
  *                                 l = 1 of the ODE's right-hand side A(t_j) c(t_j) (the derivative of
- *                                 the mean moment of the averaged equation of motion, model section)
+ *                                 the mean moment of the averaged equation of motion, model section).
+ *                                 Accuracy: about 1e-3 relative (rel-L2 over an instance), far below
+ *                                 that of m and harm_out: A's l = 1 rows are stiff (|A| ~ 1/tau) and
+ *                                 multiply the FP32 state error of the fast modes (~1e-6), which the
+ *                                 slow moment m does not see.  harm_out does not use dmdt_out.
  *   harm_out [n][ch][K_h+1][2]    float, (re, im) of Phi_k [1/s], ch = 2 or 3
  *   status   [n]                  int32, FPN_INST_* (required)
- * Instances with a non-zero status get NaN in every output.
- * Errors: FPN_E_ARG, FPN_E_RANGE (L), FPN_E_DEVICE, FPN_E_NOMEM. */
+ * Instances with a non-zero status other than FPN_INST_TOL_UNMET get NaN in every output.
+ * Errors: FPN_E_ARG, FPN_E_RANGE (L, N_s above FPN_MAX_HARM_LDS), FPN_E_DEVICE, FPN_E_NOMEM. */
 fpn_status fpn_solve(fpn_ctx ctx, const fpn_drive* drive, const fpn_solve_opts* opts,
                      const fpn_batch* batch, int64_t n,
                      float* m_out, float* dmdt_out, float* harm_out, int32_t* status, void* stream);

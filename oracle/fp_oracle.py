@@ -183,14 +183,6 @@ def drive_field(drive, offset, t):
     return np.asarray(offset, float) + amp * np.cos(2 * np.pi * fr * t[..., None] + ph)
 
 
-def drive_rate(drive, t):
-    t = np.asarray(t, float)
-    amp = np.asarray(drive["amp"], float)
-    fr = np.asarray(drive["freq"], float)
-    ph = np.asarray(drive.get("phase", (0.0, 0.0, 0.0)), float)
-    return -amp * 2 * np.pi * fr * np.sin(2 * np.pi * fr * t[..., None] + ph)
-
-
 def stationary(A):
     """Null vector of A with c_00 = 1/sqrt(4 pi) (total probability 1): drop row 0, solve."""
     N = A.shape[0]
@@ -276,21 +268,6 @@ def solve_instance(p, n, L, drive, n_samples, settle, n_harm, r=2, offset=(0, 0,
     k = np.arange(n_harm + 1)
     Phi_rect = np.exp(-2j * np.pi * np.outer(k, np.arange(Ns)) / Ns) @ mdot / Ns
     return dict(m=m, Phi=Phi, mdot=mdot, Phi_rect=Phi_rect, c_last=cs[-1], r=r, scalars=sc)
-
-
-def solve_converged(p, n, L, drive, n_samples, settle, n_harm, offset=(0, 0, 0), r0=1, tol=1e-8, r_max=16):
-    """Step doubling: double r until Phi changes by <= tol (relative L2); returns the finer run
-    plus its change against the coarser run as the error estimate."""
-    prev = solve_instance(p, n, L, drive, n_samples, settle, n_harm, r=r0, offset=offset)
-    r = r0
-    while True:
-        r *= 2
-        cur = solve_instance(p, n, L, drive, n_samples, settle, n_harm, r=r, offset=offset)
-        err = np.linalg.norm(cur["Phi"] - prev["Phi"]) / np.linalg.norm(cur["Phi"])
-        cur["err_est"] = err
-        if err <= tol or r >= r_max:
-            return cur
-        prev = cur
 
 
 # --- closed forms used by the pins -------------------------------------------------

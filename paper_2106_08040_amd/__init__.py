@@ -27,7 +27,8 @@ except ImportError:  # host-only helpers still work without torch
 _lib = ctypes.CDLL(LIB_PATH)
 
 FPN_OK, FPN_E_ARG, FPN_E_RANGE, FPN_E_DEVICE, FPN_E_NOMEM, FPN_E_UNSUPPORTED = 0, -1, -2, -3, -4, -7
-FPN_INST_OK, FPN_INST_BAD_PARAM, FPN_INST_NONFINITE, FPN_INST_SINGULAR = 0, 1, 2, 3
+FPN_INST_OK, FPN_INST_BAD_PARAM, FPN_INST_NONFINITE, FPN_INST_SINGULAR, FPN_INST_UNRESOLVED, FPN_INST_TOL_UNMET = \
+    0, 1, 2, 3, 4, 5
 FPN_OUT_M, FPN_OUT_HARM, FPN_HARM_Z, FPN_OUT_DMDT = 1, 2, 4, 8
 FPN_MAX_L = 24
 FPN_NPARAM = 5  # sensitivities: D, K, alpha, easy-axis polar angle, azimuth

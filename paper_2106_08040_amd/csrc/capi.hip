@@ -69,18 +69,19 @@ fpn_status get_tables(fpn_ctx ctx, int L, const fpn::DevTables** out) {
   const int Np = h->Np;
   std::vector<uint16_t> ecol(size_t(fpn::kNSlRow) * Np, 0), crow(size_t(fpn::kNSlCol) * Np, 0);
   std::vector<float> eval(size_t(fpn::kNSlRow) * Np, 0.0f), cvl(size_t(fpn::kNSlCol) * Np, 0.0f);
+  std::vector<float> elo(size_t(fpn::kNSlD) * Np, 0.0f);  // value - float(value) of the diagonal-block slots
   std::vector<int> blk_of(Np);
   for (int k = 0; k <= L; ++k)
     for (int p = h->boff[k]; p < h->boff[k] + h->bn[k]; ++p) blk_of[p] = k;
   auto place = [&](std::vector<uint16_t>& ix, std::vector<float>& vv, const int* kinds, int first, int count,
-                   int line, int kind, int other, float v) -> bool {
+                   int line, int kind, int other, float v) -> int {
     for (int s = first; s < first + count; ++s) {
       if (kinds[s] != kind || vv[size_t(s) * Np + line] != 0.0f) continue;
       ix[size_t(s) * Np + line] = uint16_t(other);
       vv[size_t(s) * Np + line] = v;
-      return true;
+      return s;
     }
-    return false;
+    return -1;
   };
   // padding slots (value 0) point inside the block they would address, so every index is in range
   for (int p = 0; p < Np; ++p) {
@@ -96,13 +97,14 @@ fpn_status get_tables(fpn_ctx ctx, int L, const fpn::DevTables** out) {
   for (int p = 0; p < Np; ++p) {
     for (int e = h->seg[4 * p]; e < h->seg[4 * p + 3]; ++e) {
       const int col = int(h->colkind[e] & 0xffffu), kind = int(h->colkind[e] >> 16);
-      const float v = h->val[e];
+      const float v = float(h->val64[e]);
       const int rel = blk_of[col] - blk_of[p];
       const int first = rel == 0 ? fpn::kSlD : (rel < 0 ? fpn::kSlB : fpn::kSlC);
       const int count = rel == 0 ? fpn::kNSlD : (rel < 0 ? fpn::kNSlB : fpn::kNSlC);
-      if (!place(ecol, eval, fpn::kSlotKindRow, first, count, p, kind, col, v))
-        return fail(FPN_E_RANGE, "operator row does not fit the fixed-slot layout");
-      if (rel > 0 && !place(crow, cvl, fpn::kSlotKindCol, 0, fpn::kNSlCol, col, kind, p, v))
+      const int slot = place(ecol, eval, fpn::kSlotKindRow, first, count, p, kind, col, v);
+      if (slot < 0) return fail(FPN_E_RANGE, "operator row does not fit the fixed-slot layout");
+      if (rel == 0) elo[size_t(slot - fpn::kSlD) * Np + p] = float(h->val64[e] - double(v));
+      if (rel > 0 && place(crow, cvl, fpn::kSlotKindCol, 0, fpn::kNSlCol, col, kind, p, v) < 0)
         return fail(FPN_E_RANGE, "operator column does not fit the fixed-slot layout");
     }
   }
@@ -154,6 +156,7 @@ fpn_status get_tables(fpn_ctx ctx, int L, const fpn::DevTables** out) {
   if (e == hipSuccess) e = up(&t.cval64, h->cval64);
   if (e == hipSuccess) e = up(&t.ell_col, ecol);
   if (e == hipSuccess) e = up(&t.ell_val, eval);
+  if (e == hipSuccess) e = up(&t.ell_lo, elo);
   if (e == hipSuccess) e = up(&t.ecol_row, crow);
   if (e == hipSuccess) e = up(&t.ecol_val, cvl);
   if (e == hipSuccess) e = up(&t.win_b, wb);
@@ -201,17 +204,27 @@ fpn_status validate_drive(const fpn_drive* d) {
   return FPN_OK;
 }
 
-fpn_status ensure_twiddle(fpn_ctx ctx, int Ns, hipStream_t stream) {
-  if (ctx->tw_N == Ns) return FPN_OK;
-  std::vector<double2> tw(Ns);
-  for (int j = 0; j < Ns; ++j) {
-    const double a = 2.0 * fpn::kPi * double(j) / double(Ns);
-    tw[j] = make_double2(std::cos(a), std::sin(a));
+// Twiddle table e^{2 pi i j / N_s}, j < N_s (FP64, built on the host) for `Ns`: made on first use and
+// never rewritten or freed while the context lives.
+fpn_status ensure_twiddle(fpn_ctx ctx, int Ns, hipStream_t stream, const double2** out) {
+  auto it = ctx->twiddles.find(Ns);
+  if (it == ctx->twiddles.end()) {
+    std::vector<double2> tw(Ns);
+    for (int j = 0; j < Ns; ++j) {
+      const double a = 2.0 * fpn::kPi * double(j) / double(Ns);
+      tw[j] = make_double2(std::cos(a), std::sin(a));
+    }
+    fpn_internal::DevBuf<double2> buf;
+    FPN_HIP(buf.ensure(Ns));
+    hipError_t e = hipMemcpyAsync(buf.p, tw.data(), Ns * sizeof(double2), hipMemcpyHostToDevice, stream);
+    if (e == hipSuccess) e = hipStreamSynchronize(stream);
+    if (e != hipSuccess) {
+      buf.release();
+      FPN_HIP(e);
+    }
+    it = ctx->twiddles.emplace(Ns, buf).first;
   }
-  FPN_HIP(ctx->twiddle.ensure(Ns));
-  FPN_HIP(hipMemcpyAsync(ctx->twiddle.p, tw.data(), Ns * sizeof(double2), hipMemcpyHostToDevice, stream));
-  FPN_HIP(hipStreamSynchronize(stream));
-  ctx->tw_N = Ns;
+  *out = it->second.p;
   return FPN_OK;
 }
 
@@ -312,7 +325,8 @@ fpn_status fpn_destroy(fpn_ctx ctx) {
   (void)hipDeviceSynchronize();
   for (auto& kv : ctx->tables)
     for (void* p : kv.second.allocs) (void)hipFree(p);
-  ctx->twiddle.release();
+  for (auto& kv : ctx->twiddles) kv.second.release();
+  ctx->twiddles.clear();
   ctx->ip.release();
   ctx->c0.release();
   ctx->wsinv.release();
@@ -383,6 +397,10 @@ fpn_status validate_opts(const fpn_drive* drive, const fpn_solve_opts* opts) {
   if (int64_t(Ns) * std::max(r, 1) * (opts->settle_periods + 1) > (int64_t(1) << 30))
     return fail(FPN_E_ARG, "too many time steps");
   if (opts->flags & ~uint32_t(FPN_OUT_M | FPN_OUT_HARM | FPN_HARM_Z | FPN_OUT_DMDT)) return fail(FPN_E_ARG, "unknown flag");
+  // the harmonics kernel stages one instance's samples (all channels) in 64 KiB of LDS
+  const int nch = (opts->flags & FPN_HARM_Z) ? 3 : 2;
+  if (int64_t(nch) * Ns * int64_t(sizeof(float)) > FPN_MAX_HARM_LDS)
+    return fail(FPN_E_RANGE, "samples_per_period too large for the harmonics (channels * N_s * 4 bytes > 64 KiB)");
   return FPN_OK;
 }
 
@@ -471,8 +489,8 @@ fpn_status plan_build(fpn_plan_s* p, fpn_ctx ctx, const fpn_drive* drive, const 
     g.inv_off = inv_total;
     inv_total += int64_t(g.cnt) * g.t->inv_doubles;
   }
-  if (want_h)
-    if (fpn_status s = ensure_twiddle(ctx, Ns, stream)) return s;
+  if (want_h || tangent)
+    if (fpn_status s = ensure_twiddle(ctx, Ns, stream, &p->twiddle)) return s;
   FPN_HIP(p->ip.ensure(n));
   FPN_HIP(p->c0.ensure(size_t(n) * p->np_max));
   FPN_HIP(p->idx.ensure(n));
@@ -499,8 +517,6 @@ fpn_status plan_build(fpn_plan_s* p, fpn_ctx ctx, const fpn_drive* drive, const 
       FPN_HIP(p->own_dh.ensure(size_t(n) * fpn::kNTan * nch * (opts->n_harm + 1) * 2));
       p->dharm = p->own_dh.p;
     }
-    if (!want_h)
-      if (fpn_status s = ensure_twiddle(ctx, Ns, stream)) return s;
   }
   FPN_HIP(hipMemcpyAsync(p->idx.p, p->order.data(), n * sizeof(int32_t), hipMemcpyHostToDevice, stream));
   // side streams (default priority) and fork / join events for concurrent degree buckets
@@ -609,7 +625,7 @@ fpn_status plan_launch(fpn_plan_s* p, hipStream_t stream, bool timing) {
   if (p->harm_out) {
     const int nch = (opts->flags & FPN_HARM_Z) ? 3 : 2;
     if (fpn_status s = tm(3, stream, [&]() -> fpn_status {
-          fpn::launch_harmonics(p->msamp, Ns, opts->n_harm, nch, drive->period, ctx->twiddle.p, p->harm_out,
+          fpn::launch_harmonics(p->msamp, Ns, opts->n_harm, nch, drive->period, p->twiddle, p->harm_out,
                                 p->status, n, stream);
           FPN_HIP(hipGetLastError());
           return FPN_OK;
@@ -618,7 +634,7 @@ fpn_status plan_launch(fpn_plan_s* p, hipStream_t stream, bool timing) {
   }
   if (p->tangent) {
     const int nch = (opts->flags & FPN_HARM_Z) ? 3 : 2;
-    fpn::launch_harmonics(p->mtan, Ns, opts->n_harm, nch, drive->period, ctx->twiddle.p, p->dharm, p->status,
+    fpn::launch_harmonics(p->mtan, Ns, opts->n_harm, nch, drive->period, p->twiddle, p->dharm, p->status,
                           n * fpn::kNTan, stream, fpn::kNTan);
     FPN_HIP(hipGetLastError());
   }
@@ -1004,8 +1020,9 @@ fpn_status fpn_equilibrium(fpn_ctx ctx, const fpn_drive* drive, const fpn_solve_
     FPN_HIP(ctx->eq_m.ensure(size_t(n) * 3 * Ns));
     m = ctx->eq_m.p;
   }
+  const double2* tw = nullptr;
   if (want_h)
-    if (fpn_status s = ensure_twiddle(ctx, Ns, stream)) return s;
+    if (fpn_status s = ensure_twiddle(ctx, Ns, stream, &tw)) return s;
   FPN_HIP(ctx->ip.ensure(n));
   fpn::launch_instance_prep(n, batch->D, batch->Ms, batch->K, batch->alpha, batch->temp, batch->easy_axis,
                             batch->offset, ctx->ip.p, status, stream);
@@ -1023,7 +1040,7 @@ fpn_status fpn_equilibrium(fpn_ctx ctx, const fpn_drive* drive, const fpn_solve_
     const int nch = (opts->flags & FPN_HARM_Z) ? 3 : 2;
     // timed like the solver's harmonics (fpn_timing_enable / fpn_timing_read, slot 3)
     return timed(ctx, 3, stream, [&]() -> fpn_status {
-      fpn::launch_harmonics(m, Ns, opts->n_harm, nch, drive->period, ctx->twiddle.p, harm_out, status, n, stream);
+      fpn::launch_harmonics(m, Ns, opts->n_harm, nch, drive->period, tw, harm_out, status, n, stream);
       FPN_HIP(hipGetLastError());
       return FPN_OK;
     });

@@ -74,8 +74,9 @@ struct fpn_ctx_s {
   int device = 0;
   std::mutex mu;
   std::map<int, fpn_internal::TableSet> tables;
-  fpn_internal::DevBuf<double2> twiddle;
-  int tw_N = 0;
+  // DFT twiddle tables, one per sample count N_s; a table is written once and kept until fpn_destroy,
+  // so plans and captured graphs that hold its address stay valid whatever N_s later calls use
+  std::map<int, fpn_internal::DevBuf<double2>> twiddles;
   fpn_internal::DevBuf<fpn::InstParams> ip;
   fpn_internal::DevBuf<double> c0;
   fpn_internal::DevBuf<double> wsinv;
@@ -114,6 +115,7 @@ struct fpn_plan_s {
   float* m_out = nullptr;
   float* harm_out = nullptr;
   int32_t* status = nullptr;
+  const double2* twiddle = nullptr;  // the context's table for this plan's N_s
   float* msamp = nullptr;     // m_out or the plan's own sample buffer
   float* dmdt = nullptr;      // dmdt_out of fpn_solve (null for plans and tangent solves)
   int64_t np_max = 0;

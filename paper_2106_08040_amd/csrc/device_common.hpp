@@ -6,6 +6,20 @@
 
 namespace fpn {
 
+// Per-instance status codes (the FPN_INST_* values of fpn.h).  kInstTolUnmet keeps the outputs (finite,
+// accuracy not certified); every other non-zero code leaves NaN outputs.
+enum : int {
+  kInstOk = 0,
+  kInstBadParam = 1,
+  kInstNonfinite = 2,
+  kInstSingular = 3,
+  kInstUnresolved = 4,
+  kInstTolUnmet = 5
+};
+__host__ __device__ inline bool inst_failed(int s) { return s != kInstOk && s != kInstTolUnmet; }
+// |m|^2 above which a sampled state is not a probability density: (1 + 1e-3)^2
+constexpr float kMaxM2 = 1.002001f;
+
 // Per-instance data prepared by the instance kernel (FP64).
 struct InstParams {
   double inv2tau, sigma, beta_T, alpha;  // particle scalars
@@ -70,6 +84,7 @@ struct DevTables {
   double* cval64;      // [nnzc]
   uint16_t* ell_col;   // [kNSlRow][Np] fixed-slot rows (stepper)
   float* ell_val;      // [kNSlRow][Np]
+  float* ell_lo;       // [kNSlD][Np] low-order parts of the diagonal-block slots: value = ell_val + ell_lo
   uint16_t* ecol_row;  // [kNSlCol][Np] fixed-slot columns of the lower coupling
   float* ecol_val;     // [kNSlCol][Np]
   float* win_b;        // [kNWin][Np] window coefficients (see above)
@@ -93,7 +108,8 @@ enum : int {
   kSlB = 9, kNSlB = 6,
   kSlC = 15, kNSlC = 6,
   kNSlRow = 21,
-  kNSlCol = 6
+  kNSlCol = 6,
+  kNKindD = 5  // kinds 0..4 occur in the diagonal-block slots
 };
 // kind of every row slot and column slot (kind numbering of structure.hpp)
 constexpr int kSlotKindRow[kNSlRow] = {0, 1, 1, 1, 2, 2, 3, 3, 4,   // D: LAM G G G P P FZ FZ RZ

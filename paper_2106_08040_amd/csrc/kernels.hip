@@ -397,7 +397,7 @@ __global__ void harmonics_kernel(const float* msamp, int Ns, int n_harm, int nch
   const float* src = msamp + inst * 3 * Ns;
   for (int e = threadIdx.x; e < nch * Ns; e += blockDim.x) ml[e] = src[e];
   __syncthreads();
-  const bool bad = status[inst / st_div] != 0;  // st_div > 1: several sample sets per instance
+  const bool bad = inst_failed(status[inst / st_div]);  // st_div > 1: several sample sets per instance
   const int nk = n_harm + 1;
   for (int e = threadIdx.x; e < nch * nk; e += blockDim.x) {
     const int c = e / nk, k = e % nk;
@@ -552,7 +552,7 @@ __global__ void contract_kernel(const float* dL, const float* dharm, int per, do
       for (int p = 0; p < kNTan; ++p) red[p][threadIdx.x] += red[p][threadIdx.x + o];
     __syncthreads();
   }
-  if (threadIdx.x < kNTan) grad[i * kNTan + threadIdx.x] = status[i] != 0 ? __builtin_nan("") : red[threadIdx.x][0];
+  if (threadIdx.x < kNTan) grad[i * kNTan + threadIdx.x] = inst_failed(status[i]) ? __builtin_nan("") : red[threadIdx.x][0];
 }
 
 void launch_contract(const float* dL, const float* dharm, int per, double* grad, const int32_t* status, int64_t n,

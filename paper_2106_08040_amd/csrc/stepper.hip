@@ -5,8 +5,8 @@
 // Eq. convection, easy-axis frame) is integrated over (settle + 1) drive periods.
 // Every step factors M = I - h g A(t_n) by block elimination over the |m| blocks
 // (block-tridiagonal ordering): the Schur complement of each block is inverted by
-// Gauss-Jordan with 2x2 pivots on its (cos, sin) pairs, and the inverses stay in
-// VGPRs for the six stage solves.  Moments are sampled at t_j (Eq. mean_magmom_FP).
+// Gauss-Jordan with partial pivoting, and the inverses stay in VGPRs for the six
+// stage solves.  Moments are sampled at t_j (Eq. mean_magmom_FP).
 //
 // Lane layout of a block (n <= 32 rows): lane = 32 h + i holds row i, columns
 // h, h + 2, h + 4, ... (a[q] = S[i][h + 2q]).
@@ -58,8 +58,8 @@ struct WaveLds {
   static constexpr int kTanV = NT > 0 ? 3 * NpA : 4;
   float u[kUnion];
   float T[2 * kH];     // block right-hand side [parity][kH]
-  float col[64];       // pivot columns [parity][32]
-  float row[4 * kH];   // pivot rows [r][parity][kH]
+  int pv[64];          // pivot row of every column, [parity][kH]
+  float row[4 * kH];   // pivot row [parity][kH]
   float mk[16];        // -h g * multiplier(t_n) per kind
   float ms[16];        // multiplier at the current stage time per kind
   float tv[kTanV];                     // y0 | xt | kc
@@ -80,55 +80,83 @@ struct WaveLds {
   __device__ float* kc() { return tv + 2 * NpA; }
 };
 
-// In-place inverse of the lane-distributed block by Gauss-Jordan with 2x2 pivots.
-template <int Q, typename W>
-__device__ __forceinline__ bool gj2_invert(float (&a)[Q], int i, int h, W& w) {
+// In-place inverse of the lane-distributed block by Gauss-Jordan with partial pivoting (single
+// rows).  Column c = 2 qq + hc is held by the lanes of parity hc; the remaining row with the largest
+// |S[i][c]| becomes its pivot.  The slots rotate by one after every column pair, so the pivot column
+// is always slot 0 and all register indexing is static; after Q pairs the slots are back in order.
+// The tableau then holds the inverse with rows and columns permuted (row i of the tableau belongs to
+// the column it pivoted, column c to the row that pivoted it); the LDS scratch X (row stride kXS, one
+// half of kH slots per parity) puts it back in order.  kRow0 (block 0): row 0 is e_0 (the probability
+// row of M = I - h g A, A having a zero row 0) and pivots column 0, so it stays e_0 and the total
+// probability c_00 is conserved exactly by every solve.
+template <int Q, bool kRow0, typename W>
+__device__ __forceinline__ bool gj_piv_invert(float (&a)[Q], int i, int h, W& w, float* X) {
   constexpr int n = 2 * Q;
+  constexpr int kH = W::kH;
+  constexpr int kXS = 2 * kH + 1;
   const bool act = i < n;
   bool ok = true;
+  bool cand = act;  // row not yet a pivot
+  int mycol = 0;    // column this row pivoted
+  int* pv = w.pv;  // pivot row of column c at [(c & 1) kH + (c >> 1)]
 #pragma unroll 1
   for (int qq = 0; qq < Q; ++qq) {
-    const int r0 = 2 * qq;
-    const float cv = a[qq];  // element (i, r0 + h)
-    if (act) w.col[h * 32 + i] = cv;
-    const int r = i - r0;
-    const bool inR = act && (r == 0 || r == 1);
-    if (inR) {
 #pragma unroll
-      for (int q = 0; q < Q; ++q) w.row[(r * 2 + h) * W::kH + q] = a[q];
-    }
-    wsync();
-    // every read of this elimination step is issued before the first use (one LDS wait)
-    const float P00 = w.col[r0], P01 = w.col[32 + r0];
-    const float P10 = w.col[r0 + 1], P11 = w.col[32 + r0 + 1];
-    const float g0r = w.col[i], g1r = w.col[32 + i];  // i < 32: in bounds for every lane
-    float w0[Q], w1[Q];
+    for (int hc = 0; hc < 2; ++hc) {
+      // the column's entry of this lane's row: own slot 0 (parity hc) or the partner lane's
+      const float own = a[0];
+      auto sw = __builtin_amdgcn_permlane32_swap(__float_as_uint(own), __float_as_uint(own), false, false);
+      const float g = (h == hc) ? own : __uint_as_float(h == 0 ? sw[1] : sw[0]);
+      const uint32_t best = max32_uniform(pivot_key<5>(g, i, cand));
+      const int p = (kRow0 && hc == 0 && qq == 0) ? 0 : int(best & 31u);
+      const float P = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(g), p));
+      ok = ok && (P != 0.0f) && isfinite(P);
+      const float ip = __builtin_amdgcn_rcpf(P);  // hardware reciprocal (1 ulp)
+      const bool isp = (i == p);
+      if (isp) {
 #pragma unroll
-    for (int q = 0; q < Q; ++q) {
-      w0[q] = w.row[(0 * 2 + h) * W::kH + q];
-      w1[q] = w.row[(1 * 2 + h) * W::kH + q];
-    }
-    __builtin_amdgcn_sched_barrier(0);
-    const float det = P00 * P11 - P01 * P10;
-    ok = ok && (det != 0.0f) && isfinite(det);
-    const float id = __builtin_amdgcn_rcpf(det);  // hardware reciprocal (1 ulp)
-    const float Pi00 = P11 * id, Pi01 = -P01 * id, Pi10 = -P10 * id, Pi11 = P00 * id;
-    const float g0 = act ? g0r : 0.0f, g1 = act ? g1r : 0.0f;
-    float G0 = g0 * Pi00 + g1 * Pi10;
-    float G1 = g0 * Pi01 + g1 * Pi11;
-    float s = 1.0f;
-    float newc = (h == 0) ? -G0 : -G1;
-    if (inR) {
-      s = 0.0f;
-      G0 = (r == 0) ? -Pi00 : -Pi10;
-      G1 = (r == 0) ? -Pi01 : -Pi11;
-      newc = (r == 0) ? ((h == 0) ? Pi00 : Pi01) : ((h == 0) ? Pi10 : Pi11);
-    }
+        for (int q = 0; q < Q; ++q) w.row[h * kH + q] = a[q];
+      }
+      if (i == 0 && h == 0) pv[hc * kH + qq] = p;
+      wsync();
+      float rv[Q];
 #pragma unroll
-    for (int q = 0; q < Q; ++q) a[q] = fmaf(-G1, w1[q], fmaf(-G0, w0[q], s * a[q]));
-    a[qq] = act ? newc : 0.0f;
-    wsync();
+      for (int q = 0; q < Q; ++q) rv[q] = w.row[h * kH + q];
+      __builtin_amdgcn_sched_barrier(0);
+      // pivot row: ip * row; other rows: row - g ip * pivot row; the pivot column becomes the inverse's
+      const float G = isp ? -ip : g * ip;
+      const float s = isp ? 0.0f : 1.0f;
+      const float pc = act ? (isp ? ip : -g * ip) : 0.0f;
+      if (hc == 0) {
+#pragma unroll
+        for (int q = 0; q < Q; ++q) a[q] = fmaf(-G, rv[q], s * a[q]);
+        if (h == 0) a[0] = pc;
+      } else {
+        const float a0 = fmaf(-G, rv[0], s * a[0]);
+#pragma unroll
+        for (int q = 1; q < Q; ++q) a[q - 1] = fmaf(-G, rv[q], s * a[q]);
+        a[Q - 1] = (h == 1) ? pc : a0;
+      }
+      if (isp) {
+        cand = false;
+        mycol = 2 * qq + hc;
+      }
+      wsync();
+    }
   }
+  // tableau entry (i, j) -> inverse entry (mycol, pivot row of column j)
+  int pj[Q];
+#pragma unroll
+  for (int q = 0; q < Q; ++q) pj[q] = pv[h * kH + q];
+  __builtin_amdgcn_sched_barrier(0);
+  if (act) {
+#pragma unroll
+    for (int q = 0; q < Q; ++q) X[mycol * kXS + (pj[q] & 1) * kH + (pj[q] >> 1)] = a[q];
+  }
+  wsync();
+#pragma unroll
+  for (int q = 0; q < Q; ++q) a[q] = act ? X[i * kXS + h * kH + q] : 0.0f;
+  wsync();
   return ok;
 }
 
@@ -143,19 +171,22 @@ stepper_kernel(StepArgs A, DevTables t) {
   constexpr int Np = Gm::Np;
   constexpr int S = Gm::S;
   extern __shared__ __align__(16) unsigned char smem[];
-  // fixed-slot operator tables: indices (u16) then values (f32), slot-major
+  // fixed-slot operator tables: indices (u16) then values (f32), slot-major; the diagonal-block slots
+  // also carry the low-order part of their value (elo).  The column slots of the block-1 coupling are
+  // read from global memory (once per step).
   uint16_t* ecol = reinterpret_cast<uint16_t*>(smem);          // [kNSlRow][Np]
-  uint16_t* crow = ecol + kNSlRow * Np;                        // [kNSlCol][Np]
-  constexpr size_t b16 = ((size_t(kNSlRow + kNSlCol) * Np * 2) + 15) & ~size_t(15);
+  constexpr size_t b16 = ((size_t(kNSlRow) * Np * 2) + 15) & ~size_t(15);
   float* eval = reinterpret_cast<float*>(smem + b16);          // [kNSlRow][Np]
-  float* cvl = eval + kNSlRow * Np;                            // [kNSlCol][Np]
-  float* wB = cvl + kNSlCol * Np;                              // [kNWin][Np] window coefficients
+  float* elo = eval + kNSlRow * Np;                            // [kNSlD][Np]
+  float* wB = elo + kNSlD * Np;                                // [kNWin][Np] window coefficients
   float* wC = wB + kNWin * Np;
   float* wS = wC + kNWin * Np;
-  constexpr size_t tb = (b16 + size_t(kNSlRow + kNSlCol + 3 * kNWin) * Np * 4 + 15) & ~size_t(15);
+  constexpr size_t tb = (b16 + size_t(kNSlRow + kNSlD + 3 * kNWin) * Np * 4 + 15) & ~size_t(15);
   WL* wl = reinterpret_cast<WL*>(smem + tb);
+  const uint16_t* crow = t.ecol_row;                           // [kNSlCol][Np] (global)
+  const float* cvl = t.ecol_val;                               // [kNSlCol][Np] (global)
   for (int e = threadIdx.x; e < kNSlRow * Np; e += blockDim.x) { ecol[e] = t.ell_col[e]; eval[e] = t.ell_val[e]; }
-  for (int e = threadIdx.x; e < kNSlCol * Np; e += blockDim.x) { crow[e] = t.ecol_row[e]; cvl[e] = t.ecol_val[e]; }
+  for (int e = threadIdx.x; e < kNSlD * Np; e += blockDim.x) elo[e] = t.ell_lo[e];
   // wB, wC slot-major like the global tables; wS column-major ([column][6]): the Schur update reads
   // the six weights of one column together (three 8-byte broadcast reads)
   for (int e = threadIdx.x; e < kNWin * Np; e += blockDim.x) {
@@ -271,7 +302,12 @@ stepper_kernel(StepArgs A, DevTables t) {
     if (lane >= 9 * NT || (deriv && kind < 3)) return 0.0f;
     return tan_mult_t<float>(prm, kind, inv2tau, sigma, alpha, beta, float(P.D), float(P.sigK), hh, ep);
   };
-  // dst[p] = add * dst[p] + (A(ms) src)[p] for the rows p = lane + 64 s (one row slot at a time)
+  // dst[p] = add * dst[p] + (A(ms) src)[p] for the rows p = lane + 64 s (one row slot at a time).
+  // Diagonal-block entries are applied as hi + lo (the table's FP32 value and its low-order part),
+  // summed per kind and scaled by the kind's multiplier at the end: rounding them to FP32 would bias
+  // the operator itself, and the slow relaxation modes of an anisotropic particle, whose rates are
+  // small differences of large entries, are sensitive to such a bias (rounding of the sums is not a
+  // bias: it changes with the state from one evaluation to the next).
   auto matvec = [&](float* dst, bool add, const float* xin) {
     float m[9];
 #pragma unroll
@@ -282,14 +318,39 @@ stepper_kernel(StepArgs A, DevTables t) {
       const int z = opaque_zero();
       const uint16_t* ec = ecol + z;
       const float* ev = eval + z;
+      const float* el = elo + z;
       if (p < Np) {
-        // table reads, then gathers, then the sum, seven couplings at a time: the LDS latency is paid
+        // table reads, then gathers, then the sums, one slot group at a time: the LDS latency is paid
         // twice per group rather than twice per coupling (the scheduler otherwise waits after every load)
-        constexpr int kG = 7;
-        static_assert(kNSlRow % kG == 0, "row slots come in whole groups");
         float acc = 0.0f;
+        {
+          int ci[kNSlD];
+          float hv[kNSlD], lv[kNSlD], xv[kNSlD];
 #pragma unroll
-        for (int g0 = 0; g0 < kNSlRow; g0 += kG) {
+          for (int u = 0; u < kNSlD; ++u) {
+            ci[u] = ec[(kSlD + u) * Np + p];
+            hv[u] = ev[(kSlD + u) * Np + p];
+            lv[u] = el[u * Np + p];
+          }
+          __builtin_amdgcn_sched_barrier(0);
+#pragma unroll
+          for (int u = 0; u < kNSlD; ++u) xv[u] = xin[ci[u]];
+          __builtin_amdgcn_sched_barrier(0);
+          float sh[kNKindD], sl[kNKindD];
+#pragma unroll
+          for (int k = 0; k < kNKindD; ++k) sh[k] = sl[k] = 0.0f;
+#pragma unroll
+          for (int u = 0; u < kNSlD; ++u) {
+            sh[kSlotKindRow[kSlD + u]] = fmaf(hv[u], xv[u], sh[kSlotKindRow[kSlD + u]]);
+            sl[kSlotKindRow[kSlD + u]] = fmaf(lv[u], xv[u], sl[kSlotKindRow[kSlD + u]]);
+          }
+#pragma unroll
+          for (int k = 0; k < kNKindD; ++k) acc = fmaf(m[k], sl[k], fmaf(m[k], sh[k], acc));
+        }
+        constexpr int kG = 6;
+        static_assert((kNSlB + kNSlC) % kG == 0, "coupling slots come in whole groups");
+#pragma unroll
+        for (int g0 = kSlB; g0 < kNSlRow; g0 += kG) {
           int ci[kG];
           float cv[kG], xv[kG];
 #pragma unroll
@@ -655,7 +716,7 @@ stepper_kernel(StepArgs A, DevTables t) {
           }
         }
       }
-      ok = gj2_invert<Q>(a, i, h, w) && ok;
+      ok = gj_piv_invert<Q, K == 0>(a, i, h, w, X) && ok;
       auto& sa = blk<K>(st);
 #pragma unroll
       for (int q = 0; q < Q; ++q) sa[q] = a[q];
@@ -842,19 +903,32 @@ stepper_kernel(StepArgs A, DevTables t) {
     w.ctl[4] = 0.0;
     w.ctl[5] = 0.0;
   }
+  const float c00_0 = __shfl(y[0], 0);  // c_00 = 1 / sqrt(4 pi): total probability
+  bool unres = false;   // |m| > 1 + 1e-3 or c_00 changed at a sample
+  bool forced = false;  // a step accepted at the smallest step size with its estimate above tol
   for (int j = 0; j < n_int && ok; ++j) {
     const double tj = j * dt;
+    const float vx = __shfl(y[pX >> 6], pX & 63), vy = __shfl(y[pY >> 6], pY & 63),
+                vz = __shfl(y[pZ >> 6], pZ & 63);
+    {
+      // a probability density has |m| <= 1 and keeps c_00 (conserved exactly by the solves); a state
+      // that breaks either is not resolved by the degree (status FPN_INST_UNRESOLVED, stop here)
+      const bool fin = isfinite(vx) && isfinite(vy) && isfinite(vz);
+      const bool phys = (rc * rc) * (vx * vx + vy * vy + vz * vz) <= kMaxM2 && __shfl(y[0], 0) == c00_0;
+      if (fin && !phys) unres = true;
+      if (!(fin && phys)) {
+        ok = false;
+        break;
+      }
+    }
     if (j >= first_rec) {
       const int js = j - first_rec;
-      const float vx = __shfl(y[pX >> 6], pX & 63), vy = __shfl(y[pY >> 6], pY & 63),
-                  vz = __shfl(y[pZ >> 6], pZ & 63);
       if (lane < 3) {
         const float r0 = lane == 0 ? R[0] : (lane == 1 ? R[3] : R[6]);
         const float r1 = lane == 0 ? R[1] : (lane == 1 ? R[4] : R[7]);
         const float r2 = lane == 0 ? R[2] : (lane == 1 ? R[5] : R[8]);
         ms_out[lane * A.Ns + js] = rc * (r0 * vx + r1 * vy + r2 * vz);
       }
-      ok = ok && isfinite(vx) && isfinite(vy) && isfinite(vz);
       if (dd_out) {
         // dm/dt at the sample: rows l = 1 of A(t_j) y (the ODE's right-hand side), rotated like m
         const float mt = mult_lane(tj);
@@ -869,8 +943,11 @@ stepper_kernel(StepArgs A, DevTables t) {
         float acc = 0.0f;
         if (lane < 3) {
           const int row = lane == 0 ? pX : (lane == 1 ? pY : pZ);  // rows < 64
-          for (int g = 0; g < kNSlRow; ++g)
-            acc = fmaf(w.ms[kSlotKindRow[g]] * eval[g * Np + row], xs[ecol[g * Np + row]], acc);
+          for (int g = 0; g < kNSlRow; ++g) {
+            const float x = xs[ecol[g * Np + row]], mk = w.ms[kSlotKindRow[g]];
+            acc = fmaf(mk * eval[g * Np + row], x, acc);
+            if (g < kNSlD) acc = fmaf(mk * elo[g * Np + row], x, acc);
+          }
         }
         const float ax = __shfl(acc, 0), ay = __shfl(acc, 1), az = __shfl(acc, 2);
         if (lane < 3) {
@@ -964,6 +1041,7 @@ stepper_kernel(StepArgs A, DevTables t) {
         wsync();
         continue;
       }
+      if (!fixedr && e > A.tol) forced = true;
       accept(float(hs2) * 0.25f);
       // no growth right after a rejected attempt (avoids grow / reject cycles)
       const double hn = hs2 * double(fminf(after_reject ? 1.0f : 4.0f, fmaxf(0.2f, fac)));
@@ -982,7 +1060,9 @@ stepper_kernel(StepArgs A, DevTables t) {
       for (int j = lane; j < 3 * A.Ns; j += 64) dd_out[j] = __builtin_nanf("");
     if constexpr (NT > 0)
       for (int j = lane; j < NT * 3 * A.Ns; j += 64) mt_out[j] = __builtin_nanf("");
-    if (lane == 0) A.status[inst] = 2;
+    if (lane == 0) A.status[inst] = unres ? kInstUnresolved : kInstNonfinite;
+  } else if (forced) {
+    if (lane == 0) A.status[inst] = kInstTolUnmet;
   }
   wsync();
   if (A.steps_out && lane == 0) A.steps_out[inst] = int(w.ctl[5]);
@@ -1002,8 +1082,8 @@ constexpr size_t kMaxLdsBytes = 160 * 1024;  // LDS of one compute unit
 template <int L, int WV, int NT>
 constexpr size_t stepper_lds_bytes() {
   constexpr int Np = Geo<L>::Np;
-  constexpr size_t b16 = ((size_t(kNSlRow + kNSlCol) * Np * 2) + 15) & ~size_t(15);
-  constexpr size_t tb = (b16 + size_t(kNSlRow + kNSlCol + 3 * kNWin) * Np * 4 + 15) & ~size_t(15);
+  constexpr size_t b16 = ((size_t(kNSlRow) * Np * 2) + 15) & ~size_t(15);
+  constexpr size_t tb = (b16 + size_t(kNSlRow + kNSlD + 3 * kNWin) * Np * 4 + 15) & ~size_t(15);
   return tb + WV * sizeof(WaveLds<L, NT>);
 }
 

@@ -36,10 +36,11 @@ __device__ __forceinline__ int opaque_zero() {
 
 // A (wavefront-uniform) pointer the optimiser cannot see through: addresses derived from it are
 // formed after this point, so the per-block table addresses are not all hoisted out of the time loop.
+// (The offset is an opaque zero: the asm operand is a fresh scalar, whatever register class the
+// pointer itself ends up in.)
 template <typename T>
 __device__ __forceinline__ T* opaque_ptr(T* p) {
-  asm volatile("" : "+s"(p));
-  return p;
+  return p + opaque_zero();
 }
 
 // |v| for the step-error maximum, with NaN mapped to +inf: fmaxf ignores a NaN operand, an infinity
@@ -76,6 +77,39 @@ __device__ __forceinline__ float wave_max(float v) {
   auto r = __builtin_amdgcn_permlane32_swap(__float_as_uint(v), __float_as_uint(v), false, false);
   const float m = fmaxf(__uint_as_float(r[0]), __uint_as_float(r[1]));
   return __int_as_float(__builtin_amdgcn_readfirstlane(__float_as_int(m)));
+}
+
+// Partial pivoting of the Schur-block Gauss-Jordan: the pivot of a column is the remaining row with
+// the largest |entry|.  The comparison key of a row is its |entry| with the low `B` mantissa bits
+// replaced by the row index (a candidate key is at least 2^B, a finished row's key is 0), so one
+// unsigned maximum over the lanes yields the pivot row.  NaN compares above every finite value and
+// is then caught as a non-finite pivot.
+template <int B>
+__device__ __forceinline__ uint32_t pivot_key(float v, int row, bool candidate) {
+  const uint32_t mag = __float_as_uint(v) & 0x7fffffffu;
+  return candidate ? ((((mag >> B) + 1u) << B) | uint32_t(row)) : 0u;
+}
+
+// Maximum of a key over each 16-lane row of the wavefront (every lane of the row receives it):
+// DPP butterflies within quads, then the half-row and row mirrors.
+__device__ __forceinline__ uint32_t row16_max(uint32_t k) {
+  k = max(k, uint32_t(__builtin_amdgcn_update_dpp(0, int(k), 0xB1, 0xF, 0xF, false)));   // quad: 1 0 3 2
+  k = max(k, uint32_t(__builtin_amdgcn_update_dpp(0, int(k), 0x4E, 0xF, 0xF, false)));   // quad: 2 3 0 1
+  k = max(k, uint32_t(__builtin_amdgcn_update_dpp(0, int(k), 0x141, 0xF, 0xF, false)));  // row half mirror
+  k = max(k, uint32_t(__builtin_amdgcn_update_dpp(0, int(k), 0x140, 0xF, 0xF, false)));  // row mirror
+  return k;
+}
+
+// Wavefront-uniform maximum of a key over lanes 0..31 (rows 0 and 1) or over all 64 lanes.
+__device__ __forceinline__ uint32_t max32_uniform(uint32_t k) {
+  k = row16_max(k);
+  return max(uint32_t(__builtin_amdgcn_readlane(int(k), 0)), uint32_t(__builtin_amdgcn_readlane(int(k), 16)));
+}
+__device__ __forceinline__ uint32_t max64_uniform(uint32_t k) {
+  k = row16_max(k);
+  const uint32_t a = max(uint32_t(__builtin_amdgcn_readlane(int(k), 0)), uint32_t(__builtin_amdgcn_readlane(int(k), 16)));
+  const uint32_t b = max(uint32_t(__builtin_amdgcn_readlane(int(k), 32)), uint32_t(__builtin_amdgcn_readlane(int(k), 48)));
+  return max(a, b);
 }
 
 // RODAS4 (Hairer & Wanner) in the form

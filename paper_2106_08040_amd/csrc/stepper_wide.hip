@@ -2,8 +2,8 @@
 // a block layout that fits |m| blocks of up to 64 rows.
 //
 // One wavefront per instance; lane i owns row i of the block being factored.  A block's Schur
-// complement is built and inverted in registers (Gauss-Jordan with 2 x 2 pivots on its (cos, sin)
-// pairs, columns rotated by two after every pivot so all register indexing is static) and the
+// complement is built and inverted in registers (Gauss-Jordan with partial pivoting, columns rotated
+// by one after every pivot so all register indexing is static) and the
 // inverse is written to a per-instance workspace in global memory, column-quad-major so that a
 // wavefront reads 1 KiB contiguous per quad of columns in the stage solves.  The state vector stays
 // in registers, the stage and gather vectors in LDS (xin, V, G) or in the workspace (K1..K5, f_t,
@@ -46,7 +46,7 @@ struct WideLds {
   float a[kA];        // X (factorisation) | xin, V (stages)
   float g[NpA];       // G (block-solve result)
   float T[64];        // block right-hand side
-  float prow[2][64];  // pivot rows
+  float prow[2][64];  // pivot row
   float cw[6][64];    // Schur coefficients of one block, multiplier included
   float mk[16];
   float ms[16];
@@ -57,49 +57,58 @@ struct WideLds {
   __device__ float* G() { return g; }
 };
 
-// In-place inverse of an n x n block, row `lane` in a[0..n-1], by Gauss-Jordan with 2 x 2 pivots.
-// Pivot p works on columns 0, 1 of the rotated order and appends the new pivot columns at n-2, n-1,
-// so after n/2 pivots the columns are back in their original order.
-template <int n, typename WL>
-__device__ __forceinline__ bool gj_rot_invert(float (&a)[n], int lane, WL& w) {
+// In-place inverse of an n x n block, row `lane` in a[0..n-1], by Gauss-Jordan with partial pivoting
+// (single rows).  Pivot k works on column 0 of the rotated order (original column k): the remaining
+// row with the largest |entry| pivots, and the new pivot column is appended at n - 1, so after n
+// pivots the columns are back in their original order and all register indexing is static.  The
+// tableau then holds the inverse with rows and columns permuted; X (row stride XS) puts it back.
+// kRow0 (block 0): row 0 is e_0 and pivots column 0, which conserves c_00 exactly (see stepper.hip).
+template <int n, int XS, bool kRow0, typename WL>
+__device__ __forceinline__ bool gj_piv_invert_wide(float (&a)[n], int lane, WL& w, float* X) {
   const bool act = lane < n;
   bool ok = true;
+  bool cand = act;
+  int mycol = 0;  // column this row pivoted
+  int cpiv = 0;   // lane k: pivot row of column k
 #pragma unroll 1
-  for (int p = 0; p < n / 2; ++p) {
-    const int r0 = 2 * p;
-    const int r = lane - r0;
-    const bool inR = act && (r == 0 || r == 1);
-    if (inR) {
+  for (int k = 0; k < n; ++k) {
+    const float g = a[0];
+    const uint32_t best = max64_uniform(pivot_key<6>(g, lane, cand));
+    const int p = (kRow0 && k == 0) ? 0 : int(best & 63u);
+    const float P = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(g), p));
+    ok = ok && (P != 0.0f) && isfinite(P);
+    const float ip = 1.0f / P;
+    const bool isp = (lane == p);
+    if (isp) {
 #pragma unroll
-      for (int q = 0; q < n; ++q) w.prow[r][q] = a[q];
+      for (int q = 1; q < n; ++q) w.prow[0][q] = a[q];
     }
+    if (lane == k) cpiv = p;
     wsync();
-    const float P00 = w.prow[0][0], P01 = w.prow[0][1], P10 = w.prow[1][0], P11 = w.prow[1][1];
-    const float det = P00 * P11 - P01 * P10;
-    ok = ok && (det != 0.0f) && isfinite(det);
-    const float id = 1.0f / det;
-    const float Pi00 = P11 * id, Pi01 = -P01 * id, Pi10 = -P10 * id, Pi11 = P00 * id;
-    const float g0 = a[0], g1 = a[1];
-    float G0 = g0 * Pi00 + g1 * Pi10;
-    float G1 = g0 * Pi01 + g1 * Pi11;
-    float s = 1.0f;
-    float c0 = -G0, c1 = -G1;
-    if (inR) {
-      s = 0.0f;
-      G0 = (r == 0) ? -Pi00 : -Pi10;
-      G1 = (r == 0) ? -Pi01 : -Pi11;
-      c0 = (r == 0) ? Pi00 : Pi10;
-      c1 = (r == 0) ? Pi01 : Pi11;
-    }
+    const float G = isp ? -ip : g * ip;
+    const float s = isp ? 0.0f : 1.0f;
 #pragma unroll
-    for (int q = 2; q < n; ++q) {
-      a[q - 2] = fmaf(-G1, w.prow[1][q], fmaf(-G0, w.prow[0][q], s * a[q]));
+    for (int q = 1; q < n; ++q) {
+      a[q - 1] = fmaf(-G, w.prow[0][q], s * a[q]);
       if ((q & 7) == 7) __builtin_amdgcn_sched_barrier(0);
     }
-    a[n - 2] = act ? c0 : 0.0f;
-    a[n - 1] = act ? c1 : 0.0f;
+    a[n - 1] = act ? (isp ? ip : -g * ip) : 0.0f;
+    if (isp) {
+      cand = false;
+      mycol = k;
+    }
     wsync();
   }
+  // inverse entry (a, b) = tableau entry (pivot row of column a, column pivoted by row b)
+  if (act) {
+#pragma unroll
+    for (int q = 0; q < n; ++q) X[lane * XS + q] = a[q];
+  }
+  wsync();
+  const float* xr = X + cpiv * XS;
+#pragma unroll
+  for (int q = 0; q < n; ++q) a[q] = act ? xr[__builtin_amdgcn_readlane(mycol, q)] : 0.0f;
+  wsync();
   return ok;
 }
 
@@ -134,6 +143,7 @@ stepper_wide_kernel(StepArgs A, DevTables t, float* ws) {
   float* Kg = inv + WG::INV;  // K1..K5 at j * NpA, f_t at 5 * NpA
   const uint16_t* ecol = t.ell_col;
   const float* eval = t.ell_val;
+  const float* elo = t.ell_lo;
   const float* wB = t.win_b;
   const float* wC = t.win_c;
   const float* wS = t.win_s;
@@ -193,7 +203,9 @@ stepper_wide_kernel(StepArgs A, DevTables t, float* ws) {
     const float hz = R[2] * bx + R[5] * by + R[8] * bz;
     return (lane < 3) ? 0.0f : kind_mult(lane < 9 ? lane : 0, inv2tau, sigma, alpha, beta, hx, hy, hz);
   };
-  // dst[p] = add * dst[p] + (A(ms) xin)[p] for the rows p = lane + 64 s
+  // dst[p] = add * dst[p] + (A(ms) xin)[p] for the rows p = lane + 64 s.  Diagonal-block entries are
+  // applied as hi + lo, summed per kind (see the register-layout stepper: rounded entries bias the slow
+  // relaxation modes).
   auto matvec = [&](float* dst, bool add) {
     const float* xin = w.xin();
     float m[9];
@@ -203,14 +215,38 @@ stepper_wide_kernel(StepArgs A, DevTables t, float* ws) {
     for (int s = 0; s < S; ++s) {
       const int p = lane + 64 * s;
       const float* ev = opaque_ptr(eval);
+      const float* el = opaque_ptr(elo);
       const uint16_t* ec = opaque_ptr(ecol);
       if (p < Np) {
-        // table reads, then gathers, then the sum, seven couplings at a time (one wait per phase)
-        constexpr int kG = 7;
-        static_assert(kNSlRow % kG == 0, "row slots come in whole groups");
+        // table reads, then gathers, then the sums, one slot group at a time (one wait per phase)
         float acc = 0.0f;
+        {
+          int ci[kNSlD];
+          float hv[kNSlD], lv[kNSlD], xv[kNSlD];
 #pragma unroll
-        for (int g0 = 0; g0 < kNSlRow; g0 += kG) {
+          for (int u = 0; u < kNSlD; ++u) {
+            ci[u] = ec[(kSlD + u) * Np + p];
+            hv[u] = ev[(kSlD + u) * Np + p];
+            lv[u] = el[u * Np + p];
+          }
+          __builtin_amdgcn_sched_barrier(0);
+#pragma unroll
+          for (int u = 0; u < kNSlD; ++u) xv[u] = xin[ci[u]];
+          __builtin_amdgcn_sched_barrier(0);
+          float sh[kNKindD], sl[kNKindD];
+#pragma unroll
+          for (int k = 0; k < kNKindD; ++k) sh[k] = sl[k] = 0.0f;
+#pragma unroll
+          for (int u = 0; u < kNSlD; ++u) {
+            sh[kSlotKindRow[kSlD + u]] = fmaf(hv[u], xv[u], sh[kSlotKindRow[kSlD + u]]);
+            sl[kSlotKindRow[kSlD + u]] = fmaf(lv[u], xv[u], sl[kSlotKindRow[kSlD + u]]);
+          }
+#pragma unroll
+          for (int k = 0; k < kNKindD; ++k) acc = fmaf(m[k], sl[k], fmaf(m[k], sh[k], acc));
+        }
+        constexpr int kG = 6;
+#pragma unroll
+        for (int g0 = kSlB; g0 < kNSlRow; g0 += kG) {
           int ci[kG];
           float cv[kG], xv[kG];
 #pragma unroll
@@ -504,7 +540,7 @@ stepper_wide_kernel(StepArgs A, DevTables t, float* ws) {
       float a[n];
 #pragma unroll
       for (int q = 0; q < n; ++q) a[q] = act ? X[lane * XS + q] : 0.0f;
-      ok = gj_rot_invert<n>(a, lane, w) && ok;
+      ok = gj_piv_invert_wide<n, XS, K == 0>(a, lane, w, X) && ok;
       // inverse -> workspace (column quads) and -> X rows for the next block's U
       if (act) {
         float4* iv = reinterpret_cast<float4*>(opaque_ptr(inv) + WG::ioff(K));
@@ -624,19 +660,32 @@ stepper_wide_kernel(StepArgs A, DevTables t, float* ws) {
     w.ctl[4] = 0.0;
   }
   int steps = 0;
+  const float c00_0 = __shfl(y[0], 0);  // c_00 = 1 / sqrt(4 pi): total probability
+  bool unres = false;   // |m| > 1 + 1e-3 or c_00 changed at a sample
+  bool forced = false;  // a step accepted at the smallest step size with its estimate above tol
   for (int j = 0; j < n_int && ok; ++j) {
     const double tj = j * dt;
+    const float vx = __shfl(y[pX >> 6], pX & 63), vy = __shfl(y[pY >> 6], pY & 63),
+                vz = __shfl(y[pZ >> 6], pZ & 63);
+    {
+      // a probability density has |m| <= 1 and keeps c_00 (conserved exactly by the solves); a state
+      // that breaks either is not resolved by the degree (status FPN_INST_UNRESOLVED, stop here)
+      const bool fin = isfinite(vx) && isfinite(vy) && isfinite(vz);
+      const bool phys = (rc * rc) * (vx * vx + vy * vy + vz * vz) <= kMaxM2 && __shfl(y[0], 0) == c00_0;
+      if (fin && !phys) unres = true;
+      if (!(fin && phys)) {
+        ok = false;
+        break;
+      }
+    }
     if (j >= first_rec) {
       const int js = j - first_rec;
-      const float vx = __shfl(y[pX >> 6], pX & 63), vy = __shfl(y[pY >> 6], pY & 63),
-                  vz = __shfl(y[pZ >> 6], pZ & 63);
       if (lane < 3) {
         const float r0 = lane == 0 ? R[0] : (lane == 1 ? R[3] : R[6]);
         const float r1 = lane == 0 ? R[1] : (lane == 1 ? R[4] : R[7]);
         const float r2 = lane == 0 ? R[2] : (lane == 1 ? R[5] : R[8]);
         ms_out[lane * A.Ns + js] = rc * (r0 * vx + r1 * vy + r2 * vz);
       }
-      ok = ok && isfinite(vx) && isfinite(vy) && isfinite(vz);
       if (dd_out) {
         // dm/dt at the sample: rows l = 1 of A(t_j) y (the ODE's right-hand side), rotated like m
         const float mt = mult_lane(tj);
@@ -652,7 +701,11 @@ stepper_wide_kernel(StepArgs A, DevTables t, float* ws) {
         if (lane < 3) {
           const int row = lane == 0 ? pX : (lane == 1 ? pY : pZ);  // rows < 64
           for (int g = 0; g < kNSlRow; ++g)
-            acc = fmaf(w.ms[kSlotKindRow[g]] * eval[g * Np + row], xs[ecol[g * Np + row]], acc);
+          {
+            const float x = xs[ecol[g * Np + row]], mk = w.ms[kSlotKindRow[g]];
+            acc = fmaf(mk * eval[g * Np + row], x, acc);
+            if (g < kNSlD) acc = fmaf(mk * elo[g * Np + row], x, acc);
+          }
         }
         const float ax = __shfl(acc, 0), ay = __shfl(acc, 1), az = __shfl(acc, 2);
         if (lane < 3) {
@@ -713,6 +766,7 @@ stepper_wide_kernel(StepArgs A, DevTables t, float* ws) {
         wsync();
         continue;
       }
+      if (!fixedr && e > A.tol) forced = true;
       accept(float(hs2) * 0.25f);
       // no growth right after a rejected attempt (avoids grow / reject cycles)
       const double hn = hs2 * double(fminf(after_reject ? 1.0f : 4.0f, fmaxf(0.2f, fac)));
@@ -728,7 +782,9 @@ stepper_wide_kernel(StepArgs A, DevTables t, float* ws) {
     for (int j = lane; j < 3 * A.Ns; j += 64) ms_out[j] = __builtin_nanf("");
     if (dd_out)
       for (int j = lane; j < 3 * A.Ns; j += 64) dd_out[j] = __builtin_nanf("");
-    if (lane == 0) A.status[inst] = 2;
+    if (lane == 0) A.status[inst] = unres ? kInstUnresolved : kInstNonfinite;
+  } else if (forced) {
+    if (lane == 0) A.status[inst] = kInstTolUnmet;
   }
   if (A.steps_out && lane == 0) A.steps_out[inst] = steps;
   }  // queue

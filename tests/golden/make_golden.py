@@ -46,6 +46,42 @@ def identification_a0():
     return out
 
 
+def lissajous_stratified():
+    """64 instances of the 2312-instance Lissajous system matrix: for every easy-axis angle j, the four
+    corners and the centre of the 17 x 17 offset grid and three of the four edge midpoints (the edge
+    left out turns with j).  Instance id = (j * 17 + iy) * 17 + ix."""
+    ids = []
+    mids = [(0, 8), (8, 16), (16, 8), (8, 0)]
+    for j in range(8):
+        pos = [(0, 0), (0, 16), (16, 0), (16, 16), (8, 8)] + [m for e, m in enumerate(mids) if e != j % 4]
+        ids += [(j * 17 + iy) * 17 + ix for iy, ix in pos]
+    return ids
+
+
+UNEVEN_BUCKETS = ((8, 8), (9, 12), (13, 16), (17, 20), (21, 23), (24, 24))
+
+
+def uneven_stratified():
+    """Two resolvable instances of the 4096-instance uneven sweep per degree bucket (UNEVEN_BUCKETS):
+    the band top (largest sigma - (L - 4), the stiffest particle its degree resolves) and the instance
+    with the median sigma of the bucket."""
+    ws = W.uneven_sweep(4096, seed=3)
+    inst = ws["inst"]
+    sig = W.anisotropy_ratio(inst["D"], inst["K"])
+    ok = W.resolvable(inst["D"], inst["K"], inst["L"])
+    ids = []
+    for lo, hi in UNEVEN_BUCKETS:
+        cand = np.nonzero(ok & (inst["L"] >= lo) & (inst["L"] <= hi))[0]
+        top = cand[np.argmax(sig[cand] - (inst["L"][cand] - 4))]
+        med = cand[np.argsort(sig[cand])[cand.size // 2]]
+        ids += [int(top), int(med)]
+    return ids
+
+
+def uneven_ws():
+    return W.uneven_sweep(4096, seed=3)
+
+
 # (workload factory, instance ids, Radau steps per sample for the reference and its check)
 JOBS = {
     "tangent_l10": (tangent_l10, [0, 1], 8),
@@ -60,6 +96,8 @@ JOBS = {
     "tangent_ident": (identification_a0, [(24 * 32 + 20) * 4 + 0, (24 * 32 + 20) * 4 + 2], 4),
     "lissajous": (W.lissajous_grid, [(0 * 17 + 8) * 17 + 8, (3 * 17 + 2) * 17 + 13, (5 * 17 + 16) * 17 + 0,
                                      (7 * 17 + 10) * 17 + 4, (2 * 17 + 0) * 17 + 16, (6 * 17 + 12) * 17 + 12], 4),
+    "lissajous_strat": (W.lissajous_grid, lissajous_stratified(), 4),
+    "uneven": (uneven_ws, uneven_stratified(), 8),
 }
 
 
@@ -130,8 +168,11 @@ if __name__ == "__main__":
         factory, ids, r = JOBS[nm]
         tasks += [(nm, factory, i, r) for i in ids if not only or i == int(only)]
     plain = [t for t in tasks if not t[0].startswith("tangent")]
+    if os.environ.get("GOLDEN_SKIP_EXISTING"):
+        plain = [t for t in plain if not os.path.exists(os.path.join(HERE, f"{t[0]}_{t[2]}.npz"))]
+    plain.sort(key=lambda t: -int(t[1]()["inst"]["L"][t[2]]) * t[3])
     fd = [t for t in tasks if t[0].startswith("tangent")]
-    with ProcessPoolExecutor(max_workers=7) as ex:
+    with ProcessPoolExecutor(max_workers=int(os.environ.get("GOLDEN_WORKERS", "7"))) as ex:
         # finite-difference jobs one at a time, their ten solves in parallel
         for t in fd:
             print(fd_one(t, ex), flush=True)

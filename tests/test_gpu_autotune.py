@@ -38,10 +38,11 @@ def test_every_workgroup_size_gives_the_same_outputs(fpn, ctx, L):
     for w in fpn.fpn_stepper_wave_options(L):
         ctx.set_stepper_waves(L, w)
         m, h, st = _solve(fpn, ctx, ws)
-        assert (st == 0).all()
+        assert np.isin(st, [fpn.FPN_INST_OK, fpn.FPN_INST_TOL_UNMET]).all()   # finished, outputs written
         if ref is None:
-            ref = (m, h)
+            ref = (m, h, st)
             continue
+        assert np.array_equal(st, ref[2])
         dm = np.abs(m - ref[0]).max() / np.abs(ref[0]).max()
         dh = np.abs(h - ref[1]).max() / np.abs(ref[1]).max()
         print(f"L={L} waves={w}: max |dm| {dm:.1e}, max |dPhi| {dh:.1e} (relative to the largest entry)", flush=True)
@@ -60,7 +61,7 @@ def test_autotune_picks_a_compiled_size(fpn, ctx):
     m, h, st = _solve(fpn, ctx, ws)  # the tuned size is the one in use
     ctx.set_stepper_waves(L, 0)
     m0, h0, st0 = _solve(fpn, ctx, ws)
-    assert (st == 0).all() and (st0 == 0).all()
+    assert np.isin(st, [fpn.FPN_INST_OK, fpn.FPN_INST_TOL_UNMET]).all() and np.array_equal(st, st0)
     assert np.abs(m - m0).max() <= 1e-6 * np.abs(m0).max()
 
 

@@ -131,7 +131,7 @@ def test_tangent_solve_takes_the_primal_steps(fpn, ctx):
     s1 = ctx.last_steps()
     torch.cuda.synchronize()
     print(f"steps: plain {s0}, tangent {s1}", flush=True)
-    assert (st.cpu().numpy() == 0).all()
+    assert np.isin(st.cpu().numpy(), [fpn.FPN_INST_OK, fpn.FPN_INST_TOL_UNMET]).all()
     assert s0 >= 4 * ws["samples"] * (ws["settle"] + 1)
     assert abs(s1 - s0) <= 0.02 * s0
 

@@ -26,10 +26,10 @@ def rel(a, b):
 
 
 def test_overflowing_attempts_are_retried():
-    """Every instance finishes, two of the oracle's instances are within 1e-5.  The third (component 2,
-    sigma = 11, in the strongest field of the grid: offset (12, 12) mT) is within 5e-5: 1.0e-5 on m and
-    3.3e-5 on Phi, the same (9.8e-6, 3.1e-5) with a 10x tighter step tolerance, so that is the FP32
-    floor of the unpivoted block elimination for this operator, not a step-control error."""
+    """Every instance finishes and the oracle's three instances are within 1e-5.  The third (component 2,
+    sigma = 11, in the strongest field of the grid: offset (12, 12) mT) was at 3.3e-5 on Phi while the
+    Schur blocks were inverted without pivoting (growth factor ~5e3 at a step one sample spacing long);
+    with partial pivoting it meets the same bound as the others."""
     import torch
 
     import paper_2106_08040_amd as fpn
@@ -55,7 +55,6 @@ def test_overflowing_attempts_are_retried():
     assert np.linalg.norm(m, axis=1).max() <= 1.0 + 1e-3
     if not files:
         pytest.skip("no golden files (run tests/golden/make_golden.py identification_a0)")
-    floor_case = (31 * 32 + 31) * 4 + 2
     for k, f in enumerate(files):
         g = np.load(f)
         j = len(idx) - len(gold) + k
@@ -64,16 +63,20 @@ def test_overflowing_attempts_are_retried():
         assert g["err_est"] < 3e-6
         em, eh = rel(m[j].T, g["m"]), rel(h[j].T, g["Phi"][:, :2])
         print(f"identification inst {gold[k]}: m {em:.2e} Phi {eh:.2e}", flush=True)
-        bound = 5e-5 if gold[k] == floor_case else 1e-5
-        assert em < bound and eh < bound
+        assert em < 1e-5 and eh < 1e-5
 
 
 def test_hard_particles_finish_in_bounded_steps():
+    """The L = 24 particles of the uneven sweep (sigma up to 67: above 20 no degree up to 24 resolves
+    them) on a short three-axis drive: every instance ends OK, TOL_UNMET or UNRESOLVED; those that run
+    to the end take a bounded number of steps per sample interval and have |m| <= 1 + 1e-3; the
+    unresolvable ones are flagged, not returned as OK."""
     import torch
 
     import paper_2106_08040_amd as fpn
     ws = W.uneven_sweep(4096, seed=3)
     sub = W.take(ws, np.nonzero(ws["inst"]["L"] == 24)[0])
+    ok_rule = W.resolvable(sub["inst"]["D"], sub["inst"]["K"], sub["inst"]["L"])
     ctx = fpn.Context(0)
     try:
         T = 40e-6
@@ -88,11 +91,12 @@ def test_hard_particles_finish_in_bounded_steps():
         p.close()
     finally:
         ctx.close()
-    print(f"{len(per_interval)} particles: steps per sample interval mean {per_interval.mean():.1f}, "
-          f"max {per_interval.max():.1f}", flush=True)
-    assert (status == 0).all() and np.isfinite(m).all()
-    # Accuracy is not what this test checks: with the stability-based degree rule (L = ceil(sigma) + 4)
-    # and fields up to ~27 mT these densities are not resolved at L = 24, and the FP64 oracle itself
-    # gives |m| up to 1.9 for some of them (the truncated expansion is not a positive density).
+    done = (status == fpn.FPN_INST_OK) | (status == fpn.FPN_INST_TOL_UNMET)
+    print(f"{len(status)} particles ({ok_rule.sum()} resolvable by the degree rule): status "
+          f"{dict(zip(*np.unique(status, return_counts=True)))}; finished: steps per sample interval mean "
+          f"{per_interval[done].mean():.1f}, max {per_interval[done].max():.1f}", flush=True)
+    assert np.isin(status, [fpn.FPN_INST_OK, fpn.FPN_INST_TOL_UNMET, fpn.FPN_INST_UNRESOLVED]).all()
+    assert np.isfinite(m[done]).all() and np.isnan(m[~done]).all()
+    assert np.linalg.norm(m[done], axis=1).max() <= 1.0 + 1e-3
     # the smallest step is 1/64 of the sample spacing; rejections may add to that, not multiply it
-    assert per_interval.max() <= 128 and per_interval.mean() <= 64
+    assert per_interval[done].max() <= 128 and per_interval[done].mean() <= 64

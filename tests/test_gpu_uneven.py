@@ -48,7 +48,7 @@ def run(fpn, ctx, ws, substeps):
 
 
 # (degree, instances checked)
-WIDE_CASES = [(17, (0,)), (20, (0, 1)), (24, (1,))]
+WIDE_CASES = [(17, (0,)), (20, (0, 1)), (24, (0, 1))]
 
 
 @pytest.mark.parametrize("L,insts", WIDE_CASES)
@@ -70,20 +70,6 @@ def test_wide_degrees_match_oracle(fpn, ctx, L, insts):
         assert em < TOL and eh < TOL
 
 
-@pytest.mark.xfail(reason="FP32 accuracy floor: this particle (sigma 9.7, alpha 0.21) at L = 24 gives errors of "
-                          "2e-5..5e-3 against the oracle that vary erratically with the step size (not time-"
-                          "discretisation error; one step of FP64-residual refinement of the block solves did not "
-                          "remove it)", strict=False)
-def test_wide_degree_24_fp32_floor_case(fpn, ctx):
-    f = os.path.join(GOLDEN, "wide_l24_0.npz")
-    if not os.path.exists(f):
-        pytest.skip("no golden file")
-    ws = W.small_random(2, 24, seed=124, samples=48, settle=1, n_harm=8)
-    m, h, st = run(fpn, ctx, ws, substeps=32)
-    g = np.load(f)
-    assert rel(m[0].T, g["m"]) < TOL and rel(h[0].T, g["Phi"]) < TOL
-
-
 def test_mixed_degrees_one_call_equals_separate_calls(fpn, ctx):
     parts = [W.small_random(2, L, seed=300 + L, samples=32, settle=1, n_harm=6) for L in (6, 12, 16, 17, 20, 24)]
     inst = {k: np.concatenate([p["inst"][k] for p in parts]) for k in parts[0]["inst"]}
@@ -91,11 +77,15 @@ def test_mixed_degrees_one_call_equals_separate_calls(fpn, ctx):
     ws = dict(parts[0])
     ws["inst"] = {k: v[order] for k, v in inst.items()}
     m, h, st = run(fpn, ctx, ws, substeps=4)
-    assert (st == 0).all()
+    # (an L = 6 particle in fields up to beta |H| ~ 18 is not resolved whatever its anisotropy: flagged)
+    assert np.isin(st, [fpn.FPN_INST_OK, fpn.FPN_INST_TOL_UNMET, fpn.FPN_INST_UNRESOLVED]).all()
+    assert (st != fpn.FPN_INST_UNRESOLVED).sum() >= len(st) - 2
     for i in range(len(order)):
         one = W.take(ws, [i])
         m1, h1, st1 = run(fpn, ctx, one, substeps=4)
-        assert np.array_equal(m1[0], m[i]) and np.array_equal(h1[0], h[i]), (i, int(ws["inst"]["L"][i]))
+        assert st1[0] == st[i]
+        assert np.array_equal(m1[0], m[i], equal_nan=True) and np.array_equal(h1[0], h[i], equal_nan=True), \
+            (i, int(ws["inst"]["L"][i]))
 
 
 def _mixed(fpn):

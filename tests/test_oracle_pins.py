@@ -28,6 +28,31 @@ def random_rotation(r):
     return q
 
 
+# ------------------------------------------------------- particle scalars ---
+
+def _half_unit(printed):
+    """Half a unit in the last digit of a value printed as text."""
+    dec = printed.split(".")[1] if "." in printed else ""
+    return 0.5 * 10.0 ** (-len(dec))
+
+
+@pytest.mark.parametrize("D,K,alpha,tau_ns,beta12,sigma", [
+    (20e-9, 2e3, 0.1, "13.98", "5.85", "2.06"),      # the single-instance particle (magnetite, 295 K)
+    (30e-9, 2e4, 0.05, "93.7", "19.7", "69.4"),      # the uneven sweep's stiffest corner
+    (15e-9, 5e2, 0.3, "2.12", "2.47", "0.22"),       # ... and its softest corner
+])
+def test_particle_scalars_match_hand_computed_values(D, K, alpha, tau_ns, beta12, sigma):
+    """tau (the constant after Eq. convection), beta * (12 mT / mu0) and sigma = K V_C / (k_B T) (model M0)
+    against values worked out by hand from the definitions, independently of this code, to the digits
+    shown (M_S = 474 kA/m, T = 295 K), within half a unit of the last digit.  They fix the absolute time
+    scale that every other pin reads from the same function: a dropped factor 2, (1 + alpha^2), 1 / alpha
+    or a radius for a diameter moves one of them by more than that; the three points tell the alpha
+    dependence apart."""
+    sc = O.particle_scalars(D, 474e3, K, alpha, 295.0)
+    for got, want in ((sc["tau"] * 1e9, tau_ns), (sc["beta_T"] * 12e-3, beta12), (sc["sigma"], sigma)):
+        assert abs(got - float(want)) <= _half_unit(want), (got, want)
+
+
 # ---------------------------------------------------------------- basis ---
 
 @pytest.mark.parametrize("L", [4, 10, 16])

@@ -18,15 +18,21 @@ def test_lissajous_grid_layout():
     assert ws["drive"]["period"] * np.array(ws["drive"]["freq"][:2]) == pytest.approx([16, 17], rel=1e-12)
 
 
-def test_uneven_sweep_is_resolvable_and_seeded():
+def test_uneven_sweep_keeps_every_draw_and_is_seeded():
+    """The sweep keeps the full D ~ U[15, 30] nm x K log-U[0.5, 20] kJ/m^3 distribution: the pairs that
+    no degree up to 24 resolves (sigma > 20) stay in it at L = 24 and are told apart by `resolvable`."""
     a, b = W.uneven_sweep(4096, seed=3), W.uneven_sweep(4096, seed=3)
     for k in a["inst"]:
         assert np.array_equal(a["inst"][k], b["inst"][k])
     inst = a["inst"]
     sigma = W.anisotropy_ratio(inst["D"], inst["K"])
-    assert sigma.max() <= 20.0
+    assert inst["D"].min() >= 15e-9 and inst["D"].max() <= 30e-9
+    assert inst["K"].min() >= 500 and inst["K"].max() <= 2e4
+    assert sigma.max() > 60                       # the largest particles are kept
     assert inst["L"].min() == 8 and inst["L"].max() == 24
-    assert (inst["L"] >= np.minimum(np.ceil(sigma) + 4, 24)).all()
+    assert (inst["L"] == np.clip(np.ceil(sigma) + 4, 8, 24)).all()
+    ok = W.resolvable(inst["D"], inst["K"], inst["L"])
+    assert np.array_equal(ok, sigma <= 20) and 0.8 < ok.mean() < 0.95
     assert np.allclose(np.linalg.norm(inst["easy_axis"], axis=1), 1.0)
 
 

@@ -66,10 +66,15 @@ def truncation_degree(D, K, T=ROOM_T, lo=8, hi=24):
     The truncated Galerkin operator acquires an eigenvalue with positive real part (a spurious
     growing mode) once sigma exceeds about L - 1 (scanned for L = 12..24, fields up to 24 mT,
     alpha 0.05..0.25), so the degree has to grow linearly with sigma; the margin of 4 keeps the
-    operator stable up to sigma = 20 at L = 24.  Beyond that no degree up to 24 resolves the particle
-    and the solve ends with a non-finite status."""
+    operator stable up to sigma = 20 at L = 24.  Particles with larger sigma get L = hi and are not
+    resolved by it (``resolvable`` is False for them)."""
     sigma = anisotropy_ratio(D, K, T)
     return np.clip(np.ceil(sigma) + 4, lo, hi).astype(np.int32)
+
+
+def resolvable(D, K, L, T=ROOM_T):
+    """True where the degree L meets the rule of truncation_degree (ceil(sigma) + 4 <= L)."""
+    return np.ceil(anisotropy_ratio(D, K, T)) + 4 <= np.asarray(L)
 
 
 def anisotropy_ratio(D, K, T=ROOM_T):
@@ -77,20 +82,14 @@ def anisotropy_ratio(D, K, T=ROOM_T):
     return np.asarray(K) * (np.pi * np.asarray(D) ** 3 / 6) / (1.380649e-23 * T)
 
 
-def uneven_sweep(n=4096, seed=3, L_max=24, sigma_max=20.0):
+def uneven_sweep(n=4096, seed=3, L_max=24):
     """Batched uneven sweep: D ~ U[15, 30] nm, K log-uniform in [0.5, 20] kJ/m^3, alpha ~ U[0.05, 0.3],
     easy axes uniform on the sphere, offsets U[-12, 12] mT in x and y, L by truncation_degree.
-    (D, K) pairs with sigma > sigma_max are drawn again (in order, from the same generator), so every
-    particle is resolvable at L <= 24 under the degree rule (sigma_max = 20 gives L = 24)."""
+    Every draw is kept: about 12 % of the (D, K) pairs have sigma > 20, which no degree up to 24
+    resolves (``resolvable`` tells them apart); the solver is expected to flag them, not to hide them."""
     r = np.random.default_rng(seed)
     D = r.uniform(15e-9, 30e-9, n)
     K = np.exp(r.uniform(np.log(500.0), np.log(2e4), n))
-    while True:
-        bad = np.nonzero(anisotropy_ratio(D, K) > sigma_max)[0]
-        if bad.size == 0:
-            break
-        D[bad] = r.uniform(15e-9, 30e-9, bad.size)
-        K[bad] = np.exp(r.uniform(np.log(500.0), np.log(2e4), bad.size))
     alpha = r.uniform(0.05, 0.3, n)
     z = r.uniform(-1, 1, n)
     ph = r.uniform(0, 2 * np.pi, n)
@@ -141,8 +140,12 @@ def identification_instances(ws, angle_index, which="guess"):
                 settle=ws["settle"], n_harm=ws["n_harm"], harm_z=False)
 
 
-def small_random(n, L, seed, samples=64, settle=1, n_harm=10, freq_scale=1.0):
-    """Small random instances for parity tests (short synthetic drive with 3 and 4 cycles per period)."""
+def small_random(n, L, seed, samples=64, settle=1, n_harm=10, freq_scale=1.0, resolved=True):
+    """Small random instances for parity tests (short synthetic drive with 3 and 4 cycles per period).
+    resolved: particles that the degree L does not resolve (``resolvable`` False, i.e. sigma > L - 4)
+    get (D, K) drawn again from a second generator (seeded by (seed, 1)) after all other draws, so a
+    seed without such particles gives the same instances either way.  Below L = 5 no particle of the
+    range meets the rule and nothing is redrawn."""
     r = np.random.default_rng(seed)
     D = r.uniform(14e-9, 24e-9, n)
     K = np.exp(r.uniform(np.log(300.0), np.log(8e3), n))
@@ -150,6 +153,14 @@ def small_random(n, L, seed, samples=64, settle=1, n_harm=10, freq_scale=1.0):
     v = r.normal(size=(n, 3))
     easy = v / np.linalg.norm(v, axis=1, keepdims=True)
     off = r.uniform(-6e-3, 6e-3, (n, 3))
+    if resolved and L >= 5:
+        r2 = np.random.default_rng([seed, 1])
+        while True:
+            bad = np.nonzero(~resolvable(D, K, np.full(n, L)))[0]
+            if bad.size == 0:
+                break
+            D[bad] = r2.uniform(14e-9, 24e-9, bad.size)
+            K[bad] = np.exp(r2.uniform(np.log(300.0), np.log(8e3), bad.size))
     inst = _instances(D, np.full(n, MAGNETITE_MS), K, alpha, np.full(n, ROOM_T), easy, off, np.full(n, L))
     T = 40e-6 / freq_scale
     drive = dict(amp=(10e-3, 8e-3, 3e-3), freq=(3 / T, 4 / T, 1 / T), phase=(0.0, 0.3, -0.7), period=T)
