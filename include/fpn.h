@@ -328,6 +328,25 @@ fpn_status fpn_surrogate_predict(fpn_ctx ctx, const fpn_surrogate* sur, double t
                                  float* err_out, int32_t* used_solver, int32_t* status, int64_t* n_fallback,
                                  void* stream);
 
+/* ---- allocation-free solve ----
+ * For callers that cannot allocate device memory: code under HIP graph capture, tight serving loops,
+ * harnesses that forbid hipMalloc.  The same solve as fpn_solve for a batch of ONE Galerkin degree
+ * L <= 16, with no device (or host-side library) allocation: every per-call buffer lives in a fixed
+ * device array of the library, FPN_STATIC_SCRATCH_BYTES on each GPU the library runs on, held until
+ * the process ends.  Hence n <= FPN_STATIC_MAX_N and samples_per_period <= FPN_STATIC_MAX_NS, else
+ * FPN_E_RANGE; all batch.L[i] equal, else FPN_E_ARG; FPN_OUT_DMDT is not available (FPN_E_ARG).
+ * The context must already hold the operator tables of that L and the twiddle table of that N_s,
+ * which an earlier fpn_solve on the context with the same L and N_s builds; otherwise FPN_E_ARG.
+ * All calls on one GPU share the array (whatever the context or stream), and it keeps the last call's
+ * contents: calls that overlap on one GPU race, so serialise them.  Asynchronous on `stream`;
+ * outputs, statuses and the other errors as fpn_solve. */
+#define FPN_STATIC_MAX_N 128
+#define FPN_STATIC_MAX_NS 2048
+#define FPN_STATIC_SCRATCH_BYTES (12u << 20)
+fpn_status fpn_solve_static(fpn_ctx ctx, const fpn_drive* drive, const fpn_solve_opts* opts,
+                            const fpn_batch* batch, int64_t n, float* m_out, float* harm_out, int32_t* status,
+                            void* stream);
+
 /* ---- host-only helpers (no device needed; used to check the operator build) ---- */
 
 /* Dense Galerkin operator A (1/s) of one particle in its easy-axis frame, built

@@ -31,6 +31,7 @@ FPN_INST_OK, FPN_INST_BAD_PARAM, FPN_INST_NONFINITE, FPN_INST_SINGULAR, FPN_INST
     0, 1, 2, 3, 4, 5
 FPN_OUT_M, FPN_OUT_HARM, FPN_HARM_Z, FPN_OUT_DMDT = 1, 2, 4, 8
 FPN_MAX_L = 24
+FPN_STATIC_MAX_N, FPN_STATIC_MAX_NS = 128, 2048
 FPN_NPARAM = 5  # sensitivities: D, K, alpha, easy-axis polar angle, azimuth
 
 EXPORTED = ["fpn_status_string", "fpn_last_error", "fpn_create", "fpn_destroy", "fpn_solve",
@@ -39,7 +40,8 @@ EXPORTED = ["fpn_status_string", "fpn_last_error", "fpn_create", "fpn_destroy", 
             "fpn_mlp_set_input_norm", "fpn_mlp_forward", "fpn_mlp_gradient", "fpn_mlp_train_step",
             "fpn_surrogate_features", "fpn_surrogate_predict", "fpn_plan_create", "fpn_plan_launch",
             "fpn_plan_graph_launch", "fpn_plan_steps", "fpn_plan_destroy", "fpn_solve_tangent", "fpn_adjoint",
-            "fpn_stepper_wave_options", "fpn_set_stepper_waves", "fpn_autotune", "fpn_equilibrium"]
+            "fpn_stepper_wave_options", "fpn_set_stepper_waves", "fpn_autotune", "fpn_equilibrium",
+            "fpn_solve_static"]
 
 
 class fpn_drive(ctypes.Structure):
@@ -71,6 +73,9 @@ _lib.fpn_destroy.argtypes = [_vp]
 _lib.fpn_solve.restype = ctypes.c_int32
 _lib.fpn_solve.argtypes = [_vp, ctypes.POINTER(fpn_drive), ctypes.POINTER(fpn_solve_opts),
                            ctypes.POINTER(fpn_batch), ctypes.c_int64, _vp, _vp, _vp, _vp, _vp]
+_lib.fpn_solve_static.restype = ctypes.c_int32
+_lib.fpn_solve_static.argtypes = [_vp, ctypes.POINTER(fpn_drive), ctypes.POINTER(fpn_solve_opts),
+                                  ctypes.POINTER(fpn_batch), ctypes.c_int64, _vp, _vp, _vp, _vp]
 _lib.fpn_equilibrium.restype = ctypes.c_int32
 _lib.fpn_equilibrium.argtypes = [_vp, ctypes.POINTER(fpn_drive), ctypes.POINTER(fpn_solve_opts),
                                  ctypes.POINTER(fpn_batch), ctypes.c_int64, _vp, _vp, _vp, _vp]
@@ -291,6 +296,37 @@ class Context:
         self._keep = (keep, Lh)  # inputs alive until the next call on this context
         harm = torch.view_as_complex(hm) if hm is not None else None
         return (m, harm, st, dd) if want_dmdt else (m, harm, st)
+
+    def solve_static(self, inst, L, drive, samples, settle, n_harm, substeps=0, want_m=True, want_harm=True,
+                     harm_z=False, stream=None, out=None, tol=0.0):
+        """fpn_solve_static (no device allocation inside the library; one degree L <= 16, at most
+        FPN_STATIC_MAX_N instances): (m, harm, status) as fpn_solve.  Pass `out` (dict of preallocated
+        tensors "m", "harm" [n,ch,Kh+1,2] float32, "status") to allocate nothing on this side either."""
+        torch = _torch()
+        dev = f"cuda:{self.device}"
+        b, keep, Lh = self._batch(inst, L)
+        n = keep["D"].numel()
+        ch = 3 if harm_z else 2
+        out = out or {}
+        m = out.get("m") if want_m else None
+        if want_m and m is None:
+            m = torch.empty((n, 3, samples), dtype=torch.float32, device=dev)
+        hm = out.get("harm") if want_harm else None
+        if want_harm and hm is None:
+            hm = torch.empty((n, ch, n_harm + 1, 2), dtype=torch.float32, device=dev)
+        st = out.get("status")
+        if st is None:
+            st = torch.empty((n,), dtype=torch.int32, device=dev)
+        opts = fpn_solve_opts(samples, settle, n_harm, substeps,
+                              (FPN_OUT_M if want_m else 0) | (FPN_OUT_HARM if want_harm else 0) |
+                              (FPN_HARM_Z if harm_z else 0), float(tol))
+        s = stream if stream is not None else torch.cuda.current_stream(self.device)
+        code = _lib.fpn_solve_static(self._h, ctypes.byref(drive), ctypes.byref(opts), ctypes.byref(b), n,
+                                     m.data_ptr() if m is not None else None,
+                                     hm.data_ptr() if hm is not None else None, st.data_ptr(), s.cuda_stream)
+        _check(code, "fpn_solve_static")
+        self._keep = (keep, Lh)
+        return m, (torch.view_as_complex(hm) if hm is not None else None), st
 
     def equilibrium(self, inst, drive, samples, settle, n_harm, want_m=True, harm_z=False, stream=None):
         """fpn_equilibrium (model M0): (m [n,3,Ns] float32 or None, harm [n,ch,Kh+1] complex64, status)."""

@@ -64,6 +64,7 @@ def build(jobs=8, verbose=False, out=None, build_dir=None, extra=()):
         [HIPCC, *HIP_FLAGS, "-c", os.path.join(CSRC, "surrogate.hip"), "-o", os.path.join(BUILD, "surrogate.o")],
         [HIPCC, *HIP_FLAGS, "-c", os.path.join(CSRC, "capi_surrogate.hip"), "-o",
          os.path.join(BUILD, "capi_surrogate.o")],
+        [HIPCC, *HIP_FLAGS, "-c", os.path.join(CSRC, "capi_static.hip"), "-o", os.path.join(BUILD, "capi_static.o")],
         ["g++", "-O2", "-std=c++17", "-fPIC", "-c", os.path.join(CSRC, "structure.cpp"),
          "-o", os.path.join(BUILD, "structure.o")],
     ]
@@ -80,6 +81,7 @@ def build(jobs=8, verbose=False, out=None, build_dir=None, extra=()):
           os.path.join(BUILD, "kernels.o"), os.path.join(BUILD, "capi.o"), os.path.join(BUILD, "structure.o"),
           os.path.join(BUILD, "mlp.o"), os.path.join(BUILD, "capi_mlp.o"),
           os.path.join(BUILD, "surrogate.o"), os.path.join(BUILD, "capi_surrogate.o"),
+          os.path.join(BUILD, "capi_static.o"),
           f"-L{hiplib}", "-l:libamdhip64.so", f"-Wl,-rpath,{hiplib}:/opt/rocm/lib", "-lstdc++"])
     os.replace(tmp, LIB)
     return LIB

@@ -313,6 +313,7 @@ fpn_status fpn_create(fpn_ctx* out, int device) {
   int count = 0;
   FPN_HIP(hipGetDeviceCount(&count));
   if (device < 0 || device >= count) return fail(FPN_E_ARG, "device index out of range");
+  if (fpn_status s = fpn_internal::static_scratch_init(device)) return s;
   auto* c = new fpn_ctx_s();
   c->device = device;
   *out = c;
@@ -651,6 +652,15 @@ fpn_status check_outputs(const fpn_solve_opts* opts, float* m_out, float* harm_o
 }
 
 }  // namespace
+
+namespace fpn_internal {
+fpn_status validate_solve_opts(const fpn_drive* drive, const fpn_solve_opts* opts) { return validate_opts(drive, opts); }
+fpn_status validate_solve_batch(const fpn_batch* batch, int64_t n) { return validate_batch(batch, n); }
+fpn_status validate_solve_outputs(const fpn_solve_opts* opts, float* m_out, float* harm_out, int32_t* status,
+                                  int64_t n) {
+  return check_outputs(opts, m_out, harm_out, status, n);
+}
+}  // namespace fpn_internal
 
 extern "C" {
 

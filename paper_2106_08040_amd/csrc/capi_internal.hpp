@@ -15,6 +15,13 @@
 namespace fpn_internal {
 
 fpn_status fail(fpn_status s, const std::string& msg);
+// argument checks of fpn_solve, shared with fpn_solve_static
+fpn_status validate_solve_opts(const fpn_drive* drive, const fpn_solve_opts* opts);
+fpn_status validate_solve_batch(const fpn_batch* batch, int64_t n);
+fpn_status validate_solve_outputs(const fpn_solve_opts* opts, float* m_out, float* harm_out, int32_t* status,
+                                  int64_t n);
+// looks up the device address of fpn_solve_static's scratch array on `device` (once per device)
+fpn_status static_scratch_init(int device);
 
 #define FPN_HIP(call)                                                                      \
   do {                                                                                     \
