@@ -41,7 +41,8 @@ enum {
   FPN_E_RANGE = -2,        /* value out of the supported range (e.g. L) */
   FPN_E_DEVICE = -3,       /* HIP runtime error */
   FPN_E_NOMEM = -4,        /* device allocation failed */
-  FPN_E_UNSUPPORTED = -7   /* valid request the library does not implement */
+  FPN_E_UNSUPPORTED = -7,  /* valid request the library does not implement */
+  FPN_E_IO = -8            /* a file could not be read or written, or is not a valid model file */
 };
 
 /* per-instance status codes written to `status[i]` */
@@ -282,6 +283,8 @@ fpn_status fpn_mlp_create(fpn_ctx ctx, int32_t n_layers, const int32_t* widths, 
 fpn_status fpn_mlp_destroy(fpn_mlp m);
 /* number of FP32 parameters (-1 for NULL) */
 int64_t fpn_mlp_num_params(fpn_mlp m);
+/* Layer count (HOST int32) and, when widths is not NULL, widths[0..n_layers] (HOST, capacity >= 17). */
+fpn_status fpn_mlp_shape(fpn_mlp m, int32_t* n_layers, int32_t* widths);
 /* Copy the parameters out to `dst` and/or in from `src` (DEVICE, flat layout above; either may
  * be NULL).  Asynchronous on `stream`. */
 fpn_status fpn_mlp_params(fpn_mlp m, float* dst, const float* src, void* stream);
@@ -327,6 +330,54 @@ fpn_status fpn_surrogate_predict(fpn_ctx ctx, const fpn_surrogate* sur, double t
                                  const fpn_solve_opts* opts, const fpn_batch* batch, int64_t n, float* harm_out,
                                  float* err_out, int32_t* used_solver, int32_t* status, int64_t* n_fallback,
                                  void* stream);
+
+/* ---- surrogate model ----
+ * An owning handle for a two-member ensemble (the fpn_surrogate above): both networks, the output
+ * scale and the error calibration, so a trained surrogate can be written to a file and read back
+ * (in this or another process, on any device).  Calls on one model must not overlap.
+ *
+ * File format (little-endian, written by fpn_surrogate_save):
+ *   char magic[8] = "FPNSUR1\0"; uint32 version = 1; int32 n_layers; int32 widths[n_layers + 1];
+ *   float out_scale; float err_calib;
+ *   then for each member k = 0, 1: int64 adam_steps; float norm[2 * widths[0]] (input mean, then
+ *   1 / std, as the network applies them); float params[P]; float adam_m[P]; float adam_v[P]
+ *   (P = sum over layers of (in + 1) * out, layout as fpn_mlp_params);
+ *   uint64 FNV-1a hash of every preceding byte.
+ * A model read back evaluates bit for bit as the one saved, and continues training from the same
+ * Adam state. */
+typedef struct fpn_sur_model_s* fpn_sur_model;
+
+/* A new model: two networks of widths[0..n_layers] (as fpn_mlp_create), member k initialised from
+ * seeds[k] (HOST), out_scale = err_calib = 1.  Errors: FPN_E_ARG, FPN_E_NOMEM, FPN_E_DEVICE. */
+fpn_status fpn_surrogate_init(fpn_ctx ctx, int32_t n_layers, const int32_t* widths, const uint64_t seeds[2],
+                              fpn_sur_model* out);
+/* A model read from `weights_path` (a file written by fpn_surrogate_save), on ctx's device.
+ * Errors: FPN_E_ARG (NULL argument), FPN_E_IO (unreadable, not a model file, truncated, hash
+ * mismatch, trailing bytes), FPN_E_NOMEM, FPN_E_DEVICE. */
+fpn_status fpn_surrogate_create(fpn_ctx ctx, const char* weights_path, fpn_sur_model* out);
+/* Write the model to `path` (synchronises the device).  Errors: FPN_E_ARG, FPN_E_IO, FPN_E_DEVICE. */
+fpn_status fpn_surrogate_save(fpn_sur_model m, const char* path);
+fpn_status fpn_surrogate_destroy(fpn_sur_model m);
+/* Member k (0 or 1) as an fpn_mlp handle owned by the model (for fpn_mlp_* calls: input
+ * normalisation, parameters, per-member training). */
+fpn_status fpn_surrogate_member(fpn_sur_model m, int32_t k, fpn_mlp* out);
+/* out_scale: network output = prediction * out_scale; err_calib: the estimate's constant.  Both finite
+ * and > 0, else FPN_E_ARG. */
+fpn_status fpn_surrogate_set_scales(fpn_sur_model m, float out_scale, float err_calib);
+/* Fill an fpn_surrogate (non-owning view: member handles and scales) for fpn_surrogate_predict. */
+fpn_status fpn_surrogate_view(fpn_sur_model m, fpn_surrogate* view);
+/* Ensemble evaluation without fallback: y [n][W] = (y_a + y_b) / 2 / out_scale (W = output width, the
+ * networks' layout) and err_est [n] = err_calib * ||y_a - y_b|| / ||(y_a + y_b) / 2||, from features
+ * x [n][widths[0]] (all DEVICE FP32; y or err_est may be NULL, not both).  n <= 2^30.  Asynchronous.
+ * Errors: FPN_E_ARG, FPN_E_NOMEM, FPN_E_DEVICE. */
+fpn_status fpn_surrogate_infer(fpn_ctx ctx, fpn_sur_model m, const float* x, int64_t n, float* y, float* err_est,
+                               void* stream);
+/* One Adam step (fpn_mlp_train_step) of each member on the same minibatch: features x [n][widths[0]],
+ * targets y_true [n][W] in prediction units (multiplied by out_scale inside); loss_out (DEVICE, two
+ * doubles, may be NULL) receives each member's summed squared error in network units.  1 <= n <= 2^22.
+ * Asynchronous.  Errors: FPN_E_ARG, FPN_E_NOMEM, FPN_E_DEVICE. */
+fpn_status fpn_surrogate_train_step(fpn_ctx ctx, fpn_sur_model m, const float* x, const float* y_true, int64_t n,
+                                    float lr, double* loss_out, void* stream);
 
 /* ---- allocation-free solve ----
  * For callers that cannot allocate device memory: code under HIP graph capture, tight serving loops,

@@ -26,7 +26,7 @@ except ImportError:  # host-only helpers still work without torch
 
 _lib = ctypes.CDLL(LIB_PATH)
 
-FPN_OK, FPN_E_ARG, FPN_E_RANGE, FPN_E_DEVICE, FPN_E_NOMEM, FPN_E_UNSUPPORTED = 0, -1, -2, -3, -4, -7
+FPN_OK, FPN_E_ARG, FPN_E_RANGE, FPN_E_DEVICE, FPN_E_NOMEM, FPN_E_UNSUPPORTED, FPN_E_IO = 0, -1, -2, -3, -4, -7, -8
 FPN_INST_OK, FPN_INST_BAD_PARAM, FPN_INST_NONFINITE, FPN_INST_SINGULAR, FPN_INST_UNRESOLVED, FPN_INST_TOL_UNMET = \
     0, 1, 2, 3, 4, 5
 FPN_OUT_M, FPN_OUT_HARM, FPN_HARM_Z, FPN_OUT_DMDT = 1, 2, 4, 8
@@ -41,7 +41,9 @@ EXPORTED = ["fpn_status_string", "fpn_last_error", "fpn_create", "fpn_destroy", 
             "fpn_surrogate_features", "fpn_surrogate_predict", "fpn_plan_create", "fpn_plan_launch",
             "fpn_plan_graph_launch", "fpn_plan_steps", "fpn_plan_destroy", "fpn_solve_tangent", "fpn_adjoint",
             "fpn_stepper_wave_options", "fpn_set_stepper_waves", "fpn_autotune", "fpn_equilibrium",
-            "fpn_solve_static"]
+            "fpn_solve_static", "fpn_mlp_shape", "fpn_surrogate_init", "fpn_surrogate_create", "fpn_surrogate_save",
+            "fpn_surrogate_destroy", "fpn_surrogate_member", "fpn_surrogate_set_scales", "fpn_surrogate_view",
+            "fpn_surrogate_infer", "fpn_surrogate_train_step"]
 
 
 class fpn_drive(ctypes.Structure):
@@ -106,6 +108,8 @@ _lib.fpn_mlp_params.restype = ctypes.c_int32
 _lib.fpn_mlp_params.argtypes = [_vp, _vp, _vp, _vp]
 _lib.fpn_mlp_set_input_norm.restype = ctypes.c_int32
 _lib.fpn_mlp_set_input_norm.argtypes = [_vp, ctypes.POINTER(ctypes.c_float), ctypes.POINTER(ctypes.c_float)]
+_lib.fpn_mlp_shape.restype = ctypes.c_int32
+_lib.fpn_mlp_shape.argtypes = [_vp, ctypes.POINTER(ctypes.c_int32), ctypes.POINTER(ctypes.c_int32)]
 _lib.fpn_mlp_forward.restype = ctypes.c_int32
 _lib.fpn_mlp_forward.argtypes = [_vp, _vp, ctypes.c_int64, _vp, _vp]
 _lib.fpn_mlp_gradient.restype = ctypes.c_int32
@@ -146,6 +150,25 @@ class fpn_surrogate(ctypes.Structure):
 
 _lib.fpn_surrogate_features.restype = ctypes.c_int32
 _lib.fpn_surrogate_features.argtypes = [_vp, ctypes.POINTER(fpn_batch), ctypes.c_int64, _vp, _vp, _vp]
+_lib.fpn_surrogate_init.restype = ctypes.c_int32
+_lib.fpn_surrogate_init.argtypes = [_vp, ctypes.c_int32, ctypes.POINTER(ctypes.c_int32), ctypes.POINTER(ctypes.c_uint64),
+                                    ctypes.POINTER(_vp)]
+_lib.fpn_surrogate_create.restype = ctypes.c_int32
+_lib.fpn_surrogate_create.argtypes = [_vp, ctypes.c_char_p, ctypes.POINTER(_vp)]
+_lib.fpn_surrogate_save.restype = ctypes.c_int32
+_lib.fpn_surrogate_save.argtypes = [_vp, ctypes.c_char_p]
+_lib.fpn_surrogate_destroy.restype = ctypes.c_int32
+_lib.fpn_surrogate_destroy.argtypes = [_vp]
+_lib.fpn_surrogate_member.restype = ctypes.c_int32
+_lib.fpn_surrogate_member.argtypes = [_vp, ctypes.c_int32, ctypes.POINTER(_vp)]
+_lib.fpn_surrogate_set_scales.restype = ctypes.c_int32
+_lib.fpn_surrogate_set_scales.argtypes = [_vp, ctypes.c_float, ctypes.c_float]
+_lib.fpn_surrogate_view.restype = ctypes.c_int32
+_lib.fpn_surrogate_view.argtypes = [_vp, ctypes.POINTER(fpn_surrogate)]
+_lib.fpn_surrogate_infer.restype = ctypes.c_int32
+_lib.fpn_surrogate_infer.argtypes = [_vp, _vp, _vp, ctypes.c_int64, _vp, _vp, _vp]
+_lib.fpn_surrogate_train_step.restype = ctypes.c_int32
+_lib.fpn_surrogate_train_step.argtypes = [_vp, _vp, _vp, _vp, ctypes.c_int64, ctypes.c_float, _vp, _vp]
 _lib.fpn_surrogate_predict.restype = ctypes.c_int32
 _lib.fpn_surrogate_predict.argtypes = [_vp, ctypes.POINTER(fpn_surrogate), ctypes.c_double, ctypes.POINTER(fpn_drive),
                                        ctypes.POINTER(fpn_solve_opts), ctypes.POINTER(fpn_batch), ctypes.c_int64,
@@ -442,19 +465,15 @@ class Context:
         self._keep = (keep, Lh)
         return x, st
 
-    def surrogate_predict(self, nets, out_scale, err_calib, tol, inst, L, drive, samples, settle, n_harm,
-                          substeps=0, solver_tol=0.0):
-        """fpn_surrogate_predict: returns (harm [n,2,Kh+1] complex64, err [n], used_solver [n], status [n],
-        n_fallback)."""
+    def surrogate_predict(self, model, tol, inst, L, drive, samples, settle, n_harm, substeps=0, solver_tol=0.0):
+        """fpn_surrogate_predict with a SurrogateModel: returns (harm [n,2,Kh+1] complex64, err [n],
+        used_solver [n], status [n], n_fallback)."""
         torch = _torch()
         dev = f"cuda:{self.device}"
         b, keep, Lh = self._batch(inst, L)
         n = keep["D"].numel()
         sur = fpn_surrogate()
-        sur.net[0] = nets[0]._h
-        sur.net[1] = nets[1]._h
-        sur.out_scale = float(out_scale)
-        sur.err_calib = float(err_calib)
+        _check(_lib.fpn_surrogate_view(model._h, ctypes.byref(sur)), "fpn_surrogate_view")
         opts = fpn_solve_opts(samples, settle, n_harm, substeps, FPN_OUT_HARM, float(solver_tol))
         hm = torch.empty((n, 2, n_harm + 1, 2), dtype=torch.float32, device=dev)
         err = torch.empty((n,), dtype=torch.float32, device=dev)
@@ -491,21 +510,26 @@ def _f32(x, device):
 
 class MLP:
     """A surrogate network owned by the library (fpn_mlp_*): FP32 master parameters, BF16 matrix-core
-    products.  Parameters are exchanged as one flat FP32 tensor (per layer W [out, in], then b [out])."""
+    products.  Parameters are exchanged as one flat FP32 tensor (per layer W [out, in], then b [out]).
+    A member of a SurrogateModel is a borrowed handle (``handle`` given): the model frees it."""
 
-    def __init__(self, ctx, widths, seed=0):
+    def __init__(self, ctx, widths, seed=0, handle=None):
         self.ctx = ctx
         self.widths = [int(w) for w in widths]
+        self._owned = handle is None
         self._h = _vp()
-        w = (ctypes.c_int32 * len(self.widths))(*self.widths)
-        _check(_lib.fpn_mlp_create(ctx._h, len(self.widths) - 1, w, int(seed), ctypes.byref(self._h)),
-               "fpn_mlp_create")
+        if handle is not None:
+            self._h = handle
+        else:
+            w = (ctypes.c_int32 * len(self.widths))(*self.widths)
+            _check(_lib.fpn_mlp_create(ctx._h, len(self.widths) - 1, w, int(seed), ctypes.byref(self._h)),
+                   "fpn_mlp_create")
         self.n_params = int(_lib.fpn_mlp_num_params(self._h))
 
     def close(self):
-        if self._h:
+        if self._h and self._owned:
             _lib.fpn_mlp_destroy(self._h)
-            self._h = _vp()
+        self._h = _vp()
 
     def __del__(self):
         try:
@@ -571,6 +595,79 @@ class MLP:
         loss = loss_out if loss_out is not None else torch.empty(1, dtype=torch.float64, device=self._dev)
         _check(_lib.fpn_mlp_train_step(self._h, x.data_ptr(), t.data_ptr(), x.shape[0], float(lr), loss.data_ptr(),
                                        self._stream()), "fpn_mlp_train_step")
+        return loss
+
+
+class SurrogateModel:
+    """fpn_sur_model: a two-member ensemble with its output scale and error calibration, trainable,
+    evaluable and savable (fpn_surrogate_init / _create / _save / _infer / _train_step / _destroy)."""
+
+    def __init__(self, ctx, widths=None, seeds=(1, 2), path=None):
+        self.ctx = ctx
+        self._h = _vp()
+        if path is not None:
+            _check(_lib.fpn_surrogate_create(ctx._h, os.fsencode(path), ctypes.byref(self._h)), "fpn_surrogate_create")
+        else:
+            ws = [int(w) for w in widths]
+            w = (ctypes.c_int32 * len(ws))(*ws)
+            sd = (ctypes.c_uint64 * 2)(*[int(x) for x in seeds])
+            _check(_lib.fpn_surrogate_init(ctx._h, len(ws) - 1, w, sd, ctypes.byref(self._h)), "fpn_surrogate_init")
+        sur = fpn_surrogate()
+        _check(_lib.fpn_surrogate_view(self._h, ctypes.byref(sur)), "fpn_surrogate_view")
+        self.out_scale, self.err_calib = float(sur.out_scale), float(sur.err_calib)
+        self.members = []
+        for k in range(2):
+            h = _vp()
+            _check(_lib.fpn_surrogate_member(self._h, k, ctypes.byref(h)), "fpn_surrogate_member")
+            nl = ctypes.c_int32()
+            wb = (ctypes.c_int32 * 17)()
+            _check(_lib.fpn_mlp_shape(h, ctypes.byref(nl), wb), "fpn_mlp_shape")
+            self.members.append(MLP(ctx, list(wb[:nl.value + 1]), handle=h))
+        self.widths = self.members[0].widths
+
+    def close(self):
+        for m in getattr(self, "members", []):
+            m.close()
+        if self._h:
+            _lib.fpn_surrogate_destroy(self._h)
+            self._h = _vp()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def set_scales(self, out_scale, err_calib):
+        _check(_lib.fpn_surrogate_set_scales(self._h, float(out_scale), float(err_calib)), "fpn_surrogate_set_scales")
+        self.out_scale, self.err_calib = float(out_scale), float(err_calib)
+
+    def save(self, path):
+        _check(_lib.fpn_surrogate_save(self._h, os.fsencode(path)), "fpn_surrogate_save")
+
+    def _stream(self):
+        return _torch().cuda.current_stream(self.ctx.device).cuda_stream
+
+    def infer(self, x):
+        """(y [n, W], err_est [n]) from features x [n, 8] (device float32)."""
+        torch = _torch()
+        dev = f"cuda:{self.ctx.device}"
+        x = _f32(x, dev)
+        n = x.shape[0]
+        y = torch.empty((n, self.widths[-1]), dtype=torch.float32, device=dev)
+        e = torch.empty((n,), dtype=torch.float32, device=dev)
+        _check(_lib.fpn_surrogate_infer(self.ctx._h, self._h, x.data_ptr(), n, y.data_ptr(), e.data_ptr(),
+                                        self._stream()), "fpn_surrogate_infer")
+        return y, e
+
+    def train_step(self, x, y_true, lr):
+        """One Adam step of both members on (x, y_true); returns the device tensor of the two loss sums."""
+        torch = _torch()
+        dev = f"cuda:{self.ctx.device}"
+        x, y_true = _f32(x, dev), _f32(y_true, dev)
+        loss = torch.empty(2, dtype=torch.float64, device=dev)
+        _check(_lib.fpn_surrogate_train_step(self.ctx._h, self._h, x.data_ptr(), y_true.data_ptr(), x.shape[0],
+                                             float(lr), loss.data_ptr(), self._stream()), "fpn_surrogate_train_step")
         return loss
 
 

@@ -40,7 +40,16 @@ def _run(cmd):
     return r.stdout
 
 
-def build(jobs=8, verbose=False, out=None, build_dir=None, extra=()):
+def _fresh(cmd, newest_header):
+    """True when the object a compile step writes is newer than its source and every header."""
+    src = cmd[cmd.index("-c") + 1]
+    obj = cmd[cmd.index("-o") + 1]
+    return os.path.exists(obj) and os.path.getmtime(obj) > max(os.path.getmtime(src), newest_header)
+
+
+def build(jobs=8, verbose=False, out=None, build_dir=None, extra=(), incremental=False):
+    """Compile every source and link libfpn.so.  incremental=True (development only) skips objects
+    that are newer than their source and all headers."""
     BUILD = build_dir or globals()["BUILD"]
     LIB = out or globals()["LIB"]
     HIP_FLAGS = [*globals()["HIP_FLAGS"], *extra]
@@ -65,9 +74,16 @@ def build(jobs=8, verbose=False, out=None, build_dir=None, extra=()):
         [HIPCC, *HIP_FLAGS, "-c", os.path.join(CSRC, "capi_surrogate.hip"), "-o",
          os.path.join(BUILD, "capi_surrogate.o")],
         [HIPCC, *HIP_FLAGS, "-c", os.path.join(CSRC, "capi_static.hip"), "-o", os.path.join(BUILD, "capi_static.o")],
+        [HIPCC, *HIP_FLAGS, "-c", os.path.join(CSRC, "capi_surmodel.hip"), "-o",
+         os.path.join(BUILD, "capi_surmodel.o")],
         ["g++", "-O2", "-std=c++17", "-fPIC", "-c", os.path.join(CSRC, "structure.cpp"),
          "-o", os.path.join(BUILD, "structure.o")],
     ]
+    if incremental:
+        hdrs = [os.path.join(CSRC, f) for f in os.listdir(CSRC) if f.endswith((".hpp", ".h"))]
+        hdrs.append(os.path.join(HERE, "..", "include", "fpn.h"))
+        newest = max(os.path.getmtime(h) for h in hdrs)
+        steps = [c for c in steps if not _fresh(c, newest)]
     with ThreadPoolExecutor(max_workers=jobs) as ex:
         outs = list(ex.map(_run, steps))
     if verbose:
@@ -81,11 +97,11 @@ def build(jobs=8, verbose=False, out=None, build_dir=None, extra=()):
           os.path.join(BUILD, "kernels.o"), os.path.join(BUILD, "capi.o"), os.path.join(BUILD, "structure.o"),
           os.path.join(BUILD, "mlp.o"), os.path.join(BUILD, "capi_mlp.o"),
           os.path.join(BUILD, "surrogate.o"), os.path.join(BUILD, "capi_surrogate.o"),
-          os.path.join(BUILD, "capi_static.o"),
+          os.path.join(BUILD, "capi_static.o"), os.path.join(BUILD, "capi_surmodel.o"),
           f"-L{hiplib}", "-l:libamdhip64.so", f"-Wl,-rpath,{hiplib}:/opt/rocm/lib", "-lstdc++"])
     os.replace(tmp, LIB)
     return LIB
 
 
 if __name__ == "__main__":
-    print(build(verbose="-v" in sys.argv))
+    print(build(verbose="-v" in sys.argv, incremental="--incremental" in sys.argv))

@@ -301,6 +301,7 @@ const char* fpn_status_string(fpn_status s) {
     case FPN_E_DEVICE: return "HIP device error";
     case FPN_E_NOMEM: return "device out of memory";
     case FPN_E_UNSUPPORTED: return "unsupported";
+    case FPN_E_IO: return "file error";
     default: return "unknown status";
   }
 }

@@ -166,3 +166,13 @@ struct fpn_mlp_s {
   fpn_internal::DevBuf<uint16_t> dz[2], dzT[2];
   fpn_internal::DevBuf<double> loss;
 };
+
+// A surrogate model: the two ensemble members, the output scale and the error calibration, with the
+// workspace of fpn_surrogate_infer / fpn_surrogate_train_step.
+struct fpn_sur_model_s {
+  int device = 0;
+  fpn_mlp net[2] = {nullptr, nullptr};
+  float out_scale = 1.0f;
+  float err_calib = 1.0f;
+  fpn_internal::DevBuf<float> ya, yb, t;
+};

@@ -234,6 +234,14 @@ fpn_status fpn_mlp_destroy(fpn_mlp m) {
 
 int64_t fpn_mlp_num_params(fpn_mlp m) { return m ? m->nparam : -1; }
 
+fpn_status fpn_mlp_shape(fpn_mlp m, int32_t* n_layers, int32_t* widths) {
+  if (!m || !n_layers) return fail(FPN_E_ARG, "NULL argument");
+  *n_layers = m->nl;
+  if (widths)
+    for (int l = 0; l <= m->nl; ++l) widths[l] = m->w[l];
+  return FPN_OK;
+}
+
 fpn_status fpn_mlp_params(fpn_mlp m, float* dst, const float* src, void* stream) {
   if (!m || (!dst && !src)) return fail(FPN_E_ARG, "NULL argument");
   hipStream_t s = reinterpret_cast<hipStream_t>(stream);

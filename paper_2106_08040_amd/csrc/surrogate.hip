@@ -82,6 +82,34 @@ __global__ void combine_kernel(int64_t n, int Kh, const float* ya, const float* 
   }
 }
 
+// One wavefront per row: the ensemble mean y = (ya + yb) / 2 * inv_scale (network layout kept) and
+// err = calib * 2 ||ya - yb|| / ||ya + yb||, the same estimate as combine_kernel.
+__global__ void mean_spread_kernel(int64_t n, int W, const float* ya, const float* yb, float inv_scale,
+                                   float calib, float* y, float* err) {
+  const int64_t i = int64_t(blockIdx.x) * (blockDim.x / 64) + (threadIdx.x >> 6);
+  const int lane = threadIdx.x & 63;
+  if (i >= n) return;
+  const float* a = ya + i * W;
+  const float* b = yb + i * W;
+  float dd = 0.0f, ss = 0.0f;
+  for (int j = lane; j < W; j += 64) {
+    const float u = a[j], v = b[j];
+    dd += (u - v) * (u - v);
+    ss += (u + v) * (u + v);
+    if (y) y[i * W + j] = 0.5f * (u + v) * inv_scale;
+  }
+  for (int o = 32; o > 0; o >>= 1) {
+    dd += __shfl_xor(dd, o);
+    ss += __shfl_xor(ss, o);
+  }
+  if (lane == 0 && err) err[i] = calib * 2.0f * sqrtf(dd) / sqrtf(ss);
+}
+
+__global__ void scale_kernel(int64_t n, const float* src, float a, float* dst) {
+  const int64_t j = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+  if (j < n) dst[j] = src[j] * a;
+}
+
 __global__ void gather_kernel(int cnt, const int32_t* list, const double* D, const double* Ms, const double* K,
                               const double* alpha, const double* T, const double* nax, const double* off,
                               double* out) {
@@ -133,6 +161,20 @@ hipError_t combine(int64_t n, int Kh, const float* ya, const float* yb, float in
   hipLaunchKernelGGL(zero_i32_kernel, dim3(1), dim3(64), 0, s, count, 1);
   hipLaunchKernelGGL(combine_kernel, dim3(unsigned((n + 3) / 4)), dim3(256), 0, s, n, Kh, ya, yb, inv_scale, calib,
                      tol, status, harm, err, used, list, count);
+  return hipGetLastError();
+}
+
+hipError_t mean_spread(int64_t n, int W, const float* ya, const float* yb, float inv_scale, float calib, float* y,
+                       float* err, hipStream_t s) {
+  if (n == 0) return hipSuccess;
+  hipLaunchKernelGGL(mean_spread_kernel, dim3(unsigned((n + 3) / 4)), dim3(256), 0, s, n, W, ya, yb, inv_scale,
+                     calib, y, err);
+  return hipGetLastError();
+}
+
+hipError_t scale(int64_t n, const float* src, float a, float* dst, hipStream_t s) {
+  if (n == 0) return hipSuccess;
+  hipLaunchKernelGGL(scale_kernel, dim3(unsigned((n + 255) / 256)), dim3(256), 0, s, n, src, a, dst);
   return hipGetLastError();
 }
 

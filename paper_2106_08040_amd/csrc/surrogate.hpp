@@ -13,6 +13,12 @@ hipError_t features(int64_t n, const double* D, const double* Ms, const double* 
 hipError_t combine(int64_t n, int Kh, const float* ya, const float* yb, float inv_scale, float calib, float tol,
                    const int32_t* status, float* harm, float* err, int32_t* used, int32_t* list, int32_t* count,
                    hipStream_t s);
+// y = (ya + yb) / 2 * inv_scale and err = calib * 2 ||ya - yb|| / ||ya + yb|| per row of W values
+// (either output may be NULL)
+hipError_t mean_spread(int64_t n, int W, const float* ya, const float* yb, float inv_scale, float calib, float* y,
+                       float* err, hipStream_t s);
+// dst = a * src (n values)
+hipError_t scale(int64_t n, const float* src, float a, float* dst, hipStream_t s);
 hipError_t gather(int cnt, const int32_t* list, const double* D, const double* Ms, const double* K,
                   const double* alpha, const double* T, const double* nax, const double* off, double* out,
                   hipStream_t s);

@@ -14,7 +14,7 @@ import time
 
 import numpy as np
 
-from . import MLP
+from . import SurrogateModel
 
 WIDTHS_HIDDEN = (512, 512, 512, 512)
 
@@ -33,20 +33,38 @@ def _torch():
 
 
 class Surrogate:
-    """Two networks of identical shape, the output scale and the calibrated error constant."""
+    """Two networks of identical shape, the output scale and the calibrated error constant, held by
+    one library model (fpn_sur_model), which can be saved and loaded (``save``, ``Surrogate.load``)."""
 
-    def __init__(self, ctx, n_harm, hidden=WIDTHS_HIDDEN, seeds=(1, 2)):
+    def __init__(self, ctx, n_harm, hidden=WIDTHS_HIDDEN, seeds=(1, 2), model=None):
         self.ctx = ctx
         self.n_harm = int(n_harm)
         widths = [8, *hidden, 4 * self.n_harm]
-        self.nets = [MLP(ctx, widths, seed=s) for s in seeds]
-        self.out_scale = 1.0
-        self.err_calib = 1.0
+        self.model = model if model is not None else SurrogateModel(ctx, widths, seeds=seeds)
+        if self.model.widths[0] != 8 or self.model.widths[-1] != 4 * self.n_harm:
+            raise ValueError("model widths do not map 8 features to 4 * n_harm outputs")
+        self.nets = self.model.members
         self.train_seconds = 0.0
 
+    @classmethod
+    def load(cls, ctx, path):
+        """A surrogate read from a file written by ``save`` (fpn_surrogate_create)."""
+        model = SurrogateModel(ctx, path=path)
+        return cls(ctx, model.widths[-1] // 4, model=model)
+
+    def save(self, path):
+        self.model.save(path)
+
+    @property
+    def out_scale(self):
+        return self.model.out_scale
+
+    @property
+    def err_calib(self):
+        return self.model.err_calib
+
     def close(self):
-        for n in self.nets:
-            n.close()
+        self.model.close()
 
     def fit(self, inst, harm, steps=3000, batch=4096, lr=2e-3, lr_final=2e-5, seed=0, log=None):
         """Train both members on (features(inst), harm) with Adam and a cosine learning-rate decay."""
@@ -56,7 +74,7 @@ class Surrogate:
         x = x[ok].contiguous()
         y = harm_targets(harm)[ok]
         rms = float(torch.sqrt((y.double() ** 2).mean()).item())
-        self.out_scale = 1.0 / rms
+        self.model.set_scales(1.0 / rms, self.err_calib)
         y = (y * self.out_scale).contiguous()
         mean = x.double().mean(0).cpu().numpy()
         std = x.double().std(0).cpu().numpy()
@@ -94,10 +112,10 @@ class Surrogate:
         spread = 2.0 * torch.linalg.vector_norm(ya - yb, dim=1) / torch.linalg.vector_norm(ya + yb, dim=1)
         ok = (st == 0) & torch.isfinite(true) & torch.isfinite(spread) & (spread > 0)
         ratio = (true[ok] / spread[ok]).double().cpu().numpy()
-        self.err_calib = float(np.quantile(ratio, quantile))
+        self.model.set_scales(self.out_scale, float(np.quantile(ratio, quantile)))
         return true[ok].double().cpu().numpy(), spread[ok].double().cpu().numpy()
 
     def predict(self, inst, L, drive, samples, settle, tol, substeps=0):
         """fpn_surrogate_predict: (harm, err_estimate, used_solver, status, n_fallback)."""
-        return self.ctx.surrogate_predict(self.nets, self.out_scale, self.err_calib, tol, inst, L, drive, samples,
-                                          settle, self.n_harm, substeps=substeps)
+        return self.ctx.surrogate_predict(self.model, tol, inst, L, drive, samples, settle, self.n_harm,
+                                          substeps=substeps)

@@ -133,3 +133,59 @@ def test_accepted_instances_meet_tolerance_and_save_solver_time(fpn, ctx, traine
           f"{t_solver * 1e3:.1f} ms", flush=True)
     assert np.mean(e <= tol) >= 0.97
     assert nf <= 256
+
+
+def test_model_handle_train_save_load_is_bit_identical(fpn, ctx, tmp_path):
+    """fpn_surrogate_init / _train_step / _save / _create / _infer through the C ABI: a model trained a
+    few steps, written to a file and read back, evaluates bit for bit as before and continues training
+    identically (Adam state included); _train_step equals each member's step on the scaled targets;
+    _infer equals the combination of the members' outputs; damaged files are rejected."""
+    import torch
+    r = np.random.default_rng(5)
+    widths = [8, 64, 64, 32]
+    x = torch.tensor(r.normal(size=(300, 8)), dtype=torch.float32, device="cuda:0")
+    y = torch.tensor(r.normal(size=(300, 32)) * 1e3, dtype=torch.float32, device="cuda:0")
+    a = fpn.SurrogateModel(ctx, widths, seeds=(11, 12))
+    b = fpn.SurrogateModel(ctx, widths, seeds=(11, 12))
+    for m in (a, b):
+        m.set_scales(1e-3, 2.5)
+        for net in m.members:
+            net.set_input_norm(np.linspace(-0.5, 0.5, 8), np.linspace(0.5, 2.0, 8))
+    ys = (y * np.float32(1e-3)).contiguous()
+    for it in range(5):
+        a.train_step(x, y, 1e-3)
+        for net in b.members:
+            net.train_step(x, ys, 1e-3)
+    torch.cuda.synchronize()
+    for k in range(2):
+        assert torch.equal(a.members[k].get_params(), b.members[k].get_params())
+    ya, ea = a.infer(x)
+    outs = [net.forward(x) for net in a.members]
+    inv = float(np.float32(1.0) / np.float32(1e-3))
+    assert torch.equal(ya, ((outs[0] + outs[1]) * 0.5) * inv)
+    spread = 2.5 * 2.0 * torch.linalg.vector_norm(outs[0] - outs[1], dim=1) / torch.linalg.vector_norm(outs[0] + outs[1], dim=1)
+    assert torch.allclose(ea, spread, rtol=1e-5)
+    path = str(tmp_path / "model.fpnsur")
+    a.save(path)
+    c = fpn.SurrogateModel(ctx, path=path)
+    assert c.widths == widths and c.out_scale == a.out_scale and c.err_calib == a.err_calib
+    yc, ec = c.infer(x)
+    assert torch.equal(yc, ya) and torch.equal(ec, ea)
+    a.train_step(x[:100], y[:100], 5e-4)
+    c.train_step(x[:100], y[:100], 5e-4)
+    torch.cuda.synchronize()
+    for k in range(2):
+        assert torch.equal(a.members[k].get_params(), c.members[k].get_params())
+    # a damaged file is rejected with FPN_E_IO (truncated, altered, not a model file)
+    raw = open(path, "rb").read()
+    for bad in (raw[:-9], raw[:40] + bytes([raw[40] ^ 1]) + raw[41:], b"not a model" * 10):
+        bp = str(tmp_path / "bad.fpnsur")
+        open(bp, "wb").write(bad)
+        with pytest.raises(fpn.FpnError) as e:
+            fpn.SurrogateModel(ctx, path=bp)
+        assert e.value.code == fpn.FPN_E_IO
+    with pytest.raises(fpn.FpnError) as e:
+        fpn.SurrogateModel(ctx, path=str(tmp_path / "missing.fpnsur"))
+    assert e.value.code == fpn.FPN_E_IO
+    for m in (a, b, c):
+        m.close()
