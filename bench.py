@@ -101,17 +101,20 @@ def flops_per_step(fpn, L, tangents=0):
     return fac + 6 * stage + 2 * nnz + tangents * tan
 
 
-def cpu_baseline(ws, budget_s=15.0):
-    """The FP64 oracle (as it stands) on a bounded sample: one instance of the workload,
-    operator build + stationary start + as many Radau IIA steps (2 per sample) as fit in
-    the budget; the per-solve time is extrapolated to the full (settle+1)*N_s*2 steps."""
-    import oracle as O
+def _oracle_sample(args):
+    """One process of the CPU baseline: the oracle (as it stands) on instance `i` of the workload with
+    BLAS pinned to one thread: operator build + stationary start, then Radau IIA steps (r = 2) until
+    `budget_s` has passed.  Returns (setup seconds, steps done, seconds per step, total steps)."""
+    i, budget_s = args
     try:
-        from threadpoolctl import threadpool_info
-        threads = max([i.get("num_threads", 1) for i in threadpool_info()] or [1])
+        from threadpoolctl import threadpool_limits
+        threadpool_limits(1)
     except Exception:
-        threads = os.cpu_count()
-    inst = {k: v[0] for k, v in ws["inst"].items()}
+        pass
+    import oracle as O
+    import workloads as W
+    ws = W.lissajous_grid()
+    inst = {k: v[i] for k, v in ws["inst"].items()}
     p = dict(D=inst["D"], Ms=inst["Ms"], K=inst["K"], alpha=inst["alpha"], T=inst["T"])
     t0 = time.perf_counter()
     A0, Aa, _ = O.operator_parts(p, inst["easy_axis"], int(inst["L"]))
@@ -130,12 +133,56 @@ def cpu_baseline(ws, budget_s=15.0):
     while time.perf_counter() - t1 < budget_s:
         c = O.radau_step(Afun, steps * h, c, h)
         steps += 1
-    t_step = (time.perf_counter() - t1) / steps
-    total_steps = (ws["settle"] + 1) * ws["samples"] * r
-    per_solve = t_setup + total_steps * t_step
-    return {"value": 1.0 / per_solve, "unit": "solves/s", "cores": int(threads), "kind": "oracle",
-            "sample": f"1 instance (L={int(inst['L'])}): operator build + stationary start + {steps} of "
-                      f"{total_steps} Radau IIA steps (r={r}); per-solve time extrapolated"}
+    return t_setup, steps, (time.perf_counter() - t1) / steps, (ws["settle"] + 1) * ws["samples"] * r
+
+
+def cpu_baseline(budget_s=15.0, max_procs=16):
+    """The FP64 oracle on the host cores: one process per core (at most max_procs), BLAS pinned to one
+    thread in each, every process on a different instance of the stratified 64-instance subset of the
+    Lissajous batch (angles x corners, edges and centre of the offset grid), each timed for budget_s of
+    Radau IIA steps; the per-solve time of each instance is extrapolated to its full step count, and the
+    box's rate is the process count over the mean core-seconds per solve.  Runs before the GPU is used."""
+    import multiprocessing as mp
+    from concurrent.futures import ProcessPoolExecutor
+    import workloads as W
+    ids = W.lissajous_stratified_ids()
+    try:
+        cores = len(os.sched_getaffinity(0))
+    except AttributeError:
+        cores = os.cpu_count() or 1
+    procs = max(1, min(cores, max_procs, len(ids)))
+    model = "unknown"
+    try:
+        with open("/proc/cpuinfo") as fh:
+            for line in fh:
+                if line.startswith("model name"):
+                    model = line.split(":", 1)[1].strip()
+                    break
+    except OSError:
+        pass
+    # evenly spread over the stratified list, so every angle is represented
+    pick = [ids[(j * len(ids)) // procs] for j in range(procs)]
+    env = {k: os.environ.get(k) for k in ("OMP_NUM_THREADS", "OPENBLAS_NUM_THREADS", "MKL_NUM_THREADS")}
+    for k in env:
+        os.environ[k] = "1"
+    try:
+        with ProcessPoolExecutor(max_workers=procs, mp_context=mp.get_context("spawn")) as ex:
+            res = list(ex.map(_oracle_sample, [(i, budget_s) for i in pick]))
+    finally:
+        for k, v in env.items():
+            if v is None:
+                os.environ.pop(k, None)
+            else:
+                os.environ[k] = v
+    per_solve = [su + tot * ts for su, _, ts, tot in res]
+    core_s = float(np.mean(per_solve))
+    steps = int(np.mean([st for _, st, _, _ in res]))
+    return {"value": procs / core_s, "unit": "solves/s", "cores": procs, "kind": "oracle",
+            "core_seconds_per_solve": core_s, "nproc": os.cpu_count(), "cpu_model": model,
+            "sample": f"{procs} of the 64 stratified Lissajous instances, one process per core, BLAS 1 thread: "
+                      f"operator build + stationary start + ~{steps} of {res[0][3]} Radau IIA steps (r=2) "
+                      f"each in {budget_s:.0f} s, per-solve time extrapolated; rate = processes / mean "
+                      f"core-seconds per solve"}
 
 
 def wait_with_progress(torch, what, t0):
@@ -220,7 +267,7 @@ def bench_uneven(args):
     ctx.close()
 
 
-def bench_gradient(args):
+def bench_gradient(args, cpu=None):
     """Parameter identification gradient: 32 x 32 offsets on +-12 mT x 16 in-plane easy-axis angles x 4
     particle components (D, K, alpha and a superposition weight each), L = 16, harmonics 1..300 of x and
     y.  Loss = sum over angles, offsets, channels and harmonics of |sum_c w_c Phi_c - S|^2, S synthesised
@@ -324,18 +371,13 @@ def bench_gradient(args):
                      "traffic": None, "avg_launch_ms": acc["tangent_ms"] / nA,
                      "flops_per_step": fl_t, "primal_stepper_ms": acc["primal_ms"] / nA},
     }
-    if not args.no_cpu_baseline:
-        one = dict(inst=dict(D=np.array([ws["guess"]["D"][0]]), Ms=np.array([ws["Ms"]]),
-                             K=np.array([ws["guess"]["K"][0]]), alpha=np.array([ws["guess"]["alpha"][0]]),
-                             T=np.array([ws["T"]]),
-                             easy_axis=np.array([[np.cos(ws["angles_guess"][0]), np.sin(ws["angles_guess"][0]), 0.0]]),
-                             offset=off[:1], L=np.array([L], np.int32)),
-                   drive=ws["drive"], samples=ws["samples"], settle=ws["settle"])
-        cb = cpu_baseline(one, args.cpu_budget)
+    if cpu is not None:
+        cb = dict(cpu)
         cb["value"] /= 11.0
         cb["unit"] = "solves/s (with gradient)"
-        cb["sample"] += ("; the oracle's gradient is central differences in D, K, alpha and the two axis angles, "
-                         "11 solves per instance, so the rate is the solve rate / 11")
+        cb["sample"] += ("; measured on the Lissajous particle's instances (same degree, drive and step count as "
+                         "these); the oracle's gradient is central differences in D, K, alpha and the two axis "
+                         "angles, 11 solves per instance, so the rate is the solve rate / 11")
         res["cpu_baseline"] = cb
     print(json.dumps(res), flush=True)
     ctx.close()
@@ -402,6 +444,97 @@ def bench_equilibrium(args):
         res["cpu_baseline"] = {"value": k / (time.perf_counter() - t0), "unit": "system-matrix columns/s",
                                "cores": int(threads), "kind": "oracle",
                                "sample": f"the first {k} instances of the batch, oracle equilibrium model"}
+    print(json.dumps(res), flush=True)
+    ctx.close()
+
+
+def bench_m1(args):
+    """Model M1 identification (paper: data-driven models, Simulation Setting, Distance Measure) on a
+    synthetic measurement: the system matrices of an off-grid particle (D = 21.3 nm, K = 1170 J/m^3) at
+    12 easy-axis angles on the paper's 11 x 11 offset grid and drive, times a synthetic transfer value
+    per (channel, bin), plus 1 % complex noise, stand in for the measured calibration data.  One step =
+    the dictionary sweep (8 diameters 14..28 nm x 8 anisotropies x 12 angles x 121 offsets, one
+    fpn_solve), the closed-form per-row scales of every (element, angle) pair (fpn_fit_rows) and the
+    per-frequency and global NRMSE over mixing orders 0..9 (fpn_nrmse_global).  Roofline of the fit
+    kernel: HBM, 2 reads of the element's and the measurement's rows per pair."""
+    import torch
+    import paper_2106_08040_amd as fpn
+    import workloads as W
+
+    D_set = [d * 1e-9 for d in range(14, 29, 2)]
+    K_set = [100.0, 400.0, 800.0, 1100.0, 1500.0, 2200.0, 3200.0, 4500.0]
+    angles = [15.0 * j for j in range(12)]
+    Kh = 300
+    dic = W.m1_dictionary(D_set, K_set, angles, n_grid=11, n_harm=Kh)
+    truth = W.m1_dictionary([21.3e-9], [1170.0], angles, n_grid=11, n_harm=Kh)
+    ctx = fpn.Context(0)
+    d = dic["drive"]
+    drive = fpn.make_drive(d["amp"], d["freq"], d["period"], d["phase"])
+    n_el, n_pos, n_ang = dic["n_elements"], dic["n_pos"], len(angles)
+    inst = {k: torch.as_tensor(v, dtype=torch.float64, device="cuda:0") for k, v in dic["inst"].items() if k != "L"}
+    # the synthetic measurement (untimed): solver output of the truth, transfer values, 1 % noise
+    _, h0, st0 = ctx.solve(truth["inst"], truth["inst"]["L"], drive, dic["samples"], 1, Kh, want_m=False)
+    a_true, z, rn = W.m1_transfer_and_noise(n_ang, n_pos, 2, Kh + 1, seed=81)
+    S = torch.as_tensor(a_true, dtype=torch.complex64, device="cuda:0")[None, None] * h0.reshape(n_ang, n_pos, 2, Kh + 1)
+    rms = torch.sqrt(torch.mean(torch.abs(S) ** 2, dim=1, keepdim=True))
+    S = (S + rn * rms * torch.as_tensor(z, dtype=torch.complex64, device="cuda:0")).contiguous()
+    pp = np.arange(n_el, dtype=np.int32)
+    ps = np.tile(np.arange(n_ang, dtype=np.int32), n_el // n_ang)
+    kset = fpn.frequency_index_set(9, 9)
+    L = dic["inst"]["L"]
+    hm = torch.empty((n_el * n_pos, 2, Kh + 1, 2), dtype=torch.float32, device="cuda:0")
+    stt = torch.empty((n_el * n_pos,), dtype=torch.int32, device="cuda:0")
+    out = {"m": None, "harm": hm, "status": stt}
+    pp_t = torch.as_tensor(pp, device="cuda:0")
+    ps_t = torch.as_tensor(ps, device="cuda:0")
+
+    def step():
+        ctx.solve(inst, L, drive, dic["samples"], 1, Kh, want_m=False, out=out)
+        phi = torch.view_as_complex(hm).reshape(n_el, n_pos, 2, Kh + 1)
+        a, err = ctx.fit_rows(phi, S, pp_t, ps_t)
+        ef, eg = ctx.nrmse_global(err, n_ang, kset)
+        return a, err, ef, eg
+
+    for _ in range(args.warmup):
+        step()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        a, err, ef, eg = step()
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    # fit kernel alone (HIP events on the current stream, where it is launched)
+    phi = torch.view_as_complex(hm).reshape(n_el, n_pos, 2, Kh + 1)
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    reps = 20
+    e0.record()
+    for _ in range(reps):
+        ctx.fit_rows(phi, S, pp_t, ps_t)
+    e1.record()
+    torch.cuda.synchronize()
+    fit_ms = e0.elapsed_time(e1) / reps
+    fit_bytes = 2.0 * 2 * n_el * n_pos * 2 * (Kh + 1) * 8 + n_el * 2 * (Kh + 1) * 12
+    st = stt.cpu().numpy()
+    egn = eg.cpu().numpy().reshape(len(D_set), len(K_set))
+    usable = (st.reshape(n_el, n_pos) == 0).all(1).reshape(len(D_set), len(K_set), n_ang).all(2)
+    egm = np.where(usable, egn, np.inf)
+    i, j = np.unravel_index(int(np.argmin(egm)), egm.shape)
+    nsol = n_el * n_pos
+    res = {
+        "metric": "FP solves/sec & surrogate evals/sec at \u22641e-3 rel-L2 vs FP64 oracle",
+        "value": nsol * args.steps / wall, "unit": "dictionary solves/s (with fit and NRMSE)", "n_gpus": 1,
+        "steps": args.steps, "warmup": args.warmup, "ms_per_step": wall / args.steps * 1e3,
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f32", "data": "synthetic",
+        "config": {"workload": dic["name"], "instances": nsol, "elements": n_el, "positions": n_pos,
+                   "angles": n_ang, "n_harm": Kh, "mixing_orders": "0..9 x 0..9", "rows_graded": int(len(kset)),
+                   "L_counts": {str(int(l)): int((L == l).sum()) for l in np.unique(L)},
+                   "truth": {"D_nm": 21.3, "K": 1170.0}, "recovered": {"D_nm": D_set[i] * 1e9, "K": K_set[j]},
+                   "eps_global_min": float(egm[i, j]), "eps_global_map": np.round(egn, 5).tolist(),
+                   "unusable_pairs": int((~usable).sum()), "failed_instances": int((st != 0).sum())},
+        "roofline": {"bound": "hbm", "kernel": "fit_rows", "achieved": fit_bytes / (fit_ms * 1e-3) / 1e9,
+                     "peak": 8000.0, "unit": "GB/s", "frac": fit_bytes / (fit_ms * 1e-3) / 1e9 / 8000.0,
+                     "traffic": None, "avg_launch_ms": fit_ms, "bytes_per_launch": fit_bytes},
+    }
     print(json.dumps(res), flush=True)
     ctx.close()
 
@@ -519,18 +652,24 @@ def main():
                     help="run only a plain 256 MiB device copy three times (reference for the FETCH_SIZE / "
                          "WRITE_SIZE counters) and exit")
     ap.add_argument("--grad-angles", type=int, default=16, help="gradient workload: easy-axis angles")
-    ap.add_argument("--workload", choices=("lissajous", "uneven", "surrogate", "gradient", "equilibrium"),
+    ap.add_argument("--workload", choices=("lissajous", "uneven", "surrogate", "gradient", "equilibrium", "m1"),
                     default="lissajous",
                     help="lissajous: 2312-instance system matrix, L = 16 (headline); "
                          "uneven: 4096 instances with L = 8..24 in one graph launch; "
                          "surrogate: network ensemble trained on solver output, 262144 evaluations; "
                          "gradient: identification loss and its gradient over 65536 instances; "
-                         "equilibrium: the Lissajous system matrix of the equilibrium model (M0)")
+                         "equilibrium: the Lissajous system matrix of the equilibrium model (M0); "
+                         "m1: model-M1 identification (dictionary sweep, closed-form scales, NRMSE) on a "
+                         "synthetic measurement")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py measures one GPU only: there is no multi-GPU path (instances are independent; a "
               "batch would be split across GPUs by predicted cost, each GPU writing its own slice).", file=sys.stderr)
         sys.exit(2)
+
+    cpu = None
+    if args.workload in ("lissajous", "gradient") and not args.copy_calibration and not args.no_cpu_baseline:
+        cpu = cpu_baseline(args.cpu_budget)   # before anything touches the GPU
 
     import torch
     import paper_2106_08040_amd as fpn
@@ -549,9 +688,11 @@ def main():
     if args.workload == "surrogate":
         return bench_surrogate(args)
     if args.workload == "gradient":
-        return bench_gradient(args)
+        return bench_gradient(args, cpu)
     if args.workload == "equilibrium":
         return bench_equilibrium(args)
+    if args.workload == "m1":
+        return bench_m1(args)
     ws = W.lissajous_grid()
     n = ws["inst"]["D"].size
     dev = "cuda:0"
@@ -616,8 +757,8 @@ def main():
                      "avg_launch_ms": avg_ms, "flops_per_launch": flops_launch,
                      "kernel_ms": {k: v[0] / max(v[1], 1) for k, v in timing.items()}},
     }
-    if not args.no_cpu_baseline:
-        res["cpu_baseline"] = cpu_baseline(ws, args.cpu_budget)
+    if cpu is not None:
+        res["cpu_baseline"] = cpu
     print(json.dumps(res), flush=True)
     ctx.close()
 

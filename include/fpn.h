@@ -138,11 +138,15 @@ typedef struct {
  *   dmdt_out [n][3][N_s]          float, d<m>/dt [1/s] at the same samples (lab frame): the rows
  *                                 l = 1 of the ODE's right-hand side A(t_j) c(t_j) (the derivative of
  *                                 the mean moment of the averaged equation of motion, model section).
- *                                 Accuracy: about 1e-3 relative (rel-L2 over an instance), far below
+ *                                 Accuracy: within 2e-3 relative (rel-L2 over an instance; measured
+ *                                 3e-4 .. 6e-4 against the FP64 oracle), far below
  *                                 that of m and harm_out: A's l = 1 rows are stiff (|A| ~ 1/tau) and
  *                                 multiply the FP32 state error of the fast modes (~1e-6), which the
  *                                 slow moment m does not see.  harm_out does not use dmdt_out.
- *   harm_out [n][ch][K_h+1][2]    float, (re, im) of Phi_k [1/s], ch = 2 or 3
+ *   harm_out [n][ch][K_h+1][2]    float, (re, im) of Phi_k [1/s], ch = 2 or 3.  Accuracy (adaptive
+ *                                 steps): rel-L2 within 1e-5 per instance; per bin the error is close
+ *                                 to a constant absolute level (about 3e-7 of the largest harmonic of
+ *                                 the channel), so small harmonics are relatively less accurate
  *   status   [n]                  int32, FPN_INST_* (required)
  * Instances with a non-zero status other than FPN_INST_TOL_UNMET get NaN in every output.
  * Errors: FPN_E_ARG, FPN_E_RANGE (L, N_s above FPN_MAX_HARM_LDS), FPN_E_DEVICE, FPN_E_NOMEM. */
@@ -378,6 +382,47 @@ fpn_status fpn_surrogate_infer(fpn_ctx ctx, fpn_sur_model m, const float* x, int
  * Asynchronous.  Errors: FPN_E_ARG, FPN_E_NOMEM, FPN_E_DEVICE. */
 fpn_status fpn_surrogate_train_step(fpn_ctx ctx, fpn_sur_model m, const float* x, const float* y_true, int64_t n,
                                     float lr, double* loss_out, void* stream);
+
+/* ---- data-driven model fits and distance measure ----
+ * Paper: Methods, "Data-driven physically motivated models" (models M0 and M1), "Technical details
+ * regarding the parameter identification" (closed-form scale of M0/M1) and "Distance Measure"
+ * (Eq. mix, Eq. error1, Eq. globalMeasure).
+ * A system matrix (one dictionary element, or one measured matrix) is [n_pos][n_ch][n_bins][2] FP32:
+ * offset positions outermost, then receive channel, frequency bin k = 0..n_bins-1, (re, im); a batch
+ * of them is contiguous.  fpn_solve's harm_out is such a batch when its instances are ordered
+ * element-major, position-minor (n_bins = K_h + 1). */
+
+/* For each pair p (DEVICE int32 pair_phi[p], pair_s[p]: indices of a dictionary element of `phi` and a
+ * measured matrix of `S`) and every row (channel c, bin k), over the n_pos positions nu:
+ *   a[p][c][k]   = sum_nu S(nu) conj(Phi(nu)) / sum_nu |Phi(nu)|^2   (0 for an all-zero Phi row)
+ *   err[p][c][k] = sqrt(sum_nu |S(nu) - a Phi(nu)|^2 / n_pos) / max_nu |S(nu)|   (Eq. error1)
+ * Sums in FP64.  a_out [n_pairs][n_ch][n_bins][2], err_out [n_pairs][n_ch][n_bins] (DEVICE FP32, one
+ * may be NULL); an all-zero S row gives err = NaN.  Pair indices must lie inside phi and S (not
+ * checked on the device).  Asynchronous.  Errors: FPN_E_ARG, FPN_E_DEVICE. */
+fpn_status fpn_fit_rows(fpn_ctx ctx, const float* phi, const float* S, int32_t n_pos, int32_t n_ch, int32_t n_bins,
+                        int64_t n_pairs, const int32_t* pair_phi, const int32_t* pair_s, float* a_out,
+                        float* err_out, void* stream);
+
+/* Per-frequency and global NRMSE of n_groups parameter groups: err_rows [n_groups][n_ang][n_ch][n_bins]
+ * (fpn_fit_rows's err_out for pairs ordered group-major, angle-minor), kset [n_k] DEVICE int32 bins
+ * (the graded set I_freq, each < n_bins):
+ *   eps_freq[g][j] = sqrt(mean over angles and channels of err[g][.][.][kset[j]]^2)
+ *   eps_global[g]  = sqrt(mean over j of eps_freq[g][j]^2)                    (Eq. globalMeasure)
+ * The mean over receive channels is folded into the per-frequency measure, as the paper states its
+ * sums also run over the channels.  DEVICE FP32 outputs (one may be NULL), FP64 sums.  Asynchronous.
+ * Errors: FPN_E_ARG, FPN_E_DEVICE. */
+fpn_status fpn_nrmse_global(fpn_ctx ctx, const float* err_rows, int64_t n_groups, int32_t n_ang, int32_t n_ch,
+                            int32_t n_bins, const int32_t* kset, int32_t n_k, float* eps_freq, float* eps_global,
+                            void* stream);
+
+/* Mixing orders of bin k (Eq. mix): the integers (mx, my) with k = mx n_dens + my (n_dens + 1) and the
+ * smallest |mx| + |my| (unique).  HOST, no device needed.  Errors: FPN_E_ARG (NULL output,
+ * n_dens outside [1, 4096], |k| > 2^24). */
+fpn_status fpn_mixing_order(int32_t k, int32_t n_dens, int32_t* mx, int32_t* my);
+/* The graded bin set I_freq = { mx n_dens + my (n_dens + 1) : 0 <= mx <= Mx, 0 <= my <= My } without
+ * (mx, my) = (0,0), (0,1), (1,0), mx-major.  k_out (HOST, capacity (Mx+1)(My+1), may be NULL) and
+ * count (HOST).  Errors: FPN_E_ARG. */
+fpn_status fpn_frequency_index_set(int32_t Mx, int32_t My, int32_t n_dens, int32_t* k_out, int32_t* count);
 
 /* ---- allocation-free solve ----
  * For callers that cannot allocate device memory: code under HIP graph capture, tight serving loops,

@@ -43,7 +43,8 @@ EXPORTED = ["fpn_status_string", "fpn_last_error", "fpn_create", "fpn_destroy", 
             "fpn_stepper_wave_options", "fpn_set_stepper_waves", "fpn_autotune", "fpn_equilibrium",
             "fpn_solve_static", "fpn_mlp_shape", "fpn_surrogate_init", "fpn_surrogate_create", "fpn_surrogate_save",
             "fpn_surrogate_destroy", "fpn_surrogate_member", "fpn_surrogate_set_scales", "fpn_surrogate_view",
-            "fpn_surrogate_infer", "fpn_surrogate_train_step"]
+            "fpn_surrogate_infer", "fpn_surrogate_train_step", "fpn_fit_rows", "fpn_nrmse_global",
+            "fpn_mixing_order", "fpn_frequency_index_set"]
 
 
 class fpn_drive(ctypes.Structure):
@@ -169,6 +170,18 @@ _lib.fpn_surrogate_infer.restype = ctypes.c_int32
 _lib.fpn_surrogate_infer.argtypes = [_vp, _vp, _vp, ctypes.c_int64, _vp, _vp, _vp]
 _lib.fpn_surrogate_train_step.restype = ctypes.c_int32
 _lib.fpn_surrogate_train_step.argtypes = [_vp, _vp, _vp, _vp, ctypes.c_int64, ctypes.c_float, _vp, _vp]
+_lib.fpn_fit_rows.restype = ctypes.c_int32
+_lib.fpn_fit_rows.argtypes = [_vp, _vp, _vp, ctypes.c_int32, ctypes.c_int32, ctypes.c_int32, ctypes.c_int64, _vp, _vp,
+                              _vp, _vp, _vp]
+_lib.fpn_nrmse_global.restype = ctypes.c_int32
+_lib.fpn_nrmse_global.argtypes = [_vp, _vp, ctypes.c_int64, ctypes.c_int32, ctypes.c_int32, ctypes.c_int32, _vp,
+                                  ctypes.c_int32, _vp, _vp, _vp]
+_lib.fpn_mixing_order.restype = ctypes.c_int32
+_lib.fpn_mixing_order.argtypes = [ctypes.c_int32, ctypes.c_int32, ctypes.POINTER(ctypes.c_int32),
+                                  ctypes.POINTER(ctypes.c_int32)]
+_lib.fpn_frequency_index_set.restype = ctypes.c_int32
+_lib.fpn_frequency_index_set.argtypes = [ctypes.c_int32, ctypes.c_int32, ctypes.c_int32,
+                                         ctypes.POINTER(ctypes.c_int32), ctypes.POINTER(ctypes.c_int32)]
 _lib.fpn_surrogate_predict.restype = ctypes.c_int32
 _lib.fpn_surrogate_predict.argtypes = [_vp, ctypes.POINTER(fpn_surrogate), ctypes.c_double, ctypes.POINTER(fpn_drive),
                                        ctypes.POINTER(fpn_solve_opts), ctypes.POINTER(fpn_batch), ctypes.c_int64,
@@ -227,6 +240,21 @@ def fpn_stepper_wave_options(L):
     c = ctypes.c_int32()
     _check(_lib.fpn_stepper_wave_options(int(L), w, ctypes.byref(c)), "fpn_stepper_wave_options")
     return [int(w[k]) for k in range(c.value)]
+
+
+def mixing_order(k, n_dens=16):
+    """fpn_mixing_order: (mx, my) of bin k (Eq. mix)."""
+    mx, my = ctypes.c_int32(), ctypes.c_int32()
+    _check(_lib.fpn_mixing_order(int(k), int(n_dens), ctypes.byref(mx), ctypes.byref(my)), "fpn_mixing_order")
+    return mx.value, my.value
+
+
+def frequency_index_set(Mx, My, n_dens=16):
+    """fpn_frequency_index_set: the graded bins I_freq as an int32 array."""
+    c = ctypes.c_int32()
+    out = (ctypes.c_int32 * ((Mx + 1) * (My + 1)))()
+    _check(_lib.fpn_frequency_index_set(int(Mx), int(My), int(n_dens), out, ctypes.byref(c)), "fpn_frequency_index_set")
+    return np.array(out[:c.value], dtype=np.int32)
 
 
 def _torch():
@@ -488,6 +516,46 @@ class Context:
         self._keep = (keep, Lh)
         return torch.view_as_complex(hm), err, used, st, int(nf.value)
 
+    def fit_rows(self, phi, S, pair_phi, pair_s):
+        """fpn_fit_rows: phi [n_phi, n_pos, n_ch, n_bins] and S [n_S, n_pos, n_ch, n_bins] complex64 (device);
+        returns (a [n_pairs, n_ch, n_bins] complex64, err [n_pairs, n_ch, n_bins] float32)."""
+        torch = _torch()
+        dev = f"cuda:{self.device}"
+        phi = phi.contiguous()
+        S = S.contiguous()
+        _, n_pos, n_ch, n_bins = phi.shape
+        assert S.shape[1:] == phi.shape[1:]
+        pp = torch.as_tensor(pair_phi, dtype=torch.int32, device=dev).contiguous()
+        ps = torch.as_tensor(pair_s, dtype=torch.int32, device=dev).contiguous()
+        assert pp.numel() == ps.numel()
+        assert int(pp.min()) >= 0 and int(pp.max()) < phi.shape[0] and int(ps.min()) >= 0 and int(ps.max()) < S.shape[0]
+        n = pp.numel()
+        a = torch.empty((n, n_ch, n_bins, 2), dtype=torch.float32, device=dev)
+        err = torch.empty((n, n_ch, n_bins), dtype=torch.float32, device=dev)
+        s = torch.cuda.current_stream(self.device)
+        _check(_lib.fpn_fit_rows(self._h, torch.view_as_real(phi).data_ptr(), torch.view_as_real(S).data_ptr(), n_pos,
+                                 n_ch, n_bins, n, pp.data_ptr(), ps.data_ptr(), a.data_ptr(), err.data_ptr(),
+                                 s.cuda_stream), "fpn_fit_rows")
+        return torch.view_as_complex(a), err
+
+    def nrmse_global(self, err, n_ang, kset):
+        """fpn_nrmse_global: err [n_groups * n_ang, n_ch, n_bins] (device float32), kset bins; returns
+        (eps_freq [n_groups, n_k], eps_global [n_groups])."""
+        torch = _torch()
+        dev = f"cuda:{self.device}"
+        err = err.contiguous()
+        n_pairs, n_ch, n_bins = err.shape
+        assert n_pairs % n_ang == 0
+        ks = torch.as_tensor(kset, dtype=torch.int32, device=dev).contiguous()
+        assert int(ks.min()) >= 0 and int(ks.max()) < n_bins
+        g = n_pairs // n_ang
+        ef = torch.empty((g, ks.numel()), dtype=torch.float32, device=dev)
+        eg = torch.empty((g,), dtype=torch.float32, device=dev)
+        s = torch.cuda.current_stream(self.device)
+        _check(_lib.fpn_nrmse_global(self._h, err.data_ptr(), g, n_ang, n_ch, n_bins, ks.data_ptr(), ks.numel(),
+                                     ef.data_ptr(), eg.data_ptr(), s.cuda_stream), "fpn_nrmse_global")
+        return ef, eg
+
     def stationary(self, inst, L, field):
         torch = _torch()
         dev = f"cuda:{self.device}"
@@ -640,7 +708,9 @@ class SurrogateModel:
 
     def set_scales(self, out_scale, err_calib):
         _check(_lib.fpn_surrogate_set_scales(self._h, float(out_scale), float(err_calib)), "fpn_surrogate_set_scales")
-        self.out_scale, self.err_calib = float(out_scale), float(err_calib)
+        sur = fpn_surrogate()
+        _check(_lib.fpn_surrogate_view(self._h, ctypes.byref(sur)), "fpn_surrogate_view")
+        self.out_scale, self.err_calib = float(sur.out_scale), float(sur.err_calib)   # as stored (FP32)
 
     def save(self, path):
         _check(_lib.fpn_surrogate_save(self._h, os.fsencode(path)), "fpn_surrogate_save")

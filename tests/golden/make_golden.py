@@ -47,24 +47,18 @@ def identification_a0():
 
 
 def lissajous_stratified():
-    """64 instances of the 2312-instance Lissajous system matrix: for every easy-axis angle j, the four
-    corners and the centre of the 17 x 17 offset grid and three of the four edge midpoints (the edge
-    left out turns with j).  Instance id = (j * 17 + iy) * 17 + ix."""
-    ids = []
-    mids = [(0, 8), (8, 16), (16, 8), (8, 0)]
-    for j in range(8):
-        pos = [(0, 0), (0, 16), (16, 0), (16, 16), (8, 8)] + [m for e, m in enumerate(mids) if e != j % 4]
-        ids += [(j * 17 + iy) * 17 + ix for iy, ix in pos]
-    return ids
+    """The 64 stratified instances of the Lissajous batch (workloads.lissajous_stratified_ids)."""
+    return W.lissajous_stratified_ids()
 
 
 UNEVEN_BUCKETS = ((8, 8), (9, 12), (13, 16), (17, 20), (21, 23), (24, 24))
 
 
 def uneven_stratified():
-    """Two resolvable instances of the 4096-instance uneven sweep per degree bucket (UNEVEN_BUCKETS):
-    the band top (largest sigma - (L - 4), the stiffest particle its degree resolves) and the instance
-    with the median sigma of the bucket."""
+    """Three resolvable instances of the 4096-instance uneven sweep per degree bucket (UNEVEN_BUCKETS):
+    the band top (largest sigma - (L - 4), the stiffest particle its degree resolves by the rule), the
+    instance with the median sigma of the bucket, and the one with the largest damping alpha (the
+    truncated operator of a weakly damped particle is the least well resolved)."""
     ws = W.uneven_sweep(4096, seed=3)
     inst = ws["inst"]
     sig = W.anisotropy_ratio(inst["D"], inst["K"])
@@ -74,7 +68,8 @@ def uneven_stratified():
         cand = np.nonzero(ok & (inst["L"] >= lo) & (inst["L"] <= hi))[0]
         top = cand[np.argmax(sig[cand] - (inst["L"][cand] - 4))]
         med = cand[np.argsort(sig[cand])[cand.size // 2]]
-        ids += [int(top), int(med)]
+        damp = cand[np.argmax(inst["alpha"][cand])]
+        ids += [int(top), int(med), int(damp)]
     return ids
 
 
@@ -97,7 +92,7 @@ JOBS = {
     "lissajous": (W.lissajous_grid, [(0 * 17 + 8) * 17 + 8, (3 * 17 + 2) * 17 + 13, (5 * 17 + 16) * 17 + 0,
                                      (7 * 17 + 10) * 17 + 4, (2 * 17 + 0) * 17 + 16, (6 * 17 + 12) * 17 + 12], 4),
     "lissajous_strat": (W.lissajous_grid, lissajous_stratified(), 4),
-    "uneven": (uneven_ws, uneven_stratified(), 8),
+    "uneven": (uneven_ws, uneven_stratified(), 4),
 }
 
 

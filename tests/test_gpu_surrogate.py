@@ -138,8 +138,10 @@ def test_accepted_instances_meet_tolerance_and_save_solver_time(fpn, ctx, traine
 def test_model_handle_train_save_load_is_bit_identical(fpn, ctx, tmp_path):
     """fpn_surrogate_init / _train_step / _save / _create / _infer through the C ABI: a model trained a
     few steps, written to a file and read back, evaluates bit for bit as before and continues training
-    identically (Adam state included); _train_step equals each member's step on the scaled targets;
-    _infer equals the combination of the members' outputs; damaged files are rejected."""
+    from the same state (Adam moments included); _train_step equals each member's step on the scaled
+    targets; _infer equals the combination of the members' outputs; damaged files are rejected.
+    Training steps are compared to FP32 rounding, not bitwise: the weight gradients are summed with
+    atomic adds over split K, whose order varies from run to run."""
     import torch
     r = np.random.default_rng(5)
     widths = [8, 64, 64, 32]
@@ -157,8 +159,12 @@ def test_model_handle_train_save_load_is_bit_identical(fpn, ctx, tmp_path):
         for net in b.members:
             net.train_step(x, ys, 1e-3)
     torch.cuda.synchronize()
+
+    def close(p, q):
+        return torch.allclose(p, q, rtol=1e-4, atol=1e-6 * float(q.abs().max()))
+
     for k in range(2):
-        assert torch.equal(a.members[k].get_params(), b.members[k].get_params())
+        assert close(a.members[k].get_params(), b.members[k].get_params())
     ya, ea = a.infer(x)
     outs = [net.forward(x) for net in a.members]
     inv = float(np.float32(1.0) / np.float32(1e-3))
@@ -175,7 +181,7 @@ def test_model_handle_train_save_load_is_bit_identical(fpn, ctx, tmp_path):
     c.train_step(x[:100], y[:100], 5e-4)
     torch.cuda.synchronize()
     for k in range(2):
-        assert torch.equal(a.members[k].get_params(), c.members[k].get_params())
+        assert close(a.members[k].get_params(), c.members[k].get_params())
     # a damaged file is rejected with FPN_E_IO (truncated, altered, not a model file)
     raw = open(path, "rb").read()
     for bad in (raw[:-9], raw[:40] + bytes([raw[40] ^ 1]) + raw[41:], b"not a model" * 10):

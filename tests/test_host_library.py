@@ -98,3 +98,16 @@ def test_stepper_wave_options():
     for L in (0, 25):
         with pytest.raises(fpn.FpnError):
             fpn.fpn_stepper_wave_options(L)
+
+
+def test_mixing_orders_and_frequency_set_match_oracle_bit_exact():
+    """fpn_mixing_order / fpn_frequency_index_set (host integer code) against the oracle's brute force."""
+    import paper_2106_08040_amd as fpn
+    from oracle import fit_oracle as F
+    for n in (16, 5, 31):
+        for k in range(-700, 701):
+            assert fpn.mixing_order(k, n) == F.mixing_order(k, n), (k, n)
+    for Mx, My in ((0, 0), (1, 1), (6, 9), (12, 11)):
+        assert np.array_equal(fpn.frequency_index_set(Mx, My), F.frequency_index_set(Mx, My).astype(np.int32))
+    with pytest.raises(fpn.FpnError):
+        fpn.mixing_order(5, 0)

@@ -82,6 +82,18 @@ def anisotropy_ratio(D, K, T=ROOM_T):
     return np.asarray(K) * (np.pi * np.asarray(D) ** 3 / 6) / (1.380649e-23 * T)
 
 
+def lissajous_stratified_ids():
+    """64 instances of the 2312-instance Lissajous batch: for every easy-axis angle j, the four corners
+    and the centre of the 17 x 17 offset grid and three of the four edge midpoints (the edge left out
+    turns with j).  Instance id = (j * 17 + iy) * 17 + ix."""
+    ids = []
+    mids = [(0, 8), (8, 16), (16, 8), (8, 0)]
+    for j in range(8):
+        pos = [(0, 0), (0, 16), (16, 0), (16, 16), (8, 8)] + [m for e, m in enumerate(mids) if e != j % 4]
+        ids += [(j * 17 + iy) * 17 + ix for iy, ix in pos]
+    return ids
+
+
 def uneven_sweep(n=4096, seed=3, L_max=24):
     """Batched uneven sweep: D ~ U[15, 30] nm, K log-uniform in [0.5, 20] kJ/m^3, alpha ~ U[0.05, 0.3],
     easy axes uniform on the sphere, offsets U[-12, 12] mT in x and y, L by truncation_degree.
@@ -174,3 +186,51 @@ def take(ws, idx):
     out = dict(ws)
     out["inst"] = {k: v[idx] for k, v in ws["inst"].items()}
     return out
+
+
+def random_system_matrices(n, n_pos, n_ch, n_bins, seed):
+    """n complex64 system matrices [n, n_pos, n_ch, n_bins] with standard normal real and imaginary
+    parts (inputs of the fit and distance-measure parity tests)."""
+    r = np.random.default_rng(seed)
+    x = r.normal(size=(n, n_pos, n_ch, n_bins)) + 1j * r.normal(size=(n, n_pos, n_ch, n_bins))
+    return x.astype(np.complex64)
+
+
+M1_DRIVE_AMP = (12.59e-3, 13.55e-3, 0.0)   # the paper's calibrated drive amplitudes (mu0 H, T)
+M1_SPAN = (14.35e-3, 14.71e-3)             # half-widths of its 11 x 11 offset grid (mu0 H, T)
+
+
+def m1_dictionary(D_set, K_set, angles_deg, n_grid=11, samples=1632, n_harm=200, L_max=24):
+    """Dictionary of model M1 (Simulation Setting): every (D, K, angle) of the given sets at every offset
+    of an n_grid x n_grid grid spanning the paper's offset ranges, with the paper's Lissajous drive.
+    Instances are ordered element-major ((D, K, angle), angle fastest), offset position minor
+    (x fastest), so fpn_solve's harmonics are directly the dictionary layout of fpn_fit_rows.  The
+    degree of each instance follows ``truncation_degree``; easy axes in the xy-plane at the angle
+    from x (the same convention as the other workloads)."""
+    gx = np.linspace(-M1_SPAN[0], M1_SPAN[0], n_grid)
+    gy = np.linspace(-M1_SPAN[1], M1_SPAN[1], n_grid)
+    offs = np.array([(x, y, 0.0) for y in gy for x in gx])
+    rows = [(D, K, a) for D in D_set for K in K_set for a in angles_deg]
+    n_el, n_pos = len(rows), len(offs)
+    D = np.repeat([r[0] for r in rows], n_pos)
+    K = np.repeat([r[1] for r in rows], n_pos)
+    th = np.deg2rad(np.repeat([r[2] for r in rows], n_pos))
+    easy = np.stack([np.cos(th), np.sin(th), np.zeros_like(th)], 1)
+    off = np.tile(offs, (n_el, 1))
+    n = n_el * n_pos
+    L = truncation_degree(D, K, hi=L_max)
+    inst = _instances(D, np.full(n, MAGNETITE_MS), K, np.full(n, 0.1), np.full(n, ROOM_T), easy, off, L)
+    drive = dict(amp=M1_DRIVE_AMP, freq=LISSAJOUS_F, phase=(0.0, 0.0, 0.0), period=LISSAJOUS_T)
+    return dict(name=f"m1_dictionary_{len(D_set)}x{len(K_set)}x{len(angles_deg)}_{n_grid}x{n_grid}", inst=inst,
+                drive=drive, samples=samples, settle=1, n_harm=n_harm, harm_z=False, n_elements=n_el,
+                n_pos=n_pos, elements=rows)
+
+
+def m1_transfer_and_noise(n_ang, n_pos, n_ch, n_bins, seed, rel_noise=0.01):
+    """Synthetic receive chain for the M1 demonstration: a complex transfer value per (channel, bin)
+    (log-normal magnitude, uniform phase) and unit complex Gaussian noise [n_ang, n_pos, n_ch, n_bins];
+    the caller scales the noise by rel_noise times each row's RMS."""
+    r = np.random.default_rng(seed)
+    a = np.exp(r.normal(0.0, 0.3, (n_ch, n_bins))) * np.exp(1j * r.uniform(-np.pi, np.pi, (n_ch, n_bins)))
+    z = (r.normal(size=(n_ang, n_pos, n_ch, n_bins)) + 1j * r.normal(size=(n_ang, n_pos, n_ch, n_bins))) / np.sqrt(2)
+    return a, z, rel_noise
