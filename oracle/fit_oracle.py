@@ -95,3 +95,46 @@ def m1_measures(Phi, S, kset):
     eps = nrmse_rows(S, a[..., None] * Phi)
     ef = eps_freq(eps[:, :, kset])
     return a, eps, ef, eps_global(ef)
+
+
+# --- model M2: weighted non-negative superposition with truncated-SVD regularisation -------------
+
+def m2_system(Psi, S, kset):
+    """Dictionary matrix and data of model M2 (Eq. LSfitM2 / LSfitM2_alternative).
+
+    Psi [J, angles, channels, bins, N] complex: the scaled dictionary Psi_q = diag(a_q) Phi_q of every
+    parameter pair j and angle; S [angles, channels, bins, N]: the measured matrices.  Rows are taken
+    for the bins of kset (I_freq) and weighted by Sigma = 1 / ||S_{angle; channel, k}||_inf (the
+    paper's weighting per frequency row, applied per receive channel).  Returns (M [R, J], y [R])
+    with R = angles * channels * len(kset) * N, rows in that order, columns the pairs j."""
+    Psi = np.asarray(Psi, complex)[:, :, :, kset, :]
+    S = np.asarray(S, complex)[:, :, kset, :]
+    w = 1.0 / np.max(np.abs(S), axis=-1)                     # [angles, channels, k]
+    M = (Psi * w[None, ..., None]).reshape(Psi.shape[0], -1).T
+    y = (S * w[..., None]).reshape(-1)
+    return M, y
+
+
+def m2_weights(M, y, s=None):
+    """Non-negative weights of model M2: min over real w >= 0 of || U_s^H (M w - y) ||_2 with U_s the
+    left singular vectors of the s largest singular values of M (Eq. approx_low_rank); s = None keeps
+    every singular value (the plain weighted least-squares fit, Eq. LSfitM2).  The complex problem in
+    real unknowns is solved as the real stacked system [Re; Im] by Lawson-Hanson NNLS (a library
+    routine standing in for the paper's interior-point method; both find a minimiser of the same
+    convex problem).  Returns (w, full residual ||M w - y||^2, reduced objective)."""
+    from scipy.optimize import nnls
+    U, sv, Vh = np.linalg.svd(M, full_matrices=False)
+    r = int(np.sum(sv > sv[0] * 1e-13)) if sv.size else 0
+    s = r if s is None else min(int(s), r)
+    R = sv[:s, None] * Vh[:s]                    # U_s^H M
+    c = U[:, :s].conj().T @ y                     # U_s^H y
+    A = np.vstack([R.real, R.imag])
+    rhs = np.concatenate([c.real, c.imag])
+    w, res = nnls(A, rhs, maxiter=50 * A.shape[1])
+    full = float(np.linalg.norm(M @ w - y) ** 2)
+    return w, full, float(res ** 2)
+
+
+def m2_model(Psi, w):
+    """S_model of every angle: sum_j w_j Psi_j ([angles, channels, bins, N])."""
+    return np.tensordot(np.asarray(w, float), np.asarray(Psi, complex), axes=(0, 0))

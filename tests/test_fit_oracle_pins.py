@@ -90,3 +90,60 @@ def test_m1_measures_vanish_at_the_generating_parameters():
     assert eg < 1e-14
     _, _, _, eg2 = F.m1_measures(Phi + 0.1 * r.normal(size=Phi.shape), S, kset)
     assert eg2 > 1e-3
+
+
+def test_m2_system_layout_and_weighting_by_hand():
+    # one pair, two angles, one channel, bins 0..2 (kset = [1, 2]), two positions
+    Psi = np.zeros((1, 2, 1, 3, 2), complex)
+    Psi[0, 0, 0, 1] = [1.0, 2.0]
+    Psi[0, 1, 0, 2] = [3j, 0.0]
+    S = np.zeros((2, 1, 3, 2), complex)
+    S[0, 0, 1] = [4.0, -2.0]     # ||.||_inf = 4
+    S[0, 0, 2] = [1.0, 1.0]      # 1
+    S[1, 0, 1] = [0.5, 0.0]      # 0.5
+    S[1, 0, 2] = [0.0, 2.0]      # 2
+    M, y = F.m2_system(Psi, S, np.array([1, 2]))
+    assert M.shape == (8, 1)
+    # rows: angle 0 (k = 1: pos 0, 1; k = 2: pos 0, 1), angle 1 (...)
+    assert np.allclose(M[:, 0], [1 / 4, 2 / 4, 0, 0, 0, 0, 3j / 2, 0])
+    assert np.allclose(y, [1, -0.5, 1, 1, 1, 0, 0, 1])
+
+
+def test_m2_weights_recover_a_nonnegative_superposition():
+    r = np.random.default_rng(4)
+    M = r.normal(size=(60, 6)) + 1j * r.normal(size=(60, 6))
+    w_true = np.array([0.0, 1.5, 0.0, 0.3, 2.0, 0.0])
+    w, full, red = F.m2_weights(M, M @ w_true)
+    assert np.allclose(w, w_true, atol=1e-10)
+    assert full < 1e-18
+
+
+def test_m2_weights_equal_least_squares_when_interior_and_satisfy_kkt():
+    r = np.random.default_rng(5)
+    M = r.normal(size=(80, 5)) + 1j * r.normal(size=(80, 5))
+    w_pos = np.array([1.0, 2.0, 0.5, 1.5, 0.8])
+    y = M @ w_pos + 0.01 * (r.normal(size=80) + 1j * r.normal(size=80))
+    w, _, _ = F.m2_weights(M, y)
+    ref = np.linalg.lstsq(np.vstack([M.real, M.imag]), np.concatenate([y.real, y.imag]), rcond=None)[0]
+    assert (ref > 0).all() and np.allclose(w, ref, rtol=1e-10)
+    # active constraints: KKT of min ||M w - y||^2 over w >= 0
+    y2 = M @ np.array([1.0, -1.0, 0.5, -0.2, 0.8]) + 0.05 * r.normal(size=80)
+    w2, _, _ = F.m2_weights(M, y2)
+    g = np.real(M.conj().T @ (M @ w2 - y2))
+    assert (w2 >= 0).all() and (w2 == 0).any()
+    assert np.all(np.abs(g[w2 > 0]) < 1e-9 * np.abs(g).max() + 1e-12)
+    assert np.all(g[w2 == 0] > -1e-9 * np.abs(g).max())
+
+
+def test_m2_truncation_keeping_every_singular_value_is_the_plain_fit():
+    r = np.random.default_rng(6)
+    M = r.normal(size=(50, 7)) + 1j * r.normal(size=(50, 7))
+    y = r.normal(size=50) + 1j * r.normal(size=50)
+    w0, full0, red0 = F.m2_weights(M, y)
+    w1, full1, red1 = F.m2_weights(M, y, s=7)
+    U = np.linalg.svd(M, full_matrices=False)[0]
+    out = np.linalg.norm(y - U @ (U.conj().T @ y)) ** 2
+    assert np.allclose(w0, w1, atol=1e-12) and abs(full0 - (red1 + out)) < 1e-9 * full0
+    # a stronger truncation cannot lower the full residual below the untruncated optimum
+    w3, full3, _ = F.m2_weights(M, y, s=3)
+    assert full3 >= full0 * (1 - 1e-12)
