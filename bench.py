@@ -514,6 +514,28 @@ def bench_m1(args):
     torch.cuda.synchronize()
     fit_ms = e0.elapsed_time(e1) / reps
     fit_bytes = 2.0 * 2 * n_el * n_pos * 2 * (Kh + 1) * 8 + n_el * 2 * (Kh + 1) * 12
+    # model M2 on the same dictionary (untimed): scaled dictionary of the M1 fits, non-negative weights of
+    # the (D, K) pairs shared by all angles, truncated SVD keeping 3 % of the singular values and none
+    # (pairs with an unfinished instance at any angle are left out of the dictionary)
+    pair_ok = (stt.reshape(n_el, n_pos) == 0).all(1).reshape(-1, n_ang).all(1).cpu().numpy()
+    pairs = np.nonzero(pair_ok)[0]
+    J = int(pairs.size)
+    el = torch.as_tensor((pairs[:, None] * n_ang + np.arange(n_ang)[None, :]).reshape(-1), device="cuda:0")
+    phi2, a2 = phi[el].contiguous(), a[el].contiguous()
+    G, b, yy = ctx.m2_system(phi2, a2, S, n_ang, kset)
+    Gh, bh, yyh = G.cpu().numpy(), b.cpu().numpy(), float(yy.cpu().numpy()[0])
+    m2 = {"pairs": J}
+    for s_keep in (max(1, round(0.03 * J)), 0):
+        t2 = time.perf_counter()
+        w, full, red, rank = fpn.m2_weights(Gh, bh, yyh, s=s_keep)
+        t_w = time.perf_counter() - t2
+        model = ctx.m2_model(phi2, a2, w, n_ang)
+        err2 = ctx.rows_error(model, S)
+        _, eg2 = ctx.nrmse_global(err2, n_ang, kset)
+        top = np.argsort(-w)[:3]
+        m2[f"rank_{rank}"] = {"eps_global": float(eg2.cpu().numpy()[0]), "residual": full, "weights_s": t_w,
+                              "top_pairs": [{"D_nm": D_set[pairs[t] // len(K_set)] * 1e9,
+                                             "K": K_set[pairs[t] % len(K_set)], "w": float(w[t])} for t in top]}
     st = stt.cpu().numpy()
     egn = eg.cpu().numpy().reshape(len(D_set), len(K_set))
     usable = (st.reshape(n_el, n_pos) == 0).all(1).reshape(len(D_set), len(K_set), n_ang).all(2)
@@ -530,7 +552,8 @@ def bench_m1(args):
                    "L_counts": {str(int(l)): int((L == l).sum()) for l in np.unique(L)},
                    "truth": {"D_nm": 21.3, "K": 1170.0}, "recovered": {"D_nm": D_set[i] * 1e9, "K": K_set[j]},
                    "eps_global_min": float(egm[i, j]), "eps_global_map": np.round(egn, 5).tolist(),
-                   "unusable_pairs": int((~usable).sum()), "failed_instances": int((st != 0).sum())},
+                   "unusable_pairs": int((~usable).sum()), "failed_instances": int((st != 0).sum()),
+                   "m2": m2},
         "roofline": {"bound": "hbm", "kernel": "fit_rows", "achieved": fit_bytes / (fit_ms * 1e-3) / 1e9,
                      "peak": 8000.0, "unit": "GB/s", "frac": fit_bytes / (fit_ms * 1e-3) / 1e9 / 8000.0,
                      "traffic": None, "avg_launch_ms": fit_ms, "bytes_per_launch": fit_bytes},

@@ -424,6 +424,39 @@ fpn_status fpn_mixing_order(int32_t k, int32_t n_dens, int32_t* mx, int32_t* my)
  * count (HOST).  Errors: FPN_E_ARG. */
 fpn_status fpn_frequency_index_set(int32_t Mx, int32_t My, int32_t n_dens, int32_t* k_out, int32_t* count);
 
+/* Model M2 (paper: "Technical details regarding the parameter identification", M2: Eq. LSfitM2,
+ * Eq. LSfitM2_alternative, Eq. approx_low_rank).  The dictionary holds J parameter pairs at n_ang
+ * angles: element j * n_ang + theta of phi (layout as above), its M1 scale a [J * n_ang][n_ch][n_bins][2]
+ * (fpn_fit_rows's a_out for pairs in that order) and the measured matrices S [n_ang][...].  The
+ * weighted dictionary matrix M has rows (theta, c, k in kset, position) and columns j:
+ *   M[r][j] = a_{j,theta}(c,k) Phi_{j,theta}(nu,c,k) / max_nu |S_theta(nu,c,k)|,  y[r] = S_theta(nu,c,k) / (same)
+ * (the paper's per-frequency infinity-norm weighting, per receive channel).  This call forms, on the
+ * device with FP64 sums, G = M^H M (G_out [J][J][2], Hermitian), b = M^H y (b_out [J][2]) and
+ * yy_out = ||y||^2 (all DEVICE FP64).  Workspace: the context keeps M (J * rows complex FP32).
+ * Asynchronous.  Errors: FPN_E_ARG, FPN_E_RANGE (J > 8192 or more than 2^34 entries), FPN_E_NOMEM,
+ * FPN_E_DEVICE. */
+fpn_status fpn_m2_system(fpn_ctx ctx, const float* phi, const float* a, const float* S, int32_t n_pos, int32_t n_ch,
+                         int32_t n_bins, int32_t J, int32_t n_ang, const int32_t* kset, int32_t n_k, double* G_out,
+                         double* b_out, double* yy_out, void* stream);
+/* Non-negative weights of model M2 from G, b, yy (HOST arrays as fpn_m2_system writes them): the
+ * eigenvectors of G give the truncated SVD of M; with s > 0 only the s largest singular values are kept
+ * (s = 0: every eigenvalue above 1e-14 of the largest), and min over real w >= 0 of
+ * ||U_s^H (M w - y)||^2 is solved by a primal-dual interior-point method.  w_out [J] (HOST), resid_out
+ * (HOST, may be NULL) = ||M w - y||^2, reduced_out (may be NULL) = the truncated objective, rank_out (may
+ * be NULL) = the number of singular values kept.  No device needed.  Errors: FPN_E_ARG, FPN_E_RANGE (the
+ * interior-point iteration did not converge). */
+fpn_status fpn_m2_weights(int32_t J, const double* G, const double* b, double yy, int32_t s, double* w_out,
+                          double* resid_out, double* reduced_out, int32_t* rank_out);
+/* The M2 system matrices S_model[theta] = sum_j w_j a_{j,theta} Phi_{j,theta} (w DEVICE FP64 [J]; phi and a as
+ * for fpn_m2_system; model_out [n_ang][n_pos][n_ch][n_bins][2] DEVICE FP32, FP64 sums).  Asynchronous.
+ * Errors: FPN_E_ARG, FPN_E_RANGE, FPN_E_DEVICE. */
+fpn_status fpn_m2_model(fpn_ctx ctx, const float* phi, const float* a, const double* w, int32_t n_pos, int32_t n_ch,
+                        int32_t n_bins, int32_t J, int32_t n_ang, float* model_out, void* stream);
+/* Eq. error1 rows of n_mat model matrices against the measured ones of the same index (no fit):
+ * err_out [n_mat][n_ch][n_bins] (DEVICE FP32, FP64 sums).  Asynchronous.  Errors: FPN_E_ARG, FPN_E_DEVICE. */
+fpn_status fpn_rows_error(fpn_ctx ctx, const float* model, const float* S, int32_t n_pos, int32_t n_ch, int32_t n_bins,
+                          int64_t n_mat, float* err_out, void* stream);
+
 /* ---- allocation-free solve ----
  * For callers that cannot allocate device memory: code under HIP graph capture, tight serving loops,
  * harnesses that forbid hipMalloc.  The same solve as fpn_solve for a batch of ONE Galerkin degree

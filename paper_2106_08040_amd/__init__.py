@@ -44,7 +44,8 @@ EXPORTED = ["fpn_status_string", "fpn_last_error", "fpn_create", "fpn_destroy", 
             "fpn_solve_static", "fpn_mlp_shape", "fpn_surrogate_init", "fpn_surrogate_create", "fpn_surrogate_save",
             "fpn_surrogate_destroy", "fpn_surrogate_member", "fpn_surrogate_set_scales", "fpn_surrogate_view",
             "fpn_surrogate_infer", "fpn_surrogate_train_step", "fpn_fit_rows", "fpn_nrmse_global",
-            "fpn_mixing_order", "fpn_frequency_index_set"]
+            "fpn_mixing_order", "fpn_frequency_index_set", "fpn_m2_system", "fpn_m2_weights", "fpn_m2_model",
+            "fpn_rows_error"]
 
 
 class fpn_drive(ctypes.Structure):
@@ -176,6 +177,19 @@ _lib.fpn_fit_rows.argtypes = [_vp, _vp, _vp, ctypes.c_int32, ctypes.c_int32, cty
 _lib.fpn_nrmse_global.restype = ctypes.c_int32
 _lib.fpn_nrmse_global.argtypes = [_vp, _vp, ctypes.c_int64, ctypes.c_int32, ctypes.c_int32, ctypes.c_int32, _vp,
                                   ctypes.c_int32, _vp, _vp, _vp]
+_lib.fpn_m2_system.restype = ctypes.c_int32
+_lib.fpn_m2_system.argtypes = [_vp, _vp, _vp, _vp, ctypes.c_int32, ctypes.c_int32, ctypes.c_int32, ctypes.c_int32,
+                               ctypes.c_int32, _vp, ctypes.c_int32, _vp, _vp, _vp, _vp]
+_lib.fpn_m2_weights.restype = ctypes.c_int32
+_lib.fpn_m2_weights.argtypes = [ctypes.c_int32, ctypes.POINTER(ctypes.c_double), ctypes.POINTER(ctypes.c_double),
+                                ctypes.c_double, ctypes.c_int32, ctypes.POINTER(ctypes.c_double),
+                                ctypes.POINTER(ctypes.c_double), ctypes.POINTER(ctypes.c_double),
+                                ctypes.POINTER(ctypes.c_int32)]
+_lib.fpn_m2_model.restype = ctypes.c_int32
+_lib.fpn_m2_model.argtypes = [_vp, _vp, _vp, _vp, ctypes.c_int32, ctypes.c_int32, ctypes.c_int32, ctypes.c_int32,
+                              ctypes.c_int32, _vp, _vp]
+_lib.fpn_rows_error.restype = ctypes.c_int32
+_lib.fpn_rows_error.argtypes = [_vp, _vp, _vp, ctypes.c_int32, ctypes.c_int32, ctypes.c_int32, ctypes.c_int64, _vp, _vp]
 _lib.fpn_mixing_order.restype = ctypes.c_int32
 _lib.fpn_mixing_order.argtypes = [ctypes.c_int32, ctypes.c_int32, ctypes.POINTER(ctypes.c_int32),
                                   ctypes.POINTER(ctypes.c_int32)]
@@ -255,6 +269,21 @@ def frequency_index_set(Mx, My, n_dens=16):
     out = (ctypes.c_int32 * ((Mx + 1) * (My + 1)))()
     _check(_lib.fpn_frequency_index_set(int(Mx), int(My), int(n_dens), out, ctypes.byref(c)), "fpn_frequency_index_set")
     return np.array(out[:c.value], dtype=np.int32)
+
+
+def m2_weights(G, b, yy, s=0):
+    """fpn_m2_weights (host): G [J, J] and b [J] complex (numpy), yy float; returns
+    (w [J], ||M w - y||^2, truncated objective, singular values kept)."""
+    G = np.ascontiguousarray(np.asarray(G, dtype=np.complex128))
+    b = np.ascontiguousarray(np.asarray(b, dtype=np.complex128))
+    J = b.size
+    w = np.zeros(J)
+    full, red, rank = ctypes.c_double(), ctypes.c_double(), ctypes.c_int32()
+    pd = ctypes.POINTER(ctypes.c_double)
+    _check(_lib.fpn_m2_weights(J, G.view(np.float64).ctypes.data_as(pd), b.view(np.float64).ctypes.data_as(pd),
+                               float(yy), int(s), w.ctypes.data_as(pd), ctypes.byref(full), ctypes.byref(red),
+                               ctypes.byref(rank)), "fpn_m2_weights")
+    return w, full.value, red.value, rank.value
 
 
 def _torch():
@@ -555,6 +584,55 @@ class Context:
         _check(_lib.fpn_nrmse_global(self._h, err.data_ptr(), g, n_ang, n_ch, n_bins, ks.data_ptr(), ks.numel(),
                                      ef.data_ptr(), eg.data_ptr(), s.cuda_stream), "fpn_nrmse_global")
         return ef, eg
+
+    def m2_system(self, phi, a, S, n_ang, kset):
+        """fpn_m2_system: phi [J * n_ang, n_pos, n_ch, n_bins] and S [n_ang, ...] complex64, a [J * n_ang,
+        n_ch, n_bins] complex64 (device); returns (G [J, J] complex128, b [J] complex128, ||y||^2) on the device."""
+        torch = _torch()
+        dev = f"cuda:{self.device}"
+        phi, a, S = phi.contiguous(), a.contiguous(), S.contiguous()
+        n_el, n_pos, n_ch, n_bins = phi.shape
+        assert n_el % n_ang == 0 and S.shape == (n_ang, n_pos, n_ch, n_bins) and a.shape == (n_el, n_ch, n_bins)
+        J = n_el // n_ang
+        ks = torch.as_tensor(kset, dtype=torch.int32, device=dev).contiguous()
+        assert int(ks.min()) >= 0 and int(ks.max()) < n_bins
+        G = torch.empty((J, J, 2), dtype=torch.float64, device=dev)
+        b = torch.empty((J, 2), dtype=torch.float64, device=dev)
+        yy = torch.empty((1,), dtype=torch.float64, device=dev)
+        s = torch.cuda.current_stream(self.device)
+        _check(_lib.fpn_m2_system(self._h, torch.view_as_real(phi).data_ptr(), torch.view_as_real(a).data_ptr(),
+                                  torch.view_as_real(S).data_ptr(), n_pos, n_ch, n_bins, J, n_ang, ks.data_ptr(),
+                                  ks.numel(), G.data_ptr(), b.data_ptr(), yy.data_ptr(), s.cuda_stream), "fpn_m2_system")
+        return torch.view_as_complex(G), torch.view_as_complex(b), yy
+
+    def m2_model(self, phi, a, w, n_ang):
+        """fpn_m2_model: S_model [n_ang, n_pos, n_ch, n_bins] complex64 from weights w [J] (float64)."""
+        torch = _torch()
+        dev = f"cuda:{self.device}"
+        phi, a = phi.contiguous(), a.contiguous()
+        n_el, n_pos, n_ch, n_bins = phi.shape
+        J = n_el // n_ang
+        wt = torch.as_tensor(w, dtype=torch.float64, device=dev).contiguous()
+        assert wt.numel() == J
+        out = torch.empty((n_ang, n_pos, n_ch, n_bins, 2), dtype=torch.float32, device=dev)
+        s = torch.cuda.current_stream(self.device)
+        _check(_lib.fpn_m2_model(self._h, torch.view_as_real(phi).data_ptr(), torch.view_as_real(a).data_ptr(),
+                                 wt.data_ptr(), n_pos, n_ch, n_bins, J, n_ang, out.data_ptr(), s.cuda_stream),
+               "fpn_m2_model")
+        return torch.view_as_complex(out)
+
+    def rows_error(self, model, S):
+        """fpn_rows_error: Eq. error1 rows [n_mat, n_ch, n_bins] of model against S (same shapes)."""
+        torch = _torch()
+        dev = f"cuda:{self.device}"
+        model, S = model.contiguous(), S.contiguous()
+        n_mat, n_pos, n_ch, n_bins = S.shape
+        assert model.shape == S.shape
+        err = torch.empty((n_mat, n_ch, n_bins), dtype=torch.float32, device=dev)
+        s = torch.cuda.current_stream(self.device)
+        _check(_lib.fpn_rows_error(self._h, torch.view_as_real(model).data_ptr(), torch.view_as_real(S).data_ptr(),
+                                   n_pos, n_ch, n_bins, n_mat, err.data_ptr(), s.cuda_stream), "fpn_rows_error")
+        return err
 
     def stationary(self, inst, L, field):
         torch = _torch()

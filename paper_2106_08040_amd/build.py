@@ -79,6 +79,8 @@ def build(jobs=8, verbose=False, out=None, build_dir=None, extra=(), incremental
         [HIPCC, *HIP_FLAGS, "-c", os.path.join(CSRC, "fit.hip"), "-o", os.path.join(BUILD, "fit.o")],
         ["g++", "-O2", "-std=c++17", "-fPIC", "-c", os.path.join(CSRC, "structure.cpp"),
          "-o", os.path.join(BUILD, "structure.o")],
+        ["g++", "-O2", "-std=c++17", "-fPIC", "-c", os.path.join(CSRC, "m2_host.cpp"),
+         "-o", os.path.join(BUILD, "m2_host.o")],
     ]
     if incremental:
         hdrs = [os.path.join(CSRC, f) for f in os.listdir(CSRC) if f.endswith((".hpp", ".h"))]
@@ -99,7 +101,7 @@ def build(jobs=8, verbose=False, out=None, build_dir=None, extra=(), incremental
           os.path.join(BUILD, "mlp.o"), os.path.join(BUILD, "capi_mlp.o"),
           os.path.join(BUILD, "surrogate.o"), os.path.join(BUILD, "capi_surrogate.o"),
           os.path.join(BUILD, "capi_static.o"), os.path.join(BUILD, "capi_surmodel.o"),
-          os.path.join(BUILD, "fit.o"),
+          os.path.join(BUILD, "fit.o"), os.path.join(BUILD, "m2_host.o"),
           f"-L{hiplib}", "-l:libamdhip64.so", f"-Wl,-rpath,{hiplib}:/opt/rocm/lib", "-lstdc++"])
     os.replace(tmp, LIB)
     return LIB

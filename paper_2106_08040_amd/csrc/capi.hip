@@ -337,6 +337,8 @@ fpn_status fpn_destroy(fpn_ctx ctx) {
   ctx->idx.release();
   ctx->steps.release();
   ctx->wide_ws.release();
+  ctx->m2_mt.release();
+  ctx->m2_y.release();
   for (fpn_plan_s* pl : {ctx->solve_plan, ctx->tangent_plan}) {
     if (pl) {
       plan_release(pl);

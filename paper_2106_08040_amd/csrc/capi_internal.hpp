@@ -97,6 +97,8 @@ struct fpn_ctx_s {
   fpn_internal::DevBuf<float> sur_x, sur_ya, sur_yb, sur_h;
   fpn_internal::DevBuf<int32_t> sur_list, sur_count, sur_st;
   fpn_internal::DevBuf<double> sur_g;
+  // model M2 dictionary matrix (transposed) and data vector, complex FP32 as float pairs
+  fpn_internal::DevBuf<float> m2_mt, m2_y;
   // kernel timing
   bool timing = false;
   std::vector<std::pair<int, std::pair<hipEvent_t, hipEvent_t>>> events;

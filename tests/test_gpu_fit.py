@@ -154,3 +154,68 @@ def test_m1_pipeline_matches_oracle_pipeline(fpn, ctx):
     assert np.max(np.abs(err - er)[:, :, kset] / er[:, :, kset]) < 1e-4
     assert np.allclose(eg, egr, rtol=1e-5)
     assert int(np.argmin(eg)) == int(np.argmin(egr))
+
+
+def test_m2_system_model_and_rows_error_match_oracle(fpn, ctx):
+    """fpn_m2_system (G = M^H M, b = M^H y, ||y||^2 of the weighted M2 dictionary), fpn_m2_model and
+    fpn_rows_error against the oracle's M2 system, model and Eq. error1 on seeded synthetic inputs."""
+    import torch
+    J, n_ang, n_pos, n_ch, n_bins = 5, 3, 25, 2, 20
+    phi = W.random_system_matrices(J * n_ang, n_pos, n_ch, n_bins, seed=11)
+    a = W.random_system_matrices(1, J * n_ang, n_ch, n_bins, seed=12)[0]
+    S = W.random_system_matrices(n_ang, n_pos, n_ch, n_bins, seed=13)
+    kset = np.array([1, 4, 5, 9, 17])
+    dev = "cuda:0"
+    G, b, yy = ctx.m2_system(torch.tensor(phi, device=dev), torch.tensor(a, device=dev), torch.tensor(S, device=dev),
+                             n_ang, kset)
+    G, b, yy = G.cpu().numpy(), b.cpu().numpy(), float(yy.cpu().numpy()[0])
+    # oracle: Psi [J, angles, channels, bins, N] = a * Phi
+    ph = phi.astype(complex).reshape(J, n_ang, n_pos, n_ch, n_bins).transpose(0, 1, 3, 4, 2)
+    av = a.astype(complex).reshape(J, n_ang, n_ch, n_bins)
+    Psi = av[..., None] * ph
+    Sm = S.astype(complex).transpose(0, 2, 3, 1)
+    M, y = F.m2_system(Psi, Sm, kset)
+    Gr, br, yyr = M.conj().T @ M, M.conj().T @ y, float(np.vdot(y, y).real)
+    print(f"G {np.abs(G - Gr).max() / np.abs(Gr).max():.2e}  b {np.abs(b - br).max() / np.abs(br).max():.2e}  "
+          f"yy {abs(yy - yyr) / yyr:.2e}", flush=True)
+    assert np.abs(G - Gr).max() <= 1e-6 * np.abs(Gr).max()
+    assert np.abs(b - br).max() <= 1e-6 * np.abs(br).max()
+    assert abs(yy - yyr) <= 1e-6 * yyr
+    w = np.array([0.5, 0.0, 1.25, 2.0, 0.1])
+    model = ctx.m2_model(torch.tensor(phi, device=dev), torch.tensor(a, device=dev), w, n_ang)
+    mref = F.m2_model(Psi, w)                       # [angles, channels, bins, N]
+    mg = model.cpu().numpy().astype(complex).transpose(0, 2, 3, 1)
+    assert np.abs(mg - mref).max() <= 2e-6 * np.abs(mref).max()
+    err = ctx.rows_error(model, torch.tensor(S, device=dev)).cpu().numpy()
+    eref = F.nrmse_rows(Sm, mref)
+    assert np.allclose(err, eref, rtol=2e-6)
+
+
+def test_m2_weights_from_device_system_match_oracle(fpn, ctx):
+    """The M2 weights from the device-formed system (fpn_m2_system, then fpn_m2_weights on the host)
+    against the oracle's SVD + NNLS on the same seeded dictionary: truncated objective and, untruncated,
+    the weights."""
+    import torch
+    J, n_ang, n_pos, n_ch, n_bins = 6, 2, 30, 2, 12
+    phi = W.random_system_matrices(J * n_ang, n_pos, n_ch, n_bins, seed=21)
+    a = W.random_system_matrices(1, J * n_ang, n_ch, n_bins, seed=22)[0]
+    # a measurement that is a noisy non-negative superposition of the dictionary
+    ph = phi.astype(complex).reshape(J, n_ang, n_pos, n_ch, n_bins)
+    av = a.astype(complex).reshape(J, n_ang, 1, n_ch, n_bins)
+    wt = np.array([0.7, 0.0, 1.1, 0.0, 0.4, 0.9])
+    S = (np.tensordot(wt, av * ph, axes=(0, 0)) + 0.2 * W.random_system_matrices(n_ang, n_pos, n_ch, n_bins, seed=23)
+         ).astype(np.complex64)
+    kset = np.arange(1, n_bins)
+    dev = "cuda:0"
+    G, b, yy = ctx.m2_system(torch.tensor(phi, device=dev), torch.tensor(a, device=dev), torch.tensor(S, device=dev),
+                             n_ang, kset)
+    G, b, yy = G.cpu().numpy(), b.cpu().numpy(), float(yy.cpu().numpy()[0])
+    Psi = av.transpose(0, 1, 3, 4, 2) * ph.transpose(0, 1, 3, 4, 2)
+    M, y = F.m2_system(Psi, S.astype(complex).transpose(0, 2, 3, 1), kset)
+    for s in (0, 4):
+        w, full, red, rank = fpn.m2_weights(G, b, yy, s=s)
+        wo, fullo, redo = F.m2_weights(M, y, s=None if s == 0 else s)
+        print(f"s={s}: rank {rank}, objective {red:.6e} vs oracle {redo:.6e}", flush=True)
+        assert abs(red - redo) <= 1e-5 * yy
+        if s == 0:
+            assert np.allclose(w, wo, atol=1e-4 * wo.max())

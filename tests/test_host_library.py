@@ -111,3 +111,26 @@ def test_mixing_orders_and_frequency_set_match_oracle_bit_exact():
         assert np.array_equal(fpn.frequency_index_set(Mx, My), F.frequency_index_set(Mx, My).astype(np.int32))
     with pytest.raises(fpn.FpnError):
         fpn.mixing_order(5, 0)
+
+
+@pytest.mark.parametrize("s", [0, 3, 6])
+def test_m2_weights_match_oracle(s):
+    """fpn_m2_weights (host: Hermitian Jacobi eigenvectors of G = M^H M, interior point) against the
+    oracle (SVD of M, Lawson-Hanson NNLS) on a random complex dictionary with active constraints: the
+    truncated objective (the quantity the paper minimises) agrees; untruncated, the minimiser is unique
+    and the weights agree too."""
+    import paper_2106_08040_amd as fpn
+    from oracle import fit_oracle as F
+    r = np.random.default_rng(20 + s)
+    M = r.normal(size=(300, 9)) + 1j * r.normal(size=(300, 9))
+    M[:, 1] = M[:, 0] * 0.9 + 0.1 * M[:, 1]     # nearly dependent columns, as in a fine dictionary
+    y = M @ np.array([1.0, 0.0, 0.5, 0.0, 2.0, 0.3, 0.0, 0.0, 1.0]) + 0.3 * (r.normal(size=300) + 1j * r.normal(size=300))
+    G, b, yy = M.conj().T @ M, M.conj().T @ y, float(np.vdot(y, y).real)
+    w, full, red, rank = fpn.m2_weights(G, b, yy, s=s)
+    wo, fullo, redo = F.m2_weights(M, y, s=None if s == 0 else s)
+    assert rank == (9 if s == 0 else s)
+    assert (w >= 0).all()
+    assert abs(red - redo) <= 1e-9 * yy
+    assert abs(full - float(np.linalg.norm(M @ w - y) ** 2)) <= 1e-9 * full
+    if s == 0:
+        assert np.allclose(w, wo, atol=1e-6 * wo.max())
