@@ -607,26 +607,23 @@ def bench_surrogate(args):
     hte, _, t_te, _ = solve(te)
     print(f"[bench] training targets: {len(tr['inst']['D'])} solves in {t_tr:.1f} s", file=sys.stderr, flush=True)
     sur = Surrogate(ctx, KH)
-    sur.fit(tr["inst"], htr, steps=args.sur_steps, batch=4096, lr=2e-3)
+    sur.fit(tr["inst"], htr, steps=args.sur_steps, batch=4096, lr=2e-3, residual_steps=args.sur_res_steps)
     true_va, _ = sur.calibrate(va["inst"], hva)
     ev = surrogate_domain(0, 0, n_off=64, n_ang=64)
     n_ev = ev["inst"]["D"].size
     x, _ = ctx.surrogate_features(ev["inst"])
-    ya = torch.empty((n_ev, 4 * KH), dtype=torch.float32, device="cuda:0")
-    yb = torch.empty_like(ya)
-    for net, y in zip(sur.nets, (ya, yb)):  # warm-up
-        net.forward(x, out=y)
+    sur.model.infer(x)  # warm-up
     torch.cuda.synchronize()
     reps = 5
     e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
     e0.record()
     for _ in range(reps):
-        for net, y in zip(sur.nets, (ya, yb)):
-            net.forward(x, out=y)
+        sur.model.infer(x)   # fpn_surrogate_infer: every network (residual stage included), mean and estimate
     e1.record()
     torch.cuda.synchronize()
-    t_inf = e0.elapsed_time(e1) / reps * 1e-3  # both members, all evaluations
-    flops = 2.0 * 2 * n_ev * sum(a * b for a, b in zip(sur.nets[0].widths[:-1], sur.nets[0].widths[1:]))
+    t_inf = e0.elapsed_time(e1) / reps * 1e-3
+    n_nets = 2 * (2 if sur.model.residual else 1)
+    flops = 2.0 * n_nets * n_ev * sum(a * b for a, b in zip(sur.nets[0].widths[:-1], sur.nets[0].widths[1:]))
     solver_rate = len(te["inst"]["D"]) / t_te
     res_tol = {}
     for tol in (1e-3, 1e-2, 3e-2):
@@ -645,15 +642,16 @@ def bench_surrogate(args):
         "warmup": 1, "ms_per_step": t_inf * 1e3, "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
         "dtype": "bf16", "data": "synthetic",
         "config": {"workload": "surrogate_lissajous_family_64x64x64", "evaluations": n_ev, "harmonics": KH,
-                   "network": sur.nets[0].widths, "ensemble": 2, "train_instances": len(tr["inst"]["D"]),
-                   "train_steps": args.sur_steps, "train_seconds": sur.train_seconds,
+                   "network": sur.nets[0].widths, "ensemble": 2, "residual_stage": bool(sur.model.residual),
+                   "train_instances": len(tr["inst"]["D"]), "train_steps": args.sur_steps,
+                   "residual_train_steps": args.sur_res_steps, "train_seconds": sur.train_seconds,
                    "validation_rel_l2_median": float(np.median(true_va)),
                    "validation_rel_l2_p99": float(np.quantile(true_va, 0.99)), "err_calibration": sur.err_calib,
                    "inference_evals_per_s": n_ev / t_inf, "solver_solves_per_s": solver_rate,
                    "by_tolerance": res_tol},
-        "roofline": {"bound": "mfma", "kernel": "gemm_nt_kernel (all layers, both members)", "achieved": achieved,
+        "roofline": {"bound": "mfma", "kernel": "gemm_nt_kernel (all layers, every network)", "achieved": achieved,
                      "peak": 2500.0, "unit": "TFLOP/s", "frac": achieved / 2500.0, "traffic": None,
-                     "flops_per_forward": flops / 2},
+                     "flops_per_network": flops / n_nets},
     }
     print(json.dumps(out), flush=True)
     sur.close()
@@ -671,6 +669,8 @@ def main():
     ap.add_argument("--cpu-budget", type=float, default=15.0)
     ap.add_argument("--sur-train", type=int, default=32768, help="surrogate workload: solver-generated training instances")
     ap.add_argument("--sur-steps", type=int, default=16000, help="surrogate workload: Adam steps per member")
+    ap.add_argument("--sur-res-steps", type=int, default=16000,
+                    help="surrogate workload: Adam steps per member of the residual stage (0: none)")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="run only a plain 256 MiB device copy three times (reference for the FETCH_SIZE / "
                          "WRITE_SIZE counters) and exit")

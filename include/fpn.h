@@ -309,13 +309,18 @@ fpn_status fpn_mlp_train_step(fpn_mlp m, const float* x, const float* t, int64_t
  * instance features, with the solver as the fallback and as the reference its error is measured against:
  *   features x = (log D, log K, alpha, n_x, n_y, n_z, offset_x / 12 mT, offset_y / 12 mT), the axis
  *   taken in the half-space n_z > 0 (n and -n describe the same particle); K must be > 0;
- *   prediction = (y_a + y_b) / 2 / out_scale, network output layout [channel x, y][k = 1..K_h][re, im];
+ *   prediction = (y_a + y_b) / 2 / out_scale, network output layout [channel x, y][k = 1..K_h][re, im]
+ *   (y_k = net[k](x), plus res[k](x) / res_scale with a residual stage);
  *   error estimate = err_calib * ||y_a - y_b|| / ||(y_a + y_b) / 2||  (err_calib is fitted on held-out
  *   solver results so that the estimate bounds the relative L2 error of the prediction). */
 typedef struct {
   fpn_mlp net[2];     /* widths: 8 inputs, 4 * K_h outputs, identical shapes */
   float out_scale;    /* network output = Phi [1/s] * out_scale */
   float err_calib;    /* > 0 */
+  fpn_mlp res[2];     /* optional residual stage (both NULL: none), same widths: member k's output is
+                         net[k](x) + res[k](x) / res_scale, res[k] trained on the residual of net[k]
+                         multiplied by res_scale */
+  float res_scale;    /* > 0 when res[] is set */
 } fpn_surrogate;
 
 /* Features x [n][8] (DEVICE FP32) and status [n] (FPN_INST_BAD_PARAM for non-physical instances,
@@ -341,12 +346,14 @@ fpn_status fpn_surrogate_predict(fpn_ctx ctx, const fpn_surrogate* sur, double t
  * (in this or another process, on any device).  Calls on one model must not overlap.
  *
  * File format (little-endian, written by fpn_surrogate_save):
- *   char magic[8] = "FPNSUR1\0"; uint32 version = 1; int32 n_layers; int32 widths[n_layers + 1];
- *   float out_scale; float err_calib;
- *   then for each member k = 0, 1: int64 adam_steps; float norm[2 * widths[0]] (input mean, then
- *   1 / std, as the network applies them); float params[P]; float adam_m[P]; float adam_v[P]
- *   (P = sum over layers of (in + 1) * out, layout as fpn_mlp_params);
+ *   char magic[8] = "FPNSUR1\0"; uint32 version = 2; int32 n_layers; int32 widths[n_layers + 1];
+ *   float out_scale; float err_calib; int32 has_residual; float res_scale;
+ *   then for each member k = 0, 1 (and, with a residual stage, its members 2, 3): int64 adam_steps;
+ *   float norm[2 * widths[0]] (input mean, then 1 / std, as the network applies them);
+ *   float params[P]; float adam_m[P]; float adam_v[P] (P = sum over layers of (in + 1) * out, layout
+ *   as fpn_mlp_params);
  *   uint64 FNV-1a hash of every preceding byte.
+ * Version-1 files (no residual fields or members) are read as well.
  * A model read back evaluates bit for bit as the one saved, and continues training from the same
  * Adam state. */
 typedef struct fpn_sur_model_s* fpn_sur_model;
@@ -362,21 +369,29 @@ fpn_status fpn_surrogate_create(fpn_ctx ctx, const char* weights_path, fpn_sur_m
 /* Write the model to `path` (synchronises the device).  Errors: FPN_E_ARG, FPN_E_IO, FPN_E_DEVICE. */
 fpn_status fpn_surrogate_save(fpn_sur_model m, const char* path);
 fpn_status fpn_surrogate_destroy(fpn_sur_model m);
-/* Member k (0 or 1) as an fpn_mlp handle owned by the model (for fpn_mlp_* calls: input
- * normalisation, parameters, per-member training). */
+/* Member k as an fpn_mlp handle owned by the model (for fpn_mlp_* calls: input normalisation,
+ * parameters, per-member training): k = 0, 1 the ensemble, k = 2, 3 the residual stage (FPN_E_ARG if
+ * the model has none). */
 fpn_status fpn_surrogate_member(fpn_sur_model m, int32_t k, fpn_mlp* out);
+/* Add a residual stage: two networks of the members' widths, member k initialised from seeds[k]
+ * (HOST), res_scale = 1; FPN_E_ARG if the model has one.  Errors: FPN_E_ARG, FPN_E_NOMEM, FPN_E_DEVICE. */
+fpn_status fpn_surrogate_add_residual(fpn_ctx ctx, fpn_sur_model m, const uint64_t seeds[2]);
+/* res_scale of the residual stage (finite, > 0; FPN_E_ARG without a stage). */
+fpn_status fpn_surrogate_set_residual_scale(fpn_sur_model m, float res_scale);
 /* out_scale: network output = prediction * out_scale; err_calib: the estimate's constant.  Both finite
  * and > 0, else FPN_E_ARG. */
 fpn_status fpn_surrogate_set_scales(fpn_sur_model m, float out_scale, float err_calib);
 /* Fill an fpn_surrogate (non-owning view: member handles and scales) for fpn_surrogate_predict. */
 fpn_status fpn_surrogate_view(fpn_sur_model m, fpn_surrogate* view);
 /* Ensemble evaluation without fallback: y [n][W] = (y_a + y_b) / 2 / out_scale (W = output width, the
- * networks' layout) and err_est [n] = err_calib * ||y_a - y_b|| / ||(y_a + y_b) / 2||, from features
+ * networks' layout; y_k includes the residual stage) and err_est [n] = err_calib * ||y_a - y_b|| /
+ * ||(y_a + y_b) / 2||, from features
  * x [n][widths[0]] (all DEVICE FP32; y or err_est may be NULL, not both).  n <= 2^30.  Asynchronous.
  * Errors: FPN_E_ARG, FPN_E_NOMEM, FPN_E_DEVICE. */
 fpn_status fpn_surrogate_infer(fpn_ctx ctx, fpn_sur_model m, const float* x, int64_t n, float* y, float* err_est,
                                void* stream);
-/* One Adam step (fpn_mlp_train_step) of each member on the same minibatch: features x [n][widths[0]],
+/* One Adam step (fpn_mlp_train_step) of each ensemble member (not the residual stage, which is trained
+ * through its member handles) on the same minibatch: features x [n][widths[0]],
  * targets y_true [n][W] in prediction units (multiplied by out_scale inside); loss_out (DEVICE, two
  * doubles, may be NULL) receives each member's summed squared error in network units.  1 <= n <= 2^22.
  * Asynchronous.  Errors: FPN_E_ARG, FPN_E_NOMEM, FPN_E_DEVICE. */

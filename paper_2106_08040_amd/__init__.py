@@ -45,7 +45,7 @@ EXPORTED = ["fpn_status_string", "fpn_last_error", "fpn_create", "fpn_destroy", 
             "fpn_surrogate_destroy", "fpn_surrogate_member", "fpn_surrogate_set_scales", "fpn_surrogate_view",
             "fpn_surrogate_infer", "fpn_surrogate_train_step", "fpn_fit_rows", "fpn_nrmse_global",
             "fpn_mixing_order", "fpn_frequency_index_set", "fpn_m2_system", "fpn_m2_weights", "fpn_m2_model",
-            "fpn_rows_error"]
+            "fpn_rows_error", "fpn_surrogate_add_residual", "fpn_surrogate_set_residual_scale"]
 
 
 class fpn_drive(ctypes.Structure):
@@ -147,7 +147,8 @@ _lib.fpn_plan_destroy.argtypes = [_vp]
 
 
 class fpn_surrogate(ctypes.Structure):
-    _fields_ = [("net", _vp * 2), ("out_scale", ctypes.c_float), ("err_calib", ctypes.c_float)]
+    _fields_ = [("net", _vp * 2), ("out_scale", ctypes.c_float), ("err_calib", ctypes.c_float),
+                ("res", _vp * 2), ("res_scale", ctypes.c_float)]
 
 
 _lib.fpn_surrogate_features.restype = ctypes.c_int32
@@ -163,6 +164,10 @@ _lib.fpn_surrogate_destroy.restype = ctypes.c_int32
 _lib.fpn_surrogate_destroy.argtypes = [_vp]
 _lib.fpn_surrogate_member.restype = ctypes.c_int32
 _lib.fpn_surrogate_member.argtypes = [_vp, ctypes.c_int32, ctypes.POINTER(_vp)]
+_lib.fpn_surrogate_add_residual.restype = ctypes.c_int32
+_lib.fpn_surrogate_add_residual.argtypes = [_vp, _vp, ctypes.POINTER(ctypes.c_uint64)]
+_lib.fpn_surrogate_set_residual_scale.restype = ctypes.c_int32
+_lib.fpn_surrogate_set_residual_scale.argtypes = [_vp, ctypes.c_float]
 _lib.fpn_surrogate_set_scales.restype = ctypes.c_int32
 _lib.fpn_surrogate_set_scales.argtypes = [_vp, ctypes.c_float, ctypes.c_float]
 _lib.fpn_surrogate_view.restype = ctypes.c_int32
@@ -758,21 +763,35 @@ class SurrogateModel:
             w = (ctypes.c_int32 * len(ws))(*ws)
             sd = (ctypes.c_uint64 * 2)(*[int(x) for x in seeds])
             _check(_lib.fpn_surrogate_init(ctx._h, len(ws) - 1, w, sd, ctypes.byref(self._h)), "fpn_surrogate_init")
+        self._refresh()
+
+    def _refresh(self):
         sur = fpn_surrogate()
         _check(_lib.fpn_surrogate_view(self._h, ctypes.byref(sur)), "fpn_surrogate_view")
         self.out_scale, self.err_calib = float(sur.out_scale), float(sur.err_calib)
-        self.members = []
-        for k in range(2):
+        self.res_scale = float(sur.res_scale)
+        self.members, self.residual = [], []
+        for k in range(4 if sur.res[0] else 2):
             h = _vp()
             _check(_lib.fpn_surrogate_member(self._h, k, ctypes.byref(h)), "fpn_surrogate_member")
             nl = ctypes.c_int32()
             wb = (ctypes.c_int32 * 17)()
             _check(_lib.fpn_mlp_shape(h, ctypes.byref(nl), wb), "fpn_mlp_shape")
-            self.members.append(MLP(ctx, list(wb[:nl.value + 1]), handle=h))
+            (self.members if k < 2 else self.residual).append(MLP(self.ctx, list(wb[:nl.value + 1]), handle=h))
         self.widths = self.members[0].widths
 
+    def add_residual(self, seeds=(3, 4)):
+        """fpn_surrogate_add_residual: a second stage of two networks trained on the members' residuals."""
+        sd = (ctypes.c_uint64 * 2)(*[int(x) for x in seeds])
+        _check(_lib.fpn_surrogate_add_residual(self.ctx._h, self._h, sd), "fpn_surrogate_add_residual")
+        self._refresh()
+
+    def set_residual_scale(self, res_scale):
+        _check(_lib.fpn_surrogate_set_residual_scale(self._h, float(res_scale)), "fpn_surrogate_set_residual_scale")
+        self._refresh()
+
     def close(self):
-        for m in getattr(self, "members", []):
+        for m in getattr(self, "members", []) + getattr(self, "residual", []):
             m.close()
         if self._h:
             _lib.fpn_surrogate_destroy(self._h)

@@ -69,7 +69,7 @@ fpn_status get_tables(fpn_ctx ctx, int L, const fpn::DevTables** out) {
   const int Np = h->Np;
   std::vector<uint16_t> ecol(size_t(fpn::kNSlRow) * Np, 0), crow(size_t(fpn::kNSlCol) * Np, 0);
   std::vector<float> eval(size_t(fpn::kNSlRow) * Np, 0.0f), cvl(size_t(fpn::kNSlCol) * Np, 0.0f);
-  std::vector<float> elo(size_t(fpn::kNSlD) * Np, 0.0f);  // value - float(value) of the diagonal-block slots
+  std::vector<float> elo(size_t(fpn::kNSlRow) * Np, 0.0f);  // value - float(value) of every row slot
   std::vector<int> blk_of(Np);
   for (int k = 0; k <= L; ++k)
     for (int p = h->boff[k]; p < h->boff[k] + h->bn[k]; ++p) blk_of[p] = k;
@@ -103,7 +103,7 @@ fpn_status get_tables(fpn_ctx ctx, int L, const fpn::DevTables** out) {
       const int count = rel == 0 ? fpn::kNSlD : (rel < 0 ? fpn::kNSlB : fpn::kNSlC);
       const int slot = place(ecol, eval, fpn::kSlotKindRow, first, count, p, kind, col, v);
       if (slot < 0) return fail(FPN_E_RANGE, "operator row does not fit the fixed-slot layout");
-      if (rel == 0) elo[size_t(slot - fpn::kSlD) * Np + p] = float(h->val64[e] - double(v));
+      elo[size_t(slot) * Np + p] = float(h->val64[e] - double(v));
       if (rel > 0 && place(crow, cvl, fpn::kSlotKindCol, 0, fpn::kNSlCol, col, kind, p, v) < 0)
         return fail(FPN_E_RANGE, "operator column does not fit the fixed-slot layout");
     }
@@ -345,7 +345,7 @@ fpn_status fpn_destroy(fpn_ctx ctx) {
       delete pl;
     }
   }
-  for (auto* b : {&ctx->sur_x, &ctx->sur_ya, &ctx->sur_yb, &ctx->sur_h}) b->release();
+  for (auto* b : {&ctx->sur_x, &ctx->sur_ya, &ctx->sur_yb, &ctx->sur_h, &ctx->sur_r}) b->release();
   for (auto* b : {&ctx->sur_list, &ctx->sur_count, &ctx->sur_st}) b->release();
   ctx->sur_g.release();
   for (auto& e : ctx->events) {

@@ -94,7 +94,7 @@ struct fpn_ctx_s {
   fpn_internal::DevBuf<float> wide_ws;  // wide-layout stepper: block inverses and stage vectors
   int64_t steps_n = 0;
   // surrogate evaluation workspace
-  fpn_internal::DevBuf<float> sur_x, sur_ya, sur_yb, sur_h;
+  fpn_internal::DevBuf<float> sur_x, sur_ya, sur_yb, sur_h, sur_r;
   fpn_internal::DevBuf<int32_t> sur_list, sur_count, sur_st;
   fpn_internal::DevBuf<double> sur_g;
   // model M2 dictionary matrix (transposed) and data vector, complex FP32 as float pairs
@@ -176,5 +176,7 @@ struct fpn_sur_model_s {
   fpn_mlp net[2] = {nullptr, nullptr};
   float out_scale = 1.0f;
   float err_calib = 1.0f;
-  fpn_internal::DevBuf<float> ya, yb, t;
+  fpn_mlp res[2] = {nullptr, nullptr};  // optional residual stage
+  float res_scale = 1.0f;
+  fpn_internal::DevBuf<float> ya, yb, t, r;
 };

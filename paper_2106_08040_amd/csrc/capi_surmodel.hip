@@ -18,7 +18,7 @@ using namespace fpn_internal;
 namespace {
 
 constexpr char kMagic[8] = {'F', 'P', 'N', 'S', 'U', 'R', '1', '\0'};
-constexpr uint32_t kVersion = 1;
+constexpr uint32_t kVersion = 2;
 
 // FNV-1a over the bytes written before the trailer (detects truncated or altered files)
 struct Fnv {
@@ -52,11 +52,13 @@ struct Reader {
 };
 
 fpn_status free_model(fpn_sur_model m) {
-  for (fpn_mlp& n : m->net)
-    if (n) {
-      fpn_mlp_destroy(n);
-      n = nullptr;
-    }
+  for (fpn_mlp* arr : {m->net, m->res})
+    for (int k = 0; k < 2; ++k)
+      if (arr[k]) {
+        fpn_mlp_destroy(arr[k]);
+        arr[k] = nullptr;
+      }
+  m->r.release();
   m->ya.release();
   m->yb.release();
   m->t.release();
@@ -90,8 +92,33 @@ fpn_status fpn_surrogate_destroy(fpn_sur_model m) {
 }
 
 fpn_status fpn_surrogate_member(fpn_sur_model m, int32_t k, fpn_mlp* out) {
-  if (!m || !out || k < 0 || k > 1) return fail(FPN_E_ARG, "NULL model or output, or member not 0 or 1");
-  *out = m->net[k];
+  if (!m || !out || k < 0 || k > 3) return fail(FPN_E_ARG, "NULL model or output, or member not in 0..3");
+  if (k >= 2 && !m->res[0]) return fail(FPN_E_ARG, "the model has no residual stage");
+  *out = k < 2 ? m->net[k] : m->res[k - 2];
+  return FPN_OK;
+}
+
+fpn_status fpn_surrogate_add_residual(fpn_ctx ctx, fpn_sur_model m, const uint64_t seeds[2]) {
+  if (!ctx || !m || !seeds) return fail(FPN_E_ARG, "NULL argument");
+  if (m->res[0]) return fail(FPN_E_ARG, "the model already has a residual stage");
+  if (m->device != ctx->device) return fail(FPN_E_ARG, "model on another device");
+  const std::vector<int>& w = m->net[0]->w;
+  std::vector<int32_t> w32(w.begin(), w.end());
+  for (int k = 0; k < 2; ++k)
+    if (fpn_status e = fpn_mlp_create(ctx, int32_t(w32.size()) - 1, w32.data(), seeds[k], &m->res[k])) {
+      if (m->res[0]) fpn_mlp_destroy(m->res[0]);
+      m->res[0] = m->res[1] = nullptr;
+      return e;
+    }
+  m->res_scale = 1.0f;
+  return FPN_OK;
+}
+
+fpn_status fpn_surrogate_set_residual_scale(fpn_sur_model m, float res_scale) {
+  if (!m) return fail(FPN_E_ARG, "NULL model");
+  if (!m->res[0]) return fail(FPN_E_ARG, "the model has no residual stage");
+  if (!(res_scale > 0.0f) || !std::isfinite(res_scale)) return fail(FPN_E_ARG, "res_scale must be finite and > 0");
+  m->res_scale = res_scale;
   return FPN_OK;
 }
 
@@ -110,6 +137,9 @@ fpn_status fpn_surrogate_view(fpn_sur_model m, fpn_surrogate* view) {
   view->net[1] = m->net[1];
   view->out_scale = m->out_scale;
   view->err_calib = m->err_calib;
+  view->res[0] = m->res[0];
+  view->res[1] = m->res[1];
+  view->res_scale = m->res_scale;
   return FPN_OK;
 }
 
@@ -127,6 +157,14 @@ fpn_status fpn_surrogate_infer(fpn_ctx ctx, fpn_sur_model m, const float* x, int
   FPN_HIP(m->yb.ensure(size_t(n) * W));
   if (fpn_status e = fpn_mlp_forward(m->net[0], x, n, m->ya.p, stream)) return e;
   if (fpn_status e = fpn_mlp_forward(m->net[1], x, n, m->yb.p, stream)) return e;
+  if (m->res[0]) {  // member k's output += res[k](x) / res_scale
+    FPN_HIP(m->r.ensure(size_t(n) * W));
+    float* ys[2] = {m->ya.p, m->yb.p};
+    for (int k = 0; k < 2; ++k) {
+      if (fpn_status e = fpn_mlp_forward(m->res[k], x, n, m->r.p, stream)) return e;
+      FPN_HIP(fpn::sur::axpy(n * W, 1.0f / m->res_scale, m->r.p, ys[k], s));
+    }
+  }
   FPN_HIP(fpn::sur::mean_spread(n, W, m->ya.p, m->yb.p, 1.0f / m->out_scale, m->err_calib, y, err_est, s));
   return FPN_OK;
 }
@@ -170,8 +208,11 @@ fpn_status fpn_surrogate_save(fpn_sur_model m, const char* path) {
   }
   wr.put(&m->out_scale, sizeof(float));
   wr.put(&m->err_calib, sizeof(float));
-  for (int k = 0; k < 2 && wr.ok; ++k) {
-    const fpn_mlp net = m->net[k];
+  const int32_t has_res = m->res[0] ? 1 : 0;
+  wr.put(&has_res, sizeof has_res);
+  wr.put(&m->res_scale, sizeof(float));
+  for (int k = 0; k < (has_res ? 4 : 2) && wr.ok; ++k) {
+    const fpn_mlp net = k < 2 ? m->net[k] : m->res[k - 2];
     const int64_t t = net->t;
     wr.put(&t, sizeof t);
     if (hipMemcpy(nrm.data(), net->norm.p, nrm.size() * sizeof(float), hipMemcpyDeviceToHost) != hipSuccess) {
@@ -211,13 +252,20 @@ fpn_status fpn_surrogate_create(fpn_ctx ctx, const char* weights_path, fpn_sur_m
   rd.get(&ver, sizeof ver);
   rd.get(&nl, sizeof nl);
   if (!rd.ok || std::memcmp(magic, kMagic, sizeof kMagic) != 0) return bad("not a surrogate model file");
-  if (ver != kVersion) return bad("unsupported version");
+  if (ver != 1 && ver != kVersion) return bad("unsupported version");
   if (nl < 1 || nl > 16) return bad("layer count outside [1, 16]");
   std::vector<int32_t> w(nl + 1);
   rd.get(w.data(), w.size() * sizeof(int32_t));
   float scales[2];
   rd.get(scales, sizeof scales);
+  int32_t has_res = 0;
+  float res_scale = 1.0f;
+  if (ver >= 2) {
+    rd.get(&has_res, sizeof has_res);
+    rd.get(&res_scale, sizeof res_scale);
+  }
   if (!rd.ok) return bad("truncated header");
+  if (has_res != 0 && has_res != 1) return bad("bad residual flag");
   const uint64_t seeds[2] = {0, 0};
   fpn_sur_model m = nullptr;
   if (fpn_status e = fpn_surrogate_init(ctx, nl, w.data(), seeds, &m)) {
@@ -229,10 +277,22 @@ fpn_status fpn_surrogate_create(fpn_ctx ctx, const char* weights_path, fpn_sur_m
     std::fclose(f);
     return e;
   }
+  if (has_res) {
+    if (fpn_status e = fpn_surrogate_add_residual(ctx, m, seeds)) {
+      free_model(m);
+      std::fclose(f);
+      return e;
+    }
+    if (fpn_status e = fpn_surrogate_set_residual_scale(m, res_scale)) {
+      free_model(m);
+      std::fclose(f);
+      return e;
+    }
+  }
   const int64_t np = m->net[0]->nparam;
   std::vector<float> buf(static_cast<size_t>(np)), nrm(2 * static_cast<size_t>(w[0]));
-  for (int k = 0; k < 2; ++k) {
-    const fpn_mlp net = m->net[k];
+  for (int k = 0; k < (has_res ? 4 : 2); ++k) {
+    const fpn_mlp net = k < 2 ? m->net[k] : m->res[k - 2];
     int64_t t = 0;
     rd.get(&t, sizeof t);
     rd.get(nrm.data(), nrm.size() * sizeof(float));

@@ -43,6 +43,14 @@ fpn_status fpn_surrogate_predict(fpn_ctx ctx, const fpn_surrogate* sur, double t
   if (a->w.front() != 8 || a->w.back() != 4 * Kh)
     return fail(FPN_E_ARG, "networks must map 8 features to 4 * n_harm outputs");
   if (a->device != ctx->device || b->device != ctx->device) return fail(FPN_E_ARG, "networks on another device");
+  const bool resid = sur->res[0] || sur->res[1];
+  if (resid) {
+    if (!sur->res[0] || !sur->res[1]) return fail(FPN_E_ARG, "residual stage needs two networks");
+    if (sur->res[0]->w != a->w || sur->res[1]->w != a->w) return fail(FPN_E_ARG, "residual networks differ in shape");
+    if (sur->res[0]->device != ctx->device || sur->res[1]->device != ctx->device)
+      return fail(FPN_E_ARG, "networks on another device");
+    if (!(sur->res_scale > 0.0f) || !std::isfinite(sur->res_scale)) return fail(FPN_E_ARG, "res_scale must be > 0");
+  }
   if (!(sur->out_scale > 0.0f) || !std::isfinite(sur->out_scale) || !(sur->err_calib > 0.0f) ||
       !std::isfinite(sur->err_calib))
     return fail(FPN_E_ARG, "out_scale and err_calib must be finite and > 0");
@@ -61,6 +69,14 @@ fpn_status fpn_surrogate_predict(fpn_ctx ctx, const fpn_surrogate* sur, double t
   if (fpn_status e = fpn_surrogate_features(ctx, batch, n, ctx->sur_x.p, status, stream)) return e;
   if (fpn_status e = fpn_mlp_forward(a, ctx->sur_x.p, n, ctx->sur_ya.p, stream)) return e;
   if (fpn_status e = fpn_mlp_forward(b, ctx->sur_x.p, n, ctx->sur_yb.p, stream)) return e;
+  if (resid) {  // member k's output += res[k](x) / res_scale
+    FPN_HIP(ctx->sur_r.ensure(size_t(n) * W));
+    float* ys[2] = {ctx->sur_ya.p, ctx->sur_yb.p};
+    for (int k = 0; k < 2; ++k) {
+      if (fpn_status e = fpn_mlp_forward(sur->res[k], ctx->sur_x.p, n, ctx->sur_r.p, stream)) return e;
+      FPN_HIP(fpn::sur::axpy(n * W, 1.0f / sur->res_scale, ctx->sur_r.p, ys[k], s));
+    }
+  }
   FPN_HIP(fpn::sur::combine(n, Kh, ctx->sur_ya.p, ctx->sur_yb.p, 1.0f / sur->out_scale, sur->err_calib, float(tol),
                             status, harm_out, err_out, used_solver, ctx->sur_list.p, ctx->sur_count.p, s));
   int32_t cnt = 0;

@@ -84,7 +84,8 @@ struct DevTables {
   double* cval64;      // [nnzc]
   uint16_t* ell_col;   // [kNSlRow][Np] fixed-slot rows (stepper)
   float* ell_val;      // [kNSlRow][Np]
-  float* ell_lo;       // [kNSlD][Np] low-order parts of the diagonal-block slots: value = ell_val + ell_lo
+  float* ell_lo;       // [kNSlRow][Np] low-order parts: value = ell_val + ell_lo (the register-layout
+                       // stepper reads the first kNSlD rows, the diagonal-block slots)
   uint16_t* ecol_row;  // [kNSlCol][Np] fixed-slot columns of the lower coupling
   float* ecol_val;     // [kNSlCol][Np]
   float* win_b;        // [kNWin][Np] window coefficients (see above)

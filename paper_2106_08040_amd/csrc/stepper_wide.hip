@@ -50,12 +50,51 @@ struct WideLds {
   float cw[6][64];    // Schur coefficients of one block, multiplier included
   float mk[16];
   float ms[16];
+  double msd[16];     // FP64 multipliers of the right-hand side evaluation (stage or time-derivative)
   double ctl[6];      // step controller: time, next step size, this step size, landed, last attempt rejected
+  float xlo[NpA];     // low-order part of the stage argument (xin + xlo)
   __device__ float* X() { return a; }
   __device__ float* xin() { return a; }
   __device__ float* V() { return a + NpA; }
   __device__ float* G() { return g; }
 };
+
+// FP64 multiplier of operator kind `kind` (kind numbering of structure.hpp) at time tt: the kinds of the
+// field use its value with the static offset (deriv = false) or its time derivative (deriv = true,
+// field-free kinds 0..2 give 0).  Field mu0 H_a(t) = amp_a cos(2 pi f_a t + phase_a) with the cycles
+// reduced in FP64, frame and particle scalars from the FP64 instance data.
+__device__ inline double kind_mult_d(int kind, const InstParams& Q, const double* amp, const double* freq,
+                                     const double* phase, double tt, bool deriv) {
+  double b[3];
+#pragma unroll
+  for (int a = 0; a < 3; ++a) {
+    const double cyc = freq[a] * tt;
+    const double x = 2.0 * (cyc - floor(cyc)) + phase[a] * 0.3183098861837907;
+    b[a] = deriv ? -amp[a] * 2.0 * kPi * freq[a] * sinpi(x) : amp[a] * cospi(x) + Q.off[a];
+  }
+  const double hx = Q.R[0] * b[0] + Q.R[3] * b[1] + Q.R[6] * b[2];
+  const double hy = Q.R[1] * b[0] + Q.R[4] * b[1] + Q.R[7] * b[2];
+  const double hz = Q.R[2] * b[0] + Q.R[5] * b[1] + Q.R[8] * b[2];
+  const double s2 = Q.inv2tau, sb = Q.inv2tau * Q.beta_T, ia = 1.0 / Q.alpha;
+  switch (kind) {
+    case 0: return deriv ? 0.0 : s2;
+    case 1: return deriv ? 0.0 : s2 * Q.sigma;
+    case 2: return deriv ? 0.0 : s2 * 2.0 * Q.sigma * ia;
+    case 3: return sb * hz;
+    case 4: return sb * hz * ia;
+    case 5: return sb * hx;
+    case 6: return sb * hy;
+    case 7: return sb * hx * ia;
+    default: return sb * hy * ia;
+  }
+}
+
+// s + e = a + b exactly, s = fl(a + b) (Knuth's branch-free two-sum).
+__device__ __forceinline__ void two_sum(float a, float b, float& s, float& e) {
+  s = a + b;
+  const float bb = s - a;
+  e = (a - (s - bb)) + (b - bb);
+}
 
 // In-place inverse of an n x n block, row `lane` in a[0..n-1], by Gauss-Jordan with partial pivoting
 // (single rows).  Pivot k works on column 0 of the rotated order (original column k): the remaining
@@ -162,11 +201,16 @@ stepper_wide_kernel(StepArgs A, DevTables t, float* ws) {
   for (int c = 0; c < 9; ++c) R[c] = float(P.R[c]);
   for (int c = 0; c < 3; ++c) off[c] = float(P.off[c]);
 
-  float y[S];
+  // the state is carried as an unevaluated sum y + ylo of two FP32 values (about 48 bits): the slow
+  // relaxation of a stiff particle moves it by much less than one FP32 unit per step, and a state
+  // rounded to FP32 after every step loses or biases those increments
+  float y[S], ylo[S];
 #pragma unroll
   for (int s = 0; s < S; ++s) {
     const int p = lane + 64 * s;
-    y[s] = (p < Np) ? float(A.c0[int64_t(inst) * A.c_stride + p]) : 0.0f;
+    const double c = (p < Np) ? A.c0[int64_t(inst) * A.c_stride + p] : 0.0;
+    y[s] = float(c);
+    ylo[s] = float(c - double(y[s]));
   }
   const float rc = 2.0466534158929770f;  // sqrt(4 pi / 3)
   constexpr int pX = Gm::off(1), pY = Gm::off(1) + 1, pZ = 1;
@@ -195,22 +239,21 @@ stepper_wide_kernel(StepArgs A, DevTables t, float* ws) {
     const float hz = R[2] * bx + R[5] * by + R[8] * bz;
     return kind_mult(lane < 9 ? lane : 0, inv2tau, sigma, alpha, beta, hx, hy, hz);
   };
-  auto dmult_lane = [&](double tt) -> float {
-    float bx, by, bz;
-    field(tt, bx, by, bz, true);
-    const float hx = R[0] * bx + R[3] * by + R[6] * bz;
-    const float hy = R[1] * bx + R[4] * by + R[7] * bz;
-    const float hz = R[2] * bx + R[5] * by + R[8] * bz;
-    return (lane < 3) ? 0.0f : kind_mult(lane < 9 ? lane : 0, inv2tau, sigma, alpha, beta, hx, hy, hz);
+  // FP64 multiplier of kind `lane` (lanes 0..8) at time tt (field value or its time derivative)
+  auto mult_lane_d = [&](double tt, bool deriv) -> double {
+    return kind_mult_d(lane < 9 ? lane : 0, A.ip[inst], A.amp, A.freq, A.phase, tt, deriv);
   };
-  // dst[p] = add * dst[p] + (A(ms) xin)[p] for the rows p = lane + 64 s.  Diagonal-block entries are
-  // applied as hi + lo, summed per kind (see the register-layout stepper: rounded entries bias the slow
-  // relaxation modes).
+  // dst[p] = add * dst[p] + (A(msd) (xin + xlo))[p] for the rows p = lane + 64 s, in FP64: every
+  // entry as hi + lo, the FP64 kind multipliers, the two-part stage argument.  The right-hand side of a
+  // nearly relaxed stiff particle is a small difference of large terms; FP32 rounding of the terms,
+  // the multipliers or the sums biases its slow relaxation (a resolved L = 17 particle's moment moved by
+  // 1e-5 independently of the step size), FP64 leaves only the final rounding of the small result.
   auto matvec = [&](float* dst, bool add) {
     const float* xin = w.xin();
-    float m[9];
+    const float* xl = w.xlo;
+    double m[9];
 #pragma unroll
-    for (int k = 0; k < 9; ++k) m[k] = w.ms[k];
+    for (int k = 0; k < 9; ++k) m[k] = w.msd[k];
 #pragma unroll 1
     for (int s = 0; s < S; ++s) {
       const int p = lane + 64 * s;
@@ -219,49 +262,31 @@ stepper_wide_kernel(StepArgs A, DevTables t, float* ws) {
       const uint16_t* ec = opaque_ptr(ecol);
       if (p < Np) {
         // table reads, then gathers, then the sums, one slot group at a time (one wait per phase)
-        float acc = 0.0f;
-        {
-          int ci[kNSlD];
-          float hv[kNSlD], lv[kNSlD], xv[kNSlD];
+        double acc = 0.0;
+        constexpr int kG = 7;
+        static_assert(kNSlRow % kG == 0, "row slots come in whole groups");
 #pragma unroll
-          for (int u = 0; u < kNSlD; ++u) {
-            ci[u] = ec[(kSlD + u) * Np + p];
-            hv[u] = ev[(kSlD + u) * Np + p];
-            lv[u] = el[u * Np + p];
-          }
-          __builtin_amdgcn_sched_barrier(0);
-#pragma unroll
-          for (int u = 0; u < kNSlD; ++u) xv[u] = xin[ci[u]];
-          __builtin_amdgcn_sched_barrier(0);
-          float sh[kNKindD], sl[kNKindD];
-#pragma unroll
-          for (int k = 0; k < kNKindD; ++k) sh[k] = sl[k] = 0.0f;
-#pragma unroll
-          for (int u = 0; u < kNSlD; ++u) {
-            sh[kSlotKindRow[kSlD + u]] = fmaf(hv[u], xv[u], sh[kSlotKindRow[kSlD + u]]);
-            sl[kSlotKindRow[kSlD + u]] = fmaf(lv[u], xv[u], sl[kSlotKindRow[kSlD + u]]);
-          }
-#pragma unroll
-          for (int k = 0; k < kNKindD; ++k) acc = fmaf(m[k], sl[k], fmaf(m[k], sh[k], acc));
-        }
-        constexpr int kG = 6;
-#pragma unroll
-        for (int g0 = kSlB; g0 < kNSlRow; g0 += kG) {
+        for (int g0 = 0; g0 < kNSlRow; g0 += kG) {
           int ci[kG];
-          float cv[kG], xv[kG];
+          float hv[kG], lv[kG], xh[kG], xo[kG];
 #pragma unroll
           for (int u = 0; u < kG; ++u) {
             ci[u] = ec[(g0 + u) * Np + p];
-            cv[u] = ev[(g0 + u) * Np + p];
+            hv[u] = ev[(g0 + u) * Np + p];
+            lv[u] = el[(g0 + u) * Np + p];
           }
           __builtin_amdgcn_sched_barrier(0);
 #pragma unroll
-          for (int u = 0; u < kG; ++u) xv[u] = xin[ci[u]];
+          for (int u = 0; u < kG; ++u) {
+            xh[u] = xin[ci[u]];
+            xo[u] = xl[ci[u]];
+          }
           __builtin_amdgcn_sched_barrier(0);
 #pragma unroll
-          for (int u = 0; u < kG; ++u) acc = fmaf(m[kSlotKindRow[g0 + u]] * cv[u], xv[u], acc);
+          for (int u = 0; u < kG; ++u)
+            acc = fma(m[kSlotKindRow[g0 + u]] * (double(hv[u]) + double(lv[u])), double(xh[u]) + double(xo[u]), acc);
         }
-        dst[p] = add ? dst[p] + acc : acc;
+        dst[p] = add ? float(double(dst[p]) + acc) : float(acc);
       }
     }
   };
@@ -571,10 +596,10 @@ stepper_wide_kernel(StepArgs A, DevTables t, float* ws) {
       // both multiplier sets of t_n before the factorisation (their shared sin/cos work is not kept
       // live across it): M's in mk, the time derivatives for f_t in ms
       const float mt = mult_lane(tn);
-      const float md = dmult_lane(tn);
+      const double md = mult_lane_d(tn, true);
       if (lane < 9) {
         w.mk[lane] = -hg * mt;
-        w.ms[lane] = md;
+        w.msd[lane] = md;
       }
       wsync();
     }
@@ -584,15 +609,18 @@ stepper_wide_kernel(StepArgs A, DevTables t, float* ws) {
 #pragma unroll
       for (int s = 0; s < S; ++s) {
         const int p = lane + 64 * s;
-        if (p < Np) xin[p] = y[s];
+        if (p < Np) {
+          xin[p] = y[s];
+          w.xlo[p] = ylo[s];
+        }
       }
       wsync();
       matvec(ft, false);
       wsync();
     }
     for (int stg = 0; stg < 6; ++stg) {
-      const float mt = mult_lane(tn + double(kRodasAlpha[stg]) * hs);
-      if (lane < 9) w.ms[lane] = mt;
+      const double mt = mult_lane_d(tn + double(kRodasAlpha[stg]) * hs, false);
+      if (lane < 9) w.msd[lane] = mt;
       // stage argument -> xin, extra right-hand-side terms -> V
       float* xin = w.xin();
       float* V = w.V();
@@ -600,14 +628,18 @@ stepper_wide_kernel(StepArgs A, DevTables t, float* ws) {
       for (int s = 0; s < S; ++s) {
         const int p = lane + 64 * s;
         if (p < Np) {
-          float yv = y[s];
+          // stage increment sum_j a_ij K_j added to the two-part state: xin + xlo = y + ylo + increment
+          float u = ylo[s];
           float ev = hf * kRodasGamma[stg] * ft[p];
           for (int j = 0; j < stg; ++j) {
             const float kj = Kv[j * NpA + p];
-            yv = fmaf(kRodasA[stg][j], kj, yv);
+            u = fmaf(kRodasA[stg][j], kj, u);
             ev = fmaf(kRodasC[stg][j] * ih, kj, ev);
           }
-          xin[p] = yv;
+          float hi, lo;
+          two_sum(y[s], u, hi, lo);
+          xin[p] = hi;
+          w.xlo[p] = lo;
           V[p] = ev;
         }
       }
@@ -640,14 +672,17 @@ stepper_wide_kernel(StepArgs A, DevTables t, float* ws) {
     }
     return wave_max(emax);
   };
-  // y <- y_{n+1} of the step just taken
+  // y + ylo <- y_{n+1} = (stage-6 argument) + K6 of the step just taken
   auto accept = [&](float hg) {
     const float* xin = w.xin();
     const float* G = w.G();
 #pragma unroll
     for (int s = 0; s < S; ++s) {
       const int p = lane + 64 * s;
-      y[s] = (p < Np) ? xin[p] + hg * G[p] : 0.0f;
+      float hi = 0.0f, lo = 0.0f;
+      if (p < Np) two_sum(xin[p], w.xlo[p] + hg * G[p], hi, lo);
+      y[s] = hi;
+      ylo[s] = lo;
     }
   };
 
@@ -704,7 +739,7 @@ stepper_wide_kernel(StepArgs A, DevTables t, float* ws) {
           {
             const float x = xs[ecol[g * Np + row]], mk = w.ms[kSlotKindRow[g]];
             acc = fmaf(mk * eval[g * Np + row], x, acc);
-            if (g < kNSlD) acc = fmaf(mk * elo[g * Np + row], x, acc);
+            acc = fmaf(mk * elo[g * Np + row], x, acc);
           }
         }
         const float ax = __shfl(acc, 0), ay = __shfl(acc, 1), az = __shfl(acc, 2);

@@ -105,6 +105,11 @@ __global__ void mean_spread_kernel(int64_t n, int W, const float* ya, const floa
   if (lane == 0 && err) err[i] = calib * 2.0f * sqrtf(dd) / sqrtf(ss);
 }
 
+__global__ void axpy_kernel(int64_t n, float a, const float* x, float* y) {
+  const int64_t j = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+  if (j < n) y[j] = fmaf(a, x[j], y[j]);
+}
+
 __global__ void scale_kernel(int64_t n, const float* src, float a, float* dst) {
   const int64_t j = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
   if (j < n) dst[j] = src[j] * a;
@@ -169,6 +174,12 @@ hipError_t mean_spread(int64_t n, int W, const float* ya, const float* yb, float
   if (n == 0) return hipSuccess;
   hipLaunchKernelGGL(mean_spread_kernel, dim3(unsigned((n + 3) / 4)), dim3(256), 0, s, n, W, ya, yb, inv_scale,
                      calib, y, err);
+  return hipGetLastError();
+}
+
+hipError_t axpy(int64_t n, float a, const float* x, float* y, hipStream_t s) {
+  if (n == 0) return hipSuccess;
+  hipLaunchKernelGGL(axpy_kernel, dim3(unsigned((n + 255) / 256)), dim3(256), 0, s, n, a, x, y);
   return hipGetLastError();
 }
 

@@ -17,6 +17,8 @@ hipError_t combine(int64_t n, int Kh, const float* ya, const float* yb, float in
 // (either output may be NULL)
 hipError_t mean_spread(int64_t n, int W, const float* ya, const float* yb, float inv_scale, float calib, float* y,
                        float* err, hipStream_t s);
+// y += a * x (n values)
+hipError_t axpy(int64_t n, float a, const float* x, float* y, hipStream_t s);
 // dst = a * src (n values)
 hipError_t scale(int64_t n, const float* src, float a, float* dst, hipStream_t s);
 hipError_t gather(int cnt, const int32_t* list, const double* D, const double* Ms, const double* K,

@@ -66,8 +66,10 @@ class Surrogate:
     def close(self):
         self.model.close()
 
-    def fit(self, inst, harm, steps=3000, batch=4096, lr=2e-3, lr_final=2e-5, seed=0, log=None):
-        """Train both members on (features(inst), harm) with Adam and a cosine learning-rate decay."""
+    def fit(self, inst, harm, steps=3000, batch=4096, lr=2e-3, lr_final=2e-5, seed=0, log=None, residual_steps=0):
+        """Train both members on (features(inst), harm) with Adam and a cosine learning-rate decay; with
+        residual_steps > 0 a second stage (fpn_surrogate_add_residual) is then trained the same way on each
+        member's residual, scaled to unit RMS (member k predicts net_k + res_k / res_scale)."""
         torch = _torch()
         x, st = self.ctx.surrogate_features(inst)
         ok = (st == 0) & torch.isfinite(harm.real).all(dim=(1, 2)) & torch.isfinite(harm.imag).all(dim=(1, 2))
@@ -81,25 +83,49 @@ class Surrogate:
         std = np.where(std > 1e-6, std, 1.0)
         for net in self.nets:
             net.set_input_norm(mean, std)
-        n = x.shape[0]
-        g = torch.Generator(device=x.device)
-        g.manual_seed(seed)
         t0 = time.perf_counter()
-        for it in range(steps):
-            lr_t = lr_final + 0.5 * (lr - lr_final) * (1.0 + math.cos(math.pi * it / max(steps - 1, 1)))
-            for k, net in enumerate(self.nets):
-                idx = torch.randint(0, n, (min(batch, n),), device=x.device, generator=g)
-                loss = net.train_step(x[idx].contiguous(), y[idx].contiguous(), lr_t)
-            if log is not None and (it % max(steps // 10, 1) == 0 or it == steps - 1):
-                log(f"step {it}: lr {lr_t:.2e} loss {float(loss.item()) / (min(batch, n) * y.shape[1]):.3e}")
+        self._train(self.nets, x, [y, y], steps, batch, lr, lr_final, seed, log)
+        if residual_steps > 0:
+            if not self.model.residual:
+                self.model.add_residual()
+            res = []
+            for net in self.nets:
+                r = torch.empty_like(y)
+                for b in range(0, x.shape[0], 1 << 16):
+                    net.forward(x[b:b + (1 << 16)].contiguous(), out=r[b:b + (1 << 16)])
+                res.append((y - r).contiguous())
+            rrms = float(torch.sqrt(torch.stack([(r.double() ** 2).mean() for r in res]).mean()).item())
+            self.model.set_residual_scale(1.0 / rrms)
+            sc = np.float32(self.model.res_scale)
+            for net in self.model.residual:
+                net.set_input_norm(mean, std)
+            self._train(self.model.residual, x, [(r * sc).contiguous() for r in res], residual_steps, batch, lr,
+                        lr_final, seed + 1, log)
         torch.cuda.synchronize()
         self.train_seconds = time.perf_counter() - t0
         return self
 
+    def _train(self, nets, x, targets, steps, batch, lr, lr_final, seed, log):
+        torch = _torch()
+        n = x.shape[0]
+        g = torch.Generator(device=x.device)
+        g.manual_seed(seed)
+        for it in range(steps):
+            lr_t = lr_final + 0.5 * (lr - lr_final) * (1.0 + math.cos(math.pi * it / max(steps - 1, 1)))
+            for net, t in zip(nets, targets):
+                idx = torch.randint(0, n, (min(batch, n),), device=x.device, generator=g)
+                loss = net.train_step(x[idx].contiguous(), t[idx].contiguous(), lr_t)
+            if log is not None and (it % max(steps // 10, 1) == 0 or it == steps - 1):
+                log(f"step {it}: lr {lr_t:.2e} loss {float(loss.item()) / (min(batch, n) * t.shape[1]):.3e}")
+
     def raw(self, inst):
-        """Per-member predictions (network units) and the features' status."""
+        """Per-member predictions (network units, the residual stage included) and the features' status."""
         x, st = self.ctx.surrogate_features(inst)
-        return [net.forward(x) for net in self.nets], st
+        out = [net.forward(x) for net in self.nets]
+        if self.model.residual:
+            inv = float(np.float32(1.0) / np.float32(self.model.res_scale))
+            out = [o + net.forward(x) * inv for o, net in zip(out, self.model.residual)]
+        return out, st
 
     def calibrate(self, inst, harm, quantile=0.99):
         """err_calib = quantile of (true relative L2 error) / (ensemble spread) over held-out instances,

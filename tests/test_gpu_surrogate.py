@@ -195,3 +195,64 @@ def test_model_handle_train_save_load_is_bit_identical(fpn, ctx, tmp_path):
     assert e.value.code == fpn.FPN_E_IO
     for m in (a, b, c):
         m.close()
+
+
+def test_residual_stage_infer_predict_and_file_round_trip(fpn, ctx, tmp_path):
+    """A model with a residual stage (fpn_surrogate_add_residual): member k's output is net_k(x) +
+    res_k(x) / res_scale in fpn_surrogate_infer and in fpn_surrogate_predict (tol = inf), and a version-2
+    file round trip keeps the stage, its scale and bit-identical inference."""
+    import torch
+    r = np.random.default_rng(9)
+    widths = [8, 64, 64, 32]
+    x = torch.tensor(r.normal(size=(200, 8)), dtype=torch.float32, device="cuda:0")
+    y = torch.tensor(r.normal(size=(200, 32)), dtype=torch.float32, device="cuda:0")
+    m = fpn.SurrogateModel(ctx, widths, seeds=(21, 22))
+    m.set_scales(1.0, 2.0)
+    for it in range(3):
+        m.train_step(x, y, 1e-3)
+    m.add_residual(seeds=(23, 24))
+    m.set_residual_scale(8.0)
+    assert len(m.residual) == 2
+    for net in m.residual:
+        net.train_step(x, y, 1e-3)
+    torch.cuda.synchronize()
+    ya, ea = m.infer(x)
+    inv = float(np.float32(1.0) / np.float32(8.0))
+    outs = [net.forward(x) + res.forward(x) * inv for net, res in zip(m.members, m.residual)]
+    assert torch.allclose(ya, (outs[0] + outs[1]) * 0.5, rtol=1e-6, atol=1e-6)
+    path = str(tmp_path / "res.fpnsur")
+    m.save(path)
+    c = fpn.SurrogateModel(ctx, path=path)
+    assert len(c.residual) == 2 and c.res_scale == m.res_scale
+    yc, ec = c.infer(x)
+    assert torch.equal(yc, ya) and torch.equal(ec, ea)
+    with pytest.raises(fpn.FpnError):
+        c.add_residual()
+    for mm in (m, c):
+        mm.close()
+
+
+def test_residual_stage_lowers_the_error_of_a_trained_surrogate(fpn, ctx):
+    """Training a residual stage after the ensemble (Surrogate.fit(residual_steps=...)) lowers the
+    held-out error against the solver, and predict(tol = inf) is the combined ensemble mean."""
+    import torch
+    from paper_2106_08040_amd.surrogate import Surrogate
+    tr, va = domain(3072, 41), domain(512, 42)
+    htr, _ = solve(fpn, ctx, tr)
+    hva, _ = solve(fpn, ctx, va)
+    base = Surrogate(ctx, KH, hidden=(256, 256, 256, 256))
+    base.fit(tr["inst"], htr, steps=800, batch=2048, lr=2e-3)
+    e0, _ = base.calibrate(va["inst"], hva)
+    sur = Surrogate(ctx, KH, hidden=(256, 256, 256, 256))
+    sur.fit(tr["inst"], htr, steps=800, batch=2048, lr=2e-3, residual_steps=800)
+    e1, _ = sur.calibrate(va["inst"], hva)
+    print(f"held-out median rel-L2: ensemble {np.median(e0):.2e}, with residual stage {np.median(e1):.2e}", flush=True)
+    assert np.median(e1) < np.median(e0)
+    h, err, used, st, nf = sur.predict(va["inst"], va["inst"]["L"], drive_of(fpn, va), va["samples"], va["settle"],
+                                       tol=float("inf"))
+    (ya, yb), _ = sur.raw(va["inst"])
+    inv = float(np.float32(1.0) / np.float32(sur.out_scale))
+    got = torch.view_as_real(h[:, :, 1:].contiguous()).reshape(h.shape[0], -1)
+    assert torch.allclose(got, ((ya + yb) * 0.5) * inv, rtol=1e-5, atol=1e-6 * float(got.abs().max()))
+    base.close()
+    sur.close()

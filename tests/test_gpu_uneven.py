@@ -138,39 +138,51 @@ def test_cost_ordered_plan_gives_the_same_outputs(fpn, ctx):
     p2.close()
 
 
-def test_uneven_sweep_stratified_instances_match_oracle(fpn, ctx):
+UNEVEN_GOLDENS = sorted(glob.glob(os.path.join(GOLDEN, "uneven_*.npz")))
+
+
+@pytest.fixture(scope="module")
+def uneven_golden_solve(fpn, ctx):
+    """The instances of the uneven sweep that have stored oracle results, solved in one call."""
+    import torch
+    ws = W.uneven_sweep(4096, seed=3)
+    idx = [int(np.load(f)["idx"]) for f in UNEVEN_GOLDENS]
+    sub = W.take(ws, idx)
+    d = sub["drive"]
+    drive = fpn.make_drive(d["amp"], d["freq"], d["period"], d["phase"])
+    m, h, st = ctx.solve(sub["inst"], sub["inst"]["L"], drive, sub["samples"], sub["settle"], sub["n_harm"])
+    torch.cuda.synchronize()
+    return idx, sub["inst"]["L"], m.cpu().numpy(), h.cpu().numpy(), st.cpu().numpy()
+
+
+@pytest.mark.parametrize("path", UNEVEN_GOLDENS, ids=[os.path.basename(f)[:-4] for f in UNEVEN_GOLDENS])
+def test_uneven_sweep_stratified_instances_match_oracle(fpn, uneven_golden_solve, path):
     """Instances of the 4096-instance uneven sweep itself (its Lissajous drive, 1632 samples, degrees by
     the rule) against stored oracle results at the same degree (tests/golden/make_golden.py: per degree
     bucket the band top, the median sigma and the largest damping).  An instance the solver finishes
     (status OK) matches the oracle within 1e-5 on m and Phi; one it flags FPN_INST_UNRESOLVED must be
     one whose truncated density the oracle also shows to be no density (|m| > 1 + 1e-3 in the recorded
     period): the degree rule keeps the operator stable, not the density positive."""
-    import torch
-    files = sorted(glob.glob(os.path.join(GOLDEN, "uneven_*.npz")))
-    if not files:
-        pytest.skip("no uneven golden files")
-    ws = W.uneven_sweep(4096, seed=3)
-    idx = [int(np.load(f)["idx"]) for f in files]
-    sub = W.take(ws, idx)
-    d = sub["drive"]
-    drive = fpn.make_drive(d["amp"], d["freq"], d["period"], d["phase"])
-    m, h, st = ctx.solve(sub["inst"], sub["inst"]["L"], drive, sub["samples"], sub["settle"], sub["n_harm"])
-    torch.cuda.synchronize()
-    m, h, st = m.cpu().numpy(), h.cpu().numpy(), st.cpu().numpy()
-    n_ok = 0
-    for j, f in enumerate(files):
-        g = np.load(f)
-        L = int(sub["inst"]["L"][j])
-        mmax = float(np.linalg.norm(g["m"], axis=1).max())
-        if st[j] == fpn.FPN_INST_OK:
-            em, eh = rel(m[j].T, g["m"]), rel(h[j].T, g["Phi"][:, :2])
-            print(f"uneven {idx[j]} L={L}: OK, m {em:.2e} Phi {eh:.2e} (oracle |m| max {mmax:.4f}, "
-                  f"r={int(g['r'])} change {float(g['err_est']):.1e})", flush=True)
-            assert g["err_est"] < 2e-6
-            assert em < 1e-5 and eh < 1e-5
-            n_ok += 1
-        else:
-            print(f"uneven {idx[j]} L={L}: status {st[j]}, oracle |m| max {mmax:.4f}", flush=True)
-            assert st[j] == fpn.FPN_INST_UNRESOLVED
-            assert mmax > 1.0 + 1e-3
-    assert n_ok >= 1
+    idx, Ls, m, h, st = uneven_golden_solve
+    g = np.load(path)
+    j = idx.index(int(g["idx"]))
+    L = int(Ls[j])
+    mmax = float(np.linalg.norm(g["m"], axis=1).max())
+    if st[j] == fpn.FPN_INST_OK:
+        em, eh = rel(m[j].T, g["m"]), rel(h[j].T, g["Phi"][:, :2])
+        print(f"uneven {idx[j]} L={L}: OK, m {em:.2e} Phi {eh:.2e} (oracle |m| max {mmax:.4f}, "
+              f"r={int(g['r'])} change {float(g['err_est']):.1e})", flush=True)
+        assert g["err_est"] < 2e-6
+        assert em < 1e-5 and eh < 1e-5
+    else:
+        print(f"uneven {idx[j]} L={L}: status {st[j]}, oracle |m| max {mmax:.4f}", flush=True)
+        assert st[j] == fpn.FPN_INST_UNRESOLVED
+        assert mmax > 1.0 + 1e-3
+
+
+def test_uneven_stratified_set_has_finished_instances_at_every_layout(uneven_golden_solve):
+    """The stratified set exercises both steppers on finished instances: at least one status-OK instance
+    with L <= 16 (register layout) and one with L >= 17 (wide layout)."""
+    idx, Ls, m, h, st = uneven_golden_solve
+    ok = st == 0
+    assert (ok & (Ls <= 16)).any() and (ok & (Ls >= 17)).any()

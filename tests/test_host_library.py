@@ -18,7 +18,7 @@ fpn = pytest.importorskip("paper_2106_08040_amd")
 def declared_functions():
     src = open(HEADER).read()
     src = re.sub(r"/\*.*?\*/", "", src, flags=re.S)
-    return sorted(set(re.findall(r"\b(fpn_[a-z_]+)\s*\(", src)))
+    return sorted(set(re.findall(r"\b(fpn_[a-z_0-9]+)\s*\(", src)))
 
 
 def test_library_exports_every_declared_symbol():
