@@ -464,12 +464,16 @@ fpn_status plan_build(fpn_plan_s* p, fpn_ctx ctx, const fpn_drive* drive, const 
     auto& ids = kv.second;
     double per = 0.0;  // per-step work of degree L: sum of cubed block sizes
     for (int k = 0; k <= g.L; ++k) per += std::pow(double(k == 0 ? g.t->n0 : 2 * (g.L + 1 - k)), 3.0);
+    double longest = 0.0;  // steps of the longest instance (per-step work units below)
     if (cost_hint) {
       std::stable_sort(ids.begin(), ids.end(), [&](int32_t a, int32_t b) { return cost_hint[a] > cost_hint[b]; });
-      for (int32_t i : ids) g.cost += double(cost_hint[i]);
+      for (int32_t i : ids) g.cost += per * double(cost_hint[i]);
+      longest = per * double(cost_hint[ids.front()]);
     } else {
       g.cost = per * double(ids.size());
+      longest = per;
     }
+    g.est = longest;
     g.cnt = int(ids.size());
     p->groups.push_back(g);
     byL[g.L] = ids;
@@ -486,6 +490,7 @@ fpn_status plan_build(fpn_plan_s* p, fpn_ctx ctx, const fpn_drive* drive, const 
     g.waves = (!tangent && g.L <= 16) ? ctx->stepper_waves[g.L] : 0;
     if (fpn_status s = occupancy(ctx, g.L, *g.t, tangent, g.waves, &waves, &blocks)) return s;
     g.grid = std::max(1, std::min((g.cnt + waves - 1) / waves, blocks * ctx->cus));
+    g.est = std::max(g.est, g.cost / double(int64_t(g.grid) * waves));
     g.ws_off = ws_total;
     ws_total += int64_t(g.grid) * waves * fpn::stepper_ws_floats(g.L);
     g.tws_off = tws_total;
@@ -523,8 +528,23 @@ fpn_status plan_build(fpn_plan_s* p, fpn_ctx ctx, const fpn_drive* drive, const 
     }
   }
   FPN_HIP(hipMemcpyAsync(p->idx.p, p->order.data(), n * sizeof(int32_t), hipMemcpyHostToDevice, stream));
-  // side streams (default priority) and fork / join events for concurrent degree buckets
+  // side streams (default priority) and fork / join events for concurrent degree buckets.  There are
+  // as many streams as the runtime's hardware queues by default (4): buckets on one stream run one after
+  // another, so each bucket goes, longest predicted duration first, to the stream with the least
+  // predicted time so far (the launch order within a stream stays the cost order).
   const size_t nside = std::min<size_t>(p->groups.size() > 1 ? p->groups.size() : 0, 4);
+  {
+    std::vector<size_t> by_est(p->groups.size());
+    for (size_t i = 0; i < by_est.size(); ++i) by_est[i] = i;
+    std::stable_sort(by_est.begin(), by_est.end(),
+                     [&](size_t a, size_t b) { return p->groups[a].est > p->groups[b].est; });
+    std::vector<double> load(std::max<size_t>(nside, 1), 0.0);
+    for (size_t i : by_est) {
+      const size_t k = size_t(std::min_element(load.begin(), load.end()) - load.begin());
+      p->groups[i].stream = int(k);
+      load[k] += p->groups[i].est;
+    }
+  }
   while (p->side.size() < nside) {
     hipStream_t s = nullptr;
     FPN_HIP(hipStreamCreateWithFlags(&s, hipStreamNonBlocking));
@@ -571,7 +591,7 @@ fpn_status plan_launch(fpn_plan_s* p, hipStream_t stream, bool timing) {
   d0.z = drive->amp[2] * std::cos(drive->phase[2]);
   for (size_t gi = 0; gi < p->groups.size(); ++gi) {
     const auto& g = p->groups[gi];
-    hipStream_t gs = fork ? p->side[gi % p->side.size()] : stream;
+    hipStream_t gs = fork ? p->side[size_t(g.stream) % p->side.size()] : stream;
     const int32_t* idx = p->idx.p + g.start;
     if (fpn_status s = tm(1, gs, [&]() -> fpn_status {
           fpn::launch_stationary(*g.t, idx, g.cnt, p->ip.p, nullptr, d0, p->c0.p, p->np_max, p->wsinv.p + g.inv_off,

@@ -73,6 +73,9 @@ struct PlanGroup {
   int64_t inv_off = 0;   // doubles into the stationary workspace
   int64_t tws_off = 0;   // floats into the tangent workspace
   double cost = 0.0;     // predicted work (for the launch order)
+  double est = 0.0;      // predicted duration (per-step work x the longer of total steps / slots and the
+                         // longest instance's steps), for the assignment to streams
+  int stream = 0;        // side stream of the bucket (longest-first onto the least loaded stream)
 };
 void plan_release(fpn_plan_s* p);
 }  // namespace fpn_internal
