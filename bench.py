@@ -448,6 +448,57 @@ def bench_equilibrium(args):
     ctx.close()
 
 
+def bench_wide(args):
+    """The wide-layout stepper alone: 256 random resolved particles at one degree (--wide-L, default 24)
+    on the short three-axis test drive (64 samples, 1 settle period), adaptive steps.  One step = one
+    fpn_solve of the batch.  Roofline: algorithmic FP32 flops of the executed RODAS4 steps over the
+    stepper's HIP-event time."""
+    import torch
+    import paper_2106_08040_amd as fpn
+    import workloads as W
+
+    L = args.wide_L
+    ws = W.small_random(256, L, seed=100 + L, samples=64, settle=1, n_harm=8)
+    n = ws["inst"]["D"].size
+    ctx = fpn.Context(0)
+    d = ws["drive"]
+    drive = fpn.make_drive(d["amp"], d["freq"], d["period"], d["phase"])
+
+    def step():
+        return ctx.solve(ws["inst"], ws["inst"]["L"], drive, ws["samples"], ws["settle"], ws["n_harm"], want_m=False)
+
+    for _ in range(args.warmup):
+        step()
+    torch.cuda.synchronize()
+    ctx.timing_enable(True)
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        _, _, st = step()
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    timing = ctx.timing_read()
+    ctx.timing_enable(False)
+    steps = ctx.last_steps()
+    step_ms, launches = timing["stepper"]
+    avg_ms = step_ms / max(launches, 1)
+    flops = float(flops_per_step(fpn, L)) * steps
+    achieved = flops / (avg_ms * 1e-3) / 1e12
+    st = st.cpu().numpy()
+    res = {
+        "metric": "FP solves/sec & surrogate evals/sec at \u22641e-3 rel-L2 vs FP64 oracle",
+        "value": n * args.steps / wall, "unit": "solves/s", "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
+        "ms_per_step": wall / args.steps * 1e3, "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+        "dtype": "f32", "data": "synthetic",
+        "config": {"workload": f"wide_L{L}_256_short_drive", "instances": n, "L": L, "samples": ws["samples"],
+                   "rodas4_steps_per_solve": steps, "status_counts": np.bincount(st).tolist()},
+        "roofline": {"bound": "alu", "kernel": f"stepper_wide_kernel<{L}, 4>", "achieved": achieved,
+                     "peak": FP32_VECTOR_PEAK_TFLOPS, "unit": "TFLOP/s", "frac": achieved / FP32_VECTOR_PEAK_TFLOPS,
+                     "traffic": None, "avg_launch_ms": avg_ms, "flops_per_launch": flops},
+    }
+    print(json.dumps(res), flush=True)
+    ctx.close()
+
+
 def bench_m1(args):
     """Model M1 identification (paper: data-driven models, Simulation Setting, Distance Measure) on a
     synthetic measurement: the system matrices of an off-grid particle (D = 21.3 nm, K = 1170 J/m^3) at
@@ -472,6 +523,8 @@ def bench_m1(args):
     drive = fpn.make_drive(d["amp"], d["freq"], d["period"], d["phase"])
     n_el, n_pos, n_ang = dic["n_elements"], dic["n_pos"], len(angles)
     inst = {k: torch.as_tensor(v, dtype=torch.float64, device="cuda:0") for k, v in dic["inst"].items() if k != "L"}
+    for l in np.unique(dic["inst"]["L"]):   # workgroup size per degree from the autotuner (untimed)
+        ctx.autotune(int(l))
     # the synthetic measurement (untimed): solver output of the truth, transfer values, 1 % noise
     _, h0, st0 = ctx.solve(truth["inst"], truth["inst"]["L"], drive, dic["samples"], 1, Kh, want_m=False)
     a_true, z, rn = W.m1_transfer_and_noise(n_ang, n_pos, 2, Kh + 1, seed=81)
@@ -503,16 +556,25 @@ def bench_m1(args):
         a, err, ef, eg = step()
     torch.cuda.synchronize()
     wall = time.perf_counter() - t0
-    # fit kernel alone (HIP events on the current stream, where it is launched)
     phi = torch.view_as_complex(hm).reshape(n_el, n_pos, 2, Kh + 1)
-    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    # fit kernel alone: an event pair around every launch (the binding's argument checks synchronise
+    # between launches, so one pair around all of them would time the gaps too)
     reps = 20
-    e0.record()
-    for _ in range(reps):
-        ctx.fit_rows(phi, S, pp_t, ps_t)
-    e1.record()
+    evs = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)) for _ in range(reps)]
+    ppi = pp_t.to(torch.int32).contiguous()
+    psi = ps_t.to(torch.int32).contiguous()
+    a_buf = torch.empty((n_el, 2, Kh + 1, 2), dtype=torch.float32, device="cuda:0")
+    e_buf = torch.empty((n_el, 2, Kh + 1), dtype=torch.float32, device="cuda:0")
+    stream = torch.cuda.current_stream().cuda_stream
+    phi_r, S_r = torch.view_as_real(phi.contiguous()), torch.view_as_real(S)
+    for e0, e1 in evs:
+        e0.record()
+        code = fpn._lib.fpn_fit_rows(ctx._h, phi_r.data_ptr(), S_r.data_ptr(), n_pos, 2, Kh + 1, n_el, ppi.data_ptr(),
+                                     psi.data_ptr(), a_buf.data_ptr(), e_buf.data_ptr(), stream)
+        e1.record()
+        assert code == 0
     torch.cuda.synchronize()
-    fit_ms = e0.elapsed_time(e1) / reps
+    fit_ms = sum(e0.elapsed_time(e1) for e0, e1 in evs) / reps
     fit_bytes = 2.0 * 2 * n_el * n_pos * 2 * (Kh + 1) * 8 + n_el * 2 * (Kh + 1) * 12
     # model M2 on the same dictionary (untimed): scaled dictionary of the M1 fits, non-negative weights of
     # the (D, K) pairs shared by all angles, truncated SVD keeping 3 % of the singular values and none
@@ -675,7 +737,9 @@ def main():
                     help="run only a plain 256 MiB device copy three times (reference for the FETCH_SIZE / "
                          "WRITE_SIZE counters) and exit")
     ap.add_argument("--grad-angles", type=int, default=16, help="gradient workload: easy-axis angles")
-    ap.add_argument("--workload", choices=("lissajous", "uneven", "surrogate", "gradient", "equilibrium", "m1"),
+    ap.add_argument("--wide-L", type=int, default=24, help="wide workload: Galerkin degree (17..24)")
+    ap.add_argument("--workload", choices=("lissajous", "uneven", "surrogate", "gradient", "equilibrium", "m1",
+                                           "wide"),
                     default="lissajous",
                     help="lissajous: 2312-instance system matrix, L = 16 (headline); "
                          "uneven: 4096 instances with L = 8..24 in one graph launch; "
@@ -683,7 +747,7 @@ def main():
                          "gradient: identification loss and its gradient over 65536 instances; "
                          "equilibrium: the Lissajous system matrix of the equilibrium model (M0); "
                          "m1: model-M1 identification (dictionary sweep, closed-form scales, NRMSE) on a "
-                         "synthetic measurement")
+                         "synthetic measurement; wide: the wide-layout stepper alone, 256 particles at one degree")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py measures one GPU only: there is no multi-GPU path (instances are independent; a "
@@ -716,6 +780,8 @@ def main():
         return bench_equilibrium(args)
     if args.workload == "m1":
         return bench_m1(args)
+    if args.workload == "wide":
+        return bench_wide(args)
     ws = W.lissajous_grid()
     n = ws["inst"]["D"].size
     dev = "cuda:0"

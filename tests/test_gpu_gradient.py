@@ -72,7 +72,9 @@ def test_tangents_match_oracle_finite_differences(tangent_run):
         for p in range(5):
             for got, ref, y in ((dh[i, p].T, g["dPhi"][p], h[i]), (dm[i, p].T, g["dm"][p], m[i])):
                 err = np.linalg.norm(got - ref)
-                bound = 1e-4 * np.linalg.norm(ref) + 1e-5 * np.linalg.norm(y) / scale[p]
+                # 0.2 x (1e-4 of the derivative + the FP32 floor 1e-5 |Y| / s_p): measured <= 0.04 of the
+                # unscaled bound, so this is about 5x the largest error
+                bound = 0.2 * (1e-4 * np.linalg.norm(ref) + 1e-5 * np.linalg.norm(y) / scale[p])
                 print(f"inst {i} d/d{names[p]}: rel {err / np.linalg.norm(ref):.2e}, error / bound "
                       f"{err / bound:.2f}", flush=True)
                 assert err <= bound
@@ -212,4 +214,8 @@ def test_autograd_through_a_superposition_misfit(fpn, ctx):
     scale = np.array([inst["D"], inst["K"], inst["alpha"], np.ones(2), np.ones(2)]).T  # [2, 5]
     floor = np.array([1e-5 * np.linalg.norm(2 * r_) * wn[i] * np.linalg.norm(ref_phi[i]) / scale[i] for i in range(2)])
     assert (np.abs(gg - gp) <= 1e-4 * np.abs(gp) + floor).all(), np.abs(gg - gp) / (1e-4 * np.abs(gp) + floor)
-    assert e2 < 1e-4
+    # per parameter, about 10x the measured errors (4e-7, 4e-6, 5e-3, 2e-6, 5e-6): the alpha gradient is
+    # the FP32 floor of a small sensitivity (|alpha dPhi/dalpha| is ~1e-3 of |D dPhi/dD|), so it is held
+    # to 1e-2 relative while the others are held to 1e-5 .. 5e-5
+    assert all(e < t for e, t in zip(e1, (1e-5, 5e-5, 1e-2, 2e-5, 5e-5))), e1
+    assert e2 < 1e-5
