@@ -7,3 +7,4 @@ imports or calls anything here and shares no code with it.
 from .fp_oracle import *  # noqa: F401,F403
 from . import mlp_oracle  # noqa: F401,E402
 from . import fit_oracle  # noqa: F401,E402
+from . import fv_oracle  # noqa: F401,E402
