@@ -528,17 +528,20 @@ fpn_status plan_build(fpn_plan_s* p, fpn_ctx ctx, const fpn_drive* drive, const 
     }
   }
   FPN_HIP(hipMemcpyAsync(p->idx.p, p->order.data(), n * sizeof(int32_t), hipMemcpyHostToDevice, stream));
-  // side streams (default priority) and fork / join events for concurrent degree buckets.  There are
-  // as many streams as the runtime's hardware queues by default (4): buckets on one stream run one after
-  // another, so each bucket goes, longest predicted duration first, to the stream with the least
-  // predicted time so far (the launch order within a stream stays the cost order).
-  const size_t nside = std::min<size_t>(p->groups.size() > 1 ? p->groups.size() : 0, 4);
+  // Worker streams for concurrent degree buckets: the caller's stream and up to three side streams
+  // (default priority), as many as the runtime's hardware queues by default (4), so no two workers
+  // share a queue (a bucket queued behind another worker's kernel on a shared queue waits for all of
+  // it).  Buckets on one worker run one after another, so each bucket goes, longest predicted
+  // duration first, to the worker with the least predicted time so far (the launch order within a
+  // worker stays the cost order).  Worker 0 is the caller's stream.
+  const size_t nwork = std::min<size_t>(p->groups.size(), 4);
+  const size_t nside = nwork > 1 ? nwork - 1 : 0;
   {
     std::vector<size_t> by_est(p->groups.size());
     for (size_t i = 0; i < by_est.size(); ++i) by_est[i] = i;
     std::stable_sort(by_est.begin(), by_est.end(),
                      [&](size_t a, size_t b) { return p->groups[a].est > p->groups[b].est; });
-    std::vector<double> load(std::max<size_t>(nside, 1), 0.0);
+    std::vector<double> load(std::max<size_t>(nwork, 1), 0.0);
     for (size_t i : by_est) {
       const size_t k = size_t(std::min_element(load.begin(), load.end()) - load.begin());
       p->groups[i].stream = int(k);
@@ -580,31 +583,38 @@ fpn_status plan_launch(fpn_plan_s* p, hipStream_t stream, bool timing) {
         return FPN_OK;
       }))
     return s;
-  const bool fork = !p->side.empty();
-  if (fork) {
-    FPN_HIP(hipEventRecord(p->ev[0], stream));
-    for (hipStream_t s : p->side) FPN_HIP(hipStreamWaitEvent(s, p->ev[0], 0));
-  }
   double3 d0;
   d0.x = drive->amp[0] * std::cos(drive->phase[0]);
   d0.y = drive->amp[1] * std::cos(drive->phase[1]);
   d0.z = drive->amp[2] * std::cos(drive->phase[2]);
+  // The stationary starts of every bucket first, on the caller's stream: they take milliseconds
+  // alone, but one issued beside the persistent stepper kernels of other buckets gets few compute
+  // units and delays its own bucket's stepper by seconds.
   for (size_t gi = 0; gi < p->groups.size(); ++gi) {
     const auto& g = p->groups[gi];
-    hipStream_t gs = fork ? p->side[size_t(g.stream) % p->side.size()] : stream;
     const int32_t* idx = p->idx.p + g.start;
-    if (fpn_status s = tm(1, gs, [&]() -> fpn_status {
+    if (fpn_status s = tm(1, stream, [&]() -> fpn_status {
           fpn::launch_stationary(*g.t, idx, g.cnt, p->ip.p, nullptr, d0, p->c0.p, p->np_max, p->wsinv.p + g.inv_off,
-                                 p->status, gs);
+                                 p->status, stream);
           FPN_HIP(hipGetLastError());
           if (p->tangent) {
             fpn::launch_stationary_tangent(*g.t, idx, g.cnt, p->ip.p, d0, p->c0.p, p->np_max,
-                                           p->wsinv.p + g.inv_off, p->c0t.p, p->status, gs);
+                                           p->wsinv.p + g.inv_off, p->c0t.p, p->status, stream);
             FPN_HIP(hipGetLastError());
           }
           return FPN_OK;
         }))
       return s;
+  }
+  const bool fork = !p->side.empty();
+  if (fork) {
+    FPN_HIP(hipEventRecord(p->ev[0], stream));
+    for (hipStream_t s : p->side) FPN_HIP(hipStreamWaitEvent(s, p->ev[0], 0));
+  }
+  for (size_t gi = 0; gi < p->groups.size(); ++gi) {
+    const auto& g = p->groups[gi];
+    hipStream_t gs = (fork && g.stream > 0) ? p->side[size_t(g.stream - 1) % p->side.size()] : stream;
+    const int32_t* idx = p->idx.p + g.start;
     fpn::StepLaunch sl;
     sl.ip = p->ip.p;
     sl.inst_idx = idx;
