@@ -2,7 +2,8 @@
 
 Each file holds, for one instance of a named workload: m [N_s, 3], Phi [K_h+1, 3]
 (complex), the Radau refinement r used and the change against the run with r/2
-(time-discretisation error estimate).  Run:  python tests/golden/make_golden.py [names...]
+(time-discretisation error estimate); the finite-volume cross-check files ("fv") hold the
+finite-volume solutions on three meshes and Galerkin oracle solutions at three degrees.  Run:  python tests/golden/make_golden.py [names...]
 """
 import os
 import sys
@@ -93,6 +94,8 @@ JOBS = {
                                      (7 * 17 + 10) * 17 + 4, (2 * 17 + 0) * 17 + 16, (6 * 17 + 12) * 17 + 12], 4),
     "lissajous_strat": (W.lissajous_grid, lissajous_stratified(), 4),
     "uneven": (uneven_ws, uneven_stratified(), 4),
+    # finite-volume cross-check (BDF2 steps per sample)
+    "fv": (W.fv_crosscheck, [0, 1, 2, 3, 4, 5], 32),
 }
 
 
@@ -137,6 +140,35 @@ def fd_one(args, pool=None):
     return f"{out}: finite differences of the oracle, r={r} ({time.time() - t0:.0f}s)"
 
 
+def fv_one(args):
+    """Finite-volume solutions of one instance on the refined icosahedron of levels 3, 4 and 5
+    (1280, 5120 and 20480 triangles) with BDF2 at 32 steps per sample, level 4 also at 16 (time-error
+    estimate), and the Galerkin oracle at the instance's degree L, at L + 6 and at L = 4 (a degree
+    too low for these particles, to show the cross-check sees truncation)."""
+    name, factory, idx, r = args
+    from oracle import fv_oracle as FV
+    ws = factory()
+    inst = {k: v[idx] for k, v in ws["inst"].items()}
+    p = dict(D=inst["D"], Ms=inst["Ms"], K=inst["K"], alpha=inst["alpha"], T=inst["T"])
+    t0 = time.time()
+    kw = dict(offset=inst["offset"])
+    fv = {}
+    for lev, rr in ((3, r), (4, r), (5, r), (4, r // 2)):
+        fv[(lev, rr)] = FV.fv_solve_instance(p, inst["easy_axis"], lev, ws["drive"], ws["samples"], ws["settle"],
+                                             r=rr, **kw)["m"]
+    L = int(inst["L"])
+    gal = {}
+    for LL in (L, L + 6, 4):
+        gal[LL] = O.solve_instance(p, inst["easy_axis"], LL, ws["drive"], ws["samples"], ws["settle"], ws["n_harm"],
+                                   r=8, **kw)["m"]
+    out = os.path.join(HERE, f"{name}_{idx}.npz")
+    np.savez_compressed(out, fv3=fv[(3, r)], fv4=fv[(4, r)], fv5=fv[(5, r)], fv4_half_r=fv[(4, r // 2)], r=r,
+                        gal_L=gal[L], gal_L6=gal[L + 6], gal_4=gal[4], L=L, idx=idx)
+    R45 = (4 * fv[(5, r)] - fv[(4, r)]) / 3
+    e = np.linalg.norm(gal[L] - R45) / np.linalg.norm(R45)
+    return f"{out}: L={L} Galerkin vs extrapolated finite volumes {e:.2e} ({time.time() - t0:.0f}s)"
+
+
 def one(args):
     name, factory, idx, r = args
     ws = factory()
@@ -168,7 +200,8 @@ if __name__ == "__main__":
             tasks += [(nm, factory, i, 8 if Ls[i] <= 13 else r) for i in ids if not only or i == int(only)]
         else:
             tasks += [(nm, factory, i, r) for i in ids if not only or i == int(only)]
-    plain = [t for t in tasks if not t[0].startswith("tangent")]
+    plain = [t for t in tasks if not t[0].startswith("tangent") and t[0] != "fv"]
+    fvt = [t for t in tasks if t[0] == "fv"]
     if os.environ.get("GOLDEN_SKIP_EXISTING"):
         plain = [t for t in plain if not os.path.exists(os.path.join(HERE, f"{t[0]}_{t[2]}.npz"))]
     plain.sort(key=lambda t: -int(t[1]()["inst"]["L"][t[2]]) * t[3])
@@ -178,4 +211,6 @@ if __name__ == "__main__":
         for t in fd:
             print(fd_one(t, ex), flush=True)
         for msg in ex.map(one, plain):
+            print(msg, flush=True)
+        for msg in ex.map(fv_one, fvt):
             print(msg, flush=True)

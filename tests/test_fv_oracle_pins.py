@@ -237,3 +237,29 @@ def test_finite_volumes_converge_to_the_galerkin_oracle(meshes, monkeypatch):
     monkeypatch.setattr(FP, "galerkin_components", _flipped_components)
     gf = O.solve_instance(p, n, 14, drive, 64, 1, 8, r=4, offset=off)["m"]
     assert rel(f3, gf) > 4 * e3
+
+
+# ------------------------------------------------- stored cross-check set ---
+
+def _fv_goldens():
+    import glob
+    import os
+    here = os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden")
+    return sorted(glob.glob(os.path.join(here, "fv_*.npz")))
+
+
+@pytest.mark.parametrize("path", _fv_goldens())
+def test_stored_finite_volume_solutions_pin_the_galerkin_oracle(path):
+    """tests/golden/fv_*.npz (written by tests/golden/make_golden.py from oracle/ only): the
+    finite-volume solutions on 1280, 5120 and 20480 triangles converge at second order, and their
+    extrapolation agrees with the Galerkin oracle at degree L + 6 to within its own error; the
+    Galerkin oracle at degree 4 is far outside, so the cross-check resolves truncation."""
+    z = np.load(path)
+    g = z["gal_L6"]
+    e3, e4, e5 = (rel(z[k], g) for k in ("fv3", "fv4", "fv5"))
+    assert e3 / e4 > 3.0 and e4 / e5 > 3.0
+    R45 = (4 * z["fv5"] - z["fv4"]) / 3
+    R34 = (4 * z["fv4"] - z["fv3"]) / 3
+    err = rel(R45, R34) + rel(z["fv4"], z["fv4_half_r"]) / 3
+    assert rel(g, R45) <= 2.0 * err + 1e-5
+    assert rel(z["gal_4"], R45) > 10.0 * (2.0 * err + 1e-5)

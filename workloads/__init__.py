@@ -180,6 +180,27 @@ def small_random(n, L, seed, samples=64, settle=1, n_harm=10, freq_scale=1.0, re
                 n_harm=n_harm, harm_z=True)
 
 
+def fv_crosscheck(n=6, seed=61):
+    """Instances for the finite-volume cross-check of the truncation in L: a fast drive (period 4 us,
+    components at 0.75 / 1 / 0.25 MHz, 10 / 8 / 3 mT) where the precession term moves the response by
+    about 1 %, 64 samples, one settling period; D ~ U[16, 21] nm, K log-uniform in [0.5, 6] kJ/m^3
+    (sigma up to about 7),
+    alpha ~ U[0.05, 0.2], easy axes uniform on the sphere, offsets U[-3, 3] mT, L by
+    truncation_degree."""
+    r = np.random.default_rng(seed)
+    D = r.uniform(16e-9, 21e-9, n)
+    K = np.exp(r.uniform(np.log(500.0), np.log(6e3), n))
+    alpha = r.uniform(0.05, 0.2, n)
+    v = r.normal(size=(n, 3))
+    easy = v / np.linalg.norm(v, axis=1, keepdims=True)
+    off = r.uniform(-3e-3, 3e-3, (n, 3))
+    inst = _instances(D, np.full(n, MAGNETITE_MS), K, alpha, np.full(n, ROOM_T), easy, off,
+                      truncation_degree(D, K))
+    T = 4e-6
+    drive = dict(amp=(10e-3, 8e-3, 3e-3), freq=(3 / T, 4 / T, 1 / T), phase=(0.0, 0.3, -0.7), period=T)
+    return dict(name="fv_crosscheck", inst=inst, drive=drive, samples=64, settle=1, n_harm=10, harm_z=True)
+
+
 def take(ws, idx):
     """Sub-workload with the instances at `idx`."""
     idx = np.asarray(idx, dtype=np.int64)
