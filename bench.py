@@ -198,6 +198,17 @@ def wait_with_progress(torch, what, t0):
     torch.cuda.synchronize()
 
 
+def truncation_summary(ctx, ws, drive):
+    """Degree-truncation estimates of the batch (fpn_truncation_estimate, outside any timed region):
+    how many instances the chosen degrees leave above 1e-5 and 1e-3 by that (conservative) estimate."""
+    est, st = ctx.truncation_estimate(ws["inst"], ws["inst"]["L"], drive, ws["samples"])
+    e = est.cpu().numpy()
+    ok = st.cpu().numpy() == 0
+    e = e[ok]
+    return {"estimate_median": float(np.median(e)), "estimate_max": float(e.max()),
+            "above_1e-5": int((e > 1e-5).sum()), "above_1e-3": int((e > 1e-3).sum()), "estimated": int(ok.sum())}
+
+
 def bench_uneven(args):
     """4096 instances with D, K, alpha, axis and offset drawn at random and L = 8..24 from the
     anisotropy: workgroup size per degree from the autotuner, one plan, cost-ordered by the step counts
@@ -241,6 +252,12 @@ def bench_uneven(args):
     wall = time.perf_counter() - t1
     st = plan.status.cpu().numpy()
     steps = plan.steps()
+    trunc = truncation_summary(ctx, ws, drive)
+    # degrees the truncation estimate asks for at 1e-5 (from the degree rule upward, at most 24)
+    Lsel, est_sel, _ = ctx.select_degree(ws["inst"], L, drive, ws["samples"], 1e-5)
+    est_sel = est_sel.cpu().numpy()
+    trunc["select_1e-5"] = {"degree_counts": {str(int(k)): int(v) for k, v in zip(*np.unique(Lsel, return_counts=True))},
+                            "not_met_at_24": int((~(est_sel <= 1e-5)).sum())}
     flops = 0.0
     for l in np.unique(L):
         flops += float(flops_per_step(fpn, int(l))) * float(steps[L == l].sum())
@@ -257,7 +274,7 @@ def bench_uneven(args):
                    "autotune_s": t_tune, "autotuned_waves": {str(k): v["waves"] for k, v in tuned.items()},
                    "warmup_batch_order_s": t_warm, "avg_steps_per_interval": float(steps.mean()) /
                    ((ws["settle"] + 1) * ws["samples"]), "failed_instances": int((st != 0).sum()),
-                   "failed_status_counts": np.bincount(st).tolist()},
+                   "failed_status_counts": np.bincount(st).tolist(), "truncation": trunc},
         "roofline": {"bound": "alu", "kernel": "stepper (all degree buckets, concurrent)", "achieved": achieved,
                      "peak": FP32_VECTOR_PEAK_TFLOPS, "unit": "TFLOP/s", "frac": achieved / FP32_VECTOR_PEAK_TFLOPS,
                      "traffic": None, "flops_per_launch": flops},
@@ -818,6 +835,7 @@ def main():
     value = n * args.steps / wall
 
     Lv = int(L[0])
+    trunc = truncation_summary(ctx, ws, drive)
     step_ms, launches = timing["stepper"]
     # algorithmic flops of one stepper launch: executed RODAS4 steps x flops per step
     flops_launch = float(flops_per_step(fpn, Lv)) * steps_last
@@ -840,7 +858,7 @@ def main():
         "config": {"workload": ws["name"], "instances": n, "L": Lv, "samples": ws["samples"],
                    "settle_periods": ws["settle"], "n_harm": ws["n_harm"],
                    "substeps": args.substeps if args.substeps else "adaptive", "avg_substeps": avg_sub,
-                   "integrator": "RODAS4", "failed_instances": bad},
+                   "integrator": "RODAS4", "failed_instances": bad, "truncation": trunc},
         "roofline": {"bound": "alu", "kernel": "stepper", "achieved": achieved, "peak": FP32_VECTOR_PEAK_TFLOPS,
                      "unit": "TFLOP/s", "frac": achieved / FP32_VECTOR_PEAK_TFLOPS, "traffic": measured_traffic(),
                      "avg_launch_ms": avg_ms, "flops_per_launch": flops_launch,

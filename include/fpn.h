@@ -260,6 +260,38 @@ fpn_status fpn_last_steps(fpn_ctx ctx, int64_t* total_steps);
 fpn_status fpn_stationary(fpn_ctx ctx, const fpn_batch* batch, int64_t n, const double* field,
                           double* m_out, int32_t* status, void* stream);
 
+/* Truncation estimate of the Galerkin degree (an a-posteriori indicator, not part of the paper):
+ * the paper discretises Eq. FP-general with finite volumes; a spherical-harmonic expansion cut at
+ * degree L converges spectrally to the same solution, and this call estimates how far the degree-L
+ * solution of each instance is from it.  Per instance: the field mu0 H(t_j) of largest magnitude
+ * over the samples t_j = j T / samples_per_period of one drive period (offset + drive; the first
+ * sample within a relative 1e-9 of the largest squared magnitude), the stationary moments
+ * (Eq. mean_magmom_FP / m0, FP64, as fpn_stationary) of degrees L and L - 2 under that static field,
+ * and est = |m_L - m_{L-2}| (Euclidean, dimensionless).  Checked against finite-volume solutions
+ * of Eq. FP-general and higher-degree solves, it bounds the rel-L2 truncation error of the periodic
+ * m(t) at degree L within a factor of about 2..20 from above; it is a heuristic, not a proof.
+ *   batch  as for fpn_solve (L[i] >= 3 on the host)
+ *   est_out [n] DEVICE double (NaN where status != 0)
+ *   status  [n] DEVICE int32, FPN_INST_* of the stationary solves
+ * Synchronises `stream`.  Errors: FPN_E_ARG, FPN_E_RANGE (some L < 3), FPN_E_DEVICE. */
+fpn_status fpn_truncation_estimate(fpn_ctx ctx, const fpn_batch* batch, int64_t n, const fpn_drive* drive,
+                                   int32_t samples_per_period, double* est_out, int32_t* status, void* stream);
+
+/* Degree selection by the truncation estimate: per instance the smallest L in batch->L[i] .. L_max
+ * whose fpn_truncation_estimate value is <= tol (the largest sampled field, stationary moments of
+ * degrees L and L - 2); L_max where none is (est_out then holds that degree's estimate, > tol).
+ * batch->L[i] is the smallest degree allowed (for instance a stability rule), 3 <= batch->L[i] <= L_max.
+ * Costs one batch of FP64 stationary solves per degree from min(L) - 2 to L_max.
+ *   tol     > 0, on |m_L - m_{L-2}| (dimensionless)
+ *   L_max   3..24
+ *   L_out   [n] HOST int32 (L_max where status != 0)
+ *   est_out [n] DEVICE double, may be NULL: the estimate at the chosen degree (NaN where status != 0)
+ *   status  [n] DEVICE int32, FPN_INST_* of the stationary solves
+ * Synchronises `stream`.  Errors: FPN_E_ARG, FPN_E_RANGE, FPN_E_DEVICE. */
+fpn_status fpn_select_degree(fpn_ctx ctx, const fpn_batch* batch, int64_t n, const fpn_drive* drive,
+                             int32_t samples_per_period, double tol, int32_t L_max, int32_t* L_out, double* est_out,
+                             int32_t* status, void* stream);
+
 /* Kernel timing (diagnostic).  When enabled, every kernel launch of fpn_solve and
  * fpn_stationary is bracketed by HIP events recorded on the launch stream; reading
  * synchronises those events and returns the accumulated device time.

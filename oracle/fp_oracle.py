@@ -280,6 +280,46 @@ def langevin(x):
     return np.where(small, x / 3 - x ** 3 / 45, 1 / np.tanh(xs) - 1 / xs)
 
 
+def peak_field(drive, offset, n_samples):
+    """mu0 H(t_j) at t_j = j T / N_s of largest magnitude (the first sample within a relative 1e-9 of
+    the largest squared magnitude)."""
+    T = drive["period"]
+    B = drive_field(drive, np.asarray(offset, float), np.arange(n_samples) * T / n_samples)
+    b2 = np.einsum("ij,ij->i", B, B)
+    return B[int(np.nonzero(b2 >= b2.max() * (1.0 - 1e-9))[0][0])]
+
+
+def truncation_estimate(p, n, L, drive, offset, n_samples):
+    """Estimate of the truncation error of degree L: |m_L - m_{L-2}| of the stationary moments under
+    the largest sampled field (a heuristic indicator, not from the paper; the tests check that it
+    bounds the degree-L error of the periodic m(t) against finite-volume and higher-degree solves)."""
+    B = peak_field(drive, offset, n_samples)
+    ms = []
+    for LL in (L, L - 2):
+        A0, Aa, _ = operator_parts(p, n, LL)
+        ms.append(moment(stationary(A0 + B[0] * Aa[0] + B[1] * Aa[1] + B[2] * Aa[2])))
+    return float(np.linalg.norm(ms[0] - ms[1]))
+
+
+def select_degree(p, n, L_min, drive, offset, n_samples, tol, L_max=24):
+    """Smallest degree L in L_min..L_max with truncation_estimate(L) <= tol (L_max if none); returns
+    (L, its estimate)."""
+    B = peak_field(drive, offset, n_samples)
+    ms = {}
+
+    def m_at(LL):
+        if LL not in ms:
+            A0, Aa, _ = operator_parts(p, n, LL)
+            ms[LL] = moment(stationary(A0 + B[0] * Aa[0] + B[1] * Aa[1] + B[2] * Aa[2]))
+        return ms[LL]
+
+    for L in range(L_min, L_max + 1):
+        e = float(np.linalg.norm(m_at(L) - m_at(L - 2)))
+        if e <= tol:
+            return L, e
+    return L_max, e
+
+
 def equilibrium_instance(p, drive, n_samples, settle, n_harm, offset=(0, 0, 0)):
     """Equilibrium model (model M0 of the data-driven models section, Eq. Langevin): the moment follows
     the field without delay and without anisotropy, m(t) = L(beta |H(t)|) H(t) / |H(t)| with

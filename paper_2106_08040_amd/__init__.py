@@ -35,7 +35,7 @@ FPN_STATIC_MAX_N, FPN_STATIC_MAX_NS = 128, 2048
 FPN_NPARAM = 5  # sensitivities: D, K, alpha, easy-axis polar angle, azimuth
 
 EXPORTED = ["fpn_status_string", "fpn_last_error", "fpn_create", "fpn_destroy", "fpn_solve",
-            "fpn_stationary", "fpn_last_steps", "fpn_timing_enable", "fpn_timing_read", "fpn_host_operator", "fpn_host_frame",
+            "fpn_stationary", "fpn_truncation_estimate", "fpn_select_degree", "fpn_last_steps", "fpn_timing_enable", "fpn_timing_read", "fpn_host_operator", "fpn_host_frame",
             "fpn_host_table_nnz", "fpn_mlp_create", "fpn_mlp_destroy", "fpn_mlp_num_params", "fpn_mlp_params",
             "fpn_mlp_set_input_norm", "fpn_mlp_forward", "fpn_mlp_gradient", "fpn_mlp_train_step",
             "fpn_surrogate_features", "fpn_surrogate_predict", "fpn_plan_create", "fpn_plan_launch",
@@ -85,6 +85,12 @@ _lib.fpn_equilibrium.argtypes = [_vp, ctypes.POINTER(fpn_drive), ctypes.POINTER(
                                  ctypes.POINTER(fpn_batch), ctypes.c_int64, _vp, _vp, _vp, _vp]
 _lib.fpn_stationary.restype = ctypes.c_int32
 _lib.fpn_stationary.argtypes = [_vp, ctypes.POINTER(fpn_batch), ctypes.c_int64, _vp, _vp, _vp, _vp]
+_lib.fpn_select_degree.restype = ctypes.c_int32
+_lib.fpn_select_degree.argtypes = [_vp, ctypes.POINTER(fpn_batch), ctypes.c_int64, ctypes.POINTER(fpn_drive),
+                                   ctypes.c_int32, ctypes.c_double, ctypes.c_int32, _vp, _vp, _vp, _vp]
+_lib.fpn_truncation_estimate.restype = ctypes.c_int32
+_lib.fpn_truncation_estimate.argtypes = [_vp, ctypes.POINTER(fpn_batch), ctypes.c_int64, ctypes.POINTER(fpn_drive),
+                                         ctypes.c_int32, _vp, _vp, _vp]
 _lib.fpn_last_steps.restype = ctypes.c_int32
 _lib.fpn_last_steps.argtypes = [_vp, ctypes.POINTER(ctypes.c_int64)]
 _lib.fpn_timing_enable.restype = ctypes.c_int32
@@ -652,6 +658,37 @@ class Context:
                                    s.cuda_stream), "fpn_stationary")
         torch.cuda.synchronize(self.device)
         return m, st
+
+    def select_degree(self, inst, L_min, drive, samples, tol, L_max=FPN_MAX_L):
+        """fpn_select_degree: per instance the smallest degree in L_min[i]..L_max whose truncation
+        estimate is <= tol.  Returns (L [n] int32 numpy, est [n] float64 device, status [n] int32 device)."""
+        torch = _torch()
+        dev = f"cuda:{self.device}"
+        b, keep, Lh = self._batch(inst, L_min)
+        n = keep["D"].numel()
+        Lout = np.empty(n, dtype=np.int32)
+        est = torch.empty((n,), dtype=torch.float64, device=dev)
+        st = torch.empty((n,), dtype=torch.int32, device=dev)
+        s = torch.cuda.current_stream(self.device)
+        _check(_lib.fpn_select_degree(self._h, ctypes.byref(b), n, ctypes.byref(drive), int(samples), float(tol),
+                                      int(L_max), Lout.ctypes.data, est.data_ptr(), st.data_ptr(), s.cuda_stream),
+               "fpn_select_degree")
+        return Lout, est, st
+
+    def truncation_estimate(self, inst, L, drive, samples):
+        """|m_L - m_{L-2}| of the stationary moments under each instance's largest sampled field
+        (fpn_truncation_estimate): an upper estimate of the degree-L truncation error.  Returns
+        (est [n] float64, status [n] int32) on the device."""
+        torch = _torch()
+        dev = f"cuda:{self.device}"
+        b, keep, Lh = self._batch(inst, L)
+        n = keep["D"].numel()
+        est = torch.empty((n,), dtype=torch.float64, device=dev)
+        st = torch.empty((n,), dtype=torch.int32, device=dev)
+        s = torch.cuda.current_stream(self.device)
+        _check(_lib.fpn_truncation_estimate(self._h, ctypes.byref(b), n, ctypes.byref(drive), int(samples),
+                                            est.data_ptr(), st.data_ptr(), s.cuda_stream), "fpn_truncation_estimate")
+        return est, st
 
 
 def _f32(x, device):

@@ -338,6 +338,7 @@ fpn_status fpn_destroy(fpn_ctx ctx) {
   ctx->steps.release();
   ctx->wide_ws.release();
   ctx->m2_mt.release();
+  ctx->trunc_field.release();
   ctx->m2_y.release();
   for (fpn_plan_s* pl : {ctx->solve_plan, ctx->tangent_plan}) {
     if (pl) {
@@ -1091,17 +1092,14 @@ fpn_status fpn_equilibrium(fpn_ctx ctx, const fpn_drive* drive, const fpn_solve_
   return FPN_OK;
 }
 
-fpn_status fpn_stationary(fpn_ctx ctx, const fpn_batch* batch, int64_t n, const double* field, double* m_out,
-                          int32_t* status, void* stream_) {
-  if (!ctx) return fail(FPN_E_ARG, "ctx is NULL");
-  if (n < 0) return fail(FPN_E_ARG, "n < 0");
-  if (n == 0) return FPN_OK;
-  if (!field || !m_out || !status) return fail(FPN_E_ARG, "field, m_out and status are required");
-  if (fpn_status s = validate_batch(batch, n)) return s;
-  std::lock_guard<std::mutex> lk(ctx->mu);
-  hipStream_t stream = reinterpret_cast<hipStream_t>(stream_);
-  FPN_HIP(hipSetDevice(ctx->device));
-  auto groups = group_by_L(batch->L, n);
+namespace {
+
+// Stationary states of degree L[i] (host array) under the per-instance fields `field` [n][3] (device),
+// reduced on the host to the lab-frame moments m [n][3] (host vector).  Shared by fpn_stationary and
+// fpn_truncation_estimate; the caller holds the context lock.
+fpn_status stationary_moments(fpn_ctx ctx, const fpn_batch* batch, const int32_t* L, int64_t n, const double* field,
+                              std::vector<double>* m, int32_t* status, hipStream_t stream) {
+  auto groups = group_by_L(L, n);
   std::map<int, const fpn::DevTables*> tabs;
   int64_t inv_max = 0, np_max = 0;
   size_t maxg = 0;
@@ -1140,16 +1138,129 @@ fpn_status fpn_stationary(fpn_ctx ctx, const fpn_batch* batch, int64_t n, const 
   FPN_HIP(hipMemcpyAsync(hip_ip.data(), ctx->ip.p, n * sizeof(fpn::InstParams), hipMemcpyDeviceToHost, stream));
   FPN_HIP(hipMemcpyAsync(c.data(), ctx->c0.p, c.size() * sizeof(double), hipMemcpyDeviceToHost, stream));
   FPN_HIP(hipStreamSynchronize(stream));
-  std::vector<double> m(size_t(n) * 3);
+  m->assign(size_t(n) * 3, 0.0);
   const double rc = std::sqrt(4.0 * fpn::kPi / 3.0);
   for (int64_t i = 0; i < n; ++i) {
-    const int n0 = tabs[batch->L[i]]->n0;
+    const int n0 = tabs[L[i]]->n0;
     const double* ci = c.data() + i * np_max;
     const double mp[3] = {rc * ci[n0], rc * ci[n0 + 1], rc * ci[1]};
     for (int a = 0; a < 3; ++a)
-      m[3 * i + a] = hip_ip[i].R[3 * a] * mp[0] + hip_ip[i].R[3 * a + 1] * mp[1] + hip_ip[i].R[3 * a + 2] * mp[2];
+      (*m)[3 * i + a] = hip_ip[i].R[3 * a] * mp[0] + hip_ip[i].R[3 * a + 1] * mp[1] + hip_ip[i].R[3 * a + 2] * mp[2];
   }
+  return FPN_OK;
+}
+
+}  // namespace
+
+fpn_status fpn_stationary(fpn_ctx ctx, const fpn_batch* batch, int64_t n, const double* field, double* m_out,
+                          int32_t* status, void* stream_) {
+  if (!ctx) return fail(FPN_E_ARG, "ctx is NULL");
+  if (n < 0) return fail(FPN_E_ARG, "n < 0");
+  if (n == 0) return FPN_OK;
+  if (!field || !m_out || !status) return fail(FPN_E_ARG, "field, m_out and status are required");
+  if (fpn_status s = validate_batch(batch, n)) return s;
+  std::lock_guard<std::mutex> lk(ctx->mu);
+  hipStream_t stream = reinterpret_cast<hipStream_t>(stream_);
+  FPN_HIP(hipSetDevice(ctx->device));
+  std::vector<double> m;
+  if (fpn_status s = stationary_moments(ctx, batch, batch->L, n, field, &m, status, stream)) return s;
   FPN_HIP(hipMemcpyAsync(m_out, m.data(), m.size() * sizeof(double), hipMemcpyHostToDevice, stream));
+  FPN_HIP(hipStreamSynchronize(stream));
+  return FPN_OK;
+}
+
+fpn_status fpn_select_degree(fpn_ctx ctx, const fpn_batch* batch, int64_t n, const fpn_drive* drive,
+                             int32_t samples_per_period, double tol, int32_t L_max, int32_t* L_out, double* est_out,
+                             int32_t* status, void* stream_) {
+  if (!ctx) return fail(FPN_E_ARG, "ctx is NULL");
+  if (n < 0) return fail(FPN_E_ARG, "n < 0");
+  if (n == 0) return FPN_OK;
+  if (!drive || !L_out || !status) return fail(FPN_E_ARG, "drive, L_out and status are required");
+  if (samples_per_period < 1) return fail(FPN_E_ARG, "samples_per_period < 1");
+  if (!(drive->period > 0.0) || !std::isfinite(drive->period)) return fail(FPN_E_ARG, "drive period must be > 0");
+  if (!(tol > 0.0)) return fail(FPN_E_ARG, "tol must be > 0");
+  if (L_max < 3 || L_max > FPN_MAX_L) return fail(FPN_E_RANGE, "L_max must be in 3..24");
+  if (fpn_status s = validate_batch(batch, n)) return s;
+  int lo = L_max;
+  for (int64_t i = 0; i < n; ++i) {
+    if (batch->L[i] < 3 || batch->L[i] > L_max) return fail(FPN_E_RANGE, "the starting degrees must be in 3..L_max");
+    lo = std::min(lo, int(batch->L[i]));
+  }
+  std::lock_guard<std::mutex> lk(ctx->mu);
+  hipStream_t stream = reinterpret_cast<hipStream_t>(stream_);
+  FPN_HIP(hipSetDevice(ctx->device));
+  FPN_HIP(ctx->trunc_field.ensure(size_t(n) * 3));
+  fpn::launch_peak_field(n, batch->offset, drive->amp, drive->freq, drive->phase, drive->period, samples_per_period,
+                         ctx->trunc_field.p, stream);
+  FPN_HIP(hipGetLastError());
+  // moments of every degree lo - 2 .. L_max for every instance (each degree one batch of stationary solves)
+  const int nd = L_max - (lo - 2) + 1;
+  std::vector<std::vector<double>> m(static_cast<size_t>(nd));
+  std::vector<int32_t> Ld(n);
+  for (int d = 0; d < nd; ++d) {
+    std::fill(Ld.begin(), Ld.end(), int32_t(lo - 2 + d));
+    if (fpn_status s = stationary_moments(ctx, batch, Ld.data(), n, ctx->trunc_field.p, &m[size_t(d)], status, stream))
+      return s;
+  }
+  std::vector<int32_t> st(n);
+  FPN_HIP(hipMemcpyAsync(st.data(), status, n * sizeof(int32_t), hipMemcpyDeviceToHost, stream));
+  FPN_HIP(hipStreamSynchronize(stream));
+  std::vector<double> est(n);
+  for (int64_t i = 0; i < n; ++i) {
+    L_out[i] = L_max;
+    est[i] = std::nan("");
+    if (st[i] != 0) continue;
+    for (int L = batch->L[i]; L <= L_max; ++L) {
+      const double* a = m[size_t(L - (lo - 2))].data() + 3 * i;
+      const double* b = m[size_t(L - 2 - (lo - 2))].data() + 3 * i;
+      const double e = std::sqrt((a[0] - b[0]) * (a[0] - b[0]) + (a[1] - b[1]) * (a[1] - b[1]) +
+                                 (a[2] - b[2]) * (a[2] - b[2]));
+      L_out[i] = L;
+      est[i] = e;
+      if (e <= tol) break;
+    }
+  }
+  if (est_out) {
+    FPN_HIP(hipMemcpyAsync(est_out, est.data(), n * sizeof(double), hipMemcpyHostToDevice, stream));
+    FPN_HIP(hipStreamSynchronize(stream));
+  }
+  return FPN_OK;
+}
+
+fpn_status fpn_truncation_estimate(fpn_ctx ctx, const fpn_batch* batch, int64_t n, const fpn_drive* drive,
+                                   int32_t samples_per_period, double* est_out, int32_t* status, void* stream_) {
+  if (!ctx) return fail(FPN_E_ARG, "ctx is NULL");
+  if (n < 0) return fail(FPN_E_ARG, "n < 0");
+  if (n == 0) return FPN_OK;
+  if (!drive || !est_out || !status) return fail(FPN_E_ARG, "drive, est_out and status are required");
+  if (samples_per_period < 1) return fail(FPN_E_ARG, "samples_per_period < 1");
+  if (!(drive->period > 0.0) || !std::isfinite(drive->period)) return fail(FPN_E_ARG, "drive period must be > 0");
+  if (fpn_status s = validate_batch(batch, n)) return s;
+  std::vector<int32_t> Llow(n);
+  for (int64_t i = 0; i < n; ++i) {
+    if (batch->L[i] < 3) return fail(FPN_E_RANGE, "the truncation estimate needs L >= 3");
+    Llow[i] = batch->L[i] - 2;
+  }
+  std::lock_guard<std::mutex> lk(ctx->mu);
+  hipStream_t stream = reinterpret_cast<hipStream_t>(stream_);
+  FPN_HIP(hipSetDevice(ctx->device));
+  FPN_HIP(ctx->trunc_field.ensure(size_t(n) * 3));
+  fpn::launch_peak_field(n, batch->offset, drive->amp, drive->freq, drive->phase, drive->period, samples_per_period,
+                         ctx->trunc_field.p, stream);
+  FPN_HIP(hipGetLastError());
+  std::vector<double> ma, mb;
+  if (fpn_status s = stationary_moments(ctx, batch, batch->L, n, ctx->trunc_field.p, &ma, status, stream)) return s;
+  if (fpn_status s = stationary_moments(ctx, batch, Llow.data(), n, ctx->trunc_field.p, &mb, status, stream)) return s;
+  std::vector<int32_t> st(n);
+  FPN_HIP(hipMemcpyAsync(st.data(), status, n * sizeof(int32_t), hipMemcpyDeviceToHost, stream));
+  FPN_HIP(hipStreamSynchronize(stream));
+  std::vector<double> est(n);
+  for (int64_t i = 0; i < n; ++i) {
+    double d2 = 0.0;
+    for (int a = 0; a < 3; ++a) d2 += (ma[3 * i + a] - mb[3 * i + a]) * (ma[3 * i + a] - mb[3 * i + a]);
+    est[i] = st[i] == 0 ? std::sqrt(d2) : std::nan("");
+  }
+  FPN_HIP(hipMemcpyAsync(est_out, est.data(), n * sizeof(double), hipMemcpyHostToDevice, stream));
   FPN_HIP(hipStreamSynchronize(stream));
   return FPN_OK;
 }

@@ -102,6 +102,8 @@ struct fpn_ctx_s {
   fpn_internal::DevBuf<double> sur_g;
   // model M2 dictionary matrix (transposed) and data vector, complex FP32 as float pairs
   fpn_internal::DevBuf<float> m2_mt, m2_y;
+  // truncation estimate: the field of largest magnitude per instance
+  fpn_internal::DevBuf<double> trunc_field;
   // kernel timing
   bool timing = false;
   std::vector<std::pair<int, std::pair<hipEvent_t, hipEvent_t>>> events;

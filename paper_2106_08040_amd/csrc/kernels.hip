@@ -472,6 +472,40 @@ __global__ void equilibrium_kernel(int64_t n, int Ns, int settle, EqDrive d, con
   for (int c = 0; c < 3; ++c) out[c * Ns] = float(s * b[c]);
 }
 
+// Field of largest magnitude over the samples of one period, one thread per instance (FP64).  Ties:
+// the first sample whose squared magnitude is within a relative 1e-9 of the largest, so that the choice
+// does not hang on the last bits of the cosines.
+struct PeakDrive {
+  double amp[3], freq[3], phase[3], period;
+};
+
+__global__ void peak_field_kernel(int64_t n, const double* offset, PeakDrive d, int Ns, double* field) {
+  const int64_t i = blockIdx.x * int64_t(blockDim.x) + threadIdx.x;
+  if (i >= n) return;
+  const double o[3] = {offset[3 * i], offset[3 * i + 1], offset[3 * i + 2]};
+  auto field_at = [&](int j, double* b) {
+    for (int c = 0; c < 3; ++c) {
+      double cyc = d.freq[c] * d.period * double(j) / double(Ns);
+      cyc -= floor(cyc);
+      b[c] = o[c] + d.amp[c] * cos(2.0 * kPi * cyc + d.phase[c]);
+    }
+  };
+  double best = -1.0;
+  for (int j = 0; j < Ns; ++j) {
+    double b[3];
+    field_at(j, b);
+    best = fmax(best, b[0] * b[0] + b[1] * b[1] + b[2] * b[2]);
+  }
+  for (int j = 0; j < Ns; ++j) {
+    double b[3];
+    field_at(j, b);
+    if (b[0] * b[0] + b[1] * b[1] + b[2] * b[2] >= best * (1.0 - 1e-9)) {
+      for (int c = 0; c < 3; ++c) field[3 * i + c] = b[c];
+      return;
+    }
+  }
+}
+
 __global__ void fill_i32_kernel(int32_t* p, int n, int32_t v) {
   const int i = blockIdx.x * blockDim.x + threadIdx.x;
   if (i < n) p[i] = v;
@@ -485,6 +519,20 @@ void launch_equilibrium(int64_t n, int Ns, int settle, const EqDrive& d, const I
   if (total <= 0) return;
   hipLaunchKernelGGL(equilibrium_kernel, dim3(unsigned((total + 255) / 256)), dim3(256), 0, stream, n, Ns, settle, d,
                      ip, status, m);
+}
+
+void launch_peak_field(int64_t n, const double* offset, const double* amp, const double* freq, const double* phase,
+                       double period, int Ns, double* field_out, hipStream_t stream) {
+  if (n <= 0) return;
+  PeakDrive d;
+  for (int c = 0; c < 3; ++c) {
+    d.amp[c] = amp[c];
+    d.freq[c] = freq[c];
+    d.phase[c] = phase[c];
+  }
+  d.period = period;
+  hipLaunchKernelGGL(peak_field_kernel, dim3(unsigned((n + 255) / 256)), dim3(256), 0, stream, n, offset, d, Ns,
+                     field_out);
 }
 
 void launch_fill_i32(int32_t* p, int n, int32_t v, hipStream_t stream) {

@@ -81,6 +81,10 @@ void launch_stationary(const DevTables& t, const int32_t* idx, int n_inst, const
                        const double* field_lab, double3 drive0, double* c_out, int64_t c_stride, double* wsinv,
                        int32_t* status, hipStream_t stream);
 hipError_t launch_stepper(int L, const StepLaunch& s, const DevTables& t, float* ws, hipStream_t stream);
+// field mu0 H(t_j) [T] (lab frame) of largest magnitude over the samples t_j = j T / Ns of one period,
+// per instance (offset [n][3] + the drive); field_out [n][3]
+void launch_peak_field(int64_t n, const double* offset, const double* amp, const double* freq, const double* phase,
+                       double period, int Ns, double* field_out, hipStream_t stream);
 void launch_stationary_tangent(const DevTables& t, const int32_t* idx, int n_inst, const InstParams* ip,
                                double3 drive0, const double* c0, int64_t c_stride, const double* wsinv, double* ct,
                                int32_t* status, hipStream_t stream);

@@ -263,3 +263,32 @@ def test_stored_finite_volume_solutions_pin_the_galerkin_oracle(path):
     err = rel(R45, R34) + rel(z["fv4"], z["fv4_half_r"]) / 3
     assert rel(g, R45) <= 2.0 * err + 1e-5
     assert rel(z["gal_4"], R45) > 10.0 * (2.0 * err + 1e-5)
+
+
+@pytest.mark.parametrize("path", _fv_goldens())
+def test_truncation_estimate_bounds_the_truncation_error(path):
+    """The oracle's truncation estimate (stationary moments of degrees L and L - 2 under the largest
+    sampled field) lies above the degree-L error of the periodic m(t) measured against the
+    finite-volume reference, within a factor 30."""
+    import workloads as W
+    z = np.load(path)
+    i = int(z["idx"])
+    ws = W.fv_crosscheck()
+    inst = {k: v[i] for k, v in ws["inst"].items()}
+    p = dict(D=inst["D"], Ms=inst["Ms"], K=inst["K"], alpha=inst["alpha"], T=inst["T"])
+    est = O.truncation_estimate(p, inst["easy_axis"], int(inst["L"]), ws["drive"], inst["offset"], ws["samples"])
+    R45 = (4 * z["fv5"] - z["fv4"]) / 3
+    R34 = (4 * z["fv4"] - z["fv3"]) / 3
+    err = rel(R45, R34) + rel(z["fv4"], z["fv4_half_r"]) / 3
+    trunc = rel(z["gal_L"], R45)
+    assert est >= trunc - 2.0 * err
+    assert est <= 30.0 * max(trunc, 2.0 * err)
+
+
+def test_peak_field_picks_the_first_of_equal_maxima():
+    T = 1e-5
+    drive = dict(amp=(1e-2, 1e-2, 0.0), freq=(2 / T, 3 / T, 0.0), phase=(0.0, 0.0, 0.0), period=T)
+    # at t = 0 both components are at +10 mT; at t = T/2 x is at +10 mT and y at -10 mT: a tie
+    np.testing.assert_allclose(O.peak_field(drive, (0, 0, 0), 64), [1e-2, 1e-2, 0.0])
+    # an offset in -y makes the second maximum the larger one
+    np.testing.assert_allclose(O.peak_field(drive, (0, -1e-3, 0), 64), [1e-2, -1.1e-2, 0.0])
