@@ -8,8 +8,16 @@ namespace fpn {
 
 // ------------------------------------------------------------------ helpers ---
 
-// Completes this wavefront's outstanding LDS traffic and orders memory accesses.
-__device__ __forceinline__ void wsync() { asm volatile("s_waitcnt lgkmcnt(0)" ::: "memory"); }
+// Orders the memory accesses of the lanes of one wavefront: what a lane wrote before the call is
+// seen by every lane of the same wavefront after it.  A wavefront's LDS and global-memory operations
+// are performed in program order (the AMDGPU memory model needs no wait counter at wavefront
+// scope), so this is a fence for the compiler only: a write followed by a read of another lane's
+// data does not wait for the write to complete before the read is issued.
+__device__ __forceinline__ void wsync() {
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+  __builtin_amdgcn_wave_barrier();
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
 
 template <int I, int E, typename F>
 __device__ __forceinline__ void static_for(F&& f) {

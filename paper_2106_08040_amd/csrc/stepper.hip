@@ -89,6 +89,11 @@ struct WaveLds {
 // half of kH slots per parity) puts it back in order.  kRow0 (block 0): row 0 is e_0 (the probability
 // row of M = I - h g A, A having a zero row 0) and pivots column 0, so it stays e_0 and the total
 // probability c_00 is conserved exactly by every solve.
+// Pivot rows are not divided by their pivot P when they pivot: a row is kept as P times the
+// normalised tableau row (its pivot-column entry 1 instead of 1/P) and scaled by 1/P once at the end.
+// Every later update of a row is linear in it, so the stored row stays P times the true one, and a
+// row is broadcast only at its own pivot step, before any scaling, so the broadcast rows are the ones
+// the plain algorithm uses.  This saves a multiply per entry and column.
 template <int Q, bool kRow0, typename W>
 __device__ __forceinline__ bool gj_piv_invert(float (&a)[Q], int i, int h, W& w, float* X) {
   constexpr int n = 2 * Q;
@@ -98,6 +103,7 @@ __device__ __forceinline__ bool gj_piv_invert(float (&a)[Q], int i, int h, W& w,
   bool ok = true;
   bool cand = act;  // row not yet a pivot
   int mycol = 0;    // column this row pivoted
+  float myip = 1.0f;  // 1 / pivot of this row: the row's deferred scale
   int* pv = w.pv;  // pivot row of column c at [(c & 1) kH + (c >> 1)]
 #pragma unroll 1
   for (int qq = 0; qq < Q; ++qq) {
@@ -123,23 +129,24 @@ __device__ __forceinline__ bool gj_piv_invert(float (&a)[Q], int i, int h, W& w,
 #pragma unroll
       for (int q = 0; q < Q; ++q) rv[q] = w.row[h * kH + q];
       __builtin_amdgcn_sched_barrier(0);
-      // pivot row: ip * row; other rows: row - g ip * pivot row; the pivot column becomes the inverse's
-      const float G = isp ? -ip : g * ip;
-      const float s = isp ? 0.0f : 1.0f;
-      const float pc = act ? (isp ? ip : -g * ip) : 0.0f;
+      // pivot row: unchanged (deferred scale 1 / P, pivot-column entry P / P = 1); other rows:
+      // row - g / P * pivot row, pivot-column entry -g / P
+      const float G = isp ? 0.0f : g * ip;
+      const float pc = act ? (isp ? 1.0f : -G) : 0.0f;
       if (hc == 0) {
 #pragma unroll
-        for (int q = 0; q < Q; ++q) a[q] = fmaf(-G, rv[q], s * a[q]);
+        for (int q = 0; q < Q; ++q) a[q] = fmaf(-G, rv[q], a[q]);
         if (h == 0) a[0] = pc;
       } else {
-        const float a0 = fmaf(-G, rv[0], s * a[0]);
+        const float a0 = fmaf(-G, rv[0], a[0]);
 #pragma unroll
-        for (int q = 1; q < Q; ++q) a[q - 1] = fmaf(-G, rv[q], s * a[q]);
+        for (int q = 1; q < Q; ++q) a[q - 1] = fmaf(-G, rv[q], a[q]);
         a[Q - 1] = (h == 1) ? pc : a0;
       }
       if (isp) {
         cand = false;
         mycol = 2 * qq + hc;
+        myip = ip;
       }
       wsync();
     }
@@ -151,7 +158,7 @@ __device__ __forceinline__ bool gj_piv_invert(float (&a)[Q], int i, int h, W& w,
   __builtin_amdgcn_sched_barrier(0);
   if (act) {
 #pragma unroll
-    for (int q = 0; q < Q; ++q) X[mycol * kXS + (pj[q] & 1) * kH + (pj[q] >> 1)] = a[q];
+    for (int q = 0; q < Q; ++q) X[mycol * kXS + (pj[q] & 1) * kH + (pj[q] >> 1)] = a[q] * myip;
   }
   wsync();
 #pragma unroll
@@ -235,11 +242,16 @@ stepper_kernel(StepArgs A, DevTables t) {
   for (int c = 0; c < 9; ++c) R[c] = float(P.R[c]);
   for (int c = 0; c < 3; ++c) off[c] = float(P.off[c]);
 
-  float y[S];
+  // The state is kept as an unevaluated sum y + ylo of two FP32 parts (compensated accumulation):
+  // a step adds a small increment to it, and rounding the sum to one FP32 number at every step would
+  // accumulate a relative error of order sqrt(steps) * 2^-24 over the thousands of steps of a solve.
+  float y[S], ylo[S];
 #pragma unroll
   for (int s = 0; s < S; ++s) {
     const int p = lane + 64 * s;
-    y[s] = (p < Np) ? float(A.c0[int64_t(inst) * A.c_stride + p]) : 0.0f;
+    const double c = (p < Np) ? A.c0[int64_t(inst) * A.c_stride + p] : 0.0;
+    y[s] = float(c);
+    ylo[s] = float(c - double(y[s]));
   }
   float ep[3] = {0.0f, 0.0f, 0.0f};  // R^T e for the tangent direction of this lane (lane / 9)
   if constexpr (NT > 0) {
@@ -746,7 +758,7 @@ stepper_kernel(StepArgs A, DevTables t) {
 #pragma unroll
       for (int s = 0; s < S; ++s) {
         const int p = lane + 64 * s;
-        if (p < Np) xin[p] = y[s];
+        if (p < Np) xin[p] = y[s] + ylo[s];
       }
       wsync();
       matvec(w.ft(), false, w.xin());
@@ -757,7 +769,7 @@ stepper_kernel(StepArgs A, DevTables t) {
 #pragma unroll
         for (int s = 0; s < S; ++s) {
           const int p = lane + 64 * s;
-          if (p < Np) y0[p] = y[s];
+          if (p < Np) y0[p] = y[s] + ylo[s];
         }
         const float dn = tan_lane(tn, false), dd = tan_lane(tn, true);
         if (lane < 9 * NT) {
@@ -795,14 +807,14 @@ stepper_kernel(StepArgs A, DevTables t) {
           for (int s = 0; s < S; ++s) {
             const int p = lane + 64 * s;
             if (p < Np) {
-              float yv = y[s];
+              float sv = ylo[s];
               float ev = hf * kRodasGamma[stg] * w.ft()[p];
               for (int j = 0; j < stg; ++j) {
                 const float kj = w.Kv(j)[p];
-                yv = fmaf(kRodasA[stg][j], kj, yv);
+                sv = fmaf(kRodasA[stg][j], kj, sv);
                 ev = fmaf(kRodasC[stg][j] * ih, kj, ev);
               }
-              xin[p] = yv;
+              xin[p] = y[s] + sv;
               V[p] = ev;
             }
           }
@@ -881,15 +893,23 @@ stepper_kernel(StepArgs A, DevTables t) {
     }
     return wave_max(emax);
   };
-  // y <- y_{n+1} of the step just taken
+  // y + ylo <- y_{n+1} = y_n + sum_j a_6j K_j + K6 of the step just taken (the stage-6 argument plus
+  // K6): the increment is formed apart from y and added to it by an exact two-sum
   auto accept = [&](float hg) {
-    const float* xin = w.xin();
     const float* k6 = (NT > 0) ? w.kc() : w.G();
     const float sc = (NT > 0) ? 1.0f : hg;
 #pragma unroll
     for (int s = 0; s < S; ++s) {
       const int p = lane + 64 * s;
-      y[s] = (p < Np) ? xin[p] + sc * k6[p] : 0.0f;
+      if (p < Np) {
+        float d = fmaf(sc, k6[p], ylo[s]);
+#pragma unroll
+        for (int j = 0; j < 5; ++j) d = fmaf(kRodasA[5][j], w.Kv(j)[p], d);
+        const float t = y[s] + d;
+        const float bb = t - y[s];
+        ylo[s] = (y[s] - (t - bb)) + (d - bb);
+        y[s] = t;
+      }
     }
   };
 
@@ -908,8 +928,8 @@ stepper_kernel(StepArgs A, DevTables t) {
   bool forced = false;  // a step accepted at the smallest step size with its estimate above tol
   for (int j = 0; j < n_int && ok; ++j) {
     const double tj = j * dt;
-    const float vx = __shfl(y[pX >> 6], pX & 63), vy = __shfl(y[pY >> 6], pY & 63),
-                vz = __shfl(y[pZ >> 6], pZ & 63);
+    const float vx = __shfl(y[pX >> 6] + ylo[pX >> 6], pX & 63), vy = __shfl(y[pY >> 6] + ylo[pY >> 6], pY & 63),
+                vz = __shfl(y[pZ >> 6] + ylo[pZ >> 6], pZ & 63);
     {
       // a probability density has |m| <= 1 and keeps c_00 (conserved exactly by the solves); a state
       // that breaks either is not resolved by the degree (status FPN_INST_UNRESOLVED, stop here)
@@ -937,7 +957,7 @@ stepper_kernel(StepArgs A, DevTables t) {
 #pragma unroll
         for (int s = 0; s < S; ++s) {
           const int p = lane + 64 * s;
-          if (p < Np) xs[p] = y[s];
+          if (p < Np) xs[p] = y[s] + ylo[s];
         }
         wsync();
         float acc = 0.0f;

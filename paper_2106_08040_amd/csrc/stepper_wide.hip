@@ -102,6 +102,7 @@ __device__ __forceinline__ void two_sum(float a, float b, float& s, float& e) {
 // pivots the columns are back in their original order and all register indexing is static.  The
 // tableau then holds the inverse with rows and columns permuted; X (row stride XS) puts it back.
 // kRow0 (block 0): row 0 is e_0 and pivots column 0, which conserves c_00 exactly (see stepper.hip).
+// As there, a pivot row keeps its scale P (pivot-column entry 1) and is divided by P once at the end.
 template <int n, int XS, bool kRow0, typename WL>
 __device__ __forceinline__ bool gj_piv_invert_wide(float (&a)[n], int lane, WL& w, float* X) {
   const bool act = lane < n;
@@ -109,6 +110,7 @@ __device__ __forceinline__ bool gj_piv_invert_wide(float (&a)[n], int lane, WL& 
   bool cand = act;
   int mycol = 0;  // column this row pivoted
   int cpiv = 0;   // lane k: pivot row of column k
+  float myip = 1.0f;  // 1 / pivot of this row (deferred scale)
 #pragma unroll 1
   for (int k = 0; k < n; ++k) {
     const float g = a[0];
@@ -124,24 +126,24 @@ __device__ __forceinline__ bool gj_piv_invert_wide(float (&a)[n], int lane, WL& 
     }
     if (lane == k) cpiv = p;
     wsync();
-    const float G = isp ? -ip : g * ip;
-    const float s = isp ? 0.0f : 1.0f;
+    const float G = isp ? 0.0f : g * ip;
 #pragma unroll
     for (int q = 1; q < n; ++q) {
-      a[q - 1] = fmaf(-G, w.prow[0][q], s * a[q]);
+      a[q - 1] = fmaf(-G, w.prow[0][q], a[q]);
       if ((q & 7) == 7) __builtin_amdgcn_sched_barrier(0);
     }
-    a[n - 1] = act ? (isp ? ip : -g * ip) : 0.0f;
+    a[n - 1] = act ? (isp ? 1.0f : -G) : 0.0f;
     if (isp) {
       cand = false;
       mycol = k;
+      myip = ip;
     }
     wsync();
   }
   // inverse entry (a, b) = tableau entry (pivot row of column a, column pivoted by row b)
   if (act) {
 #pragma unroll
-    for (int q = 0; q < n; ++q) X[lane * XS + q] = a[q];
+    for (int q = 0; q < n; ++q) X[lane * XS + q] = a[q] * myip;
   }
   wsync();
   const float* xr = X + cpiv * XS;
