@@ -101,7 +101,9 @@ typedef struct {
                                   0: adaptive: every RODAS4 step is accepted or redone on its own
                                   embedded error, step sizes between 1/64 of the sample spacing and
                                   the sample spacing, the last step of each interval ending on the
-                                  sample time; an attempt that overflows is redone 5x shorter, and
+                                  sample time (while settling, where nothing is sampled, up to 8
+                                  sample spacings per step, the last one ending on the first recorded
+                                  sample time); an attempt that overflows is redone 5x shorter, and
                                   the instance ends FPN_INST_NONFINITE only when that happens at the
                                   smallest step (with fixed steps: at once) */
   uint32_t flags;              /* FPN_OUT_* */

@@ -132,6 +132,10 @@ static __constant__ float kRodasC[6][5] = {
     {7.496443313967647f, -10.24680431464352f, -33.99990352819905f, 11.70890893206160f, 0},
     {8.083246795921522f, -7.981132988064893f, -31.52159432874371f, 16.31930543123136f, -6.058818238834054f}};
 
+// Adaptive settling: largest step, in sample spacings, while no sample is recorded (the error
+// control sizes the steps; this only bounds them).
+constexpr double kSettleSpan = 8.0;
+
 struct StepArgs {
   const InstParams* ip;
   const int32_t* inst_idx;

@@ -700,20 +700,21 @@ stepper_wide_kernel(StepArgs A, DevTables t, float* ws) {
   const float c00_0 = __shfl(y[0], 0);  // c_00 = 1 / sqrt(4 pi): total probability
   bool unres = false;   // |m| > 1 + 1e-3 or c_00 changed at a sample
   bool forced = false;  // a step accepted at the smallest step size with its estimate above tol
+  // a probability density has |m| <= 1 and keeps c_00 (conserved exactly by the solves); a state that
+  // breaks either is not resolved by the degree (status FPN_INST_UNRESOLVED, the instance stops)
+  auto state_ok = [&](float vx, float vy, float vz) -> bool {
+    const bool fin = isfinite(vx) && isfinite(vy) && isfinite(vz);
+    const bool phys = (rc * rc) * (vx * vx + vy * vy + vz * vz) <= kMaxM2 && __shfl(y[0], 0) == c00_0;
+    if (fin && !phys) unres = true;
+    return fin && phys;
+  };
   for (int j = 0; j < n_int && ok; ++j) {
     const double tj = j * dt;
     const float vx = __shfl(y[pX >> 6], pX & 63), vy = __shfl(y[pY >> 6], pY & 63),
                 vz = __shfl(y[pZ >> 6], pZ & 63);
-    {
-      // a probability density has |m| <= 1 and keeps c_00 (conserved exactly by the solves); a state
-      // that breaks either is not resolved by the degree (status FPN_INST_UNRESOLVED, stop here)
-      const bool fin = isfinite(vx) && isfinite(vy) && isfinite(vz);
-      const bool phys = (rc * rc) * (vx * vx + vy * vy + vz * vz) <= kMaxM2 && __shfl(y[0], 0) == c00_0;
-      if (fin && !phys) unres = true;
-      if (!(fin && phys)) {
-        ok = false;
-        break;
-      }
+    if (!state_ok(vx, vy, vz)) {
+      ok = false;
+      break;
     }
     if (j >= first_rec) {
       const int js = j - first_rec;
@@ -757,12 +758,16 @@ stepper_wide_kernel(StepArgs A, DevTables t, float* ws) {
     // fixed: r_fixed equal steps per sample interval.  adaptive: steps of any size up to the sample
     // spacing, each accepted (max |K6| <= tol) or redone on its own.  The last step of an interval
     // lands on the next sample time.  (One call site of the stage routine keeps it inlined.)
+    // Adaptive settling (span): the settling periods are one interval, stepped with up to kSettleSpan
+    // sample spacings per step, the last step landing on the first recorded sample time; the state
+    // checks then follow every accepted step (as in stepper.hip).
     const bool fixedr = A.r_fixed > 0;
+    const bool span = !fixedr && j < first_rec;
     if (lane == 0) w.ctl[0] = tj;
     wsync();
     for (;;) {
       const double dtv = A.period / A.Ns;
-      const double tend = j * dtv + dtv;
+      const double tend = double(span ? A.settle * A.Ns : j + 1) * dtv;
       const double t = w.ctl[0];
       if (!(t < tend - 1e-9 * dtv)) break;
       double hs = fixedr ? dtv / A.r_fixed : w.ctl[1];
@@ -781,7 +786,7 @@ stepper_wide_kernel(StepArgs A, DevTables t, float* ws) {
       const double hmin = dt2 / (A.r_max > 0 ? A.r_max : 64);
       const double t2 = w.ctl[0], hst = w.ctl[1], hs2 = w.ctl[2];
       const bool landed2 = w.ctl[3] != 0.0, after_reject = w.ctl[4] != 0.0;
-      const double tend2 = j * dt2 + dt2;
+      const double tend2 = double(span ? A.settle * A.Ns : j + 1) * dt2;
       // e = +inf for a non-finite attempt (an overflow of the FP32 factorisation, which a long step can
       // cause): rejected like any other (5x shorter, on cleared scratch) unless it is the smallest step
       if (!isfinite(e) && (fixedr || hs2 <= hmin * 1.06)) {
@@ -809,11 +814,20 @@ stepper_wide_kernel(StepArgs A, DevTables t, float* ws) {
       const double hn = hs2 * double(fminf(after_reject ? 1.0f : 4.0f, fmaxf(0.2f, fac)));
       if (lane == 0) {
         w.ctl[0] = landed2 ? tend2 : t2 + hs2;
-        w.ctl[1] = fmin(dt2, fmax(hmin, landed2 ? fmax(hn, hst) : hn));
+        w.ctl[1] = fmin(span ? kSettleSpan * dt2 : dt2, fmax(hmin, landed2 ? fmax(hn, hst) : hn));
         w.ctl[4] = 0.0;
       }
       wsync();
+      if (span) {
+        const float ux = __shfl(y[pX >> 6], pX & 63), uy = __shfl(y[pY >> 6], pY & 63),
+                    uz = __shfl(y[pZ >> 6], pZ & 63);
+        if (!state_ok(ux, uy, uz)) {
+          ok = false;
+          break;
+        }
+      }
     }
+    if (span) j = first_rec - 1;  // continue at the first recorded sample
   }
   if (!ok) {
     for (int j = lane; j < 3 * A.Ns; j += 64) ms_out[j] = __builtin_nanf("");
