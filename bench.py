@@ -808,18 +808,17 @@ def main():
     L = ws["inst"]["L"]
     d = ws["drive"]
     drive = fpn.make_drive(d["amp"], d["freq"], d["period"], d["phase"])
-    out = {"m": torch.empty((n, 3, ws["samples"]), dtype=torch.float32, device=dev),
-           "harm": torch.empty((n, 2, ws["n_harm"] + 1, 2), dtype=torch.float32, device=dev),
-           "status": torch.empty((n,), dtype=torch.int32, device=dev)}
+    # One plan (fpn_plan_create) bound to the batch and launched once per step: the whole solve every
+    # launch; launches after the first start each degree bucket's instances in order of the step counts
+    # of the launch before (the tail of instances beyond the resident wavefronts then holds the shortest).
+    plan = ctx.plan(inst, L, drive, ws["samples"], ws["settle"], ws["n_harm"], substeps=args.substeps, tol=args.tol)
 
     def step():
-        ctx.solve(inst, L, drive, ws["samples"], ws["settle"], ws["n_harm"], substeps=args.substeps, out=out,
-                  tol=args.tol)
+        plan.launch()
 
     for _ in range(args.warmup):
         step()
     torch.cuda.synchronize()
-    bad = int((out["status"] != 0).sum().item())
     ctx.timing_enable(True)
     torch.cuda.synchronize()
     t0 = time.perf_counter()
@@ -829,7 +828,16 @@ def main():
     t1 = time.perf_counter()
     timing = ctx.timing_read()
     ctx.timing_enable(False)
-    steps_last = ctx.last_steps()   # time steps of the last timed solve (all instances)
+    bad = int((plan.status != 0).sum().item())
+    steps_last = int(plan.steps().astype(np.int64).sum())   # time steps of the last timed launch
+    # the same batch through one fpn_solve call (a single solve: batch order, no earlier launch to order by)
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record()
+    ctx.solve(inst, L, drive, ws["samples"], ws["settle"], ws["n_harm"], substeps=args.substeps, tol=args.tol)
+    e1.record()
+    torch.cuda.synchronize()
+    solve_ms = e0.elapsed_time(e1)
+    plan.close()
     wall = t1 - t0
     ms_per_step = wall / args.steps * 1e3
     value = n * args.steps / wall
@@ -858,7 +866,9 @@ def main():
         "config": {"workload": ws["name"], "instances": n, "L": Lv, "samples": ws["samples"],
                    "settle_periods": ws["settle"], "n_harm": ws["n_harm"],
                    "substeps": args.substeps if args.substeps else "adaptive", "avg_substeps": avg_sub,
-                   "integrator": "RODAS4", "failed_instances": bad, "truncation": trunc},
+                   "integrator": "RODAS4", "failed_instances": bad, "truncation": trunc,
+                   "api": "fpn_plan_launch per step (queue ordered by the previous launch's step counts)",
+                   "single_fpn_solve_ms": solve_ms},
         "roofline": {"bound": "alu", "kernel": "stepper", "achieved": achieved, "peak": FP32_VECTOR_PEAK_TFLOPS,
                      "unit": "TFLOP/s", "frac": achieved / FP32_VECTOR_PEAK_TFLOPS, "traffic": measured_traffic(),
                      "avg_launch_ms": avg_ms, "flops_per_launch": flops_launch,

@@ -201,7 +201,12 @@ fpn_status fpn_adjoint(fpn_ctx ctx, const fpn_drive* drive, const fpn_solve_opts
  * concurrent streams, and every stepper launch is persistent (each wavefront takes instances from a
  * queue until it is drained), so uneven step counts do not idle whole workgroups.  Within a group
  * instances start in order of decreasing cost_hint (HOST [n], e.g. the step counts of an earlier run
- * from fpn_plan_steps; NULL keeps batch order).  Outputs do not depend on the schedule.
+ * from fpn_plan_steps).  With cost_hint NULL the first launch keeps batch order, and every later
+ * launch (eager or a graph captured after the first launch) starts the instances of each group that
+ * has more instances than resident wavefronts in order of decreasing step count of the launch before
+ * it, sorted on the device; the instances queued last then run after the others, and the shortest
+ * go there.  Outputs do not depend on the schedule.  Launches of one plan must be ordered (one stream,
+ * or synchronised): they share the plan's workspace and outputs.
  * The plan owns its workspace; plans are independent of fpn_solve's and of each other. */
 typedef struct fpn_plan_s* fpn_plan;
 

@@ -491,6 +491,10 @@ fpn_status plan_build(fpn_plan_s* p, fpn_ctx ctx, const fpn_drive* drive, const 
     g.waves = (!tangent && g.L <= 16) ? ctx->stepper_waves[g.L] : 0;
     if (fpn_status s = occupancy(ctx, g.L, *g.t, tangent, g.waves, &waves, &blocks)) return s;
     g.grid = std::max(1, std::min((g.cnt + waves - 1) / waves, blocks * ctx->cus));
+    // without a cost hint, a bucket with more instances than resident wavefronts is ordered on the
+    // device by the step counts of the plan's previous launch, longest first (the instances queued
+    // last run after the rest)
+    g.order = !cost_hint && int64_t(g.cnt) > int64_t(g.grid) * waves;
     g.est = std::max(g.est, g.cost / double(int64_t(g.grid) * waves));
     g.ws_off = ws_total;
     ws_total += int64_t(g.grid) * waves * fpn::stepper_ws_floats(g.L);
@@ -584,6 +588,13 @@ fpn_status plan_launch(fpn_plan_s* p, hipStream_t stream, bool timing) {
         return FPN_OK;
       }))
     return s;
+  if (p->reorder && p->history) {
+    for (const auto& g : p->groups) {
+      if (!g.order) continue;
+      fpn::launch_order(p->idx.p + g.start, g.cnt, p->steps.p, stream);
+      FPN_HIP(hipGetLastError());
+    }
+  }
   double3 d0;
   d0.x = drive->amp[0] * std::cos(drive->phase[0]);
   d0.y = drive->amp[1] * std::cos(drive->phase[1]);
@@ -673,6 +684,7 @@ fpn_status plan_launch(fpn_plan_s* p, hipStream_t stream, bool timing) {
                           n * fpn::kNTan, stream, fpn::kNTan);
     FPN_HIP(hipGetLastError());
   }
+  p->history = true;  // the steppers issued above write every instance's step count
   return FPN_OK;
 }
 
@@ -809,6 +821,7 @@ fpn_status fpn_plan_create(fpn_ctx ctx, const fpn_drive* drive, const fpn_solve_
     delete p;
     return s;
   }
+  p->reorder = true;
   FPN_HIP(hipDeviceSynchronize());
   *out = p;
   return FPN_OK;

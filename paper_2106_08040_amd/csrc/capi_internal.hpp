@@ -76,6 +76,8 @@ struct PlanGroup {
   double est = 0.0;      // predicted duration (per-step work x the longer of total steps / slots and the
                          // longest instance's steps), for the assignment to streams
   int stream = 0;        // side stream of the bucket (longest-first onto the least loaded stream)
+  bool order = false;    // no cost hint and more instances than resident wavefronts: a plan launched
+                         // again sorts the bucket's queue by the previous launch's step counts
 };
 void plan_release(fpn_plan_s* p);
 }  // namespace fpn_internal
@@ -150,6 +152,8 @@ struct fpn_plan_s {
   fpn_internal::DevBuf<float> own_mt, own_dh, tws;
   hipGraph_t graph = nullptr;
   hipGraphExec_t exec = nullptr;
+  bool history = false;         // steps holds the step counts of a completed launch of this plan
+  bool reorder = false;         // launches after the first order the buckets by those counts
 };
 
 struct fpn_mlp_s {

@@ -506,6 +506,50 @@ __global__ void peak_field_kernel(int64_t n, const double* offset, PeakDrive d, 
   }
 }
 
+// Queue order of a degree bucket of a plan launched again without a cost hint: the instances are
+// sorted by the time steps the previous launch took (steps[instance], written by the stepper), most
+// first, so the persistent stepper starts the longest solves first and ends on the shortest.  One
+// workgroup sorts one chunk of up to kOrderChunk queue entries (bitonic network in LDS; equal counts
+// by instance index, so the order does not depend on the order it starts from).  Results never
+// depend on the order.
+constexpr int kOrderChunk = 4096;
+
+__global__ void __launch_bounds__(1024) order_kernel(int32_t* idx, int cnt, const int32_t* steps) {
+  __shared__ int32_t key[kOrderChunk];
+  __shared__ int32_t val[kOrderChunk];
+  const int base = blockIdx.x * kOrderChunk;
+  const int m = min(kOrderChunk, cnt - base);
+  int P = 1;
+  while (P < m) P <<= 1;
+  for (int e = threadIdx.x; e < P; e += blockDim.x) {
+    const int32_t v = e < m ? idx[base + e] : INT32_MAX;
+    key[e] = e < m ? -steps[v] : INT32_MAX;  // padding sorts last
+    val[e] = v;
+  }
+  __syncthreads();
+  for (int k = 2; k <= P; k <<= 1) {
+    for (int j = k >> 1; j > 0; j >>= 1) {
+      for (int e = threadIdx.x; e < P; e += blockDim.x) {
+        const int x = e ^ j;
+        if (x > e) {
+          const bool up = (e & k) == 0;
+          const bool gt = key[e] > key[x] || (key[e] == key[x] && val[e] > val[x]);
+          if (gt == up) {
+            const int32_t tk = key[e];
+            key[e] = key[x];
+            key[x] = tk;
+            const int32_t tv = val[e];
+            val[e] = val[x];
+            val[x] = tv;
+          }
+        }
+      }
+      __syncthreads();
+    }
+  }
+  for (int e = threadIdx.x; e < m; e += blockDim.x) idx[base + e] = val[e];
+}
+
 __global__ void fill_i32_kernel(int32_t* p, int n, int32_t v) {
   const int i = blockIdx.x * blockDim.x + threadIdx.x;
   if (i < n) p[i] = v;
@@ -533,6 +577,12 @@ void launch_peak_field(int64_t n, const double* offset, const double* amp, const
   d.period = period;
   hipLaunchKernelGGL(peak_field_kernel, dim3(unsigned((n + 255) / 256)), dim3(256), 0, stream, n, offset, d, Ns,
                      field_out);
+}
+
+void launch_order(int32_t* idx, int cnt, const int32_t* steps, hipStream_t stream) {
+  if (cnt <= 1) return;
+  hipLaunchKernelGGL(order_kernel, dim3(unsigned((cnt + kOrderChunk - 1) / kOrderChunk)), dim3(1024), 0, stream, idx,
+                     cnt, steps);
 }
 
 void launch_fill_i32(int32_t* p, int n, int32_t v, hipStream_t stream) {

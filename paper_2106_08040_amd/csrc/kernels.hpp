@@ -96,6 +96,9 @@ struct EqDrive {
 void launch_equilibrium(int64_t n, int Ns, int settle, const EqDrive& d, const InstParams* ip,
                         const int32_t* status, float* m, hipStream_t stream);
 void launch_fill_i32(int32_t* p, int n, int32_t v, hipStream_t stream);
+// sorts the queue entries idx[0..cnt) of one degree bucket by steps[instance] (the previous launch's
+// time steps), most first; chunks of 4096 entries are sorted apart
+void launch_order(int32_t* idx, int cnt, const int32_t* steps, hipStream_t stream);
 void launch_harmonics(const float* msamp, int Ns, int n_harm, int nch, double period, const double2* tw,
                       float* harm, const int32_t* status, int64_t n, hipStream_t stream, int st_div = 1);
 void launch_contract(const float* dL, const float* dharm, int per, double* grad, const int32_t* status, int64_t n,

@@ -167,6 +167,16 @@ __device__ __forceinline__ bool gj_piv_invert(float (&a)[Q], int i, int h, W& w,
   return ok;
 }
 
+// Row i of a block inverse (this lane's half a[0..Q-1]) times the half vector t[0..Q-1], summed over
+// both halves: four independent partial sums, so the products do not form one dependent chain.
+template <int Q>
+__device__ __forceinline__ float dot_half(const float (&a)[Q], const float* t) {
+  float acc[4] = {0.0f, 0.0f, 0.0f, 0.0f};
+#pragma unroll
+  for (int q = 0; q < Q; ++q) acc[q & 3] = fmaf(a[q], t[q], acc[q & 3]);
+  return half_sum((acc[0] + acc[1]) + (acc[2] + acc[3]));
+}
+
 template <int L, int WAVES, int NT>
 __global__ void __launch_bounds__(64 * WAVES)
 stepper_kernel(StepArgs A, DevTables t) {
@@ -359,6 +369,7 @@ stepper_kernel(StepArgs A, DevTables t) {
 #pragma unroll
           for (int k = 0; k < kNKindD; ++k) acc = fmaf(m[k], sl[k], fmaf(m[k], sh[k], acc));
         }
+        float acc2 = 0.0f;  // the coupling slots: a second, independent partial sum
         constexpr int kG = 6;
         static_assert((kNSlB + kNSlC) % kG == 0, "coupling slots come in whole groups");
 #pragma unroll
@@ -375,8 +386,9 @@ stepper_kernel(StepArgs A, DevTables t) {
           for (int u = 0; u < kG; ++u) xv[u] = xin[ci[u]];
           __builtin_amdgcn_sched_barrier(0);
 #pragma unroll
-          for (int u = 0; u < kG; ++u) acc = fmaf(m[kSlotKindRow[g0 + u]] * cv[u], xv[u], acc);
+          for (int u = 0; u < kG; ++u) acc2 = fmaf(m[kSlotKindRow[g0 + u]] * cv[u], xv[u], acc2);
         }
+        acc += acc2;
         dst[p] = add ? dst[p] + acc : acc;
       }
     }
@@ -494,10 +506,7 @@ stepper_kernel(StepArgs A, DevTables t) {
       }
       wsync();
       auto& a = blk<K>(st);
-      float part = 0.0f;
-#pragma unroll
-      for (int q = 0; q < Q; ++q) part = fmaf(a[q], w.T[h * kH + q], part);
-      part = half_sum(part);
+      float part = dot_half<Q>(a, w.T + h * kH);
       if (h == 0 && i < n) G[off0 + i] = part;
       wsync();
       __builtin_amdgcn_sched_barrier(0);
@@ -533,10 +542,7 @@ stepper_kernel(StepArgs A, DevTables t) {
       }
       wsync();
       auto& a = blk<K>(st);
-      float part = 0.0f;
-#pragma unroll
-      for (int q = 0; q < Q; ++q) part = fmaf(a[q], w.T[h * kH + q], part);
-      part = half_sum(part);
+      float part = dot_half<Q>(a, w.T + h * kH);
       if (h == 0 && i < n) G[off0 + i] -= part;
       wsync();
       __builtin_amdgcn_sched_barrier(0);

@@ -309,17 +309,19 @@ stepper_wide_kernel(StepArgs A, DevTables t, float* ws) {
   auto block_apply = [&](auto KK, float* G, bool subtract, const float4 (&cq)[kNQ]) {
     constexpr int K = decltype(KK)::value;
     constexpr int n = Gm::nb(K), off0 = Gm::off(K), nq = WG::q4(K);
-    float part = 0.0f;
     if (lane < n) {
+      // four independent partial sums (one per quad component), not one dependent chain
+      float px = 0.0f, py = 0.0f, pz = 0.0f, pw = 0.0f;
 #pragma unroll
       for (int q = 0; q < nq; ++q) {
         const float4 c = cq[q];
         const float4 tv = *reinterpret_cast<const float4*>(&w.T[4 * q]);
-        part = fmaf(c.x, tv.x, part);
-        part = fmaf(c.y, tv.y, part);
-        part = fmaf(c.z, tv.z, part);
-        part = fmaf(c.w, tv.w, part);
+        px = fmaf(c.x, tv.x, px);
+        py = fmaf(c.y, tv.y, py);
+        pz = fmaf(c.z, tv.z, pz);
+        pw = fmaf(c.w, tv.w, pw);
       }
+      const float part = (px + py) + (pz + pw);
       if (subtract) G[off0 + lane] -= part;
       else G[off0 + lane] = part;
     }

@@ -276,3 +276,29 @@ def test_empty_batch(fpn, ctx):
     d = ws["drive"]
     m, h, st = ctx.solve(ws["inst"], np.zeros(0, np.int32), fpn.make_drive(d["amp"], d["freq"], d["period"]), 16, 0, 4)
     assert m.shape[0] == 0 and st.shape[0] == 0
+
+
+def test_plan_queue_order_leaves_results_bitwise_unchanged(fpn, ctx, lissajous_full):
+    """A plan without a cost hint keeps batch order on its first launch and, on later launches, starts
+    the instances of the L = 16 bucket (more instances than resident wavefronts) in order of the step
+    counts of the launch before, sorted on the device.  Every launch gives the outputs of fpn_solve
+    (batch order) bit for bit: each instance is solved on its own, whatever its place in the queue."""
+    import torch
+    ws, (m, h, st) = lissajous_full
+    d = ws["drive"]
+    drive = fpn.make_drive(d["amp"], d["freq"], d["period"], d["phase"])
+    plan = ctx.plan(ws["inst"], ws["inst"]["L"], drive, ws["samples"], ws["settle"], ws["n_harm"])
+    try:
+        steps = None
+        for launch in range(3):
+            plan.launch()
+            torch.cuda.synchronize()
+            assert np.array_equal(plan.status.cpu().numpy(), st), launch
+            assert np.array_equal(plan.m.cpu().numpy(), m), launch
+            assert np.array_equal(plan.harm.cpu().numpy(), h), launch
+            s = plan.steps()
+            if steps is not None:
+                assert np.array_equal(s, steps), launch
+            steps = s
+    finally:
+        plan.close()
