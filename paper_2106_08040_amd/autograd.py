@@ -4,6 +4,10 @@ particle parameters (D, K, alpha, easy-axis polar and azimuth angles).
 Forward runs fpn_solve; backward runs fpn_adjoint, which integrates the parameter tangents of the
 discrete solve and contracts them with the incoming gradient in FP64.  Superposition weights,
 data misfits and every other part of a loss are ordinary torch operations on the returned tensor.
+
+Instances the solver flags (status other than OK or TOL_UNMET, e.g. UNRESOLVED: the degree does not
+resolve the particle) have NaN harmonics; a loss has to leave them out (torch.where on
+torch.isfinite), and their parameter gradient is returned as 0, the gradient of such a loss.
 """
 from __future__ import annotations
 
@@ -60,6 +64,10 @@ class _HarmonicsFn(_torch().autograd.Function):
     def backward(fctx, grad_out):
         h = fctx.h
         (params,) = fctx.saved_tensors
+        torch = _torch()
         grad, _, st = h.ctx.adjoint(fctx.inst, fctx.L, h.drive, h.samples, h.settle, h.n_harm,
                                     grad_out.contiguous(), substeps=h.substeps, tol=h.tol, want_harm=False)
+        from . import FPN_INST_OK, FPN_INST_TOL_UNMET
+        failed = (st != FPN_INST_OK) & (st != FPN_INST_TOL_UNMET)
+        grad = torch.where(failed[:, None], torch.zeros_like(grad), grad)
         return grad.to(params.dtype), None, None, None, None
