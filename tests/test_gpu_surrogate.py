@@ -135,6 +135,34 @@ def test_accepted_instances_meet_tolerance_and_save_solver_time(fpn, ctx, traine
     assert nf <= 256
 
 
+def test_surrogate_with_fallback_is_faster_than_the_solver(fpn, ctx, trained):
+    """What the trained network gains: 16384 evaluations at tol = 2e-2 through fpn_surrogate_predict
+    (ensemble, error estimate, solver for the instances whose estimate exceeds tol) against the plain
+    solver on the same instances, both timed with HIP events on the launch stream after a warm-up.
+    The surrogate answers at least 97 % of the instances within the tolerance and takes at most half the
+    solver's time (measured: see the printed line)."""
+    import torch
+    ws = domain(16384, 35)
+    d = drive_of(fpn, ws)
+    ref, _ = solve(fpn, ctx, ws)  # warm-up of the solver at this size, and the reference
+    trained.predict(ws["inst"], ws["inst"]["L"], d, ws["samples"], ws["settle"], tol=2e-2)
+    torch.cuda.synchronize()
+    e0, e1, e2 = (torch.cuda.Event(enable_timing=True) for _ in range(3))
+    e0.record()
+    ctx.solve(ws["inst"], ws["inst"]["L"], d, ws["samples"], ws["settle"], KH, want_m=False)
+    e1.record()
+    h, err, used, st, nf = trained.predict(ws["inst"], ws["inst"]["L"], d, ws["samples"], ws["settle"], tol=2e-2)
+    e2.record()
+    torch.cuda.synchronize()
+    t_solver, t_sur = e0.elapsed_time(e1), e1.elapsed_time(e2)
+    e = (torch.linalg.vector_norm((h - ref).reshape(16384, -1), dim=1) /
+         torch.linalg.vector_norm(ref.reshape(16384, -1), dim=1)).cpu().numpy()
+    print(f"16384 evaluations at tol 2e-2: {nf} to the solver, within tol {np.mean(e <= 2e-2):.4f}; "
+          f"surrogate {t_sur:.1f} ms vs solver {t_solver:.1f} ms ({t_solver / t_sur:.1f}x)", flush=True)
+    assert np.mean(e <= 2e-2) >= 0.97
+    assert t_sur <= 0.5 * t_solver
+
+
 def test_model_handle_train_save_load_is_bit_identical(fpn, ctx, tmp_path):
     """fpn_surrogate_init / _train_step / _save / _create / _infer through the C ABI: a model trained a
     few steps, written to a file and read back, evaluates bit for bit as before and continues training
