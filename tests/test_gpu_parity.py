@@ -300,5 +300,14 @@ def test_plan_queue_order_leaves_results_bitwise_unchanged(fpn, ctx, lissajous_f
             if steps is not None:
                 assert np.array_equal(s, steps), launch
             steps = s
+        # captured after the eager launches, the graph holds the device sort; every replay sorts by the
+        # step counts of the launch before and still gives the same outputs
+        for rep in range(2):
+            plan.m.fill_(float("nan"))
+            plan.graph_launch()
+            torch.cuda.synchronize()
+            assert np.array_equal(plan.m.cpu().numpy(), m), rep
+            assert np.array_equal(plan.harm.cpu().numpy(), h), rep
+            assert np.array_equal(plan.steps(), steps), rep
     finally:
         plan.close()
