@@ -475,9 +475,10 @@ def bench_equilibrium(args):
 
 def bench_wide(args):
     """The wide-layout stepper alone: 256 random resolved particles at one degree (--wide-L, default 24)
-    on the short three-axis test drive (64 samples, 1 settle period), adaptive steps.  One step = one
-    fpn_solve of the batch.  Roofline: algorithmic FP32 flops of the executed RODAS4 steps over the
-    stepper's HIP-event time."""
+    on the short three-axis test drive (64 samples, 1 settle period), adaptive steps, in the layout
+    --wide-waves selects (1: workspace in LDS, one instance per workgroup, the one plans choose for this
+    batch; 4: workspace in global memory, four per workgroup).  One step = one fpn_solve of the batch.
+    Roofline: algorithmic FP32 flops of the executed RODAS4 steps over the stepper's HIP-event time."""
     import torch
     import paper_2106_08040_amd as fpn
     import workloads as W
@@ -486,6 +487,7 @@ def bench_wide(args):
     ws = W.small_random(256, L, seed=100 + L, samples=64, settle=1, n_harm=8)
     n = ws["inst"]["D"].size
     ctx = fpn.Context(0)
+    ctx.set_stepper_waves(L, args.wide_waves)
     d = ws["drive"]
     drive = fpn.make_drive(d["amp"], d["freq"], d["period"], d["phase"])
 
@@ -515,8 +517,9 @@ def bench_wide(args):
         "ms_per_step": wall / args.steps * 1e3, "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
         "dtype": "f32", "data": "synthetic",
         "config": {"workload": f"wide_L{L}_256_short_drive", "instances": n, "L": L, "samples": ws["samples"],
-                   "rodas4_steps_per_solve": steps, "status_counts": np.bincount(st).tolist()},
-        "roofline": {"bound": "alu", "kernel": f"stepper_wide_kernel<{L}, 4>", "achieved": achieved,
+                   "rodas4_steps_per_solve": steps, "status_counts": np.bincount(st).tolist(),
+                   "workspace": "LDS" if args.wide_waves == 1 else "global"},
+        "roofline": {"bound": "alu", "kernel": f"stepper_wide_kernel<{L}, {args.wide_waves}>", "achieved": achieved,
                      "peak": FP32_VECTOR_PEAK_TFLOPS, "unit": "TFLOP/s", "frac": achieved / FP32_VECTOR_PEAK_TFLOPS,
                      "traffic": None, "avg_launch_ms": avg_ms, "flops_per_launch": flops},
     }
@@ -763,6 +766,8 @@ def main():
                          "WRITE_SIZE counters) and exit")
     ap.add_argument("--grad-angles", type=int, default=16, help="gradient workload: easy-axis angles")
     ap.add_argument("--wide-L", type=int, default=24, help="wide workload: Galerkin degree (17..24)")
+    ap.add_argument("--wide-waves", type=int, default=1, choices=(1, 4),
+                    help="wide workload: 1 = workspace in LDS (one instance per workgroup), 4 = in global memory")
     ap.add_argument("--workload", choices=("lissajous", "uneven", "surrogate", "gradient", "equilibrium", "m1",
                                            "wide"),
                     default="lissajous",

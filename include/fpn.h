@@ -237,8 +237,13 @@ fpn_status fpn_plan_destroy(fpn_plan plan);
 fpn_status fpn_stepper_wave_options(int32_t L, int32_t* waves, int32_t* count);
 
 /* Use workgroup size `waves` (one of fpn_stepper_wave_options(L), or 0 for the default) for degree L
- * in this context.  Errors: FPN_E_ARG (size not compiled for L), FPN_E_DEVICE (the configuration
- * does not fit on a compute unit of this device). */
+ * in this context.  For L = 17..24 (the wide layout, whose option list is just 0) `waves` is 0, 4 or
+ * 1: 4 keeps each instance's block inverses and stage vectors in a global workspace with 4 instances
+ * per workgroup, 1 keeps them in LDS with 1 instance per workgroup (about 28 % shorter steps at L = 24,
+ * fewer instances resident), 0 lets each plan choose per degree bucket from its predicted duration
+ * (the longest instance against the bucket's work over the resident instances of each layout).
+ * Outputs do not depend on the choice.  Errors: FPN_E_ARG (size not compiled for L), FPN_E_DEVICE
+ * (the configuration does not fit on a compute unit of this device). */
 fpn_status fpn_set_stepper_waves(fpn_ctx ctx, int32_t L, int32_t waves);
 
 /* Autotuner: time every workgroup size of degree L that fits on this device on a fixed synthetic

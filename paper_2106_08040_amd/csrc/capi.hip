@@ -273,7 +273,7 @@ hipError_t stepper_occupancy(int L, const DevTables& t, bool tangents, int waves
     FPN_CASE(9) FPN_CASE(10) FPN_CASE(11) FPN_CASE(12) FPN_CASE(13) FPN_CASE(14) FPN_CASE(15) FPN_CASE(16)
 #undef FPN_CASE
 #define FPN_WCASE(LL) \
-  case LL: return stepper_wide_occupancy_L<LL>(waves_per_block, blocks_per_cu);
+  case LL: return stepper_wide_occupancy_L<LL>(waves, waves_per_block, blocks_per_cu);
     FPN_WCASE(17) FPN_WCASE(18) FPN_WCASE(19) FPN_WCASE(20) FPN_WCASE(21) FPN_WCASE(22) FPN_WCASE(23) FPN_WCASE(24)
 #undef FPN_WCASE
     default: return hipErrorInvalidValue;
@@ -488,7 +488,18 @@ fpn_status plan_build(fpn_plan_s* p, fpn_ctx ctx, const fpn_drive* drive, const 
     p->order.insert(p->order.end(), ids.begin(), ids.end());
     start += g.cnt;
     int waves = 0, blocks = 0;
-    g.waves = (!tangent && g.L <= 16) ? ctx->stepper_waves[g.L] : 0;
+    g.waves = tangent ? 0 : ctx->stepper_waves[g.L];
+    if (g.L > 16 && g.waves == 0) {
+      // wide layout: global workspace (more instances resident) or LDS workspace (shorter steps), by the
+      // predicted bucket duration max(longest instance, total work / resident instances) x step time
+      int wg = 0, bg = 0, wl = 0, bl = 0;
+      if (fpn_status s = occupancy(ctx, g.L, *g.t, false, fpn::kWideGlobalWaves, &wg, &bg)) return s;
+      if (fpn_status s = occupancy(ctx, g.L, *g.t, false, fpn::kWideLdsWaves, &wl, &bl)) return s;
+      // (g.cost: the bucket's work, g.est: its longest instance's, both in per-step work units)
+      const double eg = std::max(g.est, g.cost / double(int64_t(wg) * bg * ctx->cus));
+      const double el = fpn::kWideLdsStepRatio * std::max(g.est, g.cost / double(int64_t(wl) * bl * ctx->cus));
+      g.waves = el < eg ? fpn::kWideLdsWaves : fpn::kWideGlobalWaves;
+    }
     if (fpn_status s = occupancy(ctx, g.L, *g.t, tangent, g.waves, &waves, &blocks)) return s;
     g.grid = std::max(1, std::min((g.cnt + waves - 1) / waves, blocks * ctx->cus));
     // without a cost hint, a bucket with more instances than resident wavefronts is ordered on the
@@ -496,8 +507,9 @@ fpn_status plan_build(fpn_plan_s* p, fpn_ctx ctx, const fpn_drive* drive, const 
     // last run after the rest)
     g.order = !cost_hint && int64_t(g.cnt) > int64_t(g.grid) * waves;
     g.est = std::max(g.est, g.cost / double(int64_t(g.grid) * waves));
+    if (g.L > 16 && g.waves == fpn::kWideLdsWaves) g.est *= fpn::kWideLdsStepRatio;
     g.ws_off = ws_total;
-    ws_total += int64_t(g.grid) * waves * fpn::stepper_ws_floats(g.L);
+    if (g.waves != fpn::kWideLdsWaves) ws_total += int64_t(g.grid) * waves * fpn::stepper_ws_floats(g.L);
     g.tws_off = tws_total;
     if (g.L <= 16) tws_total += int64_t(g.grid) * waves * fpn::stepper_reg_ws_floats(g.L, tangent);
     g.inv_off = inv_total;
@@ -891,14 +903,15 @@ fpn_status set_waves_locked(fpn_ctx ctx, int L, int waves) {
   const int c = fpn::stepper_wave_options(L, opts);
   bool known = false;
   for (int k = 0; k < c; ++k) known = known || opts[k] == waves;
+  if (L > 16) known = known || waves == fpn::kWideGlobalWaves || waves == fpn::kWideLdsWaves;
   if (waves != 0 && !known) return fail(FPN_E_ARG, "workgroup size not compiled for this degree");
-  if (waves != 0 && L <= 16) {
+  if (waves != 0) {
     const fpn::DevTables* t = nullptr;
     if (fpn_status s = get_tables(ctx, L, &t)) return s;
     int w = 0, b = 0;
     if (fpn_status s = occupancy(ctx, L, *t, false, waves, &w, &b)) return s;
   }
-  ctx->stepper_waves[L] = (L <= 16) ? waves : 0;
+  ctx->stepper_waves[L] = waves;
   return FPN_OK;
 }
 }  // namespace

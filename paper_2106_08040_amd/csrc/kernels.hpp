@@ -45,7 +45,7 @@ template <int L>
 hipError_t stepper_occupancy_L(const DevTables& t, bool tangents, int waves, int* waves_per_block,
                                int* blocks_per_cu);
 template <int L>
-hipError_t stepper_wide_occupancy_L(int* waves_per_block, int* blocks_per_cu);
+hipError_t stepper_wide_occupancy_L(int waves, int* waves_per_block, int* blocks_per_cu);
 // wavefronts per workgroup and resident workgroups per CU of the stepper for degree L, for the
 // workgroup size `waves` (0: the default); blocks_per_cu = 0 when that configuration does not fit
 hipError_t stepper_occupancy(int L, const DevTables& t, bool tangents, int waves, int* waves_per_block,
@@ -55,7 +55,15 @@ hipError_t stepper_occupancy(int L, const DevTables& t, bool tangents, int waves
 constexpr int kStepperWaves = 8;
 constexpr int kStepperMultiWavesMaxL = 13;
 // workgroup sizes compiled for the primal stepper of degree L (at most 3 written to out); the wide
-// layout (L = 17..24) has one size, reported as 0 (its default)
+// layout (L = 17..24) reports one entry, 0: there a plan picks between 4 instances per workgroup with
+// the workspace in global memory and 1 instance per workgroup with the workspace in LDS (a context can
+// force either with fpn_set_stepper_waves(L, 4 or 1)); the autotuner leaves that choice to the plans
+constexpr int kWideLdsWaves = 1;
+constexpr int kWideGlobalWaves = 4;
+// time per step of the LDS-resident wide layout relative to the global-workspace one (measured on
+// MI355X: 256 instances at L = 24, both layouts holding all of them resident, 1.23 s against 1.69 s);
+// plans weigh it against the resident instances of each layout
+constexpr double kWideLdsStepRatio = 0.72;
 inline int stepper_wave_options(int L, int* out) {
   if (L < 1 || L > 24) return 0;
   if (L > 16) {

@@ -153,6 +153,17 @@ __device__ __forceinline__ bool gj_piv_invert_wide(float (&a)[n], int lane, WL& 
   return ok;
 }
 
+// Bytes of dynamic LDS before the LDS-resident workspace (WAVES = 1): the wavefront scratch, rounded
+// to 16 bytes for the float4 inverse quads.
+template <int L, int WAVES>
+constexpr size_t wide_lds_scratch_bytes() {
+  return (WAVES * sizeof(WideLds<L>) + 15) & ~size_t(15);
+}
+
+// WAVES = 4: four instances per workgroup, each wavefront's workspace (block inverses, K1..K5, f_t) in
+// global memory (`ws`, one slot per resident wavefront).  WAVES = 1: one instance per workgroup with its
+// workspace in LDS behind the scratch (48 KB at L = 17 .. 114 KB at L = 24), so the block solves read the
+// inverses at LDS rather than L2 latency; fewer instances are resident at once.
 template <int L, int WAVES>
 __global__ void __launch_bounds__(64 * WAVES)
 stepper_wide_kernel(StepArgs A, DevTables t, float* ws) {
@@ -180,7 +191,12 @@ stepper_wide_kernel(StepArgs A, DevTables t, float* ws) {
   WL& w = wl[wid];
   clear_wave_scratch(w, lane);
   wsync();
-  float* inv = ws + int64_t(slot) * WG::WS;
+  float* inv;
+  if constexpr (WAVES == 1) {
+    inv = reinterpret_cast<float*>(smem + wide_lds_scratch_bytes<L, WAVES>());
+  } else {
+    inv = ws + int64_t(slot) * WG::WS;
+  }
   float* Kg = inv + WG::INV;  // K1..K5 at j * NpA, f_t at 5 * NpA
   const uint16_t* ecol = t.ell_col;
   const float* eval = t.ell_val;
@@ -853,6 +869,11 @@ int64_t stepper_wide_ws_floats_L() {
   return WGeo<L>::WS;
 }
 
+template <int L, int WV>
+constexpr size_t wide_lds_bytes() {
+  return WV == 1 ? wide_lds_scratch_bytes<L, 1>() + size_t(WGeo<L>::WS) * sizeof(float) : WV * sizeof(WideLds<L>);
+}
+
 template <int L>
 hipError_t launch_stepper_wide_L(const StepLaunch& s, const DevTables& t, float* ws, hipStream_t stream) {
   StepArgs a;
@@ -880,32 +901,45 @@ hipError_t launch_stepper_wide_L(const StepLaunch& s, const DevTables& t, float*
   a.c0t = nullptr;  // tangents are carried by the register-layout stepper only
   a.mtan = nullptr;
   a.tws = nullptr;
-  const size_t shm = kWideWaves * sizeof(WideLds<L>);
-  auto kern = stepper_wide_kernel<L, kWideWaves>;
-  hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void*>(kern),
-                                     hipFuncAttributeMaxDynamicSharedMemorySize, int(shm));
-  if (e != hipSuccess) return e;
-  int grid = (s.n_inst + kWideWaves - 1) / kWideWaves;
-  if (s.grid > 0) grid = std::min(grid, s.grid);
-  hipLaunchKernelGGL(kern, dim3(grid), dim3(64 * kWideWaves), shm, stream, a, t, ws);
-  return hipGetLastError();
+  auto go = [&](auto WVC) -> hipError_t {
+    constexpr int WV = decltype(WVC)::value;
+    constexpr size_t shm = wide_lds_bytes<L, WV>();
+    static_assert(shm <= 160 * 1024, "wide stepper LDS exceeds a compute unit");
+    auto kern = stepper_wide_kernel<L, WV>;
+    hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void*>(kern),
+                                       hipFuncAttributeMaxDynamicSharedMemorySize, int(shm));
+    if (e != hipSuccess) return e;
+    int grid = (s.n_inst + WV - 1) / WV;
+    if (s.grid > 0) grid = std::min(grid, s.grid);
+    hipLaunchKernelGGL(kern, dim3(grid), dim3(64 * WV), shm, stream, a, t, ws);
+    return hipGetLastError();
+  };
+  if (s.waves == 1) return go(std::integral_constant<int, 1>{});
+  if (s.waves != 0 && s.waves != kWideWaves) return hipErrorInvalidValue;
+  return go(std::integral_constant<int, kWideWaves>{});
 }
 
 template <int L>
-hipError_t stepper_wide_occupancy_L(int* waves_per_block, int* blocks_per_cu) {
-  const size_t shm = kWideWaves * sizeof(WideLds<L>);
-  auto kern = stepper_wide_kernel<L, kWideWaves>;
-  hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void*>(kern),
-                                     hipFuncAttributeMaxDynamicSharedMemorySize, int(shm));
-  if (e != hipSuccess) return e;
-  *waves_per_block = kWideWaves;
-  return hipOccupancyMaxActiveBlocksPerMultiprocessor(blocks_per_cu, kern, 64 * kWideWaves, shm);
+hipError_t stepper_wide_occupancy_L(int waves, int* waves_per_block, int* blocks_per_cu) {
+  auto occ = [&](auto WVC) -> hipError_t {
+    constexpr int WV = decltype(WVC)::value;
+    constexpr size_t shm = wide_lds_bytes<L, WV>();
+    auto kern = stepper_wide_kernel<L, WV>;
+    hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void*>(kern),
+                                       hipFuncAttributeMaxDynamicSharedMemorySize, int(shm));
+    if (e != hipSuccess) return e;
+    *waves_per_block = WV;
+    return hipOccupancyMaxActiveBlocksPerMultiprocessor(blocks_per_cu, kern, 64 * WV, shm);
+  };
+  if (waves == 1) return occ(std::integral_constant<int, 1>{});
+  if (waves != 0 && waves != kWideWaves) return hipErrorInvalidValue;
+  return occ(std::integral_constant<int, kWideWaves>{});
 }
 
 #define FPN_WINST(LL)                                                                                  \
   template hipError_t launch_stepper_wide_L<LL>(const StepLaunch&, const DevTables&, float*, hipStream_t); \
   template int64_t stepper_wide_ws_floats_L<LL>();                                                     \
-  template hipError_t stepper_wide_occupancy_L<LL>(int*, int*);
+  template hipError_t stepper_wide_occupancy_L<LL>(int, int*, int*);
 #if !defined(FPN_L_BEGIN)
 #define FPN_L_BEGIN 17
 #define FPN_L_END 24

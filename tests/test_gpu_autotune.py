@@ -75,3 +75,25 @@ def test_unknown_workgroup_size_is_rejected(fpn, ctx):
         ctx.set_stepper_waves(16, 12)   # 12 is compiled for L <= 13 only
     with pytest.raises(fpn.FpnError):
         ctx.set_stepper_waves(8, 5)
+
+
+@pytest.mark.parametrize("L", [17, 24])
+def test_wide_layouts_give_the_same_outputs(fpn, ctx, L):
+    """The wide layout (L = 17..24) keeps each instance's block inverses and stage vectors either in a
+    global workspace (4 instances per workgroup) or in LDS (1 per workgroup); a plan picks one by its
+    cost estimate, fpn_set_stepper_waves(L, 4 or 1) forces it.  Same arithmetic in the same order:
+    the outputs are bitwise the same, and 0 hands the choice back to the plans."""
+    ws = W.small_random(24, L, seed=950 + L, samples=32, settle=1, n_harm=6)
+    out = {}
+    try:
+        for w in (4, 1, 0):
+            ctx.set_stepper_waves(L, w)
+            out[w] = _solve(fpn, ctx, ws)
+    finally:
+        ctx.set_stepper_waves(L, 0)
+    assert np.isin(out[4][2], [fpn.FPN_INST_OK, fpn.FPN_INST_TOL_UNMET, fpn.FPN_INST_UNRESOLVED]).all()
+    for w in (1, 0):
+        for a, b in zip(out[4], out[w]):
+            assert np.array_equal(a, b, equal_nan=True), w
+    with pytest.raises(fpn.FpnError):
+        ctx.set_stepper_waves(L, 8)
