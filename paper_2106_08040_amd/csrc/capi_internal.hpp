@@ -172,6 +172,7 @@ struct fpn_mlp_s {
   int64_t rows_cap = 0;
   bool train_cap = false;
   std::vector<fpn_internal::DevBuf<uint16_t>> act, actT;  // act[l] [rows][inpad l] (l = 0..nl-1)
+  std::vector<fpn_internal::DevBuf<uint16_t>> act_lo;     // low-order BF16 parts of act[l] (forward products)
   std::vector<fpn_internal::DevBuf<float>> z;             // z[l] pre-activation feeding act[l], l = 1..nl-1
   fpn_internal::DevBuf<float> y;                          // [rows][out]
   fpn_internal::DevBuf<uint16_t> dz[2], dzT[2];

@@ -25,12 +25,14 @@ uint64_t splitmix(uint64_t& s) {
 fpn_status ensure_work(fpn_mlp m, int64_t rows, bool train) {
   const int nl = m->nl;
   m->act.resize(nl);
+  m->act_lo.resize(nl);
   m->actT.resize(nl);
   m->z.resize(nl);
   if (rows <= m->rows_cap && (!train || m->train_cap)) return FPN_OK;
   rows = std::max(rows, m->rows_cap);
   for (int l = 0; l < nl; ++l) {
     FPN_HIP(m->act[l].ensure(size_t(rows) * m->inpad[l]));
+    FPN_HIP(m->act_lo[l].ensure(size_t(rows) * m->inpad[l]));
     if (train) {
       FPN_HIP(m->actT[l].ensure(size_t(rows) * m->inpad[l]));
       if (l > 0) FPN_HIP(m->z[l].ensure(size_t(rows) * m->inpad[l]));
@@ -59,14 +61,17 @@ fpn_status refresh_weights(fpn_mlp m, hipStream_t s) {
   return FPN_OK;
 }
 
-// Forward over `rows` rows of x (n real rows); training keeps transposes and pre-activations.
+// Forward over `rows` rows of x (n real rows); training keeps transposes and pre-activations.  The
+// activations go from layer to layer as BF16 pairs (act + act_lo); the transposed copies the weight
+// gradients read stay single BF16.
 fpn_status forward(fpn_mlp m, const float* x, int64_t n, int64_t rows, bool train, float* y_out, hipStream_t s) {
   const int nl = m->nl;
   FPN_HIP(fpn::mlp::cast_input(x, n, rows, m->w[0], m->inpad[0], m->norm.p, m->norm.p + m->w[0], m->act[0].p,
-                               train ? m->actT[0].p : nullptr, rows, s));
+                               train ? m->actT[0].p : nullptr, rows, s, m->act_lo[0].p));
   for (int l = 0; l < nl; ++l) {
     fpn::mlp::GemmArgs g{};
     g.A = m->act[l].p;
+    g.Alo = m->act_lo[l].p;
     g.lda = m->inpad[l];
     g.B = m->Wb[l].p;
     g.ldb = m->inpad[l];
@@ -76,6 +81,7 @@ fpn_status forward(fpn_mlp m, const float* x, int64_t n, int64_t rows, bool trai
     g.bias = m->P.p + m->offB[l];
     if (l < nl - 1) {
       g.C = m->act[l + 1].p;
+      g.Clo = m->act_lo[l + 1].p;
       g.ldc = m->inpad[l + 1];
       g.Ct = train ? m->actT[l + 1].p : nullptr;
       g.ldct = rows;
@@ -221,6 +227,7 @@ fpn_status fpn_mlp_destroy(fpn_mlp m) {
   for (auto& b : m->Wb) b.release();
   for (auto& b : m->Wt) b.release();
   for (auto& b : m->act) b.release();
+  for (auto& b : m->act_lo) b.release();
   for (auto& b : m->actT) b.release();
   for (auto& b : m->z) b.release();
   for (int k = 0; k < 2; ++k) {

@@ -7,6 +7,9 @@
 //   weight grad    dW = dz^T a            A = dz^T stored, B = a^T stored  (epilogue: FP32 atomic add,
 //                                                                           split over K)
 // so the forward and backward epilogues also write the transposed copies the next product needs.
+// The forward products take the activations as a pair of BF16 arrays (hi + lo, about 16 significant
+// bits): rounding every layer's activations to one BF16 value is what limits the network's accuracy,
+// the BF16 weights are what it was trained with.
 #include <hip/hip_runtime.h>
 
 #include <cstdint>
@@ -49,11 +52,13 @@ __device__ __forceinline__ float gelu_grad(float x) {
 constexpr int BM = 128, BN = 128, BK = 32, LDT = BK + 8;  // LDS row stride 80 B (bank spread)
 
 // Tile of 128 x 128 per 256-thread workgroup; wave w owns rows 64 (w >> 1), cols 64 (w & 1),
-// as 4 x 4 MFMA 16x16x32 tiles.  blockIdx.z splits K (weight gradients).
-template <int EPI>
+// as 4 x 4 MFMA 16x16x32 tiles.  blockIdx.z splits K (weight gradients).  SPLIT: A is given as
+// g.A + g.Alo (a second LDS tile and a second product per k-step).
+template <int EPI, bool SPLIT>
 __global__ void __launch_bounds__(256) gemm_nt_kernel(GemmArgs g) {
   __shared__ __align__(16) uint16_t As[2][BM * LDT];
   __shared__ __align__(16) uint16_t Bs[2][BN * LDT];
+  __shared__ __align__(16) uint16_t Al[SPLIT ? 2 : 1][SPLIT ? BM * LDT : 8];
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   const int m0 = blockIdx.y * BM, n0 = blockIdx.x * BN;
   const int ksplit = gridDim.z;
@@ -70,7 +75,7 @@ __global__ void __launch_bounds__(256) gemm_nt_kernel(GemmArgs g) {
 
   // global -> register staging: thread t loads rows (t >> 2) and 64 + (t >> 2), 8 elements at k (t & 3) * 8
   const int lr = tid >> 2, lk = (tid & 3) * 8;
-  uint4 ra[2], rb[2];
+  uint4 ra[2], rb[2], rl[2];
   auto load = [&](int k0) {
 #pragma unroll
     for (int p = 0; p < 2; ++p) {
@@ -80,6 +85,9 @@ __global__ void __launch_bounds__(256) gemm_nt_kernel(GemmArgs g) {
                                       : make_uint4(0, 0, 0, 0);
       rb[p] = (gn < g.N && k0 < kend) ? *reinterpret_cast<const uint4*>(g.B + int64_t(gn) * g.ldb + k0 + lk)
                                       : make_uint4(0, 0, 0, 0);
+      if constexpr (SPLIT)
+        rl[p] = (gm < g.M && k0 < kend) ? *reinterpret_cast<const uint4*>(g.Alo + int64_t(gm) * g.lda + k0 + lk)
+                                        : make_uint4(0, 0, 0, 0);
     }
   };
   auto stash = [&](int buf) {
@@ -88,6 +96,7 @@ __global__ void __launch_bounds__(256) gemm_nt_kernel(GemmArgs g) {
       const int r = lr + 64 * p;
       *reinterpret_cast<uint4*>(&As[buf][r * LDT + lk]) = ra[p];
       *reinterpret_cast<uint4*>(&Bs[buf][r * LDT + lk]) = rb[p];
+      if constexpr (SPLIT) *reinterpret_cast<uint4*>(&Al[buf][r * LDT + lk]) = rl[p];
     }
   };
   const int nk = (kend - kbeg + BK - 1) / BK;
@@ -109,6 +118,15 @@ __global__ void __launch_bounds__(256) gemm_nt_kernel(GemmArgs g) {
     for (int a = 0; a < 4; ++a)
 #pragma unroll
       for (int b = 0; b < 4; ++b) acc[a][b] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(af[a], bfr[b], acc[a][b], 0, 0, 0);
+    if constexpr (SPLIT) {
+#pragma unroll
+      for (int a = 0; a < 4; ++a) af[a] = *reinterpret_cast<const bf16x8*>(&Al[buf][(wm + 16 * a + ar) * LDT + ak]);
+#pragma unroll
+      for (int a = 0; a < 4; ++a)
+#pragma unroll
+        for (int b = 0; b < 4; ++b)
+          acc[a][b] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(af[a], bfr[b], acc[a][b], 0, 0, 0);
+    }
     if (it + 1 < nk) stash(buf ^ 1);
     __syncthreads();
   }
@@ -130,8 +148,10 @@ __global__ void __launch_bounds__(256) gemm_nt_kernel(GemmArgs g) {
         if constexpr (EPI == kEpiBiasGelu) {
           const float z = v + bias;
           if (g.z_out) g.z_out[int64_t(m) * g.ldz + n] = z;
-          const uint16_t o = f2bf(gelu(z));
+          const float av = gelu(z);
+          const uint16_t o = f2bf(av);
           g.C[int64_t(m) * g.ldc + n] = o;
+          if (g.Clo) g.Clo[int64_t(m) * g.ldc + n] = f2bf(av - bf2f(o));
           if (g.Ct) g.Ct[int64_t(n) * g.ldct + m] = o;
         } else if constexpr (EPI == kEpiBias) {
           g.Cf[int64_t(m) * g.ldc + n] = v + bias;
@@ -152,11 +172,19 @@ hipError_t gemm_nt(int epi, const GemmArgs& g, int ksplit, hipStream_t stream) {
   if (g.K % BK != 0 || g.M < 0 || g.N < 0 || ksplit < 1) return hipErrorInvalidValue;
   if (g.M == 0 || g.N == 0) return hipSuccess;
   dim3 grid((g.N + BN - 1) / BN, (g.M + BM - 1) / BM, ksplit);
+  const bool split = g.Alo != nullptr;
+  if (split && (epi == kEpiGeluGrad || epi == kEpiAtomic)) return hipErrorInvalidValue;  // forward products only
   switch (epi) {
-    case kEpiBiasGelu: hipLaunchKernelGGL(gemm_nt_kernel<kEpiBiasGelu>, grid, dim3(256), 0, stream, g); break;
-    case kEpiBias: hipLaunchKernelGGL(gemm_nt_kernel<kEpiBias>, grid, dim3(256), 0, stream, g); break;
-    case kEpiGeluGrad: hipLaunchKernelGGL(gemm_nt_kernel<kEpiGeluGrad>, grid, dim3(256), 0, stream, g); break;
-    case kEpiAtomic: hipLaunchKernelGGL(gemm_nt_kernel<kEpiAtomic>, grid, dim3(256), 0, stream, g); break;
+    case kEpiBiasGelu:
+      if (split) hipLaunchKernelGGL((gemm_nt_kernel<kEpiBiasGelu, true>), grid, dim3(256), 0, stream, g);
+      else hipLaunchKernelGGL((gemm_nt_kernel<kEpiBiasGelu, false>), grid, dim3(256), 0, stream, g);
+      break;
+    case kEpiBias:
+      if (split) hipLaunchKernelGGL((gemm_nt_kernel<kEpiBias, true>), grid, dim3(256), 0, stream, g);
+      else hipLaunchKernelGGL((gemm_nt_kernel<kEpiBias, false>), grid, dim3(256), 0, stream, g);
+      break;
+    case kEpiGeluGrad: hipLaunchKernelGGL((gemm_nt_kernel<kEpiGeluGrad, false>), grid, dim3(256), 0, stream, g); break;
+    case kEpiAtomic: hipLaunchKernelGGL((gemm_nt_kernel<kEpiAtomic, false>), grid, dim3(256), 0, stream, g); break;
     default: return hipErrorInvalidValue;
   }
   return hipGetLastError();
@@ -175,7 +203,7 @@ __global__ void cast_weights_kernel(const float* W, int out, int in, int in_pad,
 // Standardised input rows: xb[m][j] = (x[m][j] - mean[j]) / std[j] for j < in, 0 up to in_pad;
 // rows m >= n (padding to the tile) are zero.  Optional transposed copy xt[in_pad][ldt].
 __global__ void cast_input_kernel(const float* x, int64_t n, int64_t rows, int in, int in_pad, const float* mean,
-                                  const float* istd, uint16_t* xb, uint16_t* xt, int64_t ldt) {
+                                  const float* istd, uint16_t* xb, uint16_t* xt, int64_t ldt, uint16_t* xlo) {
   const int64_t e = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
   if (e >= rows * in_pad) return;
   const int64_t m = e / in_pad;
@@ -184,6 +212,7 @@ __global__ void cast_input_kernel(const float* x, int64_t n, int64_t rows, int i
   if (m < n && j < in) v = (x[m * in + j] - mean[j]) * istd[j];
   const uint16_t b = f2bf(v);
   xb[e] = b;
+  if (xlo) xlo[e] = f2bf(v - bf2f(b));
   if (xt) xt[int64_t(j) * ldt + m] = b;
 }
 
@@ -252,11 +281,11 @@ hipError_t cast_weights(const float* W, int out, int in, int in_pad, uint16_t* W
   return hipGetLastError();
 }
 hipError_t cast_input(const float* x, int64_t n, int64_t rows, int in, int in_pad, const float* mean,
-                      const float* istd, uint16_t* xb, uint16_t* xt, int64_t ldt, hipStream_t s) {
+                      const float* istd, uint16_t* xb, uint16_t* xt, int64_t ldt, hipStream_t s, uint16_t* xlo) {
   const int64_t e = rows * in_pad;
   if (e == 0) return hipSuccess;
   hipLaunchKernelGGL(cast_input_kernel, dim3(blocks(e, 256)), dim3(256), 0, s, x, n, rows, in, in_pad, mean, istd,
-                     xb, xt, ldt);
+                     xb, xt, ldt, xlo);
   return hipGetLastError();
 }
 hipError_t loss_grad(const float* y, const float* t, int64_t n, int64_t rows, int out, uint16_t* dz, uint16_t* dzt,

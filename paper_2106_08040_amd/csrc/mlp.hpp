@@ -28,12 +28,18 @@ struct GemmArgs {
   float* z_out;      // optional FP32 pre-activation [M][ldz] (kEpiBiasGelu)
   const float* zin;  // pre-activation read by kEpiGeluGrad [M][ldz]
   int64_t ldz;
+  // optional low-order BF16 parts (same layouts as A and C): with Alo the product is
+  // (A + Alo) B^T, two matrix-core products per tile; with Clo (kEpiBiasGelu) the output is written
+  // as C + Clo, Clo = bf16(value - C), so an activation carries about 16 significant bits
+  const uint16_t* Alo;
+  uint16_t* Clo;
 };
 
 hipError_t gemm_nt(int epi, const GemmArgs& g, int ksplit, hipStream_t stream);
 hipError_t cast_weights(const float* W, int out, int in, int in_pad, uint16_t* Wb, uint16_t* Wt, hipStream_t s);
 hipError_t cast_input(const float* x, int64_t n, int64_t rows, int in, int in_pad, const float* mean,
-                      const float* istd, uint16_t* xb, uint16_t* xt, int64_t ldt, hipStream_t s);
+                      const float* istd, uint16_t* xb, uint16_t* xt, int64_t ldt, hipStream_t s,
+                      uint16_t* xlo = nullptr);
 hipError_t loss_grad(const float* y, const float* t, int64_t n, int64_t rows, int out, uint16_t* dz, uint16_t* dzt,
                      int64_t ldt, double* loss_sum, hipStream_t s);
 hipError_t bias_grad(const uint16_t* dzt, int64_t ldt, int64_t rows, int out, float* db, hipStream_t s);

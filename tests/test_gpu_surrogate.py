@@ -169,7 +169,10 @@ def test_model_handle_train_save_load_is_bit_identical(fpn, ctx, tmp_path):
     from the same state (Adam moments included); _train_step equals each member's step on the scaled
     targets; _infer equals the combination of the members' outputs; damaged files are rejected.
     Training steps are compared to FP32 rounding, not bitwise: the weight gradients are summed with
-    atomic adds over split K, whose order varies from run to run."""
+    atomic adds over split K, whose order varies from run to run, and Adam's first steps move every
+    parameter by about lr whatever its gradient's size, so a component whose gradient is at the level
+    of that rounding may move either way.  Asserted: 99.9 % of the parameters agree to 1e-4 relative,
+    and none differs by more than 2 lr per step taken."""
     import torch
     r = np.random.default_rng(5)
     widths = [8, 64, 64, 32]
@@ -188,11 +191,16 @@ def test_model_handle_train_save_load_is_bit_identical(fpn, ctx, tmp_path):
             net.train_step(x, ys, 1e-3)
     torch.cuda.synchronize()
 
-    def close(p, q):
-        return torch.allclose(p, q, rtol=1e-4, atol=1e-6 * float(q.abs().max()))
+    def close(p, q, lr_sum):
+        d = (p - q).abs()
+        scale = float(q.abs().max())
+        tight = float((d <= 1e-4 * q.abs() + 1e-6 * scale).float().mean())
+        print(f"parameters within 1e-4: {tight:.5f}, largest difference {float(d.max()):.2e} (bound {2 * lr_sum:.1e})",
+              flush=True)
+        return tight >= 0.999 and float(d.max()) <= 2.0 * lr_sum + 1e-6 * scale
 
     for k in range(2):
-        assert close(a.members[k].get_params(), b.members[k].get_params())
+        assert close(a.members[k].get_params(), b.members[k].get_params(), 5 * 1e-3)
     ya, ea = a.infer(x)
     outs = [net.forward(x) for net in a.members]
     inv = float(np.float32(1.0) / np.float32(1e-3))
@@ -209,7 +217,7 @@ def test_model_handle_train_save_load_is_bit_identical(fpn, ctx, tmp_path):
     c.train_step(x[:100], y[:100], 5e-4)
     torch.cuda.synchronize()
     for k in range(2):
-        assert close(a.members[k].get_params(), c.members[k].get_params())
+        assert close(a.members[k].get_params(), c.members[k].get_params(), 5e-4)
     # a damaged file is rejected with FPN_E_IO (truncated, altered, not a model file)
     raw = open(path, "rb").read()
     for bad in (raw[:-9], raw[:40] + bytes([raw[40] ^ 1]) + raw[41:], b"not a model" * 10):
