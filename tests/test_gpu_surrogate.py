@@ -270,7 +270,9 @@ def test_residual_stage_infer_predict_and_file_round_trip(fpn, ctx, tmp_path):
 
 def test_residual_stage_lowers_the_error_of_a_trained_surrogate(fpn, ctx):
     """Training a residual stage after the ensemble (Surrogate.fit(residual_steps=...)) lowers the
-    held-out error against the solver, and predict(tol = inf) is the combined ensemble mean."""
+    held-out error against the solver, predict(tol = inf) is the combined ensemble mean, and at the
+    1e-3 tolerance the surrogate with solver fallback answers 97 % of 16384 instances within it in at
+    most half the plain solver's time."""
     import torch
     from paper_2106_08040_amd.surrogate import Surrogate
     tr, va = domain(3072, 41), domain(512, 42)
@@ -290,5 +292,26 @@ def test_residual_stage_lowers_the_error_of_a_trained_surrogate(fpn, ctx):
     inv = float(np.float32(1.0) / np.float32(sur.out_scale))
     got = torch.view_as_real(h[:, :, 1:].contiguous()).reshape(h.shape[0], -1)
     assert torch.allclose(got, ((ya + yb) * 0.5) * inv, rtol=1e-5, atol=1e-6 * float(got.abs().max()))
+    # the gain at the 1e-3 target: 16384 evaluations at tol = 1e-3 (calibrated on the held-out set above)
+    # against the plain solver on the same instances, both timed with HIP events after a warm-up
+    ws = domain(16384, 43)
+    d = drive_of(fpn, ws)
+    ref, _ = solve(fpn, ctx, ws)
+    sur.predict(ws["inst"], ws["inst"]["L"], d, ws["samples"], ws["settle"], tol=1e-3)
+    torch.cuda.synchronize()
+    t = [torch.cuda.Event(enable_timing=True) for _ in range(3)]
+    t[0].record()
+    ctx.solve(ws["inst"], ws["inst"]["L"], d, ws["samples"], ws["settle"], KH, want_m=False)
+    t[1].record()
+    h, err, used, st, nf = sur.predict(ws["inst"], ws["inst"]["L"], d, ws["samples"], ws["settle"], tol=1e-3)
+    t[2].record()
+    torch.cuda.synchronize()
+    t_solver, t_sur = t[0].elapsed_time(t[1]), t[1].elapsed_time(t[2])
+    e = (torch.linalg.vector_norm((h - ref).reshape(16384, -1), dim=1) /
+         torch.linalg.vector_norm(ref.reshape(16384, -1), dim=1)).cpu().numpy()
+    print(f"16384 evaluations at tol 1e-3: {nf} to the solver, within tol {np.mean(e <= 1e-3):.4f}; "
+          f"surrogate {t_sur:.1f} ms vs solver {t_solver:.1f} ms ({t_solver / t_sur:.1f}x)", flush=True)
+    assert np.mean(e <= 1e-3) >= 0.97
+    assert t_sur <= 0.5 * t_solver
     base.close()
     sur.close()
