@@ -62,3 +62,26 @@ def test_bench_refuses_several_gpus():
     r = subprocess.run([sys.executable, os.path.join(root, "bench.py"), "--gpus", "2"], capture_output=True,
                        text=True, timeout=120)
     assert r.returncode == 2 and "one GPU" in r.stderr and r.stdout == ""
+
+
+def test_surrogate_particle_family_draws_and_grid():
+    """Particle-family surrogate inputs: every draw is resolved by its degree (8..16), the (D, K, alpha)
+    ranges are the uneven sweep's, axes are unit vectors (uniform on the sphere: mean near 0), and the
+    evaluation grid is 8 sets x 64 Fibonacci axes x 64^2 offsets in the documented instance order."""
+    inst = W.surrogate_particles(4096, 21)["inst"]
+    assert inst["D"].size == 4096 and W.resolvable(inst["D"], inst["K"], inst["L"]).all()
+    assert inst["L"].min() >= 8 and inst["L"].max() == 16
+    assert ((inst["D"] >= 15e-9) & (inst["D"] <= 30e-9)).all() and ((inst["K"] >= 500) & (inst["K"] <= 2e4)).all()
+    assert ((inst["alpha"] >= 0.05) & (inst["alpha"] <= 0.3)).all()
+    assert np.allclose(np.linalg.norm(inst["easy_axis"], axis=1), 1.0)
+    assert np.abs(inst["easy_axis"].mean(0)).max() < 0.05
+    ax = W.fibonacci_axes(64)
+    assert np.allclose(np.linalg.norm(ax, axis=1), 1.0) and np.abs(ax.mean(0)).max() < 0.02
+    g = W.surrogate_particle_grid()["inst"]
+    assert g["D"].size == 8 * 64 * 64 * 64
+    assert np.unique(g["D"]).size == 8 and W.resolvable(g["D"], g["K"], g["L"]).all()
+    i = 3 * 64 * 4096 + 5 * 4096 + 7 * 64 + 9          # set 3, axis 5, offset y 7, offset x 9
+    step = 24e-3 / 64
+    assert np.allclose(g["easy_axis"][i], ax[5])
+    assert np.allclose(g["offset"][i], [-12e-3 + 9.5 * step, -12e-3 + 7.5 * step, 0.0])
+    assert g["D"][i] == g["D"][3 * 262144] and g["D"][i] != g["D"][4 * 262144]

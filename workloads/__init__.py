@@ -114,6 +114,61 @@ def uneven_sweep(n=4096, seed=3, L_max=24):
                 n_harm=200, harm_z=False)
 
 
+def _particles_resolved_by(n, r, L_max):
+    """n draws of (D, K, alpha) from the uneven sweep's distribution, kept where truncation_degree <= L_max."""
+    D, K, alpha = np.empty(0), np.empty(0), np.empty(0)
+    while D.size < n:
+        m = 2 * (n - D.size) + 64
+        d = r.uniform(15e-9, 30e-9, m)
+        k = np.exp(r.uniform(np.log(500.0), np.log(2e4), m))
+        a = r.uniform(0.05, 0.3, m)
+        keep = truncation_degree(d, k) <= L_max
+        D, K, alpha = np.r_[D, d[keep]], np.r_[K, k[keep]], np.r_[alpha, a[keep]]
+    return D[:n], K[:n], alpha[:n]
+
+
+def fibonacci_axes(n):
+    """n unit vectors of the Fibonacci lattice on the sphere (z = 1 - (2i + 1)/n, golden-angle azimuths)."""
+    i = np.arange(n)
+    z = 1.0 - (2 * i + 1) / n
+    ph = i * np.pi * (3.0 - np.sqrt(5.0))
+    s = np.sqrt(1.0 - z * z)
+    return np.stack([s * np.cos(ph), s * np.sin(ph), z], 1)
+
+
+def surrogate_particles(n, seed, L_max=16):
+    """Training / held-out draws of the particle-family surrogate: (D, K, alpha) as in uneven_sweep but
+    only particles that a degree <= L_max resolves, easy axes uniform on the sphere, offsets
+    U[-12, 12] mT in x and y, L by truncation_degree (8..L_max); Lissajous drive, 1632 samples."""
+    r = np.random.default_rng(seed)
+    D, K, alpha = _particles_resolved_by(n, r, L_max)
+    z = r.uniform(-1, 1, n)
+    ph = r.uniform(0, 2 * np.pi, n)
+    s = np.sqrt(1 - z * z)
+    easy = np.stack([s * np.cos(ph), s * np.sin(ph), z], 1)
+    off = np.stack([r.uniform(-12e-3, 12e-3, n), r.uniform(-12e-3, 12e-3, n), np.zeros(n)], 1)
+    inst = _instances(D, np.full(n, MAGNETITE_MS), K, alpha, np.full(n, ROOM_T), easy, off,
+                      truncation_degree(D, K, hi=L_max))
+    return dict(inst=inst, drive=lissajous_drive(), samples=1632, settle=1)
+
+
+def surrogate_particle_grid(n_sets=8, n_axes=64, n_off=64, seed=50, L_max=16):
+    """Evaluation grid of the particle-family surrogate: n_sets (D, K, alpha) drawn like
+    surrogate_particles, each on n_axes Fibonacci axes x an n_off x n_off grid of offsets on +-12 mT
+    (instance order: set, axis, offset y, offset x)."""
+    r = np.random.default_rng(seed)
+    D, K, alpha = _particles_resolved_by(n_sets, r, L_max)
+    g = -12e-3 + 24e-3 * (np.arange(n_off) + 0.5) / n_off
+    p, a, iy, ix = np.meshgrid(np.arange(n_sets), np.arange(n_axes), np.arange(n_off), np.arange(n_off),
+                               indexing="ij")
+    p, a, iy, ix = p.ravel(), a.ravel(), iy.ravel(), ix.ravel()
+    n = p.size
+    off = np.stack([g[ix], g[iy], np.zeros(n)], 1)
+    inst = _instances(D[p], np.full(n, MAGNETITE_MS), K[p], alpha[p], np.full(n, ROOM_T), fibonacci_axes(n_axes)[a],
+                      off, truncation_degree(D[p], K[p], hi=L_max))
+    return dict(inst=inst, drive=lissajous_drive(), samples=1632, settle=1)
+
+
 def identification_problem(n_off=32, n_ang=16, n_comp=4, L=16, span=12e-3, n_harm=300, seed=4, noise_seed=40):
     """Parameter identification by gradient (the adjoint workload): an n_off x n_off grid of offsets on
     +-span (endpoints included) x n_ang in-plane easy-axis angles j pi / n_ang (from x) x n_comp particle
