@@ -311,3 +311,74 @@ def test_plan_queue_order_leaves_results_bitwise_unchanged(fpn, ctx, lissajous_f
             assert np.array_equal(plan.steps(), steps), rep
     finally:
         plan.close()
+
+
+def _bits(t):
+    """Bit patterns of a float32 tensor (NaN outputs of flagged instances compare equal)."""
+    import torch
+    return t.contiguous().view(torch.int32).cpu().numpy()
+
+
+@pytest.mark.gpu
+@pytest.mark.skip(reason="resumable parts (8 parts per instance, the state saved between them, a per-instance counter of finished parts polled by the next part) went silent on the GPU twice, the second time after the counter was moved to read-modify-write atomics; the cause is not found and the part-wise path is taken out of the library (no plan or solve accepts whole=)")
+def test_resumable_parts_leave_results_bitwise_unchanged(fpn, ctx, lissajous_full):
+    """The L = 16 bucket of the Lissajous batch (2312 instances, more than resident wavefronts) runs in
+    resumable parts: 8 per instance, cut at sample boundaries, the state saved between them.  A plan
+    with FPN_WHOLE_INSTANCES (every instance on one wavefront from start to end) gives the same samples,
+    harmonics, status and step counts bit for bit, and so do the part-wise plan's ordered launches."""
+    import torch
+    ws, (m, h, st) = lissajous_full
+    d = ws["drive"]
+    drive = fpn.make_drive(d["amp"], d["freq"], d["period"], d["phase"])
+    args = (ws["inst"], ws["inst"]["L"], drive, ws["samples"], ws["settle"], ws["n_harm"])
+    pw, pp = ctx.plan(*args, whole=True), ctx.plan(*args)
+    try:
+        pw.launch()
+        torch.cuda.synchronize()
+        print("whole-instance plan done", flush=True)
+        steps = pw.steps()
+        assert np.array_equal(pw.status.cpu().numpy(), st)
+        assert np.array_equal(pw.m.cpu().numpy(), m) and np.array_equal(pw.harm.cpu().numpy(), h)
+        for launch in range(2):
+            pp.launch()
+            torch.cuda.synchronize()
+            print(f"part-wise plan launch {launch} done", flush=True)
+            assert np.array_equal(pp.status.cpu().numpy(), st), launch
+            assert np.array_equal(_bits(pp.m), _bits(pw.m)), launch
+            assert np.array_equal(pp.steps(), steps), launch
+    finally:
+        pw.close()
+        pp.close()
+
+
+@pytest.mark.gpu
+@pytest.mark.skip(reason="resumable parts (8 parts per instance, the state saved between them, a per-instance counter of finished parts polled by the next part) went silent on the GPU twice, the second time after the counter was moved to read-modify-write atomics; the cause is not found and the part-wise path is taken out of the library (no plan or solve accepts whole=)")
+def test_resumable_parts_with_flagged_instances(fpn, ctx):
+    """8192 particles of the uneven sweep's distribution (sigma <= 12) all solved at L = 12, which does not
+    resolve the stiffest: instances stop in any part (UNRESOLVED, NaN outputs) and the later parts skip
+    them.  Part-wise and whole-instance plans agree bit for bit on samples (NaN included), harmonics,
+    status and step counts."""
+    import torch
+    ws = W.surrogate_particles(8192, 31)
+    d = ws["drive"]
+    drive = fpn.make_drive(d["amp"], d["freq"], d["period"], d["phase"])
+    L = np.full(8192, 12, np.int32)
+    args = (ws["inst"], L, drive, ws["samples"], ws["settle"], 32)
+    pw, pp = ctx.plan(*args, whole=True), ctx.plan(*args)
+    try:
+        pw.launch()
+        torch.cuda.synchronize()
+        print("whole-instance plan done", flush=True)
+        pp.launch()
+        torch.cuda.synchronize()
+        print("part-wise plan done", flush=True)
+        s = pw.status.cpu().numpy()
+        print("status counts", np.unique(s, return_counts=True), flush=True)
+        assert (s == fpn.FPN_INST_UNRESOLVED).sum() >= 10 and (s == fpn.FPN_INST_OK).sum() >= 4096
+        assert np.array_equal(pp.status.cpu().numpy(), s)
+        assert np.array_equal(_bits(pp.m), _bits(pw.m))
+        assert np.array_equal(_bits(pp._hm), _bits(pw._hm))
+        assert np.array_equal(pp.steps(), pw.steps())
+    finally:
+        pw.close()
+        pp.close()
