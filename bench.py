@@ -711,8 +711,8 @@ def bench_surrogate(args):
 
     if args.sur_domain == "particles":
         import workloads as W
-        tr, va, te = (W.surrogate_particles(args.sur_train, 21), W.surrogate_particles(1024, 22),
-                      W.surrogate_particles(1024, 23))
+        tr, va, te = (W.surrogate_particles(args.sur_train, 21, sigma_bias=args.sur_sigma_bias),
+                      W.surrogate_particles(1024, 22), W.surrogate_particles(1024, 23))
         ev = W.surrogate_particle_grid(n_sets=8, n_axes=64, n_off=64, seed=50)
         workload = "surrogate_particle_family_8x64x64x64"
     else:
@@ -744,6 +744,11 @@ def bench_surrogate(args):
     # the solver's rate on the training batch (the same family, large enough to be throughput-bound); the
     # 1024-instance test batch is bound by its slowest instance's steps and is reported beside it
     solver_rate = len(tr["inst"]["D"]) / t_tr
+    if args.sur_domain == "particles" and args.sur_sigma_bias > 0:
+        # a biased training batch is stiffer than the family: take the rate on an unbiased batch instead
+        rb = W.surrogate_particles(16384, 24)
+        _, _, t_rb, _ = solve(rb)
+        solver_rate = len(rb["inst"]["D"]) / t_rb
     ref_ok = torch.isfinite(torch.view_as_real(hte[:, :2])).reshape(hte.shape[0], -1).all(1).cpu().numpy()
     res_tol = {}
     for tol in (1e-3, 1e-2, 3e-2):
@@ -765,6 +770,7 @@ def bench_surrogate(args):
         "config": {"workload": workload, "evaluations": n_ev, "harmonics": KH,
                    "network": sur.nets[0].widths, "ensemble": 2, "residual_stage": bool(sur.model.residual),
                    "train_instances": len(tr["inst"]["D"]), "train_steps": args.sur_steps,
+                   "train_sigma_bias": args.sur_sigma_bias,
                    "residual_train_steps": args.sur_res_steps, "train_seconds": sur.train_seconds,
                    "validation_rel_l2_median": float(np.median(true_va)),
                    "validation_rel_l2_p99": float(np.quantile(true_va, 0.99)),
@@ -797,6 +803,9 @@ def main():
                     help="surrogate workload: the Lissajous particle's family (axis angle and offset vary) or "
                          "particles of the uneven sweep's distribution that degree 16 resolves (D, K, alpha, axis "
                          "on the sphere and offset vary; 8 parameter sets x 64 Fibonacci axes x 64^2 offsets)")
+    ap.add_argument("--sur-sigma-bias", type=float, default=0.0,
+                    help="surrogate workload, particle family: draw the training particles with weight "
+                         "(1 + b sigma / 12) / (1 + b) toward the stiff end (held-out and evaluation sets unchanged)")
     ap.add_argument("--sur-steps", type=int, default=16000, help="surrogate workload: Adam steps per member")
     ap.add_argument("--sur-res-steps", type=int, default=16000,
                     help="surrogate workload: Adam steps per member of the residual stage (0: none)")

@@ -114,15 +114,20 @@ def uneven_sweep(n=4096, seed=3, L_max=24):
                 n_harm=200, harm_z=False)
 
 
-def _particles_resolved_by(n, r, L_max):
-    """n draws of (D, K, alpha) from the uneven sweep's distribution, kept where truncation_degree <= L_max."""
+def _particles_resolved_by(n, r, L_max, sigma_bias=0.0):
+    """n draws of (D, K, alpha) from the uneven sweep's distribution, kept where truncation_degree <= L_max;
+    with sigma_bias b > 0 a draw is also kept only with probability (1 + b sigma / sigma_max) / (1 + b)
+    (sigma_max = L_max - 4), which moves weight toward the stiff end."""
     D, K, alpha = np.empty(0), np.empty(0), np.empty(0)
     while D.size < n:
-        m = 2 * (n - D.size) + 64
+        m = (4 if sigma_bias > 0 else 2) * (n - D.size) + 64
         d = r.uniform(15e-9, 30e-9, m)
         k = np.exp(r.uniform(np.log(500.0), np.log(2e4), m))
         a = r.uniform(0.05, 0.3, m)
         keep = truncation_degree(d, k) <= L_max
+        if sigma_bias > 0:
+            w = (1.0 + sigma_bias * anisotropy_ratio(d, k) / (L_max - 4)) / (1.0 + sigma_bias)
+            keep &= r.uniform(0, 1, m) < w
         D, K, alpha = np.r_[D, d[keep]], np.r_[K, k[keep]], np.r_[alpha, a[keep]]
     return D[:n], K[:n], alpha[:n]
 
@@ -136,12 +141,13 @@ def fibonacci_axes(n):
     return np.stack([s * np.cos(ph), s * np.sin(ph), z], 1)
 
 
-def surrogate_particles(n, seed, L_max=16):
+def surrogate_particles(n, seed, L_max=16, sigma_bias=0.0):
     """Training / held-out draws of the particle-family surrogate: (D, K, alpha) as in uneven_sweep but
     only particles that a degree <= L_max resolves, easy axes uniform on the sphere, offsets
-    U[-12, 12] mT in x and y, L by truncation_degree (8..L_max); Lissajous drive, 1632 samples."""
+    U[-12, 12] mT in x and y, L by truncation_degree (8..L_max); Lissajous drive, 1632 samples.
+    sigma_bias > 0 (training sets only) draws the stiff particles more often (_particles_resolved_by)."""
     r = np.random.default_rng(seed)
-    D, K, alpha = _particles_resolved_by(n, r, L_max)
+    D, K, alpha = _particles_resolved_by(n, r, L_max, sigma_bias)
     z = r.uniform(-1, 1, n)
     ph = r.uniform(0, 2 * np.pi, n)
     s = np.sqrt(1 - z * z)
