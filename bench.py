@@ -723,8 +723,10 @@ def bench_surrogate(args):
     hva, _, _, _ = solve(va)
     hte, _, t_te, _ = solve(te)
     print(f"[bench] training targets: {len(tr['inst']['D'])} solves in {t_tr:.1f} s", file=sys.stderr, flush=True)
-    sur = Surrogate(ctx, KH)
-    sur.fit(tr["inst"], htr, steps=args.sur_steps, batch=4096, lr=2e-3, residual_steps=args.sur_res_steps)
+    w, d = (int(v) for v in args.sur_hidden.lower().split("x"))
+    sur = Surrogate(ctx, KH, hidden=[w] * d)
+    sur.fit(tr["inst"], htr, steps=args.sur_steps, batch=4096, lr=2e-3, residual_steps=args.sur_res_steps,
+            log=lambda msg: print(f"[bench] train {msg}", file=sys.stderr, flush=True))
     true_va, _ = sur.calibrate(va["inst"], hva)
     by_sigma = validation_error_by_sigma(sur, va, hva)
     n_ev = ev["inst"]["D"].size
@@ -806,6 +808,8 @@ def main():
     ap.add_argument("--sur-sigma-bias", type=float, default=0.0,
                     help="surrogate workload, particle family: draw the training particles with weight "
                          "(1 + b sigma / 12) / (1 + b) toward the stiff end (held-out and evaluation sets unchanged)")
+    ap.add_argument("--sur-hidden", default="512x4",
+                    help="surrogate workload: hidden layers as WIDTHxDEPTH (width a multiple of 128)")
     ap.add_argument("--sur-steps", type=int, default=16000, help="surrogate workload: Adam steps per member")
     ap.add_argument("--sur-res-steps", type=int, default=16000,
                     help="surrogate workload: Adam steps per member of the residual stage (0: none)")
