@@ -351,8 +351,10 @@ fpn_status fpn_mlp_train_step(fpn_mlp m, const float* x, const float* t, int64_t
 /* ---- surrogate evaluation ----
  * Harmonics 1..K_h of the x and y channels predicted by a two-member network ensemble from the
  * instance features, with the solver as the fallback and as the reference its error is measured against:
- *   features x = (log D, log K, alpha, n_x, n_y, n_z, offset_x / 12 mT, offset_y / 12 mT), the axis
- *   taken in the half-space n_z > 0 (n and -n describe the same particle); K must be > 0;
+ *   features x = (log D, sigma, alpha, n_x, n_y, n_z, offset_x / 12 mT, offset_y / 12 mT) with
+ *   sigma = K (pi D^3 / 6) / (k_B T) (the anisotropy barrier in units of k_B T, which sets the Neel
+ *   relaxation time), the axis taken in the half-space n_z > 0 (n and -n describe the same particle);
+ *   K must be > 0;
  *   prediction = (y_a + y_b) / 2 / out_scale, network output layout [channel x, y][k = 1..K_h][re, im]
  *   (y_k = net[k](x), plus res[k](x) / res_scale with a residual stage);
  *   error estimate = err_calib * ||y_a - y_b|| / ||(y_a + y_b) / 2||  (err_calib is fitted on held-out

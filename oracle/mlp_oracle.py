@@ -3,7 +3,7 @@
 Imported only by tests/, __graft_entry__.smoke() and bench.py's cpu_baseline leg; the
 product library never calls it and shares no code with it.
 
-The paper has no learned part: the network maps a particle instance (log D, log K,
+The paper has no learned part: the network maps a particle instance (log D, sigma = K V / (k_B T),
 alpha, easy axis n as a unit 3-vector, 2D offset field) to the real and imaginary parts of
 the first harmonics of dm/dt (the phi-hat of model M1).  What is fixed here is ordinary
 deep-learning arithmetic, written out plainly:

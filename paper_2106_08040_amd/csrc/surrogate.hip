@@ -4,12 +4,15 @@
 
 #include <cstdint>
 
+#include "physics.hpp"
 #include "surrogate.hpp"
 
 namespace fpn {
 namespace sur {
 
-// x[i] = (log D, log K, alpha, n_x, n_y, n_z, offset_x / 12 mT, offset_y / 12 mT).
+// x[i] = (log D, sigma, alpha, n_x, n_y, n_z, offset_x / 12 mT, offset_y / 12 mT), sigma = K V / (k_B T)
+// with V = pi D^3 / 6: the anisotropy barrier in units of k_B T, the exponent of the Neel relaxation
+// time, which the response of stiff particles follows (K is log D, sigma and T away).
 // n and -n describe the same particle (the anisotropy energy is even in n), so the axis is
 // mapped to the half-space n_z > 0 (ties broken by n_y, then n_x).  Instances with
 // non-physical parameters get status 1 and NaN features.
@@ -36,7 +39,7 @@ __global__ void features_kernel(int64_t n, const double* D, const double* Ms, co
     a2 = -a2;
   }
   xi[0] = float(log(D[i]));
-  xi[1] = float(log(K[i]));
+  xi[1] = float(K[i] * (kPi / 6.0) * D[i] * D[i] * D[i] / (kBoltzmann * T[i]));
   xi[2] = float(alpha[i]);
   xi[3] = float(a0);
   xi[4] = float(a1);

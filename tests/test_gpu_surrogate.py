@@ -1,7 +1,8 @@
 """GPU tests of the learned surrogate (fpn_surrogate_features / fpn_surrogate_predict) trained on the
 solver's own output.
 
-* Features equal their definition (log D, log K, alpha, axis in the n_z > 0 half-space, offset / 12 mT).
+* Features equal their definition (log D, sigma = K V / (k_B T), alpha, axis in the n_z > 0 half-space,
+  offset / 12 mT).
 * tol = 0 hands every instance to the solver: the output is the solver's, bit for bit.
 * tol = inf keeps every instance on the ensemble: the output is the mean of the two networks.
 * After training, the calibrated error estimate bounds the true error (against the solver, itself
@@ -67,7 +68,8 @@ def test_features_match_definition(fpn, ctx):
     n = inst["easy_axis"].copy()
     flip = (n[:, 2] < 0) | ((n[:, 2] == 0) & (n[:, 1] < 0))
     n[flip] *= -1
-    ref = np.column_stack([np.log(inst["D"]), np.log(inst["K"]), inst["alpha"], n,
+    sigma = inst["K"] * (np.pi * inst["D"] ** 3 / 6) / (1.380649e-23 * inst["T"])
+    ref = np.column_stack([np.log(inst["D"]), sigma, inst["alpha"], n,
                            inst["offset"][:, 0] / 12e-3, inst["offset"][:, 1] / 12e-3])
     assert (st.cpu().numpy() == 0).all()
     assert np.abs(x - ref).max() <= 1e-6 * np.abs(ref).max()
